@@ -1,0 +1,172 @@
+"""Pins of the oracle's Newton / sparse-LU step against results fixed by the
+mathematics: the stability function on linear problems (scalar and per
+Fourier mode), an independent nonlinear solver (MINPACK), the order of
+accuracy against an independent explicit reference, conservation of quadratic
+invariants by Gauss methods, and the exact reduction of the index-1 DAE."""
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.optimize as so
+import scipy.sparse as sp
+
+from oracle import newton as nw
+from oracle import problems as pb
+from oracle import tableau as tb
+from paper_2101_01776_amd import inputs
+
+FAMS = [("gauss", s) for s in (1, 2, 3, 4, 5)] + [("radau", s) for s in (1, 2, 3, 4, 5)]
+
+
+class _Diagonal:
+    """u' = diag(lam) u (a stack of Dahlquist test equations)."""
+
+    def __init__(self, lam):
+        self.lam = np.asarray(lam, dtype=float)
+        self.size = len(self.lam)
+        self.mass = np.ones(self.size)
+
+    def rhs(self, u, t=0.0):
+        return self.lam * u
+
+    def jac(self, u, t=0.0):
+        return sp.diags(self.lam).tocsr(), None, None
+
+    def initial_k(self, u, t):
+        return self.rhs(u, t)
+
+
+@pytest.mark.parametrize("family,s", FAMS)
+def test_scalar_step_is_stability_function(family, s):
+    A, b, c = tb.tableau(family, s)
+    lam = np.array([-0.5, -7.0, -3000.0, 0.7])
+    u0 = np.array([1.0, -2.0, 0.5, 3.0])
+    dt = 0.1
+    u1, _, _ = nw.irk_step(_Diagonal(lam), A, b, c, u0, 0.0, dt)
+    want = np.array([tb.stability_function(A, b, dt * l).real for l in lam]) * u0
+    assert np.max(np.abs(u1 - want) / np.maximum(np.abs(want), 1e-300)) < 1e-13
+
+
+@pytest.mark.parametrize("family,s", [("gauss", 3), ("radau", 3), ("gauss", 5)])
+def test_linear_diffusion_fourier_symbol(family, s):
+    """Frozen-coefficient (kappa = 1) periodic diffusion: each Fourier mode is
+    multiplied by R(dt lambda_k), lambda_k = -(4/h^2)(sin^2(pi kx/n) + sin^2(pi ky/n))."""
+    n = 16
+    A, b, c = tb.tableau(family, s)
+    p = pb.NonlinearDiffusion2D(n, forcing="none", kappa_quadratic=False)
+    u0 = inputs.nldiff_random_u0(n, 7)
+    dt = 5e-3
+    u1, _, _ = nw.irk_step(p, A, b, c, u0.ravel(), 0.0, dt)
+    k = np.arange(n)
+    s1 = (4.0 * n * n) * np.sin(np.pi * k / n) ** 2
+    lam = -(s1[:, None] + s1[None, :])
+    R = np.vectorize(lambda z: tb.stability_function(A, b, z).real)(dt * lam)
+    want = np.real(np.fft.ifft2(R * np.fft.fft2(u0)))
+    assert np.linalg.norm(u1 - want.ravel()) / np.linalg.norm(want) < 1e-12
+
+
+@pytest.mark.parametrize("family,s", [("gauss", 2), ("gauss", 3), ("radau", 2), ("radau", 3)])
+def test_matches_minpack_root(family, s):
+    """Stage solution equals MINPACK's hybrid root of the same residual."""
+    A, b, c = tb.tableau(family, s)
+    for prob, u0, dt in ((pb.Burgers1D(32, 0.01), inputs.burgers_u0(32, 1), 1e-2),
+                         (pb.NonlinearDiffusion2D(8), inputs.nldiff_u0(8).ravel(), 5e-3)):
+        K, _ = nw.irk_stages(prob, A, c, u0, 0.2, dt)
+        K0 = nw.initial_stages(prob, u0, 0.2, s)
+        sol = so.root(lambda z: nw.stage_residual(prob, A, c, u0, 0.2, dt, z.reshape(K.shape)).ravel(),
+                      K0.ravel(), method="hybr", options={"xtol": 1e-15, "maxfev": 200000})
+        Kr = sol.x.reshape(K.shape)
+        assert np.linalg.norm(K - Kr) / np.linalg.norm(K) < 1e-11
+
+
+@pytest.mark.parametrize("family,s", [("gauss", 1), ("gauss", 2), ("gauss", 3),
+                                      ("radau", 1), ("radau", 2), ("radau", 3)])
+def test_order_of_accuracy(family, s):
+    """Observed order 2s (Gauss) / 2s-1 (Radau IIA) on 1-D Burgers (n=32),
+    against an explicit DOP853 reference at rtol 1e-13."""
+    n, nu, T = 32, 0.01, 0.4
+    prob = pb.Burgers1D(n, nu)
+    u0 = 0.5 * inputs.burgers_u0(n, 4)
+    ref = si.solve_ivp(lambda t, u: prob.rhs(u, t), (0, T), u0, method="DOP853",
+                       rtol=1e-13, atol=1e-15).y[:, -1]
+    A, b, c = tb.tableau(family, s)
+    p = 2 * s if family == "gauss" else 2 * s - 1
+    dts = [0.1, 0.05, 0.025] if p >= 5 else [0.05, 0.025, 0.0125]
+    errs = []
+    for dt in dts:
+        u = u0.copy()
+        for m in range(int(round(T / dt))):
+            u, _, _ = nw.irk_step(prob, A, b, c, u, m * dt, dt)
+        errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert min(errs) > 1e-12, errs          # still above the solver floor
+    assert abs(rates[-1] - p) < 0.3, (errs, rates)
+
+
+def test_gauss_conserves_quadratic_invariants_vsf():
+    """With nu = 0, the Arakawa semi-discretization conserves enstrophy
+    sum(omega^2) and energy sum(psi omega); Gauss methods conserve quadratic
+    invariants, Radau IIA dissipates them."""
+    n = 12
+    prob = pb.VorticityStreamfunction2D(n, 0.0)
+    st0 = inputs.vsf_state0(n, 3, 6).ravel()
+    nn = n * n
+    ens = lambda u: np.sum(u[:nn] ** 2)
+    energy = lambda u: np.sum(u[:nn] * u[nn:])
+    for fam, s in (("gauss", 2), ("gauss", 3)):
+        A, b, c = tb.tableau(fam, s)
+        u1, _, _ = nw.irk_step(prob, A, b, c, st0, 0.0, 5e-2)
+        assert abs(ens(u1) - ens(st0)) / ens(st0) < 1e-12
+        assert abs(energy(u1) - energy(st0)) / energy(st0) < 1e-12
+    A, b, c = tb.tableau("radau", 2)
+    u1, _, _ = nw.irk_step(prob, A, b, c, st0, 0.0, 0.5)
+    assert ens(u1) < ens(st0) * (1 - 1e-8)
+
+
+def test_dae_equals_reduced_ode():
+    """A linear, uniquely solvable constraint: the DAE step equals the step of
+    the reduced ODE omega' = J_A(psi(omega), omega) + nu Lap omega with
+    psi(omega) the spectral inverse of -Lap_h; psi_{n+1} stays consistent."""
+    n, nu, dt = 12, 1e-2, 1e-2
+    prob = pb.VorticityStreamfunction2D(n, nu)
+    st0 = inputs.vsf_state0(n, 5, 5)
+    h = 1.0 / n
+
+    def reduced_rhs(om_flat):
+        om = om_flat.reshape(n, n)
+        psi = inputs.vsf_psi0(om)
+        return (pb.arakawa(psi, om, h) + nu * pb.laplacian(om, h)).ravel()
+
+    for fam, s in (("radau", 2), ("gauss", 2), ("radau", 3)):
+        A, b, c = tb.tableau(fam, s)
+        u1, _, _ = nw.irk_step(prob, A, b, c, st0.ravel(), 0.0, dt)
+        om0 = st0[0].ravel()
+        res = lambda z: np.concatenate([
+            z.reshape(s, -1)[i] - reduced_rhs(om0 + dt * (A[i] @ z.reshape(s, -1))) for i in range(s)])
+        # plain Newton on the reduced stage equations with a dense
+        # central-difference Jacobian (independent of the DAE formulation)
+        z = np.concatenate([reduced_rhs(om0)] * s)
+        for _ in range(30):
+            r = res(z)
+            if np.linalg.norm(r) <= 1e-13 * np.linalg.norm(z):
+                break
+            eps = 1e-7 * max(1.0, np.abs(z).max())
+            Jd = np.empty((z.size, z.size))
+            for q in range(z.size):
+                e = np.zeros(z.size)
+                e[q] = eps
+                Jd[:, q] = (res(z + e) - res(z - e)) / (2 * eps)
+            z = z - np.linalg.solve(Jd, r)
+        om1 = om0 + dt * (b @ z.reshape(s, -1))
+        assert np.linalg.norm(u1[: n * n] - om1) / np.linalg.norm(om1) < 1e-11
+        psi1 = u1[n * n:].reshape(n, n)
+        assert np.max(np.abs(psi1 - inputs.vsf_psi0(u1[: n * n].reshape(n, n)))) < 1e-11 * np.abs(psi1).max()
+
+
+def test_radau_update_equals_last_stage():
+    """Radau IIA is stiffly accurate: u_n + dt sum b_i k_i = U_s."""
+    A, b, c = tb.tableau("radau", 3)
+    prob = pb.NonlinearDiffusion2D(8)
+    u0 = inputs.nldiff_u0(8).ravel()
+    u1, K, _ = nw.irk_step(prob, A, b, c, u0, 0.0, 5e-3)
+    Us = nw.stage_values(A, u0, 5e-3, K)[-1]
+    assert np.max(np.abs(u1 - Us)) < 1e-15 * max(1.0, np.abs(u1).max()) * 10
