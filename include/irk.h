@@ -1,0 +1,199 @@
+/*
+ * irk.h -- C ABI of the MI355X (gfx950) fully implicit Runge-Kutta stage
+ * solver.
+ *
+ * The library advances a method-of-lines system  M u' = N(u, t)  (paper,
+ * Section 1.1, equation (problem)) by one step of an s-stage Gauss or
+ * Radau IIA method: it solves the nonlinear stage equations (equation
+ * (stages); for the index-1 DAE, equation (dae_stage) of Section 6) and
+ * applies the update (equation (update)).  Each nonlinear iteration is the
+ * Newton-like iteration of Section 3.2 (Algorithm 1 of Section 5) written in
+ * the real eigenbasis of A0^{-1}: one preconditioned FGMRES solve per real
+ * eigenvalue and per conjugate pair, the pair blocks preconditioned with the
+ * block lower-triangular preconditioner of equation (Lprec) with the Schur
+ * complement approximation gamma_* of equation (gamma*), whose diagonal
+ * inverses are one geometric-multigrid V-cycle each.
+ *
+ * Conventions for every entry point:
+ *   - Nothing throws across the ABI; every call returns an irk_status
+ *     (irk_destroy returns nothing and accepts NULL).
+ *   - "device" pointers are HIP device addresses on the device that is
+ *     current when irk_create is called; "host" pointers are ordinary host
+ *     memory.  All device pointers must be 8-byte aligned; the workspace
+ *     256-byte aligned.
+ *   - The caller owns every buffer it passes; the library owns only the
+ *     context (host memory plus a small pinned host staging buffer).
+ *   - All device work is issued on the HIP stream given to irk_create.
+ *     Calls on one context must not overlap; distinct contexts may run
+ *     concurrently on distinct streams.
+ *
+ * Field layout: a scalar field is row-major [ny][nx] float64, x fastest
+ * (1-D problems have ny = 1).  The vorticity-streamfunction state is
+ * [2][ny][nx]: omega then psi.
+ */
+#ifndef IRK_H
+#define IRK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IRK_MAX_STAGES 5
+#define IRK_MAX_RESTART 64
+
+typedef enum irk_status {
+    IRK_OK = 0,
+    IRK_E_ARG = -1,         /* invalid argument (sizes, pointers, options)   */
+    IRK_E_NOMEM = -2,       /* workspace too small / budget exceeded         */
+    IRK_E_NOCONV = -3,      /* Newton-like iteration did not converge        */
+    IRK_E_NONFINITE = -4,   /* NaN or Inf in the input or in a residual      */
+    IRK_E_DEVICE = -5,      /* a HIP runtime call failed                     */
+    IRK_E_UNSUPPORTED = -6, /* option combination not implemented            */
+    IRK_E_BUSY = -7         /* serving: request not finished yet             */
+} irk_status;
+
+typedef enum irk_family {
+    IRK_GAUSS = 0,          /* s-stage Gauss, order 2s                       */
+    IRK_RADAU_IIA = 1       /* s-stage Radau IIA, order 2s-1                 */
+} irk_family;
+
+typedef enum irk_op_kind {
+    /* u_t + (u^2/2)_x = nu u_xx: N_i = -(u_{i+1}^2-u_{i-1}^2)/(4h)
+       + nu (u_{i+1}-2u_i+u_{i-1})/h^2, periodic, M = I                       */
+    IRK_OP_BURGERS_1D = 0,
+    /* u_t = div((1+u^2) grad u) + f: 5-point flux form with face
+       coefficient (kappa(u_c)+kappa(u_nb))/2, periodic, M = I               */
+    IRK_OP_NLDIFF_2D = 1,
+    /* omega_t = J_A(psi, omega) + nu Lap omega (Arakawa Jacobian),
+       0 = Lap psi + omega - mean(omega) - mean(psi) (index-1 constraint
+       with the gauge mean(psi) = 0), periodic, M = diag(I, 0)               */
+    IRK_OP_VSF_2D = 2
+} irk_op_kind;
+
+typedef enum irk_forcing {
+    IRK_FORCING_NONE = 0,
+    /* f = u*_t - div((1+u*^2) grad u*), u* = sin(2 pi x) sin(2 pi y) cos t  */
+    IRK_FORCING_MMS = 1,
+    /* f = u*_t - N_h(u*): u* solves the semi-discrete system exactly        */
+    IRK_FORCING_MMS_DISCRETE = 2
+} irk_forcing;
+
+/* Spatial operator on the periodic domain [0, length)^d, nodes x_i = i h,
+ * h = length / nx (nx = ny required in 2-D).                               */
+typedef struct irk_operator {
+    int kind;               /* irk_op_kind                                    */
+    int nx, ny;             /* grid; 1-D: ny = 1                              */
+    double length;          /* domain side                                    */
+    double nu;              /* viscosity (Burgers, VSF); unused for NLDIFF    */
+    int forcing;            /* irk_forcing (NLDIFF only)                      */
+} irk_operator;
+
+typedef struct irk_options {
+    double newton_rtol;     /* stop when ||F(K)|| <= rtol ||F(K0)|| + atol    */
+    double newton_atol;
+    double krylov_rtol;     /* relative FGMRES tolerance per block solve      */
+    int restart;            /* FGMRES restart length (1..IRK_MAX_RESTART)     */
+    int max_krylov;         /* FGMRES iteration cap per block solve           */
+    int max_newton;         /* Newton-like iteration cap                      */
+    int newton_like;        /* 0: simplified Newton (last-stage Jacobian),
+                               1: lump each block to its argmax |d_kk| stage  */
+    int gamma_mode;         /* 0: gamma_* = eta + beta^2/eta, 1: gamma = eta  */
+    int prec_fp32;          /* 1: V-cycles in float32, 0: float64            */
+    int cheb_degree;        /* Chebyshev pre- and post-smoothing degree       */
+    int mg_coarsest;        /* coarsest grid side of the V-cycle hierarchy    */
+    int coarse_iters;       /* Chebyshev iterations on the coarsest level     */
+} irk_options;
+
+/* Per-step counters.  "Preconditioner applications" follow the paper's
+ * accounting (Section 7.1): one per Krylov iteration on a 1x1 block, two per
+ * Krylov iteration on a 2x2 block.                                          */
+typedef struct irk_stats {
+    int newton_its;
+    int krylov_its;             /* all blocks, all Newton iterations          */
+    int krylov_its_block[IRK_MAX_STAGES];
+    int vcycles;
+    int prec_applications;
+    double res0;                /* ||F(K0)||_2                                */
+    double final_res;           /* ||F(K)||_2 at acceptance                   */
+} irk_stats;
+
+/* ---------------- host-only entry points (no GPU needed) ---------------- */
+
+const char *irk_status_str(irk_status st);
+
+/* Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||M K0||),
+ * krylov_rtol 1e-5 (the paper's GMRES tolerance, Section 7.1), restart 30,
+ * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
+ * cheb_degree 3, mg_coarsest 8, coarse_iters 24.                           */
+void irk_default_options(irk_options *opt);
+
+/* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,
+ * b and c of length s, written to host arrays.  Nodes are the roots of
+ * P_s(2x-1) (Gauss) or P_s(2x-1) - P_{s-1}(2x-1) (Radau IIA), A and b the
+ * collocation integrals; computed in long double.  1 <= s <= 5.            */
+irk_status irk_tableau(irk_family family, int s, double *A, double *b, double *c);
+
+/* Real eigenbasis of A0^{-1} (Sections 3.1 and 5): A0^{-1} = T Lambda T^{-1},
+ * Lambda block diagonal with a 1x1 block eta per real eigenvalue and a 2x2
+ * block [[eta, beta], [-beta, eta]] per pair eta +- i beta (beta > 0; this is
+ * the form [[eta, phi], [-beta^2/phi, eta]] of Section 3.1 with phi = beta).
+ * Blocks are ordered real first, then pairs by decreasing beta.  Host
+ * outputs: T, Tinv (s x s row-major), nblocks, and per block its width
+ * (1 or 2), eta, beta, gamma_* = eta + beta^2/eta (equation (gamma*)) and the
+ * first transformed row it covers.  Arrays sized IRK_MAX_STAGES suffice.   */
+irk_status irk_eigen_blocks(irk_family family, int s, double *T, double *Tinv,
+                            int *nblocks, int *width, double *eta, double *beta,
+                            double *gamma_star, int *first_row);
+
+/* Bytes of device workspace irk_create needs for this problem (0 on bad
+ * arguments).                                                               */
+size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op,
+                           const irk_options *opt);
+
+/* ---------------------------- device entry points ------------------------ */
+
+typedef struct irk_ctx irk_ctx;   /* opaque, library-owned */
+
+/* Build the tableau, its eigenbasis and the solver state for one problem.
+ * device_workspace: caller-owned device buffer of at least
+ * irk_workspace_bytes(...) bytes, 256-byte aligned, kept alive and unused by
+ * the caller until irk_destroy.  hip_stream: a hipStream_t (NULL = default
+ * stream).  opt may be NULL (defaults).  On success *out receives the
+ * context.  Errors: IRK_E_ARG (bad sizes: s outside 1..5, grid not divisible
+ * by 2 down to mg_coarsest, nx != ny in 2-D), IRK_E_NOMEM (workspace too
+ * small), IRK_E_DEVICE.                                                     */
+irk_status irk_create(irk_family family, int s, const irk_operator *op,
+                      const irk_options *opt, void *device_workspace,
+                      size_t workspace_bytes, void *hip_stream, irk_ctx **out);
+
+/* One step from (u_n, t_n) with step dt (Algorithm 1): device input u_n,
+ * device output u_np1 (may alias u_n), both in the field layout above.
+ * tol > 0 overrides options.newton_rtol for this step.  stats (host) may be
+ * NULL.  The call returns after the step has completed on the stream.
+ * Errors: IRK_E_NONFINITE (NaN/Inf in u_n or a residual), IRK_E_NOCONV
+ * (max_newton reached or the residual grows by 1e8), IRK_E_DEVICE.  On any
+ * error u_np1 is not written.                                               */
+irk_status irk_step(irk_ctx *ctx, const double *u_n, double t_n, double dt,
+                    double tol, double *u_np1, irk_stats *stats);
+
+/* Stage residual F_i(K) = M k_i - N(u_n + dt sum_j a_ij k_j, t_n + c_i dt)
+ * (equation (stages) / (dae_stage)) for caller stage vectors K (device,
+ * [s][field]) into F (device, [s][field]).  Evaluates exactly the residual
+ * the Newton loop of irk_step uses.                                        */
+irk_status irk_eval_residual(irk_ctx *ctx, const double *u_n, double t_n,
+                             double dt, const double *K, double *F);
+
+/* Copy the stage vectors K of the last successful irk_step (device, [s][field])
+ * into the caller's device buffer.                                          */
+irk_status irk_get_stages(irk_ctx *ctx, double *K);
+
+/* Release the context (not the caller's workspace).  NULL is accepted.     */
+void irk_destroy(irk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRK_H */

@@ -1,0 +1,702 @@
+// Host driver of the IRK stage solve: workspace layout, the Newton-like loop
+// of Algorithm 1 in the real eigenbasis of A0^{-1}, right-preconditioned
+// FGMRES per eigen-block with the block lower-triangular preconditioner of
+// equation (Lprec), and the geometric-multigrid V-cycle that applies each
+// diagonal inverse.  All arithmetic on fields runs in the kernels of
+// kernels.hip; the host does the s x s algebra, the Hessenberg least-squares
+// problem and the control flow.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "irk_internal.h"
+#include "kernels.h"
+
+namespace irk {
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Multigrid level geometry for a problem (level 0 = the grid).
+struct LevelGeom {
+    int nlev = 0;
+    int nx[IRK_MAX_LEVELS], ny[IRK_MAX_LEVELS];
+};
+
+static bool level_geometry(const irk_operator &op, int coarsest, LevelGeom *lg) {
+    int nx = op.nx, ny = op.ny;
+    const bool one_d = (ny == 1);
+    int L = 0;
+    while (true) {
+        if (L >= IRK_MAX_LEVELS) return false;
+        lg->nx[L] = nx;
+        lg->ny[L] = ny;
+        ++L;
+        const bool can = (nx % 2 == 0) && (nx / 2 >= coarsest) &&
+                         (one_d || ((ny % 2 == 0) && (ny / 2 >= coarsest)));
+        if (!can) break;
+        nx /= 2;
+        if (!one_d) ny /= 2;
+    }
+    lg->nlev = L;
+    // the coarsest level is solved inside one work-group
+    return (size_t)lg->nx[L - 1] * lg->ny[L - 1] <= 1024;
+}
+
+// Everything irk_create decides before touching the device.
+struct Plan {
+    irk_operator op;
+    irk_options opt;
+    EigenBlocks eb;
+    int family = 0, s = 0, nvar = 1;
+    size_t npts = 0, nf = 0;
+    int maxw = 1;                       // widest eigen-block
+    int m = 30;                         // restart length
+    LevelGeom lg;
+    size_t tsz = 4;                     // bytes per V-cycle scalar
+    int nhier = 0;                      // distinct linearization stages
+    int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
+    int row_hier[IRK_MAX_STAGES];       // transformed row -> hierarchy
+    // workspace offsets
+    size_t off_K, off_Y, off_Fh, off_U, off_V, off_Z, off_part, off_dv, off_ctr, off_tab;
+    size_t off_lev[IRK_MAX_LEVELS][4];
+    size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
+    size_t total = 0;
+};
+
+static bool valid_options(const irk_options &o) {
+    return o.restart >= 1 && o.restart <= IRK_MAX_RESTART && o.max_krylov >= 1 && o.max_newton >= 1 &&
+           (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
+           (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 8 &&
+           o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.krylov_rtol > 0 && o.krylov_rtol < 1 &&
+           o.newton_rtol >= 0 && o.newton_atol >= 0;
+}
+
+static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
+    if (!op || s < 1 || s > IRK_MAX_STAGES) return IRK_E_ARG;
+    if (family != IRK_GAUSS && family != IRK_RADAU_IIA) return IRK_E_ARG;
+    P->op = *op;
+    if (opt) P->opt = *opt; else irk_default_options(&P->opt);
+    if (!valid_options(P->opt)) return IRK_E_ARG;
+    const irk_operator &o = P->op;
+    if (o.nx < 3 || o.ny < 1 || !(o.length > 0)) return IRK_E_ARG;
+    if (o.kind == IRK_OP_BURGERS_1D) {
+        if (o.ny != 1 || !(o.nu >= 0)) return IRK_E_ARG;
+    } else if (o.kind == IRK_OP_NLDIFF_2D || o.kind == IRK_OP_VSF_2D) {
+        if (o.ny != o.nx) return IRK_E_ARG;
+        if (o.kind == IRK_OP_VSF_2D && !(o.nu >= 0)) return IRK_E_ARG;
+        if (o.kind == IRK_OP_NLDIFF_2D && (o.forcing < 0 || o.forcing > 2)) return IRK_E_ARG;
+    } else {
+        return IRK_E_ARG;
+    }
+    if (!build_eigen_blocks(family, s, &P->eb)) return IRK_E_ARG;
+    for (int k = 0; k < P->eb.nblocks; ++k)
+        if (!(P->eb.eta[k] > 0)) return IRK_E_UNSUPPORTED;     // Assumption 1
+    P->family = family;
+    P->s = s;
+    P->nvar = (o.kind == IRK_OP_VSF_2D) ? 2 : 1;
+    P->npts = (size_t)o.nx * o.ny;
+    P->nf = P->nvar * P->npts;
+    P->maxw = 1;
+    for (int k = 0; k < P->eb.nblocks; ++k) P->maxw = std::max(P->maxw, P->eb.width[k]);
+    P->m = P->opt.restart;
+    if (!level_geometry(o, P->opt.mg_coarsest, &P->lg)) return IRK_E_ARG;
+    P->tsz = P->opt.prec_fp32 ? sizeof(float) : sizeof(double);
+
+    // linearization stage of every transformed row (Newton-like (0) or (1))
+    P->nhier = 0;
+    for (int r = 0; r < s; ++r) {
+        const int stage = P->opt.newton_like == 1 ? P->eb.argmax_stage[r] : s - 1;
+        int hidx = -1;
+        for (int q = 0; q < P->nhier; ++q)
+            if (P->hier_stage[q] == stage) hidx = q;
+        if (hidx < 0) { hidx = P->nhier++; P->hier_stage[hidx] = stage; }
+        P->row_hier[r] = hidx;
+    }
+
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    const size_t f64 = sizeof(double);
+    P->off_K = take(s * P->nf * f64);
+    P->off_Y = take(s * P->nf * f64);
+    P->off_Fh = take(s * P->nf * f64);
+    P->off_U = take(s * P->nf * f64);
+    const size_t veclen = (size_t)P->maxw * P->nf;
+    P->off_V = take((size_t)(P->m + 1) * veclen * f64);
+    P->off_Z = take((size_t)P->m * veclen * f64);
+    P->off_part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
+    P->off_dv = take(4096 * f64);
+    P->off_ctr = take(64 * sizeof(unsigned));
+    P->off_tab = take((size_t)2 * (o.nx + o.ny) * f64);
+    for (int l = 0; l < P->lg.nlev; ++l) {
+        const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
+        for (int q = 0; q < 4; ++q) P->off_lev[l][q] = take(n * P->tsz);
+    }
+    for (int hq = 0; hq < P->nhier; ++hq)
+        for (int l = 0; l < P->lg.nlev; ++l)
+            P->off_coef[hq][l] = take((size_t)P->lg.nx[l] * P->lg.ny[l] * P->tsz);
+    P->total = off;
+    return IRK_OK;
+}
+
+}  // namespace irk
+
+using namespace irk;
+
+// dvals slots (float64 scalars on the device)
+enum {
+    DV_RES = 0,        // ||F||^2
+    DV_K0 = 1,         // ||K0||^2
+    DV_BETA = 2,       // ||r0||^2 of a block solve
+    DV_NRM = 3,        // ||w||^2 after orthogonalization
+    DV_SUMS = 8,       // field sums (up to 16)
+    DV_MEANS = 24,     // VSF stage means (2 s)
+    DV_XMEANS = 40,    // VSF matvec input means (4)
+    DV_H1 = 64,        // first Gram-Schmidt coefficients (<= 64)
+    DV_H2 = 160,       // second pass (<= 64)
+    DV_Y = 256,        // least-squares solution (<= 64)
+};
+enum { CTR_RED = 0 };
+
+struct irk_ctx {
+    Plan P;
+    hipStream_t stream = nullptr;
+    unsigned char *ws = nullptr;
+    double *K, *Y, *Fh, *U, *V, *Z, *part, *dv, *tab;
+    unsigned *ctr;
+    DeviceProblem dp;
+    double *pinned = nullptr;      // host staging, 4096 doubles
+    bool have_stages = false;
+    // Chebyshev smoothing coefficients
+    double cheb_cd[8], cheb_cr[8];
+    double lmax = 2.0, lmin = 0.5, coarse_lmin = 0.1;
+    irk_stats *st = nullptr;
+    double dt = 0;
+
+    template <class T> T *lev(int l, int q) { return reinterpret_cast<T *>(ws + P.off_lev[l][q]); }
+    template <class T> T *coef(int h, int l) { return reinterpret_cast<T *>(ws + P.off_coef[h][l]); }
+};
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return IRK_E_DEVICE;  \
+    } while (0)
+
+static irk_status sync_read(irk_ctx *c, const double *dev, int count) {
+    HIP_TRY(hipMemcpyAsync(c->pinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IRK_OK;
+}
+
+static irk_status write_dev(irk_ctx *c, double *dev, const double *host, int count) {
+    // staged through pinned memory; the copy is ordered on the stream and the
+    // staging area is reused only after the next synchronizing read
+    double *stage = c->pinned + 2048;
+    std::memcpy(stage, host, sizeof(double) * count);
+    HIP_TRY(hipMemcpyAsync(dev, stage, sizeof(double) * count, hipMemcpyHostToDevice, c->stream));
+    return IRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle on level hierarchy: right-hand side in lev(0).b, result pointer out
+// ---------------------------------------------------------------------------
+template <class T>
+static T *vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier) {
+    const Plan &P = c->P;
+    const int L = P.lg.nlev;
+    const int deg = P.opt.cheb_degree;
+    const double nu = P.op.nu;
+    T *cur[IRK_MAX_LEVELS];
+    for (int l = 0; l < L - 1; ++l) {
+        const int nx = P.lg.nx[l], ny = P.lg.ny[l];
+        const double h = P.op.length / P.op.nx * (double)(1 << l);
+        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
+        T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
+        T *xin = nullptr, *xout = X0;
+        for (int k = 0; k < deg; ++k) {
+            launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
+                              c->cheb_cr[k]);
+            xin = xout;
+            xout = (xout == X0) ? X1 : X0;
+        }
+        cur[l] = xin;
+        launch_mg_restrict_res<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, B, c->lev<T>(l + 1, 3));
+    }
+    {
+        const int l = L - 1;
+        const double h = P.op.length / P.op.nx * (double)(1 << l);
+        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
+        launch_mg_coarse<T>(c->stream, opk, P.lg.nx[l], P.lg.ny[l], h, nu, sigma, dtop, cf, c->lev<T>(l, 3),
+                            c->lev<T>(l, 0), P.opt.coarse_iters, c->lmax, c->coarse_lmin);
+        cur[l] = c->lev<T>(l, 0);
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        const int nx = P.lg.nx[l], ny = P.lg.ny[l];
+        const double h = P.op.length / P.op.nx * (double)(1 << l);
+        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
+        T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
+        launch_mg_prolong<T>(c->stream, nx, ny, cur[l], cur[l + 1]);
+        T *xin = cur[l], *xout = (xin == X0) ? X1 : X0;
+        for (int k = 0; k < deg; ++k) {
+            launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
+                              c->cheb_cr[k]);
+            T *t = xin;
+            xin = xout;
+            xout = t;
+        }
+        cur[l] = xin;
+    }
+    if (c->st) c->st->vcycles++;
+    return cur[0];
+}
+
+
+static int mg_op_of(int kind) {
+    return kind == IRK_OP_NLDIFF_2D ? MG_NLDIFF : (kind == IRK_OP_BURGERS_1D ? MG_BURGERS : MG_VSF_OMEGA);
+}
+
+// z = (sigma M - dt L_hier)^{-1} (a1 v1 + a2 v2), one V-cycle, for the
+// differential variable.
+template <class T>
+static void prec_component(irk_ctx *c, double *z, const double *v1, double a1, const double *v2, double a2,
+                           double sigma, int hier) {
+    const size_t npts = c->P.npts;
+    launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), v1, a1, v2, a2, nullptr, npts);
+    T *x = vcycle<T>(c, mg_op_of(c->P.op.kind), sigma, c->dt, hier);
+    launch_mg_cast_out<T>(c->stream, z, x, 1.0, nullptr, 0.0, npts);
+}
+
+// VSF streamfunction row of a block: solve B psi = q, B = -dt (Lap - mean),
+// q = r_psi + dt (z_omega - mean z_omega).  The mean-free part comes from one
+// Poisson V-cycle on -dt Lap, the mean exactly: mean(psi) = mean(r_psi)/dt.
+template <class T>
+static void prec_psi(irk_ctx *c, double *zpsi, const double *rpsi, const double *zomega) {
+    const size_t npts = c->P.npts;
+    double *means = c->dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
+    launch_field_sums(c->stream, rpsi, 0, 1, npts, 1.0 / npts, c->part, means, c->ctr + CTR_RED);
+    launch_field_sums(c->stream, zomega, 0, 1, npts, 1.0 / npts, c->part, means + 1, c->ctr + CTR_RED);
+    launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), rpsi, 1.0, zomega, c->dt, means, npts);
+    T *x = vcycle<T>(c, MG_POISSON, 0.0, c->dt, -1);
+    launch_mg_cast_out<T>(c->stream, zpsi, x, 1.0, means, 1.0 / c->dt, npts);
+}
+
+// z = L_P^{-1} v for eigen-block blk: the block lower-triangular
+// preconditioner of equation (Lprec) with diagonal inverses (eta M - dt L_a)
+// and the Schur complement approximation (gamma M - dt L_b) of equation
+// (schur-approx), each applied as one V-cycle; the (2,1) block of D is
+// -beta M (phi = beta in the eigenbasis).
+template <class T>
+static void apply_prec(irk_ctx *c, int blk, const double *v, double *z) {
+    const Plan &P = c->P;
+    const EigenBlocks &eb = P.eb;
+    const int r = eb.first[blk];
+    const size_t nf = P.nf, npts = P.npts;
+    const double eta = eb.eta[blk];
+    const bool vsf = (P.op.kind == IRK_OP_VSF_2D);
+    const int ha = P.row_hier[r];
+    prec_component<T>(c, z, v, 1.0, nullptr, 0.0, eta, ha);
+    if (vsf) prec_psi<T>(c, z + npts, v + npts, z);
+    if (eb.width[blk] == 2) {
+        const double beta = eb.beta[blk];
+        const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eta;
+        const int hb = P.row_hier[r + 1];
+        prec_component<T>(c, z + nf, v + nf, 1.0, z, beta, gam, hb);
+        if (vsf) prec_psi<T>(c, z + nf + npts, v + nf + npts, z + nf);
+    }
+    if (c->st) c->st->prec_applications += eb.width[blk];
+}
+
+static const double *stage_field(irk_ctx *c, int stage) { return c->U + (size_t)stage * c->P.nf; }
+
+static void block_matvec(irk_ctx *c, int blk, const double *x, double *w) {
+    const Plan &P = c->P;
+    const EigenBlocks &eb = P.eb;
+    const int r = eb.first[blk];
+    const int width = eb.width[blk];
+    const double *Ua = stage_field(c, P.hier_stage[P.row_hier[r]]);
+    const double *Ub = width == 2 ? stage_field(c, P.hier_stage[P.row_hier[r + 1]]) : Ua;
+    const double *xm = nullptr;
+    if (P.op.kind == IRK_OP_VSF_2D) {
+        launch_field_sums(c->stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, c->part, c->dv + DV_XMEANS,
+                          c->ctr + CTR_RED);
+        xm = c->dv + DV_XMEANS;
+    }
+    launch_block_matvec(c->stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm);
+}
+
+// ---------------------------------------------------------------------------
+// Right-preconditioned FGMRES(m) on D_b y = fhat_b, y in Y (transformed rows
+// of the block), classical Gram-Schmidt with reorthogonalization, Givens QR
+// of the Hessenberg matrix on the host.
+// ---------------------------------------------------------------------------
+template <class T>
+static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int *its_out) {
+    const Plan &P = c->P;
+    const EigenBlocks &eb = P.eb;
+    const int r = eb.first[blk];
+    const size_t len = (size_t)eb.width[blk] * P.nf;
+    const size_t ldv = (size_t)P.maxw * P.nf;
+    const int m = P.m;
+    const double *rhs = c->Fh + (size_t)r * P.nf;
+    double *sol = c->Y + (size_t)r * P.nf;
+    double *V = c->V, *Z = c->Z, *dv = c->dv;
+    unsigned *ctr = c->ctr + CTR_RED;
+    irk_status stt;
+
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    int total = 0;
+    bool first_cycle = true;
+    double beta0 = 0.0;
+    while (true) {
+        // r0 = rhs - D sol (sol = 0 on the first cycle)
+        if (first_cycle) {
+            launch_dot_multi(c->stream, V, ldv, 0, rhs, len, 1, c->part, dv + DV_BETA, ctr);
+        } else {
+            block_matvec(c, blk, sol, V);                       // V0 <- D sol
+            launch_axpby(c->stream, V, 1.0, rhs, -1.0, V, len);  // V0 <- rhs - D sol
+            launch_dot_multi(c->stream, V, ldv, 0, V, len, 1, c->part, dv + DV_BETA, ctr);
+        }
+        if ((stt = sync_read(c, dv + DV_BETA, 1)) != IRK_OK) return stt;
+        const double bnorm = std::sqrt(c->pinned[0]);
+        if (!std::isfinite(bnorm)) return IRK_E_NONFINITE;
+        if (first_cycle) {
+            beta0 = bnorm;
+            if (bnorm == 0.0) {
+                launch_fill(c->stream, sol, 0.0, len);
+                *its_out = 0;
+                return IRK_OK;
+            }
+        }
+        if (bnorm <= rtol * beta0 || total >= maxit) break;
+        launch_scale_copy(c->stream, V, first_cycle ? rhs : V, dv + DV_BETA, len);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = bnorm;
+        int j = 0;
+        bool converged = false;
+        for (; j < m && total < maxit; ++j) {
+            double *vj = V + (size_t)j * ldv, *zj = Z + (size_t)j * ldv, *w = V + (size_t)(j + 1) * ldv;
+            apply_prec<T>(c, blk, vj, zj);
+            block_matvec(c, blk, zj, w);
+            launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H1, ctr);
+            launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H1, len);
+            launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H2, ctr);
+            launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H2, len);
+            launch_dot_multi(c->stream, V, ldv, 0, w, len, 1, c->part, dv + DV_NRM, ctr);
+            if ((stt = sync_read(c, dv, DV_Y)) != IRK_OK) return stt;
+            const double *hb = c->pinned;
+            const double hn = std::sqrt(hb[DV_NRM]);
+            if (!std::isfinite(hn)) return IRK_E_NONFINITE;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[DV_H1 + i] + hb[DV_H2 + i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            // apply previous rotations, then a new one that zeroes H[j+1][j]
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a, b);
+            cs[j] = rr > 0 ? a / rr : 1.0;
+            sn[j] = rr > 0 ? b / rr : 0.0;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            if (std::fabs(g[j + 1]) <= rtol * beta0 || hn <= 1e-300) { ++j; converged = true; break; }
+            launch_scale_copy(c->stream, w, w, dv + DV_NRM, len);
+        }
+        // y = R^{-1} g on the j x j leading block
+        for (int i = j - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k < j; ++k) acc -= H[(size_t)i * m + k] * y[k];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        if (first_cycle) {
+            if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
+            launch_lincomb(c->stream, sol, Z, ldv, j, dv + DV_Y, len);
+        } else {
+            // sol += Z y, as sol -= Z (-y)
+            for (int i = 0; i < j; ++i) y[i] = -y[i];
+            if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
+            launch_axpy_multi(c->stream, sol, Z, ldv, j, dv + DV_Y, len);
+        }
+        first_cycle = false;
+        if (converged || total >= maxit) break;
+    }
+    *its_out = total;
+    return IRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One step: Algorithm 1 in the eigenbasis.
+// ---------------------------------------------------------------------------
+static void fill_stage_coefs(const irk_ctx *c, double t_n, double dt, StageCoefs *C) {
+    const EigenBlocks &eb = c->P.eb;
+    const int s = eb.s;
+    std::memset(C, 0, sizeof(*C));
+    for (int i = 0; i < s * s; ++i) {
+        C->A[i] = eb.A[i];
+        C->TLam[i] = -eb.TLam[i];     // the block solves return y = D^{-1} fhat; the correction is -T Lambda y
+        C->Tinv[i] = eb.Tinv[i];
+    }
+    for (int i = 0; i < s; ++i) {
+        C->b[i] = eb.b[i];
+        C->tstage[i] = t_n + eb.c[i] * dt;
+        C->sin_t[i] = std::sin(C->tstage[i]);
+        C->cos_t[i] = std::cos(C->tstage[i]);
+    }
+}
+
+template <class T>
+static void setup_hierarchies(irk_ctx *c) {
+    const Plan &P = c->P;
+    for (int hq = 0; hq < P.nhier; ++hq) {
+        const double *Um = stage_field(c, P.hier_stage[hq]);
+        // coefficient field of the linearization: U_m (NLDIFF, Burgers) or Psi_m (VSF)
+        const double *src = P.op.kind == IRK_OP_VSF_2D ? Um + P.npts : Um;
+        launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts);
+        for (int l = 0; l + 1 < P.lg.nlev; ++l)
+            launch_mg_coef_restrict<T>(c->stream, P.lg.nx[l], P.lg.ny[l], c->coef<T>(hq, l), c->coef<T>(hq, l + 1));
+    }
+}
+
+template <class T>
+static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double dt, double rtol, irk_stats *st) {
+    const Plan &P = c->P;
+    const int s = P.s;
+    const size_t nf = P.nf;
+    StageCoefs C;
+    fill_stage_coefs(c, t_n, dt, &C);
+    c->dt = dt;
+    irk_status stt;
+    launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n));
+    // ||M K0|| for the absolute floor
+    launch_dot_multi(c->stream, c->V, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, c->ctr + CTR_RED);
+    double res0 = -1, thresh = 0;
+    int fold = 0;
+    for (int it = 0;; ++it) {
+        launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold);
+        if (P.op.kind == IRK_OP_VSF_2D)
+            launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
+                              c->ctr + CTR_RED);
+        launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+                        c->ctr + CTR_RED);
+        if ((stt = sync_read(c, c->dv, 2)) != IRK_OK) return stt;
+        const double res = std::sqrt(c->pinned[DV_RES]);
+        if (!std::isfinite(res)) return IRK_E_NONFINITE;
+        if (it == 0) {
+            res0 = res;
+            const double k0 = std::sqrt(c->pinned[DV_K0]);
+            if (!std::isfinite(k0)) return IRK_E_NONFINITE;
+            const double atol = P.opt.newton_atol > 0 ? P.opt.newton_atol : 1e-14 * k0;
+            thresh = rtol * res0 + atol;
+            if (st) st->res0 = res0;
+        }
+        if (st) st->final_res = res;
+        if (res <= thresh) break;
+        if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return IRK_E_NOCONV;
+        setup_hierarchies<T>(c);
+        for (int blk = 0; blk < P.eb.nblocks; ++blk) {
+            int its = 0;
+            if ((stt = fgmres_block<T>(c, blk, P.opt.krylov_rtol, P.opt.max_krylov, &its)) != IRK_OK) return stt;
+            if (st) {
+                st->krylov_its += its;
+                st->krylov_its_block[blk] += its;
+            }
+        }
+        if (st) st->newton_its++;
+        fold = 1;
+    }
+    return IRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" const char *irk_status_str(irk_status st) {
+    switch (st) {
+        case IRK_OK: return "ok";
+        case IRK_E_ARG: return "invalid argument";
+        case IRK_E_NOMEM: return "workspace too small or budget exceeded";
+        case IRK_E_NOCONV: return "nonlinear iteration did not converge";
+        case IRK_E_NONFINITE: return "non-finite value";
+        case IRK_E_DEVICE: return "HIP runtime error";
+        case IRK_E_UNSUPPORTED: return "unsupported option combination";
+        case IRK_E_BUSY: return "request not finished";
+    }
+    return "unknown status";
+}
+
+extern "C" void irk_default_options(irk_options *o) {
+    if (!o) return;
+    o->newton_rtol = 1e-12;
+    o->newton_atol = 0.0;
+    o->krylov_rtol = 1e-5;
+    o->restart = 30;
+    o->max_krylov = 200;
+    o->max_newton = 30;
+    o->newton_like = 1;
+    o->gamma_mode = 0;
+    o->prec_fp32 = 1;
+    o->cheb_degree = 3;
+    o->mg_coarsest = 8;
+    o->coarse_iters = 24;
+}
+
+extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
+    Plan P;
+    if (make_plan(family, s, op, opt, &P) != IRK_OK) return 0;
+    return P.total;
+}
+
+static void set_chebyshev(irk_ctx *c) {
+    const double theta = 0.5 * (c->lmax + c->lmin), delta = 0.5 * (c->lmax - c->lmin);
+    const double sig1 = theta / delta;
+    double rho = 1.0 / sig1;
+    for (int k = 0; k < c->P.opt.cheb_degree; ++k) {
+        if (k == 0) {
+            c->cheb_cd[0] = 0.0;
+            c->cheb_cr[0] = 1.0 / theta;
+        } else {
+            const double rn = 1.0 / (2.0 * sig1 - rho);
+            c->cheb_cd[k] = rn * rho;
+            c->cheb_cr[k] = 2.0 * rn / delta;
+            rho = rn;
+        }
+    }
+}
+
+extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,
+                                 void *device_workspace, size_t workspace_bytes, void *hip_stream, irk_ctx **out) {
+    if (!out) return IRK_E_ARG;
+    *out = nullptr;
+    irk_ctx *c = new (std::nothrow) irk_ctx();
+    if (!c) return IRK_E_NOMEM;
+    irk_status stt = make_plan(family, s, op, opt, &c->P);
+    if (stt != IRK_OK) { delete c; return stt; }
+    if (!device_workspace || ((uintptr_t)device_workspace & 255) != 0) { delete c; return IRK_E_ARG; }
+    if (workspace_bytes < c->P.total) { delete c; return IRK_E_NOMEM; }
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (unsigned char *)device_workspace;
+    const Plan &P = c->P;
+    c->K = (double *)(c->ws + P.off_K);
+    c->Y = (double *)(c->ws + P.off_Y);
+    c->Fh = (double *)(c->ws + P.off_Fh);
+    c->U = (double *)(c->ws + P.off_U);
+    c->V = (double *)(c->ws + P.off_V);
+    c->Z = (double *)(c->ws + P.off_Z);
+    c->part = (double *)(c->ws + P.off_part);
+    c->dv = (double *)(c->ws + P.off_dv);
+    c->ctr = (unsigned *)(c->ws + P.off_ctr);
+    c->tab = (double *)(c->ws + P.off_tab);
+    if (hipHostMalloc((void **)&c->pinned, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return IRK_E_DEVICE;
+    }
+    set_chebyshev(c);
+    // device problem descriptor and forcing tables sin/cos(2 pi x_i)
+    c->dp.kind = P.op.kind;
+    c->dp.forcing = P.op.kind == IRK_OP_NLDIFF_2D ? P.op.forcing : IRK_FORCING_NONE;
+    c->dp.nvar = P.nvar;
+    c->dp.g.nx = P.op.nx;
+    c->dp.g.ny = P.op.ny;
+    c->dp.g.h = P.op.length / P.op.nx;
+    c->dp.g.nu = P.op.nu;
+    const int nx = P.op.nx, ny = P.op.ny;
+    std::vector<double> tab(2 * (nx + ny));
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    for (int i = 0; i < nx; ++i) {
+        tab[i] = std::sin(two_pi * (i * c->dp.g.h));
+        tab[nx + i] = std::cos(two_pi * (i * c->dp.g.h));
+    }
+    for (int j = 0; j < ny; ++j) {
+        tab[2 * nx + j] = std::sin(two_pi * (j * c->dp.g.h));
+        tab[2 * nx + ny + j] = std::cos(two_pi * (j * c->dp.g.h));
+    }
+    c->dp.sinx = c->tab;
+    c->dp.cosx = c->tab + nx;
+    c->dp.siny = c->tab + 2 * nx;
+    c->dp.cosy = c->tab + 2 * nx + ny;
+    if (hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return IRK_E_DEVICE;
+    }
+    launch_zero_u32(c->stream, c->ctr, 64);
+    launch_fill(c->stream, c->Y, 0.0, (size_t)s * P.nf);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return IRK_E_DEVICE;
+    }
+    *out = c;
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1,
+                               irk_stats *stats) {
+    if (!c || !u_n || !u_np1 || !(dt > 0) || !std::isfinite(t_n)) return IRK_E_ARG;
+    irk_stats local;
+    std::memset(&local, 0, sizeof(local));
+    c->st = &local;
+    const double rtol = tol > 0 ? tol : c->P.opt.newton_rtol;
+    irk_status stt = c->P.opt.prec_fp32 ? newton_solve<float>(c, u_n, t_n, dt, rtol, &local)
+                                        : newton_solve<double>(c, u_n, t_n, dt, rtol, &local);
+    if (stt == IRK_OK) {
+        StageCoefs C;
+        fill_stage_coefs(c, t_n, dt, &C);
+        launch_final_update(c->stream, c->P.s, c->P.nf, u_n, c->K, u_np1, C, dt);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) stt = IRK_E_DEVICE;
+    } else {
+        (void)hipStreamSynchronize(c->stream);
+    }
+    c->have_stages = (stt == IRK_OK);
+    c->st = nullptr;
+    if (stats) *stats = local;
+    return stt;
+}
+
+extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_n, double dt, const double *K,
+                                        double *F) {
+    if (!c || !u_n || !K || !F || !(dt > 0)) return IRK_E_ARG;
+    const Plan &P = c->P;
+    const int s = P.s;
+    const size_t bytes = (size_t)s * P.nf * sizeof(double);
+    StageCoefs C;
+    fill_stage_coefs(c, t_n, dt, &C);
+    HIP_TRY(hipMemcpyAsync(c->K, K, bytes, hipMemcpyDeviceToDevice, c->stream));
+    launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
+    if (P.op.kind == IRK_OP_VSF_2D)
+        launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
+                          c->ctr + CTR_RED);
+    // identity transform: Tinv = I gives F itself
+    for (int i = 0; i < s * s; ++i) C.Tinv[i] = (i / s == i % s) ? 1.0 : 0.0;
+    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+                    c->ctr + CTR_RED);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_stages = false;
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_get_stages(irk_ctx *c, double *K) {
+    if (!c || !K) return IRK_E_ARG;
+    if (!c->have_stages) return IRK_E_ARG;
+    HIP_TRY(hipMemcpyAsync(K, c->K, (size_t)c->P.s * c->P.nf * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IRK_OK;
+}
+
+extern "C" void irk_destroy(irk_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}

@@ -1,0 +1,65 @@
+// Internal declarations shared by the host driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/irk.h"
+
+#define IRK_MAX_LEVELS 14
+#define IRK_WG 256
+#define IRK_RED_BLOCKS 512   // work-groups of the reduction kernels
+
+namespace irk {
+
+// Tableau and the real eigenbasis of A0^{-1} (host, float64 after a long
+// double construction).
+struct EigenBlocks {
+    int s = 0, nblocks = 0;
+    double A[IRK_MAX_STAGES * IRK_MAX_STAGES], Ainv[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    double b[IRK_MAX_STAGES], c[IRK_MAX_STAGES];
+    double T[IRK_MAX_STAGES * IRK_MAX_STAGES], Tinv[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    double TLam[IRK_MAX_STAGES * IRK_MAX_STAGES];          // T Lambda
+    int width[IRK_MAX_STAGES], first[IRK_MAX_STAGES];
+    double eta[IRK_MAX_STAGES], beta[IRK_MAX_STAGES], gamma_star[IRK_MAX_STAGES];
+    int argmax_stage[IRK_MAX_STAGES];                     // per transformed row
+};
+
+bool build_tableau_ld(int family, int s, long double *A, long double *b, long double *c);
+bool build_eigen_blocks(int family, int s, EigenBlocks *eb);
+
+// Small constant blocks passed to kernels by value.
+struct StageCoefs {
+    double A[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    double TLam[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    double Tinv[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    double b[IRK_MAX_STAGES];
+    double tstage[IRK_MAX_STAGES];      // t_n + c_i dt
+    double sin_t[IRK_MAX_STAGES], cos_t[IRK_MAX_STAGES];
+};
+
+// Geometry and physical parameters of one grid level.
+struct Grid {
+    int nx, ny;
+    double h;       // spacing on this level
+    double nu;
+};
+
+// One multigrid level's work arrays (precision of the V-cycle).
+struct Level {
+    int nx, ny;
+    double h;
+    void *x, *x2, *d, *b;
+};
+
+// Operator-specific kernel launchers (defined in kernels.hip).
+struct DeviceProblem {
+    int kind;               // irk_op_kind
+    int forcing;
+    int nvar;               // 1, or 2 for (omega, psi)
+    Grid g;
+    const double *sinx, *cosx, *siny, *cosy;   // forcing tables (NLDIFF)
+};
+
+}  // namespace irk

@@ -1,0 +1,56 @@
+// Host-callable launchers of the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "irk_internal.h"
+
+namespace irk {
+
+// operator of a multigrid hierarchy (the diagonal block being inverted)
+enum MgOp { MG_NLDIFF = 0, MG_BURGERS = 1, MG_VSF_OMEGA = 2, MG_POISSON = 3 };
+
+void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, double *K, const double *Y, double *U,
+                       const StageCoefs &C, double dt, int fold);
+void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
+                     const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr);
+void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
+                     double cos_tn);
+void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, const double *K, double *out,
+                         const StageCoefs &C, double dt);
+void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, size_t len, double scale,
+                       double *partials, double *out, unsigned *ctr);
+void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
+                         const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
+void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
+                      int with_norm, double *partials, double *out, unsigned *ctr);
+void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);
+void launch_lincomb(hipStream_t st, double *dst, const double *V, size_t ldv, int nv, const double *c, size_t len);
+void launch_scale_copy(hipStream_t st, double *dst, const double *src, const double *nrm2, size_t len);
+void launch_axpby(hipStream_t st, double *dst, double a, const double *x, double b, const double *y, size_t len);
+void launch_zero_u32(hipStream_t st, unsigned *p, int n);
+void launch_fill(hipStream_t st, double *p, double v, size_t len);
+
+template <class T>
+void launch_mg_cheb(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
+                    const T *coef, const T *xin, T *xout, const T *b, T *d, double cd, double cr);
+template <class T>
+void launch_mg_restrict_res(hipStream_t st, int opk, int nxf, int nyf, double hf, double nu, double sigma,
+                            double dt, const T *coef, const T *x, const T *b, T *bc);
+template <class T>
+void launch_mg_prolong(hipStream_t st, int nxf, int nyf, T *xf, const T *xc);
+template <class T>
+void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc);
+template <class T>
+void launch_mg_cast_in(hipStream_t st, T *b0, const double *v1, double a1, const double *v2, double a2,
+                       const double *means, size_t len);
+template <class T>
+void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const double *shift, double c,
+                        size_t len);
+template <class T>
+void launch_mg_coarse(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
+                      const T *coef, const T *b, T *x, int iters, double lmax, double lmin);
+template <class T>
+void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len);
+
+}  // namespace irk

@@ -1,0 +1,817 @@
+// HIP kernels of the IRK stage solve for gfx950 (wave64).
+//
+//   stage_prep      k <- k + (T Lambda (x) I) y ;  U_i = u_n + dt sum_j a_ij k_j
+//   residual        F_i = M k_i - N(U_i, t_n + c_i dt) ; fhat = (T^{-1} (x) I) F ;
+//                   ||F||^2 (Algorithm 1, equations (stages), (dae_stage))
+//   rhs_init        k_i = N(u_n, t_n) (initial guess)
+//   final_update    u_{n+1} = u_n + dt sum_i b_i k_i (equation (update))
+//   block_matvec    w = D_b x for a 1x1 or 2x2 eigen-block (equation (diag_blocks))
+//   dot / axpy      Arnoldi (classical Gram-Schmidt, two passes)
+//   mg_*            geometric-multigrid V-cycle pieces (Chebyshev smoother,
+//                   residual + full-weighting restriction, bilinear
+//                   prolongation, coarsest-level solve in one work-group)
+//
+// Reductions are deterministic: per-work-group partial sums in a fixed order,
+// then the last work-group to finish sums the partials in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "irk_internal.h"
+#include "kernels.h"
+#include "stencils.h"
+
+namespace irk {
+
+static constexpr double kPi = 3.14159265358979323846;
+
+// blockIdx -> tile mapping that keeps consecutive tiles on one XCD (work-
+// groups are dealt round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// sum over the 256 threads of a work-group; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *sh /* >= 4 */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Each work-group stores `nv` partial sums; the last one to arrive sums all
+// partials (fixed order) into out[0..nv-1] and re-arms the counter.
+__device__ void finish_partials(const double *myvals, int nv, double *partials, double *out,
+                                unsigned *counter) {
+    __shared__ bool is_last;
+    __shared__ double sh[8];
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k) partials[(size_t)blockIdx.x * nv + k] = myvals[k];
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const volatile double *vp = partials;
+    for (int k = 0; k < nv; ++k) {
+        double acc = 0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) acc += vp[(size_t)b * nv + k];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) out[k] = acc;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ------------------------------------------------------------------------
+// Stage preparation (pointwise over the s stage fields).
+// ------------------------------------------------------------------------
+template <int S>
+__global__ void __launch_bounds__(IRK_WG) k_stage_prep(size_t nf, const double *__restrict__ un,
+                                                       double *__restrict__ K, const double *__restrict__ Y,
+                                                       double *__restrict__ U, StageCoefs C, double dt,
+                                                       int fold) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < nf; e += stride) {
+        double k[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) k[j] = K[j * nf + e];
+        if (fold) {
+            double y[S];
+#pragma unroll
+            for (int l = 0; l < S; ++l) y[l] = Y[l * nf + e];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                double acc = k[j];
+#pragma unroll
+                for (int l = 0; l < S; ++l) acc += C.TLam[j * S + l] * y[l];
+                k[j] = acc;
+                K[j * nf + e] = acc;
+            }
+        }
+        const double u = un[e];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double acc = 0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc += C.A[i * S + j] * k[j];
+            U[i * nf + e] = u + dt * acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// N(U) at one point for each operator (float64).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double mms_forcing(const DeviceProblem &P, int i, int j, double st, double ct) {
+    const double sx = P.sinx[i], cx = P.cosx[i], sy = P.siny[j], cy = P.cosy[j];
+    const double S = sx * sy;
+    if (P.forcing == IRK_FORCING_MMS) {
+        const double G = cx * cx * sy * sy + sx * sx * cy * cy;
+        const double u = S * ct;
+        const double lap = -8.0 * kPi * kPi * u;
+        const double grad2 = 4.0 * kPi * kPi * G * ct * ct;
+        return -S * st - ((1.0 + u * u) * lap + 2.0 * u * grad2);
+    }
+    // discrete manufactured solution: f = du*/dt - N_h(u*)
+    const int nx = P.g.nx, ny = P.g.ny;
+    const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
+    const double inv_h2 = 1.0 / (P.g.h * P.g.h);
+    const double fl = nldiff_flux5(S * ct, P.sinx[ip] * sy * ct, P.sinx[im] * sy * ct,
+                                   sx * P.siny[jp] * ct, sx * P.siny[jm] * ct, inv_h2);
+    return -S * st - fl;
+}
+
+// ------------------------------------------------------------------------
+// Residual F_i = M k_i - N(U_i), transformed residual and ||F||^2.
+// Layout: U, K, Fh are [S][nvar][npts]; means (VSF) = [S][2] (omega, psi).
+// ------------------------------------------------------------------------
+template <int S, int OP>
+__global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const double *__restrict__ U,
+                                                     const double *__restrict__ K, double *__restrict__ Fh,
+                                                     StageCoefs C, const double *__restrict__ means,
+                                                     double *partials, double *out, unsigned *counter) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    double sumsq = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double F[S][NV];
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const double *Ui = U + st * nf;
+            if constexpr (OP == IRK_OP_NLDIFF_2D) {
+                const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
+                double N = nldiff_flux5(Ui[p], Ui[j * nx + ip], Ui[j * nx + im], Ui[jp * nx + i], Ui[jm * nx + i], inv_h2);
+                if (P.forcing != IRK_FORCING_NONE) N += mms_forcing(P, i, j, C.sin_t[st], C.cos_t[st]);
+                F[st][0] = K[st * nf + p] - N;
+            } else if constexpr (OP == IRK_OP_BURGERS_1D) {
+                const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
+                const double ue = Ui[ip], uw = Ui[im], uc = Ui[p];
+                const double N = -(ue * ue - uw * uw) / (4.0 * h) + P.g.nu * (ue - 2.0 * uc + uw) * inv_h2;
+                F[st][0] = K[st * nf + p] - N;
+            } else {
+                double w[3][3], ps[3][3];
+                load3x3(Ui, i, j, nx, ny, w);
+                load3x3(Ui + npts, i, j, nx, ny, ps);
+                const double Nw = arakawa9(ps, w, inv_h2 / 12.0) + P.g.nu * lap5(w, inv_h2);
+                F[st][0] = K[st * nf + p] - Nw;
+                // algebraic rows: 0 * l_i - (Lap Psi + Omega - mean Omega - mean Psi)
+                F[st][1] = -(lap5(ps, inv_h2) + w[1][1] - means[2 * st] - means[2 * st + 1]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int st = 0; st < S; ++st) sumsq += F[st][v] * F[st][v];
+#pragma unroll
+            for (int m = 0; m < S; ++m) {
+                double acc = 0;
+#pragma unroll
+                for (int st = 0; st < S; ++st) acc += C.Tinv[m * S + st] * F[st][v];
+                Fh[m * nf + v * npts + p] = acc;
+            }
+        }
+    }
+    __shared__ double sh[8];
+    const double tot = block_sum(sumsq, sh);
+    finish_partials(&tot, 1, partials, out, counter);
+}
+
+// k_i <- N(u_n, t_n) on differential rows, 0 on algebraic rows (initial guess)
+template <int S, int OP>
+__global__ void __launch_bounds__(IRK_WG) k_rhs_init(DeviceProblem P, const double *__restrict__ un,
+                                                     double *__restrict__ K, double st_n, double ct_n) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double N;
+        if constexpr (OP == IRK_OP_NLDIFF_2D) {
+            const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
+            N = nldiff_flux5(un[p], un[j * nx + ip], un[j * nx + im], un[jp * nx + i], un[jm * nx + i], inv_h2);
+            if (P.forcing != IRK_FORCING_NONE) N += mms_forcing(P, i, j, st_n, ct_n);
+        } else if constexpr (OP == IRK_OP_BURGERS_1D) {
+            const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
+            N = -(un[ip] * un[ip] - un[im] * un[im]) / (4.0 * h) + P.g.nu * (un[ip] - 2.0 * un[p] + un[im]) * inv_h2;
+        } else {
+            double w[3][3], ps[3][3];
+            load3x3(un, i, j, nx, ny, w);
+            load3x3(un + npts, i, j, nx, ny, ps);
+            N = arakawa9(ps, w, inv_h2 / 12.0) + P.g.nu * lap5(w, inv_h2);
+        }
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            K[st * nf + p] = N;
+            if constexpr (NV == 2) K[st * nf + npts + p] = 0.0;
+        }
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(IRK_WG) k_final_update(size_t nf, const double *__restrict__ un,
+                                                         const double *__restrict__ K, double *__restrict__ out,
+                                                         StageCoefs C, double dt) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < nf; e += stride) {
+        double acc = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i) acc += C.b[i] * K[i * nf + e];
+        out[e] = un[e] + dt * acc;
+    }
+}
+
+// sums of `nfields` consecutive fields of length len (VSF means)
+__global__ void __launch_bounds__(IRK_WG) k_field_sums(const double *__restrict__ X, size_t ld, int nfields,
+                                                       size_t len, double scale, double *partials, double *out,
+                                                       unsigned *counter) {
+    double acc[2 * IRK_MAX_STAGES];
+    for (int f = 0; f < nfields; ++f) acc[f] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride)
+        for (int f = 0; f < nfields; ++f) acc[f] += X[f * ld + e];
+    __shared__ double sh[8];
+    double tot[2 * IRK_MAX_STAGES];
+    for (int f = 0; f < nfields; ++f) tot[f] = scale * block_sum(acc[f], sh);
+    finish_partials(tot, nfields, partials, out, counter);
+}
+
+// ------------------------------------------------------------------------
+// Eigen-block matvec w = D_b x (float64).
+//   width 1: w = eta M x - dt L_a x
+//   width 2: w_a = eta M x_a + beta M x_b - dt L_a x_a
+//            w_b = -beta M x_a + eta M x_b - dt L_b x_b
+// For VSF each component is (omega, psi); omega rows use the Picard
+// linearization K(Psi_m) = J_A(Psi_m, .) + nu Lap, psi rows
+// -dt [(x_omega - mean x_omega) + Lap x_psi - mean x_psi] (mass 0).
+// ------------------------------------------------------------------------
+template <int OP>
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int width, double eta, double beta,
+                                                         double dt, const double *__restrict__ Ua,
+                                                         const double *__restrict__ Ub,
+                                                         const double *__restrict__ x, double *__restrict__ w,
+                                                         const double *__restrict__ xmeans) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double Lx[2], xc[2];
+        for (int comp = 0; comp < width; ++comp) {
+            const double *Uc = comp == 0 ? Ua : Ub;
+            const double *xx = x + comp * nf;
+            double lx, ld;
+            if constexpr (OP == IRK_OP_NLDIFF_2D) nldiff_lin<double, true>(Uc, xx, i, j, nx, ny, inv_h2, lx, ld);
+            else if constexpr (OP == IRK_OP_BURGERS_1D) burgers_lin<double, true>(Uc, xx, i, nx, h, P.g.nu, lx, ld);
+            else vsf_omega_lin<double, true>(Uc + npts, xx, i, j, nx, ny, h, P.g.nu, lx, ld);
+            Lx[comp] = lx;
+            xc[comp] = xx[p];
+        }
+        if (width == 1) {
+            w[p] = eta * xc[0] - dt * Lx[0];
+        } else {
+            w[p] = eta * xc[0] + beta * xc[1] - dt * Lx[0];
+            w[nf + p] = -beta * xc[0] + eta * xc[1] - dt * Lx[1];
+        }
+        if constexpr (NV == 2) {
+            for (int comp = 0; comp < width; ++comp) {
+                const double *xx = x + comp * nf;
+                double lp, ld;
+                poisson_lin<double, true>(xx + npts, i, j, nx, ny, h, lp, ld);
+                const double mw = xmeans[2 * comp], mp = xmeans[2 * comp + 1];
+                w[comp * nf + npts + p] = -dt * ((xc[comp] - mw) + lp - mp);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Arnoldi kernels
+// ------------------------------------------------------------------------
+#define DOT_CHUNK 16
+// out[k] = <V_k, w> for k < nv (nv <= 16); out[nv] = <w, w> when with_norm
+__global__ void __launch_bounds__(IRK_WG) k_dot_multi(const double *__restrict__ V, size_t ldv, int nv,
+                                                      const double *__restrict__ w, size_t len, int with_norm,
+                                                      double *partials, double *out, unsigned *counter) {
+    double acc[DOT_CHUNK + 1];
+#pragma unroll
+    for (int k = 0; k <= DOT_CHUNK; ++k) acc[k] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        const double we = w[e];
+#pragma unroll
+        for (int k = 0; k < DOT_CHUNK; ++k)
+            if (k < nv) acc[k] += V[k * ldv + e] * we;
+        acc[DOT_CHUNK] += we * we;
+    }
+    __shared__ double sh[8];
+    double tot[DOT_CHUNK + 1];
+    const int nout = nv + (with_norm ? 1 : 0);
+#pragma unroll
+    for (int k = 0; k < DOT_CHUNK; ++k)
+        if (k < nv) tot[k] = block_sum(acc[k], sh);
+    if (with_norm) tot[nv] = block_sum(acc[DOT_CHUNK], sh);
+    finish_partials(tot, nout, partials, out, counter);
+}
+
+// w <- w - sum_k h[k] V_k
+__global__ void __launch_bounds__(IRK_WG) k_axpy_multi(double *__restrict__ w, const double *__restrict__ V,
+                                                       size_t ldv, int nv, const double *__restrict__ hcoef,
+                                                       size_t len) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double acc = w[e];
+        for (int k = 0; k < nv; ++k) acc -= hcoef[k] * V[k * ldv + e];
+        w[e] = acc;
+    }
+}
+
+// dst <- sum_k c[k] V_k
+__global__ void __launch_bounds__(IRK_WG) k_lincomb(double *__restrict__ dst, const double *__restrict__ V,
+                                                    size_t ldv, int nv, const double *__restrict__ c, size_t len) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double acc = 0;
+        for (int k = 0; k < nv; ++k) acc += c[k] * V[k * ldv + e];
+        dst[e] = acc;
+    }
+}
+
+// dst <- src / sqrt(*nrm2)
+__global__ void __launch_bounds__(IRK_WG) k_scale_copy(double *__restrict__ dst, const double *__restrict__ src,
+                                                       const double *__restrict__ nrm2, size_t len) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) dst[e] = src[e] * inv;
+}
+
+// dst <- a x + b y  (dst may alias x or y)
+__global__ void __launch_bounds__(IRK_WG) k_axpby(double *dst, double a, const double *x, double b,
+                                                  const double *y, size_t len) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) dst[e] = a * x[e] + b * y[e];
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------------
+// Multigrid (precision T).  Level operator A = sigma M - dt L(coef) with the
+// operator's linearization rediscretized at the level spacing.
+// ------------------------------------------------------------------------
+template <class T, int OPK, bool HAS_X>
+__device__ __forceinline__ void level_op(const T *coef, const T *x, int i, int j, int nx, int ny, T h, T nu,
+                                         T &Lx, T &Ld) {
+    if constexpr (OPK == MG_NLDIFF) nldiff_lin<T, HAS_X>(coef, x, i, j, nx, ny, T(1) / (h * h), Lx, Ld);
+    else if constexpr (OPK == MG_BURGERS) burgers_lin<T, HAS_X>(coef, x, i, nx, h, nu, Lx, Ld);
+    else if constexpr (OPK == MG_VSF_OMEGA) vsf_omega_lin<T, HAS_X>(coef, x, i, j, nx, ny, h, nu, Lx, Ld);
+    else poisson_lin<T, HAS_X>(x, i, j, nx, ny, h, Lx, Ld);
+}
+
+// One Chebyshev step on D^{-1} A (D = diag A):
+//   r = b - A x ; d = cd d + cr D^{-1} r ; x_out = x + d
+// x_in == nullptr means x = 0.
+template <class T, int OPK>
+__global__ void __launch_bounds__(IRK_WG) k_mg_cheb(int nx, int ny, T h, T nu, T sigma, T dt,
+                                                    const T *__restrict__ coef, const T *__restrict__ xin,
+                                                    T *__restrict__ xout, const T *__restrict__ b,
+                                                    T *__restrict__ d, T cd, T cr) {
+    const size_t npts = (size_t)nx * ny;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        T Lx, Ld, r, xc;
+        if (xin) {
+            level_op<T, OPK, true>(coef, xin, i, j, nx, ny, h, nu, Lx, Ld);
+            xc = xin[p];
+            r = b[p] - (sigma * xc - dt * Lx);
+        } else {
+            level_op<T, OPK, false>(coef, nullptr, i, j, nx, ny, h, nu, Lx, Ld);
+            xc = T(0);
+            r = b[p];
+        }
+        const T diag = sigma - dt * Ld;
+        const T dn = (cd != T(0) ? cd * d[p] : T(0)) + cr * r / diag;
+        d[p] = dn;
+        xout[p] = xc + dn;
+    }
+}
+
+// coarse b = full-weighting restriction of the fine residual b - A x
+template <class T, int OPK>
+__global__ void __launch_bounds__(IRK_WG) k_mg_restrict_res(int nxf, int nyf, T hf, T nu, T sigma, T dt,
+                                                            const T *__restrict__ coef, const T *__restrict__ x,
+                                                            const T *__restrict__ b, T *__restrict__ bc) {
+    const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
+    const size_t npc = (size_t)nxc * nyc;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const T wgt[3] = {T(0.25), T(0.5), T(0.25)};
+    for (size_t q = (size_t)xcd_block() * blockDim.x + threadIdx.x; q < npc; q += stride) {
+        const int I = (int)(q % nxc), J = (int)(q / nxc);
+        T acc = 0;
+        if (nyf == 1) {
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                const int i = wrapm(2 * I + a, nxf);
+                T Lx, Ld;
+                level_op<T, OPK, true>(coef, x, i, 0, nxf, 1, hf, nu, Lx, Ld);
+                acc += wgt[a + 1] * (b[i] - (sigma * x[i] - dt * Lx));
+            }
+        } else {
+#pragma unroll
+            for (int bb = -1; bb <= 1; ++bb) {
+                const int j = wrapm(2 * J + bb, nyf);
+#pragma unroll
+                for (int a = -1; a <= 1; ++a) {
+                    const int i = wrapm(2 * I + a, nxf);
+                    T Lx, Ld;
+                    level_op<T, OPK, true>(coef, x, i, j, nxf, nyf, hf, nu, Lx, Ld);
+                    const size_t p = (size_t)j * nxf + i;
+                    acc += wgt[a + 1] * wgt[bb + 1] * (b[p] - (sigma * x[p] - dt * Lx));
+                }
+            }
+        }
+        bc[q] = acc;
+    }
+}
+
+// x_f += P x_c (bilinear / linear interpolation, coarse node I at fine 2I)
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mg_prolong(int nxf, int nyf, T *__restrict__ xf,
+                                                       const T *__restrict__ xc) {
+    const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
+    const size_t npf = (size_t)nxf * nyf;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npf; p += stride) {
+        const int i = (int)(p % nxf), j = (int)(p / nxf);
+        const int I0 = i >> 1, I1 = (i & 1) ? wrapm(I0 + 1, nxc) : I0;
+        T e;
+        if (nyf == 1) {
+            e = T(0.5) * (xc[I0] + xc[I1]);
+        } else {
+            const int J0 = j >> 1, J1 = (j & 1) ? wrapm(J0 + 1, nyc) : J0;
+            e = T(0.25) * (xc[J0 * nxc + I0] + xc[J0 * nxc + I1] + xc[J1 * nxc + I0] + xc[J1 * nxc + I1]);
+        }
+        xf[p] += e;
+    }
+}
+
+// coarse coefficient = full-weighting restriction of the fine coefficient
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict(int nxf, int nyf, const T *__restrict__ cf,
+                                                             T *__restrict__ cc) {
+    const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
+    const size_t npc = (size_t)nxc * nyc;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const T wgt[3] = {T(0.25), T(0.5), T(0.25)};
+    for (size_t q = (size_t)xcd_block() * blockDim.x + threadIdx.x; q < npc; q += stride) {
+        const int I = (int)(q % nxc), J = (int)(q / nxc);
+        T acc = 0;
+        if (nyf == 1) {
+            for (int a = -1; a <= 1; ++a) acc += wgt[a + 1] * cf[wrapm(2 * I + a, nxf)];
+        } else {
+            for (int bb = -1; bb <= 1; ++bb)
+                for (int a = -1; a <= 1; ++a)
+                    acc += wgt[a + 1] * wgt[bb + 1] * cf[(size_t)wrapm(2 * J + bb, nyf) * nxf + wrapm(2 * I + a, nxf)];
+        }
+        cc[q] = acc;
+    }
+}
+
+// b0 = T(a1 v1 + a2 v2 - (a1 m[0] + a2 m[1]))   (v2 and m may be null; m holds
+// the means of v1, v2 when the result must be mean-free)
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mg_cast_in(T *__restrict__ b0, const double *__restrict__ v1,
+                                                       double a1, const double *__restrict__ v2, double a2,
+                                                       const double *__restrict__ m, size_t len) {
+    double shift = 0.0;
+    if (m) shift = a1 * m[0] + (v2 ? a2 * m[1] : 0.0);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double v = a1 * v1[e];
+        if (v2) v += a2 * v2[e];
+        b0[e] = (T)(v - shift);
+    }
+}
+
+// z = a * double(x) + c * shift[0]   (shift may be null)
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mg_cast_out(double *__restrict__ z, const T *__restrict__ x, double a,
+                                                        const double *__restrict__ shift, double c, size_t len) {
+    const double off = shift ? c * shift[0] : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride)
+        z[e] = a * (double)x[e] + off;
+}
+
+__global__ void __launch_bounds__(IRK_WG) k_fill_f64(double *__restrict__ p, double v, size_t len) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride) p[e] = v;
+}
+
+// Coarsest level: `iters` Chebyshev iterations on [lmax/ratio, lmax] in one
+// work-group with the level in LDS; for the singular periodic Poisson
+// operator the right-hand side and iterate are kept mean-free.
+template <class T, int OPK>
+__global__ void __launch_bounds__(1024) k_mg_coarse(int nx, int ny, T h, T nu, T sigma, T dt,
+                                                    const T *__restrict__ coef, const T *__restrict__ b,
+                                                    T *__restrict__ xout, int iters, T lmax, T lmin) {
+    extern __shared__ unsigned char smem_raw[];
+    const int np = nx * ny;
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    T *sx2 = sx + np;
+    T *sd = sx2 + np;
+    T *sb = sd + np;
+    T *sc = sb + np;
+    __shared__ double red[16];
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        sb[p] = b[p];
+        sc[p] = coef ? coef[p] : T(0);
+        sx[p] = T(0);
+        sd[p] = T(0);
+    }
+    __syncthreads();
+    const bool singular = (OPK == MG_POISSON) && sigma == T(0);
+    if (singular) {
+        double acc = 0;
+        for (int p = threadIdx.x; p < np; p += blockDim.x) acc += (double)sb[p];
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        double tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+        const T m = (T)(tot / np);
+        __syncthreads();
+        for (int p = threadIdx.x; p < np; p += blockDim.x) sb[p] -= m;
+        __syncthreads();
+    }
+    const T theta = T(0.5) * (lmax + lmin), delta = T(0.5) * (lmax - lmin);
+    const T sig1 = theta / delta;
+    T rho = T(1) / sig1;
+    for (int k = 0; k < iters; ++k) {
+        T cd, cr;
+        if (k == 0) { cd = T(0); cr = T(1) / theta; }
+        else { const T rn = T(1) / (T(2) * sig1 - rho); cd = rn * rho; cr = T(2) * rn / delta; rho = rn; }
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            const int i = p % nx, j = p / nx;
+            T Lx, Ld;
+            level_op<T, OPK, true>(sc, sx, i, j, nx, ny, h, nu, Lx, Ld);
+            const T r = sb[p] - (sigma * sx[p] - dt * Lx);
+            const T diag = sigma - dt * Ld;
+            const T dn = cd * sd[p] + cr * r / diag;
+            sd[p] = dn;
+            sx2[p] = sx[p] + dn;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < np; p += blockDim.x) sx[p] = sx2[p];
+        __syncthreads();
+    }
+    for (int p = threadIdx.x; p < np; p += blockDim.x) xout[p] = sx[p];
+}
+
+// ------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------
+static inline unsigned grid_for(size_t n, unsigned cap = 8192) {
+    size_t g = (n + IRK_WG - 1) / IRK_WG;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, double *K, const double *Y, double *U,
+                       const StageCoefs &C, double dt, int fold) {
+    const unsigned g = grid_for(nf);
+    switch (s) {
+        case 1: k_stage_prep<1><<<g, IRK_WG, 0, st>>>(nf, un, K, Y, U, C, dt, fold); break;
+        case 2: k_stage_prep<2><<<g, IRK_WG, 0, st>>>(nf, un, K, Y, U, C, dt, fold); break;
+        case 3: k_stage_prep<3><<<g, IRK_WG, 0, st>>>(nf, un, K, Y, U, C, dt, fold); break;
+        case 4: k_stage_prep<4><<<g, IRK_WG, 0, st>>>(nf, un, K, Y, U, C, dt, fold); break;
+        case 5: k_stage_prep<5><<<g, IRK_WG, 0, st>>>(nf, un, K, Y, U, C, dt, fold); break;
+    }
+}
+
+template <int S>
+static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, const double *K, double *Fh,
+                       const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr) {
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
+    if (P.kind == IRK_OP_NLDIFF_2D)
+        k_residual<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
+    else if (P.kind == IRK_OP_BURGERS_1D)
+        k_residual<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
+    else
+        k_residual<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
+}
+
+void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
+                     const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr) {
+    switch (s) {
+        case 1: residual_s<1>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+        case 2: residual_s<2>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+        case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+        case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+        case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+    }
+}
+
+template <int S>
+static void rhs_init_s(hipStream_t st, const DeviceProblem &P, const double *un, double *K, double s_n, double c_n) {
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const unsigned g = grid_for(npts);
+    if (P.kind == IRK_OP_NLDIFF_2D) k_rhs_init<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+    else if (P.kind == IRK_OP_BURGERS_1D) k_rhs_init<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+    else k_rhs_init<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+}
+
+void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
+                     double cos_tn) {
+    switch (s) {
+        case 1: rhs_init_s<1>(st, P, un, K, sin_tn, cos_tn); break;
+        case 2: rhs_init_s<2>(st, P, un, K, sin_tn, cos_tn); break;
+        case 3: rhs_init_s<3>(st, P, un, K, sin_tn, cos_tn); break;
+        case 4: rhs_init_s<4>(st, P, un, K, sin_tn, cos_tn); break;
+        case 5: rhs_init_s<5>(st, P, un, K, sin_tn, cos_tn); break;
+    }
+}
+
+void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, const double *K, double *out,
+                         const StageCoefs &C, double dt) {
+    const unsigned g = grid_for(nf);
+    switch (s) {
+        case 1: k_final_update<1><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+        case 2: k_final_update<2><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+        case 3: k_final_update<3><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+        case 4: k_final_update<4><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+        case 5: k_final_update<5><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+    }
+}
+
+void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, size_t len, double scale,
+                       double *partials, double *out, unsigned *ctr) {
+    k_field_sums<<<grid_for(len, IRK_RED_BLOCKS), IRK_WG, 0, st>>>(X, ld, nfields, len, scale, partials, out, ctr);
+}
+
+void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
+                         const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans) {
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const unsigned g = grid_for(npts);
+    if (P.kind == IRK_OP_NLDIFF_2D)
+        k_block_matvec<IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+    else if (P.kind == IRK_OP_BURGERS_1D)
+        k_block_matvec<IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+    else
+        k_block_matvec<IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+}
+
+void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
+                      int with_norm, double *partials, double *out, unsigned *ctr) {
+    // chunks of DOT_CHUNK vectors; the norm (if any) rides on the last chunk
+    int done = 0;
+    do {
+        const int c = (nv - done) > DOT_CHUNK ? DOT_CHUNK : (nv - done);
+        const int last = (done + c == nv);
+        k_dot_multi<<<grid_for(len, IRK_RED_BLOCKS), IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len,
+                                                                       last ? with_norm : 0, partials,
+                                                                       out + done, ctr);
+        done += c;
+    } while (done < nv);
+}
+
+void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len) {
+    k_axpy_multi<<<grid_for(len), IRK_WG, 0, st>>>(w, V, ldv, nv, h, len);
+}
+
+void launch_lincomb(hipStream_t st, double *dst, const double *V, size_t ldv, int nv, const double *c, size_t len) {
+    k_lincomb<<<grid_for(len), IRK_WG, 0, st>>>(dst, V, ldv, nv, c, len);
+}
+
+void launch_scale_copy(hipStream_t st, double *dst, const double *src, const double *nrm2, size_t len) {
+    k_scale_copy<<<grid_for(len), IRK_WG, 0, st>>>(dst, src, nrm2, len);
+}
+
+void launch_axpby(hipStream_t st, double *dst, double a, const double *x, double b, const double *y, size_t len) {
+    k_axpby<<<grid_for(len), IRK_WG, 0, st>>>(dst, a, x, b, y, len);
+}
+
+void launch_zero_u32(hipStream_t st, unsigned *p, int n) { k_zero_u32<<<1, 256, 0, st>>>(p, n); }
+
+void launch_fill(hipStream_t st, double *p, double v, size_t len) {
+    k_fill_f64<<<grid_for(len), IRK_WG, 0, st>>>(p, v, len);
+}
+
+template <class T>
+void launch_mg_cheb(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
+                    const T *coef, const T *xin, T *xout, const T *b, T *d, double cd, double cr) {
+    const unsigned g = grid_for((size_t)nx * ny);
+#define CHEB(K) k_mg_cheb<T, K><<<g, IRK_WG, 0, st>>>(nx, ny, (T)h, (T)nu, (T)sigma, (T)dt, coef, xin, xout, b, d, (T)cd, (T)cr)
+    switch (opk) {
+        case MG_NLDIFF: CHEB(MG_NLDIFF); break;
+        case MG_BURGERS: CHEB(MG_BURGERS); break;
+        case MG_VSF_OMEGA: CHEB(MG_VSF_OMEGA); break;
+        default: CHEB(MG_POISSON); break;
+    }
+#undef CHEB
+}
+
+template <class T>
+void launch_mg_restrict_res(hipStream_t st, int opk, int nxf, int nyf, double hf, double nu, double sigma,
+                            double dt, const T *coef, const T *x, const T *b, T *bc) {
+    const size_t npc = (size_t)(nxf / 2) * (nyf > 1 ? nyf / 2 : 1);
+    const unsigned g = grid_for(npc);
+#define RR(K) k_mg_restrict_res<T, K><<<g, IRK_WG, 0, st>>>(nxf, nyf, (T)hf, (T)nu, (T)sigma, (T)dt, coef, x, b, bc)
+    switch (opk) {
+        case MG_NLDIFF: RR(MG_NLDIFF); break;
+        case MG_BURGERS: RR(MG_BURGERS); break;
+        case MG_VSF_OMEGA: RR(MG_VSF_OMEGA); break;
+        default: RR(MG_POISSON); break;
+    }
+#undef RR
+}
+
+template <class T>
+void launch_mg_prolong(hipStream_t st, int nxf, int nyf, T *xf, const T *xc) {
+    k_mg_prolong<T><<<grid_for((size_t)nxf * nyf), IRK_WG, 0, st>>>(nxf, nyf, xf, xc);
+}
+
+template <class T>
+void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc) {
+    const size_t npc = (size_t)(nxf / 2) * (nyf > 1 ? nyf / 2 : 1);
+    k_mg_coef_restrict<T><<<grid_for(npc), IRK_WG, 0, st>>>(nxf, nyf, cf, cc);
+}
+
+template <class T>
+void launch_mg_cast_in(hipStream_t st, T *b0, const double *v1, double a1, const double *v2, double a2,
+                       const double *means, size_t len) {
+    k_mg_cast_in<T><<<grid_for(len), IRK_WG, 0, st>>>(b0, v1, a1, v2, a2, means, len);
+}
+
+template <class T>
+void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const double *shift, double c,
+                        size_t len) {
+    k_mg_cast_out<T><<<grid_for(len), IRK_WG, 0, st>>>(z, x, a, shift, c, len);
+}
+
+template <class T>
+void launch_mg_coarse(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
+                      const T *coef, const T *b, T *x, int iters, double lmax, double lmin) {
+    const size_t shm = (size_t)5 * nx * ny * sizeof(T);
+    const unsigned nt = (nx * ny >= 1024) ? 1024 : ((nx * ny + 63) / 64) * 64;
+#define CO(K) k_mg_coarse<T, K><<<1, nt, shm, st>>>(nx, ny, (T)h, (T)nu, (T)sigma, (T)dt, coef, b, x, iters, (T)lmax, (T)lmin)
+    switch (opk) {
+        case MG_NLDIFF: CO(MG_NLDIFF); break;
+        case MG_BURGERS: CO(MG_BURGERS); break;
+        case MG_VSF_OMEGA: CO(MG_VSF_OMEGA); break;
+        default: CO(MG_POISSON); break;
+    }
+#undef CO
+}
+
+template <class T>
+void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len) {
+    launch_mg_cast_in<T>(st, dst, src, 1.0, nullptr, 0.0, nullptr, len);
+}
+
+#define INST(T)                                                                                                    \
+    template void launch_mg_cheb<T>(hipStream_t, int, int, int, double, double, double, double, const T *,          \
+                                    const T *, T *, const T *, T *, double, double);                               \
+    template void launch_mg_restrict_res<T>(hipStream_t, int, int, int, double, double, double, double, const T *,  \
+                                            const T *, const T *, T *);                                            \
+    template void launch_mg_prolong<T>(hipStream_t, int, int, T *, const T *);                                     \
+    template void launch_mg_coef_restrict<T>(hipStream_t, int, int, const T *, T *);                               \
+    template void launch_mg_cast_in<T>(hipStream_t, T *, const double *, double, const double *, double,           \
+                                       const double *, size_t);                                                    \
+    template void launch_mg_cast_out<T>(hipStream_t, double *, const T *, double, const double *, double, size_t); \
+    template void launch_mg_coarse<T>(hipStream_t, int, int, int, double, double, double, double, const T *,        \
+                                      const T *, T *, int, double, double);                                        \
+    template void launch_cast_coef<T>(hipStream_t, T *, const double *, size_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace irk

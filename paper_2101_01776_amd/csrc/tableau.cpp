@@ -1,0 +1,371 @@
+// Host construction of the Runge-Kutta tableaux and of the real eigenbasis
+// of A0^{-1} (paper Sections 1.1, 3.1 and 5).  Pure host code, long double.
+//
+// * Nodes: roots of the shifted Legendre polynomial P_s(2x-1) (Gauss) or of
+//   P_s(2x-1) - P_{s-1}(2x-1) (Radau IIA, c_s = 1), found by bracketing on a
+//   fine grid and Newton polishing.
+// * A, b: collocation integrals a_ij = int_0^{c_i} l_j, b_j = int_0^1 l_j of
+//   the Lagrange basis on the nodes.
+// * Eigenbasis: characteristic polynomial of A0^{-1} (Faddeev-LeVerrier),
+//   roots by the Aberth-Ehrlich iteration, eigenvectors as null vectors of
+//   (A0^{-1} - lambda I) by complex elimination with full pivoting.  Complex
+//   pairs eta +- i beta give the real 2x2 block [[eta, beta], [-beta, eta]]
+//   with the columns (Re v, Im v) of the eigenvector of eta + i beta, phased so
+//   that Re v is orthogonal to Im v (the form [[eta, phi], [-beta^2/phi, eta]]
+//   of Section 3.1 with phi = beta).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "irk_internal.h"
+
+namespace irk {
+
+typedef long double ld;
+typedef std::complex<long double> cld;
+
+static ld binom(int n, int k) {
+    ld r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// ascending coefficients of P_n(2x - 1) = sum_k (-1)^(n+k) C(n,k) C(n+k,k) x^k
+static std::vector<ld> shifted_legendre(int n) {
+    std::vector<ld> c(n + 1);
+    for (int k = 0; k <= n; ++k)
+        c[k] = (((n + k) % 2) ? -1.0L : 1.0L) * binom(n, k) * binom(n + k, k);
+    return c;
+}
+
+static ld horner(const std::vector<ld> &c, ld x, ld *deriv) {
+    ld p = 0, dp = 0;
+    for (int k = (int)c.size() - 1; k >= 0; --k) {
+        dp = dp * x + p;
+        p = p * x + c[k];
+    }
+    if (deriv) *deriv = dp;
+    return p;
+}
+
+// real roots of c in [0, 1] (all simple), ascending
+static std::vector<ld> roots_unit_interval(const std::vector<ld> &c, int expect) {
+    std::vector<ld> r;
+    const int G = 20000;
+    ld xa = 0, fa = horner(c, 0, nullptr);
+    for (int g = 1; g <= G && (int)r.size() < expect; ++g) {
+        ld xb = (ld)g / G, fb = horner(c, xb, nullptr);
+        if (fb == 0) { r.push_back(xb); xa = xb; fa = fb; continue; }
+        if ((fa < 0) != (fb < 0) && fa != 0) {
+            ld lo = xa, hi = xb, flo = fa;
+            for (int it = 0; it < 200; ++it) {          // bisection
+                ld mid = 0.5L * (lo + hi), fm = horner(c, mid, nullptr);
+                if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+            }
+            ld x = 0.5L * (lo + hi);
+            for (int it = 0; it < 5; ++it) {             // Newton polish
+                ld d, f = horner(c, x, &d);
+                if (d != 0) x -= f / d;
+            }
+            r.push_back(x);
+        }
+        xa = xb; fa = fb;
+    }
+    return r;
+}
+
+static std::vector<ld> lagrange(const std::vector<ld> &c, int j) {
+    std::vector<ld> p(1, 1.0L);
+    ld den = 1;
+    for (size_t m = 0; m < c.size(); ++m) {
+        if ((int)m == j) continue;
+        std::vector<ld> q(p.size() + 1, 0.0L);
+        for (size_t k = 0; k < p.size(); ++k) { q[k] -= p[k] * c[m]; q[k + 1] += p[k]; }
+        p.swap(q);
+        den *= (c[j] - c[m]);
+    }
+    for (auto &v : p) v /= den;
+    return p;
+}
+
+static ld integrate0(const std::vector<ld> &p, ld x) {
+    ld s = 0, xp = x;
+    for (size_t k = 0; k < p.size(); ++k) { s += p[k] * xp / (ld)(k + 1); xp *= x; }
+    return s;
+}
+
+bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
+    if (s < 1 || s > IRK_MAX_STAGES) return false;
+    std::vector<ld> nodes;
+    if (family == IRK_GAUSS) {
+        nodes = roots_unit_interval(shifted_legendre(s), s);
+    } else if (family == IRK_RADAU_IIA) {
+        if (s == 1) {
+            nodes.push_back(1.0L);
+        } else {
+            std::vector<ld> p = shifted_legendre(s), q = shifted_legendre(s - 1);
+            for (size_t k = 0; k < q.size(); ++k) p[k] -= q[k];
+            // deflate the root at x = 1: divide by (x - 1) (synthetic division)
+            int deg = s;
+            std::vector<ld> d(deg);
+            ld carry = p[deg];
+            for (int k = deg - 1; k >= 0; --k) { d[k] = carry; carry = p[k] + carry; }
+            nodes = roots_unit_interval(d, s - 1);
+            nodes.push_back(1.0L);
+        }
+    } else {
+        return false;
+    }
+    if ((int)nodes.size() != s) return false;
+    std::sort(nodes.begin(), nodes.end());
+    for (int j = 0; j < s; ++j) {
+        std::vector<ld> l = lagrange(nodes, j);
+        for (int i = 0; i < s; ++i) A[i * s + j] = integrate0(l, nodes[i]);
+        b[j] = integrate0(l, 1.0L);
+    }
+    for (int i = 0; i < s; ++i) c[i] = nodes[i];
+    return true;
+}
+
+// Gauss-Jordan inverse with partial pivoting (n <= 5)
+static bool invert_ld(int n, const ld *M, ld *Minv) {
+    ld a[IRK_MAX_STAGES][2 * IRK_MAX_STAGES];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j)
+            a[i][j] = j < n ? M[i * n + j] : (j - n == i ? 1.0L : 0.0L);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabsl(a[r][col]) > fabsl(a[piv][col])) piv = r;
+        if (a[piv][col] == 0) return false;
+        for (int j = 0; j < 2 * n; ++j) std::swap(a[col][j], a[piv][j]);
+        ld inv = 1.0L / a[col][col];
+        for (int j = 0; j < 2 * n; ++j) a[col][j] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            ld f = a[r][col];
+            if (f == 0) continue;
+            for (int j = 0; j < 2 * n; ++j) a[r][j] -= f * a[col][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Minv[i * n + j] = a[i][n + j];
+    return true;
+}
+
+// characteristic polynomial coefficients (ascending, monic) by Faddeev-LeVerrier
+static std::vector<ld> charpoly(int n, const ld *M) {
+    std::vector<ld> cp(n + 1, 0.0L);
+    cp[n] = 1.0L;
+    std::vector<ld> Mk(n * n, 0.0L), AMk(n * n);
+    for (int k = 1; k <= n; ++k) {
+        // Mk = M * M_{k-1} + c_{n-k+1} I
+        std::vector<ld> T(n * n, 0.0L);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                ld sacc = 0;
+                for (int q = 0; q < n; ++q) sacc += M[i * n + q] * Mk[q * n + j];
+                T[i * n + j] = sacc + (i == j ? cp[n - k + 1] : 0.0L);
+            }
+        Mk = T;
+        ld tr = 0;
+        for (int i = 0; i < n; ++i) {
+            ld sacc = 0;
+            for (int q = 0; q < n; ++q) sacc += M[i * n + q] * Mk[q * n + i];
+            tr += sacc;
+        }
+        cp[n - k] = -tr / (ld)k;
+    }
+    return cp;
+}
+
+static std::vector<cld> aberth(const std::vector<ld> &cp) {
+    int n = (int)cp.size() - 1;
+    std::vector<cld> z(n);
+    // initial guesses on a circle of the Cauchy bound radius
+    ld rad = 0;
+    for (int k = 0; k < n; ++k) rad = std::max(rad, fabsl(cp[k]));
+    rad = 1 + rad;
+    for (int k = 0; k < n; ++k) z[k] = std::polar(rad * 0.5L, (ld)(2 * M_PI * (k + 0.25) / n));
+    auto evalp = [&](cld x, cld *d) {
+        cld p = 0, dp = 0;
+        for (int k = n; k >= 0; --k) { dp = dp * x + p; p = p * x + cp[k]; }
+        *d = dp;
+        return p;
+    };
+    for (int it = 0; it < 500; ++it) {
+        ld maxstep = 0;
+        for (int k = 0; k < n; ++k) {
+            cld d, p = evalp(z[k], &d);
+            if (std::abs(p) == 0) continue;
+            cld ratio = p / d, sum = 0;
+            for (int j = 0; j < n; ++j)
+                if (j != k) sum += 1.0L / (z[k] - z[j]);
+            cld w = ratio / (1.0L - ratio * sum);
+            z[k] -= w;
+            maxstep = std::max(maxstep, std::abs(w) / std::max((ld)1, std::abs(z[k])));
+        }
+        if (maxstep < 1e-30L) break;
+    }
+    for (int k = 0; k < n; ++k) {                          // Newton polish
+        for (int it = 0; it < 3; ++it) {
+            cld d, p = evalp(z[k], &d);
+            if (std::abs(d) > 0) z[k] -= p / d;
+        }
+    }
+    return z;
+}
+
+// null vector of (M - lam I) by complex elimination with full pivoting
+static std::vector<cld> null_vector(int n, const ld *M, cld lam) {
+    cld a[IRK_MAX_STAGES][IRK_MAX_STAGES];
+    int colperm[IRK_MAX_STAGES];
+    for (int i = 0; i < n; ++i) {
+        colperm[i] = i;
+        for (int j = 0; j < n; ++j) a[i][j] = cld(M[i * n + j]) - (i == j ? lam : cld(0));
+    }
+    for (int k = 0; k < n - 1; ++k) {
+        int pr = k, pc = k;
+        ld best = -1;
+        for (int i = k; i < n; ++i)
+            for (int j = k; j < n; ++j)
+                if (std::abs(a[i][j]) > best) { best = std::abs(a[i][j]); pr = i; pc = j; }
+        for (int j = 0; j < n; ++j) std::swap(a[k][j], a[pr][j]);
+        for (int i = 0; i < n; ++i) std::swap(a[i][k], a[i][pc]);
+        std::swap(colperm[k], colperm[pc]);
+        for (int i = k + 1; i < n; ++i) {
+            cld f = a[i][k] / a[k][k];
+            for (int j = k; j < n; ++j) a[i][j] -= f * a[k][j];
+        }
+    }
+    // the last pivot is ~0: set the last permuted unknown to 1, back-substitute
+    std::vector<cld> y(n);
+    y[n - 1] = 1;
+    for (int k = n - 2; k >= 0; --k) {
+        cld sacc = 0;
+        for (int j = k + 1; j < n; ++j) sacc += a[k][j] * y[j];
+        y[k] = -sacc / a[k][k];
+    }
+    std::vector<cld> v(n);
+    for (int k = 0; k < n; ++k) v[colperm[k]] = y[k];
+    return v;
+}
+
+bool build_eigen_blocks(int family, int s, EigenBlocks *eb) {
+    ld A[IRK_MAX_STAGES * IRK_MAX_STAGES], b[IRK_MAX_STAGES], c[IRK_MAX_STAGES];
+    if (!build_tableau_ld(family, s, A, b, c)) return false;
+    ld Ai[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    if (!invert_ld(s, A, Ai)) return false;
+    for (int i = 0; i < s * s; ++i) { eb->A[i] = (double)A[i]; eb->Ainv[i] = (double)Ai[i]; }
+    for (int i = 0; i < s; ++i) { eb->b[i] = (double)b[i]; eb->c[i] = (double)c[i]; }
+    eb->s = s;
+
+    std::vector<cld> lam = s == 1 ? std::vector<cld>{cld(Ai[0])} : aberth(charpoly(s, Ai));
+    std::vector<ld> reals;
+    std::vector<cld> ups;                                   // eigenvalues with Im > 0
+    for (auto &l : lam) {
+        if (fabsl(l.imag()) < 1e-12L * std::max((ld)1, std::abs(l))) reals.push_back(l.real());
+        else if (l.imag() > 0) ups.push_back(l);
+    }
+    std::sort(reals.begin(), reals.end());
+    std::sort(ups.begin(), ups.end(), [](const cld &x, const cld &y) { return x.imag() > y.imag(); });
+    if ((int)(reals.size() + 2 * ups.size()) != s) return false;
+
+    ld T[IRK_MAX_STAGES * IRK_MAX_STAGES] = {0};
+    int row = 0, nb = 0;
+    for (ld lr : reals) {
+        std::vector<cld> v = null_vector(s, Ai, cld(lr));
+        ld nrm = 0, big = 0;
+        int ib = 0;
+        for (int i = 0; i < s; ++i) { nrm += std::norm(v[i]); if (fabsl(v[i].real()) > big) { big = fabsl(v[i].real()); ib = i; } }
+        ld sg = v[ib].real() < 0 ? -1.0L : 1.0L;
+        for (int i = 0; i < s; ++i) T[i * s + row] = sg * v[i].real() / sqrtl(nrm);
+        eb->width[nb] = 1; eb->eta[nb] = (double)lr; eb->beta[nb] = 0.0; eb->first[nb] = row;
+        ++nb; ++row;
+    }
+    for (cld l : ups) {
+        std::vector<cld> v = null_vector(s, Ai, l);
+        ld nrm = 0;
+        for (int i = 0; i < s; ++i) nrm += std::norm(v[i]);
+        for (int i = 0; i < s; ++i) v[i] /= sqrtl(nrm);
+        // phase: Re v orthogonal to Im v, |Re v| >= |Im v|
+        ld aa = 0, bb = 0, ab = 0;
+        for (int i = 0; i < s; ++i) { aa += v[i].real() * v[i].real(); bb += v[i].imag() * v[i].imag(); ab += v[i].real() * v[i].imag(); }
+        ld th = 0.5L * atan2l(-2.0L * ab, aa - bb);
+        cld rot = std::polar((ld)1, th);
+        for (int i = 0; i < s; ++i) v[i] *= rot;
+        aa = bb = 0;
+        for (int i = 0; i < s; ++i) { aa += v[i].real() * v[i].real(); bb += v[i].imag() * v[i].imag(); }
+        if (bb > aa) for (int i = 0; i < s; ++i) v[i] *= cld(0, 1);   // quarter turn
+        int ib = 0;
+        ld big = 0;
+        for (int i = 0; i < s; ++i) if (fabsl(v[i].real()) > big) { big = fabsl(v[i].real()); ib = i; }
+        if (v[ib].real() < 0) for (int i = 0; i < s; ++i) v[i] = -v[i];
+        for (int i = 0; i < s; ++i) { T[i * s + row] = v[i].real(); T[i * s + row + 1] = v[i].imag(); }
+        eb->width[nb] = 2; eb->eta[nb] = (double)l.real(); eb->beta[nb] = (double)l.imag(); eb->first[nb] = row;
+        ++nb; row += 2;
+    }
+    eb->nblocks = nb;
+    ld Ti[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    if (!invert_ld(s, T, Ti)) return false;
+    // Lambda (block diagonal) and T Lambda, used for the stage update
+    ld Lam[IRK_MAX_STAGES * IRK_MAX_STAGES] = {0};
+    for (int k = 0; k < nb; ++k) {
+        int r = eb->first[k];
+        ld e = eb->eta[k], bt = eb->beta[k];
+        Lam[r * s + r] = e;
+        if (eb->width[k] == 2) {
+            Lam[r * s + r + 1] = bt; Lam[(r + 1) * s + r] = -bt; Lam[(r + 1) * s + r + 1] = e;
+        }
+        eb->gamma_star[k] = (double)(e + bt * bt / e);
+    }
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+            ld tl = 0;
+            for (int q = 0; q < s; ++q) tl += T[i * s + q] * Lam[q * s + j];
+            eb->TLam[i * s + j] = (double)tl;
+            eb->T[i * s + j] = (double)T[i * s + j];
+            eb->Tinv[i * s + j] = (double)Ti[i * s + j];
+        }
+    // d weights d[k][l][i] = Tinv[k][i] T[i][l] (equation (Q0approx)), and the
+    // argmax stage of each diagonal weight vector (Newton-like(1))
+    for (int k = 0; k < s; ++k) {
+        int best = 0;
+        ld bv = -1;
+        for (int i = 0; i < s; ++i) {
+            ld d = fabsl(Ti[k * s + i] * T[i * s + k]);
+            if (d > bv) { bv = d; best = i; }
+        }
+        eb->argmax_stage[k] = best;
+    }
+    return true;
+}
+
+}  // namespace irk
+
+extern "C" irk_status irk_tableau(irk_family family, int s, double *A, double *b, double *c) {
+    if (!A || !b || !c || s < 1 || s > IRK_MAX_STAGES) return IRK_E_ARG;
+    long double Al[IRK_MAX_STAGES * IRK_MAX_STAGES], bl[IRK_MAX_STAGES], cl[IRK_MAX_STAGES];
+    if (!irk::build_tableau_ld(family, s, Al, bl, cl)) return IRK_E_ARG;
+    for (int i = 0; i < s * s; ++i) A[i] = (double)Al[i];
+    for (int i = 0; i < s; ++i) { b[i] = (double)bl[i]; c[i] = (double)cl[i]; }
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_eigen_blocks(irk_family family, int s, double *T, double *Tinv,
+                                       int *nblocks, int *width, double *eta, double *beta,
+                                       double *gamma_star, int *first_row) {
+    if (!T || !Tinv || !nblocks || !width || !eta || !beta || !gamma_star || !first_row) return IRK_E_ARG;
+    irk::EigenBlocks eb;
+    if (!irk::build_eigen_blocks(family, s, &eb)) return IRK_E_ARG;
+    std::memcpy(T, eb.T, sizeof(double) * s * s);
+    std::memcpy(Tinv, eb.Tinv, sizeof(double) * s * s);
+    *nblocks = eb.nblocks;
+    for (int k = 0; k < eb.nblocks; ++k) {
+        width[k] = eb.width[k]; eta[k] = eb.eta[k]; beta[k] = eb.beta[k];
+        gamma_star[k] = eb.gamma_star[k]; first_row[k] = eb.first[k];
+    }
+    return IRK_OK;
+}

@@ -1,0 +1,111 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, and its host-only logic (tableaux, eigenbasis of A0^{-1},
+options, workspace sizing, argument validation) agrees with the oracle and
+the paper."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import tableau as tb
+from paper_2101_01776_amd import irk
+
+HEADER = os.path.join(ROOT, "include", "irk.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(irk_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = irk.lib()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_status_strings_and_defaults():
+    L = irk.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.irk_status_str(code)
+    o = irk.irk_default_options()
+    assert o.newton_rtol == 1e-12 and o.krylov_rtol == 1e-5 and o.restart == 30
+    assert o.prec_fp32 == 1 and o.cheb_degree == 3 and o.newton_like == 1 and o.gamma_mode == 0
+
+
+@pytest.mark.parametrize("family", ["gauss", "radau"])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5])
+def test_host_tableau_matches_oracle(family, s):
+    A, b, c = irk.irk_tableau(family, s)
+    A2, b2, c2 = tb.tableau(family, s)
+    assert np.max(np.abs(A - A2)) <= 1e-16 and np.max(np.abs(b - b2)) <= 1e-16
+    assert np.max(np.abs(c - c2)) <= 1e-16
+
+
+@pytest.mark.parametrize("family", ["gauss", "radau"])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5])
+def test_host_eigenbasis(family, s):
+    """A0^{-1} = T Lambda T^{-1} with Lambda in the real block form, eigenvalues
+    and gamma_* equal to the oracle's."""
+    e = irk.irk_eigen_blocks(family, s)
+    A2, _, _ = tb.tableau(family, s)
+    Ainv = np.linalg.inv(A2)
+    Lam = np.zeros((s, s))
+    for k in range(e["nblocks"]):
+        r = e["first_row"][k]
+        Lam[r, r] = e["eta"][k]
+        if e["width"][k] == 2:
+            Lam[r, r + 1] = e["beta"][k]
+            Lam[r + 1, r] = -e["beta"][k]
+            Lam[r + 1, r + 1] = e["eta"][k]
+    assert np.max(np.abs(e["T"] @ Lam @ e["Tinv"] - Ainv)) <= 1e-14 * np.abs(Ainv).max()
+    assert np.max(np.abs(e["T"] @ e["Tinv"] - np.eye(s))) <= 1e-14
+    want = tb.inverse_eigs(A2)
+    got = list(zip(e["eta"], e["beta"]))
+    assert len(got) == len(want)
+    for (ge, gb), (we, wb) in zip(got, want):
+        assert abs(ge - we) < 1e-12 * we and abs(gb - wb) < 1e-12 * max(1.0, wb)
+    for k in range(e["nblocks"]):
+        assert abs(e["gamma_star"][k] - tb.gamma_star(e["eta"][k], e["beta"][k])) < 1e-13 * e["gamma_star"][k]
+    # columns of a pair: Re v orthogonal to Im v
+    for k in range(e["nblocks"]):
+        if e["width"][k] == 2:
+            r = e["first_row"][k]
+            assert abs(e["T"][:, r] @ e["T"][:, r + 1]) < 1e-14
+
+
+def test_workspace_sizing_and_validation():
+    op = irk.make_operator(irk.OP_NLDIFF_2D, 512, forcing=irk.FORCING_MMS)
+    n = irk.irk_workspace_bytes("gauss", 3, op)
+    # at least K, Y, Fh, U (4 s fields) and the Krylov bases V (31 vectors of 2
+    # fields) and Z (30 vectors of 2 fields)
+    assert n >= (4 * 3 + 31 * 2 + 30 * 2) * 512 * 512 * 8
+    fp64 = irk.irk_workspace_bytes("gauss", 3, op, irk.make_options(prec_fp32=0))
+    assert fp64 > n
+    bad = [irk.make_operator(irk.OP_NLDIFF_2D, 512, 256),            # nx != ny
+           irk.make_operator(irk.OP_BURGERS_1D, 256, 2),             # 1-D with ny > 1
+           irk.make_operator(7, 64)]                                 # unknown kind
+    for b in bad:
+        assert irk.irk_workspace_bytes("gauss", 3, b) == 0
+    assert irk.irk_workspace_bytes("gauss", 6, op) == 0              # s > 5
+    assert irk.irk_workspace_bytes("gauss", 3, op, irk.make_options(restart=0)) == 0
+    # a coarsest level larger than one work-group can hold is refused
+    assert irk.irk_workspace_bytes("gauss", 3, irk.make_operator(irk.OP_NLDIFF_2D, 66)) == 0
+
+
+def test_create_rejects_bad_workspace_without_gpu_work():
+    op = irk.make_operator(irk.OP_NLDIFF_2D, 32)
+    ctx = ctypes.c_void_p()
+    L = irk.lib()
+    st = L.irk_create(irk.GAUSS, 3, ctypes.byref(op), None, None, 0, None, ctypes.byref(ctx))
+    assert st == -1 and not ctx.value
+    st = L.irk_create(irk.GAUSS, 3, ctypes.byref(op), None, ctypes.c_void_p(256), 16, None, ctypes.byref(ctx))
+    assert st == -2 and not ctx.value
+    L.irk_destroy(None)
