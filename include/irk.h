@@ -189,6 +189,22 @@ irk_status irk_eval_residual(irk_ctx *ctx, const double *u_n, double t_n,
  * into the caller's device buffer.                                          */
 irk_status irk_get_stages(irk_ctx *ctx, double *K);
 
+/* ------------------------------ measurement ------------------------------ */
+
+/* Per-kernel timing for roofline measurement (not part of the method).
+ * enable != 0 starts (and resets) recording: every kernel launch of later
+ * irk_step calls is bracketed by HIP events on the context's stream and
+ * attributed its algorithmic bytes (compulsory field traffic of that launch).
+ * Results are grouped by kernel symbol (template instance); irk_profile_count
+ * gives the number of groups, irk_profile_entry group idx: its name (written
+ * to name, at most name_len bytes including the terminator), launches, summed
+ * event time in milliseconds and summed algorithmic bytes.  Recording adds
+ * event overhead; do not time throughput with it enabled.                  */
+irk_status irk_profile_enable(irk_ctx *ctx, int enable);
+int irk_profile_count(irk_ctx *ctx);
+irk_status irk_profile_entry(irk_ctx *ctx, int idx, char *name, int name_len, long *launches,
+                             double *total_ms, double *total_bytes);
+
 /* Release the context (not the caller's workspace).  NULL is accepted.     */
 void irk_destroy(irk_ctx *ctx);
 

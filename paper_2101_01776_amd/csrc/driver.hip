@@ -10,8 +10,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "irk_internal.h"
@@ -150,10 +152,11 @@ using namespace irk;
 
 // dvals slots (float64 scalars on the device)
 enum {
-    DV_RES = 0,        // ||F||^2
-    DV_K0 = 1,         // ||K0||^2
-    DV_BETA = 2,       // ||r0||^2 of a block solve
-    DV_NRM = 3,        // ||w||^2 after orthogonalization
+    DV_RES = 0,        // ||F||^2, then the squared norm of |terms of F| (DV_RES + 1)
+    DV_ABS = 1,
+    DV_K0 = 2,         // ||K0||^2
+    DV_BETA = 4,       // ||r0||^2 of a block solve
+    DV_NRM = 5,        // ||w||^2 after orthogonalization
     DV_SUMS = 8,       // field sums (up to 16)
     DV_MEANS = 24,     // VSF stage means (2 s)
     DV_XMEANS = 40,    // VSF matvec input means (4)
@@ -177,10 +180,76 @@ struct irk_ctx {
     double lmax = 2.0, lmin = 0.5, coarse_lmin = 0.1;
     irk_stats *st = nullptr;
     double dt = 0;
+    // optional per-kernel timing with HIP events (irk_profile_enable)
+    bool prof = false;
+    std::vector<std::string> prof_names;
+    std::vector<double> prof_ms, prof_bytes;
+    std::vector<long> prof_launches;
+    struct Rec { int id; double bytes; long n; hipEvent_t e0, e1; };
+    std::vector<Rec> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
 
     template <class T> T *lev(int l, int q) { return reinterpret_cast<T *>(ws + P.off_lev[l][q]); }
     template <class T> T *coef(int h, int l) { return reinterpret_cast<T *>(ws + P.off_coef[h][l]); }
 };
+
+static hipEvent_t prof_event(irk_ctx *c) {
+    if (c->ev_next < c->ev_pool.size()) return c->ev_pool[c->ev_next++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+    c->ev_next = c->ev_pool.size();
+    return e;
+}
+
+static int prof_id(irk_ctx *c, const std::string &name) {
+    for (size_t i = 0; i < c->prof_names.size(); ++i)
+        if (c->prof_names[i] == name) return (int)i;
+    c->prof_names.push_back(name);
+    c->prof_ms.push_back(0.0);
+    c->prof_bytes.push_back(0.0);
+    c->prof_launches.push_back(0);
+    return (int)c->prof_names.size() - 1;
+}
+
+// harvest the recorded event pairs (call after the stream has synchronized)
+static void prof_harvest(irk_ctx *c) {
+    for (auto &r : c->prof_pending) {
+        float ms = 0.f;
+        if (r.e0 && r.e1 && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+            c->prof_ms[r.id] += ms;
+            c->prof_bytes[r.id] += r.bytes;
+            c->prof_launches[r.id] += r.n;
+        }
+    }
+    c->prof_pending.clear();
+    c->ev_next = 0;
+}
+
+// time one launch site: algorithmic bytes `bytes`, `n` kernel launches
+#define PROF(c, name, bytes, n, stmt)                                                  \
+    do {                                                                               \
+        if ((c)->prof) {                                                               \
+            hipEvent_t e0_ = prof_event(c);                                            \
+            if (e0_) (void)hipEventRecord(e0_, (c)->stream);                           \
+            stmt;                                                                      \
+            hipEvent_t e1_ = prof_event(c);                                            \
+            if (e1_) (void)hipEventRecord(e1_, (c)->stream);                           \
+            (c)->prof_pending.push_back({prof_id(c, name), (double)(bytes), (long)(n), e0_, e1_}); \
+        } else {                                                                       \
+            stmt;                                                                      \
+        }                                                                              \
+    } while (0)
+
+template <class T> static const char *tname();
+template <> const char *tname<float>() { return "float"; }
+template <> const char *tname<double>() { return "double"; }
+template <class T> static std::string kn(const char *base, int opk = -1) {
+    std::string r = std::string(base) + "<" + tname<T>();
+    if (opk >= 0) r += "," + std::to_string(opk);
+    return r + ">";
+}
 
 #define HIP_TRY(x)                                   \
     do {                                             \
@@ -217,22 +286,30 @@ static T *vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier) {
         const double h = P.op.length / P.op.nx * (double)(1 << l);
         const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
         T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
+        const double np = (double)nx * ny, ts = sizeof(T), hc = cf ? 1.0 : 0.0;
         T *xin = nullptr, *xout = X0;
         for (int k = 0; k < deg; ++k) {
-            launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
-                              c->cheb_cr[k]);
+            // reads x (if any), coef, b, d (if carried); writes x_out, d
+            const double by = ts * np * ((xin ? 1 : 0) + hc + 1 + (c->cheb_cd[k] != 0.0 ? 1 : 0) + 2);
+            PROF(c, kn<T>("k_mg_cheb", opk), by, 1,
+                 launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
+                                   c->cheb_cr[k]));
             xin = xout;
             xout = (xout == X0) ? X1 : X0;
         }
         cur[l] = xin;
-        launch_mg_restrict_res<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, B, c->lev<T>(l + 1, 3));
+        const double npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+        PROF(c, kn<T>("k_mg_restrict_res", opk), ts * (np * (2 + hc) + npc), 1,
+             launch_mg_restrict_res<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, B, c->lev<T>(l + 1, 3)));
     }
     {
         const int l = L - 1;
         const double h = P.op.length / P.op.nx * (double)(1 << l);
         const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
-        launch_mg_coarse<T>(c->stream, opk, P.lg.nx[l], P.lg.ny[l], h, nu, sigma, dtop, cf, c->lev<T>(l, 3),
-                            c->lev<T>(l, 0), P.opt.coarse_iters, c->lmax, c->coarse_lmin);
+        const double np = (double)P.lg.nx[l] * P.lg.ny[l];
+        PROF(c, kn<T>("k_mg_coarse", opk), sizeof(T) * np * (cf ? 3 : 2), 1,
+             launch_mg_coarse<T>(c->stream, opk, P.lg.nx[l], P.lg.ny[l], h, nu, sigma, dtop, cf, c->lev<T>(l, 3),
+                                 c->lev<T>(l, 0), P.opt.coarse_iters, c->lmax, c->coarse_lmin));
         cur[l] = c->lev<T>(l, 0);
     }
     for (int l = L - 2; l >= 0; --l) {
@@ -240,11 +317,16 @@ static T *vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier) {
         const double h = P.op.length / P.op.nx * (double)(1 << l);
         const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
         T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
-        launch_mg_prolong<T>(c->stream, nx, ny, cur[l], cur[l + 1]);
+        const double np = (double)nx * ny, ts = sizeof(T), hc = cf ? 1.0 : 0.0;
+        const double npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+        PROF(c, kn<T>("k_mg_prolong"), ts * (2 * np + npc), 1,
+             launch_mg_prolong<T>(c->stream, nx, ny, cur[l], cur[l + 1]));
         T *xin = cur[l], *xout = (xin == X0) ? X1 : X0;
         for (int k = 0; k < deg; ++k) {
-            launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
-                              c->cheb_cr[k]);
+            const double by = ts * np * (1 + hc + 1 + (c->cheb_cd[k] != 0.0 ? 1 : 0) + 2);
+            PROF(c, kn<T>("k_mg_cheb", opk), by, 1,
+                 launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
+                                   c->cheb_cr[k]));
             T *t = xin;
             xin = xout;
             xout = t;
@@ -256,6 +338,17 @@ static T *vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier) {
 }
 
 
+// IRK_DEBUG=1 in the environment traces the Newton and FGMRES iterations
+// on stderr.
+static int debug_level() {
+    static int lvl = -1;
+    if (lvl < 0) {
+        const char *e = getenv("IRK_DEBUG");
+        lvl = e ? atoi(e) : 0;
+    }
+    return lvl;
+}
+
 static int mg_op_of(int kind) {
     return kind == IRK_OP_NLDIFF_2D ? MG_NLDIFF : (kind == IRK_OP_BURGERS_1D ? MG_BURGERS : MG_VSF_OMEGA);
 }
@@ -266,9 +359,11 @@ template <class T>
 static void prec_component(irk_ctx *c, double *z, const double *v1, double a1, const double *v2, double a2,
                            double sigma, int hier) {
     const size_t npts = c->P.npts;
-    launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), v1, a1, v2, a2, nullptr, npts);
+    PROF(c, kn<T>("k_mg_cast_in"), (double)npts * ((v2 ? 16 : 8) + sizeof(T)), 1,
+         launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), v1, a1, v2, a2, nullptr, npts));
     T *x = vcycle<T>(c, mg_op_of(c->P.op.kind), sigma, c->dt, hier);
-    launch_mg_cast_out<T>(c->stream, z, x, 1.0, nullptr, 0.0, npts);
+    PROF(c, kn<T>("k_mg_cast_out"), (double)npts * (8 + sizeof(T)), 1,
+         launch_mg_cast_out<T>(c->stream, z, x, 1.0, nullptr, 0.0, npts));
 }
 
 // VSF streamfunction row of a block: solve B psi = q, B = -dt (Lap - mean),
@@ -278,11 +373,14 @@ template <class T>
 static void prec_psi(irk_ctx *c, double *zpsi, const double *rpsi, const double *zomega) {
     const size_t npts = c->P.npts;
     double *means = c->dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
-    launch_field_sums(c->stream, rpsi, 0, 1, npts, 1.0 / npts, c->part, means, c->ctr + CTR_RED);
-    launch_field_sums(c->stream, zomega, 0, 1, npts, 1.0 / npts, c->part, means + 1, c->ctr + CTR_RED);
-    launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), rpsi, 1.0, zomega, c->dt, means, npts);
+    PROF(c, "k_field_sums", 16.0 * npts, 2,
+         launch_field_sums(c->stream, rpsi, 0, 1, npts, 1.0 / npts, c->part, means, c->ctr + CTR_RED);
+         launch_field_sums(c->stream, zomega, 0, 1, npts, 1.0 / npts, c->part, means + 1, c->ctr + CTR_RED));
+    PROF(c, kn<T>("k_mg_cast_in"), (double)npts * (16 + sizeof(T)), 1,
+         launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), rpsi, 1.0, zomega, c->dt, means, npts));
     T *x = vcycle<T>(c, MG_POISSON, 0.0, c->dt, -1);
-    launch_mg_cast_out<T>(c->stream, zpsi, x, 1.0, means, 1.0 / c->dt, npts);
+    PROF(c, kn<T>("k_mg_cast_out"), (double)npts * (8 + sizeof(T)), 1,
+         launch_mg_cast_out<T>(c->stream, zpsi, x, 1.0, means, 1.0 / c->dt, npts));
 }
 
 // z = L_P^{-1} v for eigen-block blk: the block lower-triangular
@@ -322,11 +420,15 @@ static void block_matvec(irk_ctx *c, int blk, const double *x, double *w) {
     const double *Ub = width == 2 ? stage_field(c, P.hier_stage[P.row_hier[r + 1]]) : Ua;
     const double *xm = nullptr;
     if (P.op.kind == IRK_OP_VSF_2D) {
-        launch_field_sums(c->stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, c->part, c->dv + DV_XMEANS,
-                          c->ctr + CTR_RED);
+        PROF(c, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
+             launch_field_sums(c->stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, c->part, c->dv + DV_XMEANS,
+                               c->ctr + CTR_RED));
         xm = c->dv + DV_XMEANS;
     }
-    launch_block_matvec(c->stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm);
+    // reads x and writes w (width * nvar fields each), reads one linearization field per component
+    const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0);
+    PROF(c, "k_block_matvec<" + std::to_string(P.op.kind) + ">", by, 1,
+         launch_block_matvec(c->stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm));
 }
 
 // ---------------------------------------------------------------------------
@@ -355,11 +457,13 @@ static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int 
     while (true) {
         // r0 = rhs - D sol (sol = 0 on the first cycle)
         if (first_cycle) {
-            launch_dot_multi(c->stream, V, ldv, 0, rhs, len, 1, c->part, dv + DV_BETA, ctr);
+            PROF(c, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(c->stream, V, ldv, 0, rhs, len, 1, c->part, dv + DV_BETA, ctr));
         } else {
             block_matvec(c, blk, sol, V);                       // V0 <- D sol
-            launch_axpby(c->stream, V, 1.0, rhs, -1.0, V, len);  // V0 <- rhs - D sol
-            launch_dot_multi(c->stream, V, ldv, 0, V, len, 1, c->part, dv + DV_BETA, ctr);
+            PROF(c, "k_axpby", 24.0 * len, 1, launch_axpby(c->stream, V, 1.0, rhs, -1.0, V, len));
+            PROF(c, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(c->stream, V, ldv, 0, V, len, 1, c->part, dv + DV_BETA, ctr));
         }
         if ((stt = sync_read(c, dv + DV_BETA, 1)) != IRK_OK) return stt;
         const double bnorm = std::sqrt(c->pinned[0]);
@@ -373,7 +477,8 @@ static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int 
             }
         }
         if (bnorm <= rtol * beta0 || total >= maxit) break;
-        launch_scale_copy(c->stream, V, first_cycle ? rhs : V, dv + DV_BETA, len);
+        PROF(c, "k_scale_copy", 16.0 * len, 1,
+             launch_scale_copy(c->stream, V, first_cycle ? rhs : V, dv + DV_BETA, len));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = bnorm;
         int j = 0;
@@ -382,11 +487,17 @@ static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int 
             double *vj = V + (size_t)j * ldv, *zj = Z + (size_t)j * ldv, *w = V + (size_t)(j + 1) * ldv;
             apply_prec<T>(c, blk, vj, zj);
             block_matvec(c, blk, zj, w);
-            launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H1, ctr);
-            launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H1, len);
-            launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H2, ctr);
-            launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H2, len);
-            launch_dot_multi(c->stream, V, ldv, 0, w, len, 1, c->part, dv + DV_NRM, ctr);
+            const int nch = (j + 1 + 15) / 16;   // dot launches (16 basis vectors each)
+            PROF(c, "k_dot_multi", 8.0 * len * (j + 1 + nch), nch,
+                 launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H1, ctr));
+            PROF(c, "k_axpy_multi", 8.0 * len * (j + 3), 1,
+                 launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H1, len));
+            PROF(c, "k_dot_multi", 8.0 * len * (j + 1 + nch), nch,
+                 launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H2, ctr));
+            PROF(c, "k_axpy_multi", 8.0 * len * (j + 3), 1,
+                 launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H2, len));
+            PROF(c, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(c->stream, V, ldv, 0, w, len, 1, c->part, dv + DV_NRM, ctr));
             if ((stt = sync_read(c, dv, DV_Y)) != IRK_OK) return stt;
             const double *hb = c->pinned;
             const double hn = std::sqrt(hb[DV_NRM]);
@@ -409,7 +520,7 @@ static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int 
             g[j] = cs[j] * g[j];
             ++total;
             if (std::fabs(g[j + 1]) <= rtol * beta0 || hn <= 1e-300) { ++j; converged = true; break; }
-            launch_scale_copy(c->stream, w, w, dv + DV_NRM, len);
+            PROF(c, "k_scale_copy", 16.0 * len, 1, launch_scale_copy(c->stream, w, w, dv + DV_NRM, len));
         }
         // y = R^{-1} g on the j x j leading block
         for (int i = j - 1; i >= 0; --i) {
@@ -419,16 +530,19 @@ static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int 
         }
         if (first_cycle) {
             if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
-            launch_lincomb(c->stream, sol, Z, ldv, j, dv + DV_Y, len);
+            PROF(c, "k_lincomb", 8.0 * len * (j + 1), 1, launch_lincomb(c->stream, sol, Z, ldv, j, dv + DV_Y, len));
         } else {
             // sol += Z y, as sol -= Z (-y)
             for (int i = 0; i < j; ++i) y[i] = -y[i];
             if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
-            launch_axpy_multi(c->stream, sol, Z, ldv, j, dv + DV_Y, len);
+            PROF(c, "k_axpy_multi", 8.0 * len * (j + 2), 1,
+                 launch_axpy_multi(c->stream, sol, Z, ldv, j, dv + DV_Y, len));
         }
         first_cycle = false;
         if (converged || total >= maxit) break;
     }
+    if (debug_level() > 1)
+        fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", blk, total, beta0);
     *its_out = total;
     return IRK_OK;
 }
@@ -460,9 +574,14 @@ static void setup_hierarchies(irk_ctx *c) {
         const double *Um = stage_field(c, P.hier_stage[hq]);
         // coefficient field of the linearization: U_m (NLDIFF, Burgers) or Psi_m (VSF)
         const double *src = P.op.kind == IRK_OP_VSF_2D ? Um + P.npts : Um;
-        launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts);
-        for (int l = 0; l + 1 < P.lg.nlev; ++l)
-            launch_mg_coef_restrict<T>(c->stream, P.lg.nx[l], P.lg.ny[l], c->coef<T>(hq, l), c->coef<T>(hq, l + 1));
+        PROF(c, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
+             launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts));
+        for (int l = 0; l + 1 < P.lg.nlev; ++l) {
+            const double np = (double)P.lg.nx[l] * P.lg.ny[l], npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+            PROF(c, kn<T>("k_mg_coef_restrict"), sizeof(T) * (np + npc), 1,
+                 launch_mg_coef_restrict<T>(c->stream, P.lg.nx[l], P.lg.ny[l], c->coef<T>(hq, l),
+                                            c->coef<T>(hq, l + 1)));
+        }
     }
 }
 
@@ -475,20 +594,29 @@ static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double
     fill_stage_coefs(c, t_n, dt, &C);
     c->dt = dt;
     irk_status stt;
-    launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n));
+    PROF(c, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">", 8.0 * nf * (1 + s), 1,
+         launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
     // ||M K0|| for the absolute floor
-    launch_dot_multi(c->stream, c->V, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, c->ctr + CTR_RED);
-    double res0 = -1, thresh = 0;
-    int fold = 0;
+    PROF(c, "k_dot_multi", 8.0 * s * nf, 1,
+         launch_dot_multi(c->stream, c->V, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, c->ctr + CTR_RED));
+    double res0 = -1, thresh = 0, prev = 0;
+    int fold = 0, flat = 0;
     for (int it = 0;; ++it) {
-        launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold);
+        PROF(c, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
+             launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
         if (P.op.kind == IRK_OP_VSF_2D)
-            launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
-                              c->ctr + CTR_RED);
-        launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
-                        c->ctr + CTR_RED);
-        if ((stt = sync_read(c, c->dv, 2)) != IRK_OK) return stt;
+            PROF(c, "k_field_sums", 8.0 * s * nf, 1,
+                 launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
+                                   c->ctr + CTR_RED));
+        // reads U and K, writes the transformed residual: 3 s fields
+        PROF(c, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">", 8.0 * nf * 3 * s, 1,
+             launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+                             c->ctr + CTR_RED));
+        if ((stt = sync_read(c, c->dv, 3)) != IRK_OK) return stt;
         const double res = std::sqrt(c->pinned[DV_RES]);
+        // the residual cannot be resolved below the rounding error of its own
+        // evaluation: 64 eps times the norm of the magnitudes of its terms
+        const double floor_res = 64.0 * 2.220446049250313e-16 * std::sqrt(c->pinned[DV_ABS]);
         if (!std::isfinite(res)) return IRK_E_NONFINITE;
         if (it == 0) {
             res0 = res;
@@ -499,7 +627,17 @@ static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double
             if (st) st->res0 = res0;
         }
         if (st) st->final_res = res;
-        if (res <= thresh) break;
+        if (debug_level())
+            fprintf(stderr, "[irk] newton it %d res %.6e thresh %.3e floor %.3e\n", it, res, thresh, floor_res);
+        if (res <= std::max(thresh, floor_res)) break;
+        // stagnation within a small factor of the estimated floor: the
+        // iteration has reached rounding level
+        if (it > 0 && res <= 16.0 * floor_res && res > 0.25 * prev) break;
+        // safety net: three non-decreasing iterations far below res0 mean the
+        // rounding floor was underestimated
+        flat = (it > 0 && res > 0.5 * prev) ? flat + 1 : 0;
+        if (flat >= 3 && res <= 1e-8 * res0) break;
+        prev = res;
         if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return IRK_E_NOCONV;
         setup_hierarchies<T>(c);
         for (int blk = 0; blk < P.eb.nblocks; ++blk) {
@@ -582,6 +720,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     if (stt != IRK_OK) { delete c; return stt; }
     if (!device_workspace || ((uintptr_t)device_workspace & 255) != 0) { delete c; return IRK_E_ARG; }
     if (workspace_bytes < c->P.total) { delete c; return IRK_E_NOMEM; }
+    (void)hipGetLastError();   // clear an error left by earlier, unrelated HIP calls
     c->stream = (hipStream_t)hip_stream;
     c->ws = (unsigned char *)device_workspace;
     const Plan &P = c->P;
@@ -646,21 +785,48 @@ extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double
     irk_stats local;
     std::memset(&local, 0, sizeof(local));
     c->st = &local;
+    (void)hipGetLastError();
     const double rtol = tol > 0 ? tol : c->P.opt.newton_rtol;
     irk_status stt = c->P.opt.prec_fp32 ? newton_solve<float>(c, u_n, t_n, dt, rtol, &local)
                                         : newton_solve<double>(c, u_n, t_n, dt, rtol, &local);
     if (stt == IRK_OK) {
         StageCoefs C;
         fill_stage_coefs(c, t_n, dt, &C);
-        launch_final_update(c->stream, c->P.s, c->P.nf, u_n, c->K, u_np1, C, dt);
+        PROF(c, "k_final_update<" + std::to_string(c->P.s) + ">", 8.0 * c->P.nf * (c->P.s + 2), 1,
+             launch_final_update(c->stream, c->P.s, c->P.nf, u_n, c->K, u_np1, C, dt));
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) stt = IRK_E_DEVICE;
     } else {
         (void)hipStreamSynchronize(c->stream);
     }
     c->have_stages = (stt == IRK_OK);
     c->st = nullptr;
+    if (c->prof) prof_harvest(c);
     if (stats) *stats = local;
     return stt;
+}
+
+extern "C" irk_status irk_profile_enable(irk_ctx *c, int enable) {
+    if (!c) return IRK_E_ARG;
+    c->prof = enable != 0;
+    c->prof_names.clear();
+    c->prof_ms.clear();
+    c->prof_bytes.clear();
+    c->prof_launches.clear();
+    c->prof_pending.clear();
+    c->ev_next = 0;
+    return IRK_OK;
+}
+
+extern "C" int irk_profile_count(irk_ctx *c) { return c ? (int)c->prof_names.size() : 0; }
+
+extern "C" irk_status irk_profile_entry(irk_ctx *c, int idx, char *name, int name_len, long *launches,
+                                        double *total_ms, double *total_bytes) {
+    if (!c || idx < 0 || idx >= (int)c->prof_names.size() || !name || name_len < 1) return IRK_E_ARG;
+    std::snprintf(name, (size_t)name_len, "%s", c->prof_names[idx].c_str());
+    if (launches) *launches = c->prof_launches[idx];
+    if (total_ms) *total_ms = c->prof_ms[idx];
+    if (total_bytes) *total_bytes = c->prof_bytes[idx];
+    return IRK_OK;
 }
 
 extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_n, double dt, const double *K,
@@ -671,6 +837,7 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
     const size_t bytes = (size_t)s * P.nf * sizeof(double);
     StageCoefs C;
     fill_stage_coefs(c, t_n, dt, &C);
+    (void)hipGetLastError();
     HIP_TRY(hipMemcpyAsync(c->K, K, bytes, hipMemcpyDeviceToDevice, c->stream));
     launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
     if (P.op.kind == IRK_OP_VSF_2D)
@@ -698,5 +865,6 @@ extern "C" void irk_destroy(irk_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }

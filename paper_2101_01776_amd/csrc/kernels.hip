@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
     constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
     const size_t nf = NV * npts;
     const double h = P.g.h, inv_h2 = 1.0 / (h * h);
-    double sumsq = 0.0;
+    double sumsq = 0.0, abssq = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
         const int i = (int)(p % nx), j = (int)(p / nx);
@@ -157,24 +157,44 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
 #pragma unroll
         for (int st = 0; st < S; ++st) {
             const double *Ui = U + st * nf;
+            // a: sum of the magnitudes of the terms of F (its rounding scale)
             if constexpr (OP == IRK_OP_NLDIFF_2D) {
                 const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
-                double N = nldiff_flux5(Ui[p], Ui[j * nx + ip], Ui[j * nx + im], Ui[jp * nx + i], Ui[jm * nx + i], inv_h2);
-                if (P.forcing != IRK_FORCING_NONE) N += mms_forcing(P, i, j, C.sin_t[st], C.cos_t[st]);
-                F[st][0] = K[st * nf + p] - N;
+                const double uc = Ui[p], ue = Ui[j * nx + ip], uw = Ui[j * nx + im], un = Ui[jp * nx + i], us = Ui[jm * nx + i];
+                double N = nldiff_flux5(uc, ue, uw, un, us, inv_h2);
+                double a = nldiff_flux5_abs(uc, ue, uw, un, us, inv_h2);
+                if (P.forcing != IRK_FORCING_NONE) {
+                    const double f = mms_forcing(P, i, j, C.sin_t[st], C.cos_t[st]);
+                    N += f;
+                    a += fabs(f);
+                }
+                const double k = K[st * nf + p];
+                F[st][0] = k - N;
+                a += fabs(k);
+                abssq += a * a;
             } else if constexpr (OP == IRK_OP_BURGERS_1D) {
                 const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
                 const double ue = Ui[ip], uw = Ui[im], uc = Ui[p];
                 const double N = -(ue * ue - uw * uw) / (4.0 * h) + P.g.nu * (ue - 2.0 * uc + uw) * inv_h2;
-                F[st][0] = K[st * nf + p] - N;
+                const double k = K[st * nf + p];
+                F[st][0] = k - N;
+                const double a = fabs(k) + (ue * ue + uw * uw) / (4.0 * h) +
+                                 P.g.nu * (fabs(ue) + 2.0 * fabs(uc) + fabs(uw)) * inv_h2;
+                abssq += a * a;
             } else {
                 double w[3][3], ps[3][3];
                 load3x3(Ui, i, j, nx, ny, w);
                 load3x3(Ui + npts, i, j, nx, ny, ps);
                 const double Nw = arakawa9(ps, w, inv_h2 / 12.0) + P.g.nu * lap5(w, inv_h2);
-                F[st][0] = K[st * nf + p] - Nw;
+                const double k = K[st * nf + p];
+                F[st][0] = k - Nw;
                 // algebraic rows: 0 * l_i - (Lap Psi + Omega - mean Omega - mean Psi)
                 F[st][1] = -(lap5(ps, inv_h2) + w[1][1] - means[2 * st] - means[2 * st + 1]);
+                const double a0 = fabs(k) + arakawa9_abs(ps, w, inv_h2 / 12.0) +
+                                  P.g.nu * (fabs(w[1][2]) + fabs(w[1][0]) + fabs(w[2][1]) + fabs(w[0][1]) + 4.0 * fabs(w[1][1])) * inv_h2;
+                const double a1 = (fabs(ps[1][2]) + fabs(ps[1][0]) + fabs(ps[2][1]) + fabs(ps[0][1]) + 4.0 * fabs(ps[1][1])) * inv_h2 +
+                                  fabs(w[1][1]) + fabs(means[2 * st]) + fabs(means[2 * st + 1]);
+                abssq += a0 * a0 + a1 * a1;
             }
         }
 #pragma unroll
@@ -191,8 +211,10 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
         }
     }
     __shared__ double sh[8];
-    const double tot = block_sum(sumsq, sh);
-    finish_partials(&tot, 1, partials, out, counter);
+    double tot[2];
+    tot[0] = block_sum(sumsq, sh);
+    tot[1] = block_sum(abssq, sh);
+    finish_partials(tot, 2, partials, out, counter);
 }
 
 // k_i <- N(u_n, t_n) on differential rows, 0 on algebraic rows (initial guess)

@@ -22,6 +22,17 @@ __device__ __forceinline__ T nldiff_flux5(T uc, T ue, T uw, T un, T us, T inv_h2
     return sacc * inv_h2;
 }
 
+// sum of the magnitudes of the four face terms (rounding scale of the flux)
+template <class T>
+__device__ __forceinline__ T nldiff_flux5_abs(T uc, T ue, T uw, T un, T us, T inv_h2) {
+    const T kc = T(1) + uc * uc;
+    T sacc = T(0.5) * (kc + T(1) + ue * ue) * fabs(ue - uc);
+    sacc += T(0.5) * (kc + T(1) + uw * uw) * fabs(uw - uc);
+    sacc += T(0.5) * (kc + T(1) + un * un) * fabs(un - uc);
+    sacc += T(0.5) * (kc + T(1) + us * us) * fabs(us - uc);
+    return sacc * inv_h2;
+}
+
 // Linearization L(U) x = h^{-2} sum_f [kappa_f (x_nb - x_c)
 //                                      + (U_nb - U_c)(U_c x_c + U_nb x_nb)]
 // (kappa'(u) = 2u), and its diagonal coefficient.
@@ -82,6 +93,22 @@ __device__ __forceinline__ T arakawa9(const T p[3][3], const T w[3][3], T inv_12
                 - PP(1, 0) * (WW(1, 1) - WW(1, -1)) + PP(-1, 0) * (WW(-1, 1) - WW(-1, -1));
     const T jxp = WW(1, 0) * (PP(1, 1) - PP(1, -1)) - WW(-1, 0) * (PP(-1, 1) - PP(-1, -1))
                 - WW(0, 1) * (PP(1, 1) - PP(-1, 1)) + WW(0, -1) * (PP(1, -1) - PP(-1, -1));
+#undef PP
+#undef WW
+    return (jpp + jpx + jxp) * inv_12h2;
+}
+
+// sum of the magnitudes of the products that make up arakawa9 (the scale of
+// its rounding error)
+template <class T>
+__device__ __forceinline__ T arakawa9_abs(const T p[3][3], const T w[3][3], T inv_12h2) {
+#define PP(dj, di) p[(dj) + 1][(di) + 1]
+#define WW(dj, di) w[(dj) + 1][(di) + 1]
+    const T jpp = fabs((PP(0, 1) - PP(0, -1)) * (WW(1, 0) - WW(-1, 0))) + fabs((PP(1, 0) - PP(-1, 0)) * (WW(0, 1) - WW(0, -1)));
+    const T jpx = fabs(PP(0, 1) * (WW(1, 1) - WW(-1, 1))) + fabs(PP(0, -1) * (WW(1, -1) - WW(-1, -1)))
+                + fabs(PP(1, 0) * (WW(1, 1) - WW(1, -1))) + fabs(PP(-1, 0) * (WW(-1, 1) - WW(-1, -1)));
+    const T jxp = fabs(WW(1, 0) * (PP(1, 1) - PP(1, -1))) + fabs(WW(-1, 0) * (PP(-1, 1) - PP(-1, -1)))
+                + fabs(WW(0, 1) * (PP(1, 1) - PP(-1, 1))) + fabs(WW(0, -1) * (PP(1, -1) - PP(-1, -1)));
 #undef PP
 #undef WW
     return (jpp + jpx + jxp) * inv_12h2;

@@ -71,6 +71,10 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2101_01776_amd.build`")
+    # PyTorch ships its own HIP runtime with the same soname; loading torch
+    # first makes libirk bind to that one, so that torch's device pointers and
+    # streams are valid in the library (one runtime per process).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, D, I, Z = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
     L.irk_status_str.restype = ctypes.c_char_p
@@ -94,6 +98,13 @@ def lib() -> ctypes.CDLL:
     L.irk_get_stages.argtypes = [P, P]
     L.irk_destroy.restype = None
     L.irk_destroy.argtypes = [P]
+    L.irk_profile_enable.restype = I
+    L.irk_profile_enable.argtypes = [P, I]
+    L.irk_profile_count.restype = I
+    L.irk_profile_count.argtypes = [P]
+    L.irk_profile_entry.restype = I
+    L.irk_profile_entry.argtypes = [P, I, ctypes.c_char_p, I, ctypes.POINTER(ctypes.c_long),
+                                    ctypes.POINTER(D), ctypes.POINTER(D)]
     _lib = L
     return L
 
@@ -168,8 +179,11 @@ def irk_create(family: str, s: int, op: Operator, opt: Options, workspace_ptr: i
 
 def irk_step(ctx, u_ptr: int, t_n: float, dt: float, tol: float, out_ptr: int) -> Stats:
     st = Stats()
-    _check(lib().irk_step(ctx, ctypes.c_void_p(u_ptr), t_n, dt, tol, ctypes.c_void_p(out_ptr),
-                          ctypes.byref(st)), "irk_step")
+    code = lib().irk_step(ctx, ctypes.c_void_p(u_ptr), t_n, dt, tol, ctypes.c_void_p(out_ptr), ctypes.byref(st))
+    if code != 0:
+        err = IrkError(code, "irk_step")
+        err.stats = st.as_dict()
+        raise err
     return st
 
 
@@ -184,6 +198,25 @@ def irk_get_stages(ctx, K_ptr: int):
 
 def irk_destroy(ctx):
     lib().irk_destroy(ctx)
+
+
+def irk_profile_enable(ctx, enable: bool):
+    _check(lib().irk_profile_enable(ctx, 1 if enable else 0), "irk_profile_enable")
+
+
+def irk_profile_read(ctx) -> list:
+    """[{name, launches, ms, bytes}] per kernel symbol."""
+    L = lib()
+    out = []
+    buf = ctypes.create_string_buffer(256)
+    for i in range(L.irk_profile_count(ctx)):
+        n = ctypes.c_long()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(L.irk_profile_entry(ctx, i, buf, 256, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+               "irk_profile_entry")
+        out.append({"name": buf.value.decode(), "launches": n.value, "ms": ms.value, "bytes": by.value})
+    return out
 
 
 class Solver:
