@@ -18,6 +18,7 @@
 
 #include "irk_internal.h"
 #include "kernels.h"
+#include "mg_tiled.h"
 
 namespace irk {
 
@@ -60,6 +61,7 @@ struct Plan {
     int m = 30;                         // restart length
     LevelGeom lg;
     size_t tsz = 4;                     // bytes per V-cycle scalar
+    int l0 = 0;                         // first level of the one-work-group sub-cycle
     int nhier = 0;                      // distinct linearization stages
     int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
     int row_hier[IRK_MAX_STAGES];       // transformed row -> hierarchy
@@ -74,7 +76,8 @@ static bool valid_options(const irk_options &o) {
     return o.restart >= 1 && o.restart <= IRK_MAX_RESTART && o.max_krylov >= 1 && o.max_newton >= 1 &&
            (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 8 &&
-           o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.krylov_rtol > 0 && o.krylov_rtol < 1 &&
+           o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
+           o.krylov_rtol < 1 &&
            o.newton_rtol >= 0 && o.newton_atol >= 0;
 }
 
@@ -108,6 +111,15 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->m = P->opt.restart;
     if (!level_geometry(o, P->opt.mg_coarsest, &P->lg)) return IRK_E_ARG;
     P->tsz = P->opt.prec_fp32 ? sizeof(float) : sizeof(double);
+    // levels from l0 down run inside one work-group with everything in LDS
+    // (at most 60 KiB and 4096 points on its finest level)
+    P->l0 = P->lg.nlev - 1;
+    for (int l = 0; l < P->lg.nlev; ++l) {
+        size_t sum = 0;
+        for (int q = l; q < P->lg.nlev; ++q) sum += (size_t)P->lg.nx[q] * P->lg.ny[q];
+        const size_t top = (size_t)P->lg.nx[l] * P->lg.ny[l];
+        if ((3 * sum + 2 * top) * P->tsz <= 60 * 1024 && top <= 4096) { P->l0 = l; break; }
+    }
 
     // linearization stage of every transformed row (Newton-like (0) or (1))
     P->nhier = 0;
@@ -177,6 +189,7 @@ struct irk_ctx {
     bool have_stages = false;
     // Chebyshev smoothing coefficients
     double cheb_cd[8], cheb_cr[8];
+    double coarse_cd[64], coarse_cr[64];
     double lmax = 2.0, lmin = 0.5, coarse_lmin = 0.1;
     irk_stats *st = nullptr;
     double dt = 0;
@@ -272,71 +285,89 @@ static irk_status write_dev(irk_ctx *c, double *dev, const double *host, int cou
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle on level hierarchy: right-hand side in lev(0).b, result pointer out
+// One V-cycle on the hierarchy: tiled down sweeps on levels 0..l0-1, the rest
+// of the cycle inside one work-group, tiled up sweeps back to level 0.  The
+// finest level reads its right-hand side from float64 vectors (in) and writes
+// the float64 result (out).
 // ---------------------------------------------------------------------------
 template <class T>
-static T *vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier) {
+static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, const MgIn &in, const MgOut &out) {
     const Plan &P = c->P;
-    const int L = P.lg.nlev;
-    const int deg = P.opt.cheb_degree;
+    const int L = P.lg.nlev, l0 = P.l0, deg = P.opt.cheb_degree;
     const double nu = P.op.nu;
-    T *cur[IRK_MAX_LEVELS];
-    for (int l = 0; l < L - 1; ++l) {
-        const int nx = P.lg.nx[l], ny = P.lg.ny[l];
-        const double h = P.op.length / P.op.nx * (double)(1 << l);
-        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
-        T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
-        const double np = (double)nx * ny, ts = sizeof(T), hc = cf ? 1.0 : 0.0;
-        T *xin = nullptr, *xout = X0;
-        for (int k = 0; k < deg; ++k) {
-            // reads x (if any), coef, b, d (if carried); writes x_out, d
-            const double by = ts * np * ((xin ? 1 : 0) + hc + 1 + (c->cheb_cd[k] != 0.0 ? 1 : 0) + 2);
-            PROF(c, kn<T>("k_mg_cheb", opk), by, 1,
-                 launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
-                                   c->cheb_cr[k]));
-            xin = xout;
-            xout = (xout == X0) ? X1 : X0;
+    const double ts = sizeof(T);
+    auto hl = [&](int l) { return P.op.length / P.op.nx * (double)(1 << l); };
+    auto mk = [&](int l) {
+        MgLevelArgs<T> a;
+        a.nx = P.lg.nx[l];
+        a.ny = P.lg.ny[l];
+        a.h = (T)hl(l);
+        a.nu = (T)nu;
+        a.sigma = (T)sigma;
+        a.dt = (T)dtop;
+        a.coef = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
+        a.b = c->lev<T>(l, 3);
+        a.x = c->lev<T>(l, 0);
+        a.xout = c->lev<T>(l, 1);
+        a.bc = l + 1 < L ? c->lev<T>(l + 1, 3) : nullptr;
+        // the up sweep of level l+1 left its result in buffer 1; the
+        // one-work-group sub-cycle leaves it in buffer 0
+        a.xc = l + 1 < L ? c->lev<T>(l + 1, l + 1 < l0 ? 1 : 0) : nullptr;
+        for (int k = 0; k < IRK_MAX_CHEB; ++k) {
+            a.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
+            a.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
         }
-        cur[l] = xin;
-        const double npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-        PROF(c, kn<T>("k_mg_restrict_res", opk), ts * (np * (2 + hc) + npc), 1,
-             launch_mg_restrict_res<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, B, c->lev<T>(l + 1, 3)));
+        return a;
+    };
+    const double hc = hier >= 0 ? 1.0 : 0.0;
+    const double nin = in.v1 ? (in.v2 ? 16.0 : 8.0) : ts;      // bytes per point of the finest b
+    for (int l = 0; l < l0; ++l) {
+        const MgLevelArgs<T> a = mk(l);
+        const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+        // reads coef, b; writes x and the coarse right-hand side
+        const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts) + npc * ts;
+        PROF(c, kn<T>("k_mg_down", opk), by, 1, launch_mg_down<T>(c->stream, opk, a, l == 0 ? in : MgIn{}, deg));
     }
     {
-        const int l = L - 1;
-        const double h = P.op.length / P.op.nx * (double)(1 << l);
-        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
-        const double np = (double)P.lg.nx[l] * P.lg.ny[l];
-        PROF(c, kn<T>("k_mg_coarse", opk), sizeof(T) * np * (cf ? 3 : 2), 1,
-             launch_mg_coarse<T>(c->stream, opk, P.lg.nx[l], P.lg.ny[l], h, nu, sigma, dtop, cf, c->lev<T>(l, 3),
-                                 c->lev<T>(l, 0), P.opt.coarse_iters, c->lmax, c->coarse_lmin));
-        cur[l] = c->lev<T>(l, 0);
-    }
-    for (int l = L - 2; l >= 0; --l) {
-        const int nx = P.lg.nx[l], ny = P.lg.ny[l];
-        const double h = P.op.length / P.op.nx * (double)(1 << l);
-        const T *cf = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
-        T *X0 = c->lev<T>(l, 0), *X1 = c->lev<T>(l, 1), *D = c->lev<T>(l, 2), *B = c->lev<T>(l, 3);
-        const double np = (double)nx * ny, ts = sizeof(T), hc = cf ? 1.0 : 0.0;
-        const double npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-        PROF(c, kn<T>("k_mg_prolong"), ts * (2 * np + npc), 1,
-             launch_mg_prolong<T>(c->stream, nx, ny, cur[l], cur[l + 1]));
-        T *xin = cur[l], *xout = (xin == X0) ? X1 : X0;
-        for (int k = 0; k < deg; ++k) {
-            const double by = ts * np * (1 + hc + 1 + (c->cheb_cd[k] != 0.0 ? 1 : 0) + 2);
-            PROF(c, kn<T>("k_mg_cheb", opk), by, 1,
-                 launch_mg_cheb<T>(c->stream, opk, nx, ny, h, nu, sigma, dtop, cf, xin, xout, B, D, c->cheb_cd[k],
-                                   c->cheb_cr[k]));
-            T *t = xin;
-            xin = xout;
-            xout = t;
+        MgSubArgs<T> sa;
+        sa.nlev = L - l0;
+        double np_all = 0;
+        for (int q = 0; q < sa.nlev; ++q) {
+            sa.nx[q] = P.lg.nx[l0 + q];
+            sa.ny[q] = P.lg.ny[l0 + q];
+            sa.h[q] = (T)hl(l0 + q);
+            sa.coef[q] = hier >= 0 ? c->coef<T>(hier, l0 + q) : nullptr;
+            np_all += (double)sa.nx[q] * sa.ny[q];
         }
-        cur[l] = xin;
+        sa.nu = (T)nu;
+        sa.sigma = (T)sigma;
+        sa.dt = (T)dtop;
+        sa.b0 = c->lev<T>(l0, 3);
+        sa.x0 = c->lev<T>(l0, 0);
+        sa.deg = deg;
+        sa.coarse_iters = P.opt.coarse_iters;
+        for (int k = 0; k < IRK_MAX_CHEB; ++k) {
+            sa.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
+            sa.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
+        }
+        for (int k = 0; k < IRK_MAX_COARSE_ITERS; ++k) {
+            sa.ccd[k] = (T)c->coarse_cd[k];
+            sa.ccr[k] = (T)c->coarse_cr[k];
+        }
+        const double np0 = (double)sa.nx[0] * sa.ny[0];
+        const double by = np_all * hc * ts + np0 * ((l0 == 0 ? nin : ts) + (l0 == 0 && out.z ? 8.0 : ts));
+        PROF(c, kn<T>("k_mg_subcycle", opk), by, 1,
+             launch_mg_subcycle<T>(c->stream, opk, sa, l0 == 0 ? in : MgIn{}, l0 == 0 ? out : MgOut{}));
+    }
+    for (int l = l0 - 1; l >= 0; --l) {
+        const MgLevelArgs<T> a = mk(l);
+        const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+        // reads coef, b, x, coarse correction; writes x (float64 z on level 0)
+        const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts + (l == 0 && out.z ? 8.0 : ts)) + npc * ts;
+        PROF(c, kn<T>("k_mg_up", opk), by, 1, launch_mg_up<T>(c->stream, opk, a, l == 0 ? out : MgOut{}, deg));
     }
     if (c->st) c->st->vcycles++;
-    return cur[0];
 }
-
 
 // IRK_DEBUG=1 in the environment traces the Newton and FGMRES iterations
 // on stderr.
@@ -358,12 +389,11 @@ static int mg_op_of(int kind) {
 template <class T>
 static void prec_component(irk_ctx *c, double *z, const double *v1, double a1, const double *v2, double a2,
                            double sigma, int hier) {
-    const size_t npts = c->P.npts;
-    PROF(c, kn<T>("k_mg_cast_in"), (double)npts * ((v2 ? 16 : 8) + sizeof(T)), 1,
-         launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), v1, a1, v2, a2, nullptr, npts));
-    T *x = vcycle<T>(c, mg_op_of(c->P.op.kind), sigma, c->dt, hier);
-    PROF(c, kn<T>("k_mg_cast_out"), (double)npts * (8 + sizeof(T)), 1,
-         launch_mg_cast_out<T>(c->stream, z, x, 1.0, nullptr, 0.0, npts));
+    MgIn in;
+    in.v1 = v1; in.a1 = a1; in.v2 = v2; in.a2 = a2;
+    MgOut out;
+    out.z = z; out.v1 = v1; out.a1 = a1; out.v2 = v2; out.a2 = a2;
+    vcycle<T>(c, mg_op_of(c->P.op.kind), sigma, c->dt, hier, in, out);
 }
 
 // VSF streamfunction row of a block: solve B psi = q, B = -dt (Lap - mean),
@@ -376,11 +406,12 @@ static void prec_psi(irk_ctx *c, double *zpsi, const double *rpsi, const double 
     PROF(c, "k_field_sums", 16.0 * npts, 2,
          launch_field_sums(c->stream, rpsi, 0, 1, npts, 1.0 / npts, c->part, means, c->ctr + CTR_RED);
          launch_field_sums(c->stream, zomega, 0, 1, npts, 1.0 / npts, c->part, means + 1, c->ctr + CTR_RED));
-    PROF(c, kn<T>("k_mg_cast_in"), (double)npts * (16 + sizeof(T)), 1,
-         launch_mg_cast_in<T>(c->stream, c->lev<T>(0, 3), rpsi, 1.0, zomega, c->dt, means, npts));
-    T *x = vcycle<T>(c, MG_POISSON, 0.0, c->dt, -1);
-    PROF(c, kn<T>("k_mg_cast_out"), (double)npts * (8 + sizeof(T)), 1,
-         launch_mg_cast_out<T>(c->stream, zpsi, x, 1.0, means, 1.0 / c->dt, npts));
+    MgIn in;
+    in.v1 = rpsi; in.a1 = 1.0; in.v2 = zomega; in.a2 = c->dt; in.mean = means;
+    MgOut out;
+    out.z = zpsi; out.shift = means; out.shift_scale = 1.0 / c->dt;
+    out.v1 = rpsi; out.a1 = 1.0; out.v2 = zomega; out.a2 = c->dt; out.mean_in = means;
+    vcycle<T>(c, MG_POISSON, 0.0, c->dt, -1, in, out);
 }
 
 // z = L_P^{-1} v for eigen-block blk: the block lower-triangular
@@ -693,21 +724,32 @@ extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operat
     return P.total;
 }
 
-static void set_chebyshev(irk_ctx *c) {
-    const double theta = 0.5 * (c->lmax + c->lmin), delta = 0.5 * (c->lmax - c->lmin);
+// Chebyshev iteration on D^{-1} A with spectrum in [lmin, lmax]: step k
+// updates d <- cd[k] d + cr[k] D^{-1} r, x <- x + d (three-term recurrence).
+static void chebyshev_coefs(double lmin, double lmax, int n, double *cd, double *cr) {
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sig1 = theta / delta;
     double rho = 1.0 / sig1;
-    for (int k = 0; k < c->P.opt.cheb_degree; ++k) {
+    for (int k = 0; k < n; ++k) {
         if (k == 0) {
-            c->cheb_cd[0] = 0.0;
-            c->cheb_cr[0] = 1.0 / theta;
+            cd[0] = 0.0;
+            cr[0] = 1.0 / theta;
         } else {
             const double rn = 1.0 / (2.0 * sig1 - rho);
-            c->cheb_cd[k] = rn * rho;
-            c->cheb_cr[k] = 2.0 * rn / delta;
+            cd[k] = rn * rho;
+            cr[k] = 2.0 * rn / delta;
             rho = rn;
         }
     }
+}
+
+static void set_chebyshev(irk_ctx *c) {
+    std::memset(c->cheb_cd, 0, sizeof(c->cheb_cd));
+    std::memset(c->cheb_cr, 0, sizeof(c->cheb_cr));
+    std::memset(c->coarse_cd, 0, sizeof(c->coarse_cd));
+    std::memset(c->coarse_cr, 0, sizeof(c->coarse_cr));
+    chebyshev_coefs(c->lmin, c->lmax, c->P.opt.cheb_degree, c->cheb_cd, c->cheb_cr);
+    chebyshev_coefs(c->coarse_lmin, c->lmax, c->P.opt.coarse_iters, c->coarse_cd, c->coarse_cr);
 }
 
 extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,

@@ -32,14 +32,6 @@ void launch_zero_u32(hipStream_t st, unsigned *p, int n);
 void launch_fill(hipStream_t st, double *p, double v, size_t len);
 
 template <class T>
-void launch_mg_cheb(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
-                    const T *coef, const T *xin, T *xout, const T *b, T *d, double cd, double cr);
-template <class T>
-void launch_mg_restrict_res(hipStream_t st, int opk, int nxf, int nyf, double hf, double nu, double sigma,
-                            double dt, const T *coef, const T *x, const T *b, T *bc);
-template <class T>
-void launch_mg_prolong(hipStream_t st, int nxf, int nyf, T *xf, const T *xc);
-template <class T>
 void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc);
 template <class T>
 void launch_mg_cast_in(hipStream_t st, T *b0, const double *v1, double a1, const double *v2, double a2,
@@ -47,9 +39,6 @@ void launch_mg_cast_in(hipStream_t st, T *b0, const double *v1, double a1, const
 template <class T>
 void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const double *shift, double c,
                         size_t len);
-template <class T>
-void launch_mg_coarse(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
-                      const T *coef, const T *b, T *x, int iters, double lmax, double lmin);
 template <class T>
 void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len);
 

@@ -406,103 +406,6 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 // Multigrid (precision T).  Level operator A = sigma M - dt L(coef) with the
 // operator's linearization rediscretized at the level spacing.
 // ------------------------------------------------------------------------
-template <class T, int OPK, bool HAS_X>
-__device__ __forceinline__ void level_op(const T *coef, const T *x, int i, int j, int nx, int ny, T h, T nu,
-                                         T &Lx, T &Ld) {
-    if constexpr (OPK == MG_NLDIFF) nldiff_lin<T, HAS_X>(coef, x, i, j, nx, ny, T(1) / (h * h), Lx, Ld);
-    else if constexpr (OPK == MG_BURGERS) burgers_lin<T, HAS_X>(coef, x, i, nx, h, nu, Lx, Ld);
-    else if constexpr (OPK == MG_VSF_OMEGA) vsf_omega_lin<T, HAS_X>(coef, x, i, j, nx, ny, h, nu, Lx, Ld);
-    else poisson_lin<T, HAS_X>(x, i, j, nx, ny, h, Lx, Ld);
-}
-
-// One Chebyshev step on D^{-1} A (D = diag A):
-//   r = b - A x ; d = cd d + cr D^{-1} r ; x_out = x + d
-// x_in == nullptr means x = 0.
-template <class T, int OPK>
-__global__ void __launch_bounds__(IRK_WG) k_mg_cheb(int nx, int ny, T h, T nu, T sigma, T dt,
-                                                    const T *__restrict__ coef, const T *__restrict__ xin,
-                                                    T *__restrict__ xout, const T *__restrict__ b,
-                                                    T *__restrict__ d, T cd, T cr) {
-    const size_t npts = (size_t)nx * ny;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        T Lx, Ld, r, xc;
-        if (xin) {
-            level_op<T, OPK, true>(coef, xin, i, j, nx, ny, h, nu, Lx, Ld);
-            xc = xin[p];
-            r = b[p] - (sigma * xc - dt * Lx);
-        } else {
-            level_op<T, OPK, false>(coef, nullptr, i, j, nx, ny, h, nu, Lx, Ld);
-            xc = T(0);
-            r = b[p];
-        }
-        const T diag = sigma - dt * Ld;
-        const T dn = (cd != T(0) ? cd * d[p] : T(0)) + cr * r / diag;
-        d[p] = dn;
-        xout[p] = xc + dn;
-    }
-}
-
-// coarse b = full-weighting restriction of the fine residual b - A x
-template <class T, int OPK>
-__global__ void __launch_bounds__(IRK_WG) k_mg_restrict_res(int nxf, int nyf, T hf, T nu, T sigma, T dt,
-                                                            const T *__restrict__ coef, const T *__restrict__ x,
-                                                            const T *__restrict__ b, T *__restrict__ bc) {
-    const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
-    const size_t npc = (size_t)nxc * nyc;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const T wgt[3] = {T(0.25), T(0.5), T(0.25)};
-    for (size_t q = (size_t)xcd_block() * blockDim.x + threadIdx.x; q < npc; q += stride) {
-        const int I = (int)(q % nxc), J = (int)(q / nxc);
-        T acc = 0;
-        if (nyf == 1) {
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-                const int i = wrapm(2 * I + a, nxf);
-                T Lx, Ld;
-                level_op<T, OPK, true>(coef, x, i, 0, nxf, 1, hf, nu, Lx, Ld);
-                acc += wgt[a + 1] * (b[i] - (sigma * x[i] - dt * Lx));
-            }
-        } else {
-#pragma unroll
-            for (int bb = -1; bb <= 1; ++bb) {
-                const int j = wrapm(2 * J + bb, nyf);
-#pragma unroll
-                for (int a = -1; a <= 1; ++a) {
-                    const int i = wrapm(2 * I + a, nxf);
-                    T Lx, Ld;
-                    level_op<T, OPK, true>(coef, x, i, j, nxf, nyf, hf, nu, Lx, Ld);
-                    const size_t p = (size_t)j * nxf + i;
-                    acc += wgt[a + 1] * wgt[bb + 1] * (b[p] - (sigma * x[p] - dt * Lx));
-                }
-            }
-        }
-        bc[q] = acc;
-    }
-}
-
-// x_f += P x_c (bilinear / linear interpolation, coarse node I at fine 2I)
-template <class T>
-__global__ void __launch_bounds__(IRK_WG) k_mg_prolong(int nxf, int nyf, T *__restrict__ xf,
-                                                       const T *__restrict__ xc) {
-    const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
-    const size_t npf = (size_t)nxf * nyf;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npf; p += stride) {
-        const int i = (int)(p % nxf), j = (int)(p / nxf);
-        const int I0 = i >> 1, I1 = (i & 1) ? wrapm(I0 + 1, nxc) : I0;
-        T e;
-        if (nyf == 1) {
-            e = T(0.5) * (xc[I0] + xc[I1]);
-        } else {
-            const int J0 = j >> 1, J1 = (j & 1) ? wrapm(J0 + 1, nyc) : J0;
-            e = T(0.25) * (xc[J0 * nxc + I0] + xc[J0 * nxc + I1] + xc[J1 * nxc + I0] + xc[J1 * nxc + I1]);
-        }
-        xf[p] += e;
-    }
-}
-
 // coarse coefficient = full-weighting restriction of the fine coefficient
 template <class T>
 __global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict(int nxf, int nyf, const T *__restrict__ cf,
@@ -554,66 +457,6 @@ __global__ void __launch_bounds__(IRK_WG) k_mg_cast_out(double *__restrict__ z, 
 __global__ void __launch_bounds__(IRK_WG) k_fill_f64(double *__restrict__ p, double v, size_t len) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride) p[e] = v;
-}
-
-// Coarsest level: `iters` Chebyshev iterations on [lmax/ratio, lmax] in one
-// work-group with the level in LDS; for the singular periodic Poisson
-// operator the right-hand side and iterate are kept mean-free.
-template <class T, int OPK>
-__global__ void __launch_bounds__(1024) k_mg_coarse(int nx, int ny, T h, T nu, T sigma, T dt,
-                                                    const T *__restrict__ coef, const T *__restrict__ b,
-                                                    T *__restrict__ xout, int iters, T lmax, T lmin) {
-    extern __shared__ unsigned char smem_raw[];
-    const int np = nx * ny;
-    T *sx = reinterpret_cast<T *>(smem_raw);
-    T *sx2 = sx + np;
-    T *sd = sx2 + np;
-    T *sb = sd + np;
-    T *sc = sb + np;
-    __shared__ double red[16];
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        sb[p] = b[p];
-        sc[p] = coef ? coef[p] : T(0);
-        sx[p] = T(0);
-        sd[p] = T(0);
-    }
-    __syncthreads();
-    const bool singular = (OPK == MG_POISSON) && sigma == T(0);
-    if (singular) {
-        double acc = 0;
-        for (int p = threadIdx.x; p < np; p += blockDim.x) acc += (double)sb[p];
-        acc = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        double tot = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
-        const T m = (T)(tot / np);
-        __syncthreads();
-        for (int p = threadIdx.x; p < np; p += blockDim.x) sb[p] -= m;
-        __syncthreads();
-    }
-    const T theta = T(0.5) * (lmax + lmin), delta = T(0.5) * (lmax - lmin);
-    const T sig1 = theta / delta;
-    T rho = T(1) / sig1;
-    for (int k = 0; k < iters; ++k) {
-        T cd, cr;
-        if (k == 0) { cd = T(0); cr = T(1) / theta; }
-        else { const T rn = T(1) / (T(2) * sig1 - rho); cd = rn * rho; cr = T(2) * rn / delta; rho = rn; }
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int i = p % nx, j = p / nx;
-            T Lx, Ld;
-            level_op<T, OPK, true>(sc, sx, i, j, nx, ny, h, nu, Lx, Ld);
-            const T r = sb[p] - (sigma * sx[p] - dt * Lx);
-            const T diag = sigma - dt * Ld;
-            const T dn = cd * sd[p] + cr * r / diag;
-            sd[p] = dn;
-            sx2[p] = sx[p] + dn;
-        }
-        __syncthreads();
-        for (int p = threadIdx.x; p < np; p += blockDim.x) sx[p] = sx2[p];
-        __syncthreads();
-    }
-    for (int p = threadIdx.x; p < np; p += blockDim.x) xout[p] = sx[p];
 }
 
 // ------------------------------------------------------------------------
@@ -748,40 +591,6 @@ void launch_fill(hipStream_t st, double *p, double v, size_t len) {
 }
 
 template <class T>
-void launch_mg_cheb(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
-                    const T *coef, const T *xin, T *xout, const T *b, T *d, double cd, double cr) {
-    const unsigned g = grid_for((size_t)nx * ny);
-#define CHEB(K) k_mg_cheb<T, K><<<g, IRK_WG, 0, st>>>(nx, ny, (T)h, (T)nu, (T)sigma, (T)dt, coef, xin, xout, b, d, (T)cd, (T)cr)
-    switch (opk) {
-        case MG_NLDIFF: CHEB(MG_NLDIFF); break;
-        case MG_BURGERS: CHEB(MG_BURGERS); break;
-        case MG_VSF_OMEGA: CHEB(MG_VSF_OMEGA); break;
-        default: CHEB(MG_POISSON); break;
-    }
-#undef CHEB
-}
-
-template <class T>
-void launch_mg_restrict_res(hipStream_t st, int opk, int nxf, int nyf, double hf, double nu, double sigma,
-                            double dt, const T *coef, const T *x, const T *b, T *bc) {
-    const size_t npc = (size_t)(nxf / 2) * (nyf > 1 ? nyf / 2 : 1);
-    const unsigned g = grid_for(npc);
-#define RR(K) k_mg_restrict_res<T, K><<<g, IRK_WG, 0, st>>>(nxf, nyf, (T)hf, (T)nu, (T)sigma, (T)dt, coef, x, b, bc)
-    switch (opk) {
-        case MG_NLDIFF: RR(MG_NLDIFF); break;
-        case MG_BURGERS: RR(MG_BURGERS); break;
-        case MG_VSF_OMEGA: RR(MG_VSF_OMEGA); break;
-        default: RR(MG_POISSON); break;
-    }
-#undef RR
-}
-
-template <class T>
-void launch_mg_prolong(hipStream_t st, int nxf, int nyf, T *xf, const T *xc) {
-    k_mg_prolong<T><<<grid_for((size_t)nxf * nyf), IRK_WG, 0, st>>>(nxf, nyf, xf, xc);
-}
-
-template <class T>
 void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc) {
     const size_t npc = (size_t)(nxf / 2) * (nyf > 1 ? nyf / 2 : 1);
     k_mg_coef_restrict<T><<<grid_for(npc), IRK_WG, 0, st>>>(nxf, nyf, cf, cc);
@@ -800,37 +609,15 @@ void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const d
 }
 
 template <class T>
-void launch_mg_coarse(hipStream_t st, int opk, int nx, int ny, double h, double nu, double sigma, double dt,
-                      const T *coef, const T *b, T *x, int iters, double lmax, double lmin) {
-    const size_t shm = (size_t)5 * nx * ny * sizeof(T);
-    const unsigned nt = (nx * ny >= 1024) ? 1024 : ((nx * ny + 63) / 64) * 64;
-#define CO(K) k_mg_coarse<T, K><<<1, nt, shm, st>>>(nx, ny, (T)h, (T)nu, (T)sigma, (T)dt, coef, b, x, iters, (T)lmax, (T)lmin)
-    switch (opk) {
-        case MG_NLDIFF: CO(MG_NLDIFF); break;
-        case MG_BURGERS: CO(MG_BURGERS); break;
-        case MG_VSF_OMEGA: CO(MG_VSF_OMEGA); break;
-        default: CO(MG_POISSON); break;
-    }
-#undef CO
-}
-
-template <class T>
 void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len) {
     launch_mg_cast_in<T>(st, dst, src, 1.0, nullptr, 0.0, nullptr, len);
 }
 
 #define INST(T)                                                                                                    \
-    template void launch_mg_cheb<T>(hipStream_t, int, int, int, double, double, double, double, const T *,          \
-                                    const T *, T *, const T *, T *, double, double);                               \
-    template void launch_mg_restrict_res<T>(hipStream_t, int, int, int, double, double, double, double, const T *,  \
-                                            const T *, const T *, T *);                                            \
-    template void launch_mg_prolong<T>(hipStream_t, int, int, T *, const T *);                                     \
     template void launch_mg_coef_restrict<T>(hipStream_t, int, int, const T *, T *);                               \
     template void launch_mg_cast_in<T>(hipStream_t, T *, const double *, double, const double *, double,           \
                                        const double *, size_t);                                                    \
     template void launch_mg_cast_out<T>(hipStream_t, double *, const T *, double, const double *, double, size_t); \
-    template void launch_mg_coarse<T>(hipStream_t, int, int, int, double, double, double, double, const T *,        \
-                                      const T *, T *, int, double, double);                                        \
     template void launch_cast_coef<T>(hipStream_t, T *, const double *, size_t);
 INST(float)
 INST(double)
