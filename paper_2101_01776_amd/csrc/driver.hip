@@ -3,8 +3,15 @@
 // FGMRES per eigen-block with the block lower-triangular preconditioner of
 // equation (Lprec), and the geometric-multigrid V-cycle that applies each
 // diagonal inverse.  All arithmetic on fields runs in the kernels of
-// kernels.hip; the host does the s x s algebra, the Hessenberg least-squares
-// problem and the control flow.
+// kernels.hip and mg_tiled.hip; the host does the s x s algebra, the
+// Hessenberg least-squares problem and the control flow.
+//
+// In the eigenbasis the eigen-blocks are independent (no back-substitution),
+// so each block's FGMRES solve runs on a "lane" of its own: a HIP stream,
+// Krylov bases, multigrid work arrays and reduction scratch.  The host
+// interleaves the lanes' FGMRES state machines, so that the kernels of
+// different blocks overlap on the device and one lane's host round trip is
+// hidden behind the others' device work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,6 +57,13 @@ static bool level_geometry(const irk_operator &op, int coarsest, LevelGeom *lg) 
     return (size_t)lg->nx[L - 1] * lg->ny[L - 1] <= 1024;
 }
 
+// Workspace offsets of one lane (one eigen-block's concurrent solve).
+struct LaneLayout {
+    size_t V, Z, part, dv;
+    size_t lev[IRK_MAX_LEVELS][4];
+    size_t ldv;                         // Krylov vector length (block width * field)
+};
+
 // Everything irk_create decides before touching the device.
 struct Plan {
     irk_operator op;
@@ -57,28 +71,25 @@ struct Plan {
     EigenBlocks eb;
     int family = 0, s = 0, nvar = 1;
     size_t npts = 0, nf = 0;
-    int maxw = 1;                       // widest eigen-block
     int m = 30;                         // restart length
     LevelGeom lg;
-    size_t tsz = 4;                     // bytes per V-cycle scalar
     int l0 = 0;                         // first level of the one-work-group sub-cycle
+    size_t tsz = 4;                     // bytes per V-cycle scalar
     int nhier = 0;                      // distinct linearization stages
     int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
     int row_hier[IRK_MAX_STAGES];       // transformed row -> hierarchy
-    // workspace offsets
-    size_t off_K, off_Y, off_Fh, off_U, off_V, off_Z, off_part, off_dv, off_ctr, off_tab;
-    size_t off_lev[IRK_MAX_LEVELS][4];
+    size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
+    LaneLayout lane[IRK_MAX_STAGES];
     size_t total = 0;
 };
 
 static bool valid_options(const irk_options &o) {
     return o.restart >= 1 && o.restart <= IRK_MAX_RESTART && o.max_krylov >= 1 && o.max_newton >= 1 &&
            (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
-           (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 8 &&
+           (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
-           o.krylov_rtol < 1 &&
-           o.newton_rtol >= 0 && o.newton_atol >= 0;
+           o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0;
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -106,8 +117,6 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->nvar = (o.kind == IRK_OP_VSF_2D) ? 2 : 1;
     P->npts = (size_t)o.nx * o.ny;
     P->nf = P->nvar * P->npts;
-    P->maxw = 1;
-    for (int k = 0; k < P->eb.nblocks; ++k) P->maxw = std::max(P->maxw, P->eb.width[k]);
     P->m = P->opt.restart;
     if (!level_geometry(o, P->opt.mg_coarsest, &P->lg)) return IRK_E_ARG;
     P->tsz = P->opt.prec_fp32 ? sizeof(float) : sizeof(double);
@@ -140,20 +149,24 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->off_Y = take(s * P->nf * f64);
     P->off_Fh = take(s * P->nf * f64);
     P->off_U = take(s * P->nf * f64);
-    const size_t veclen = (size_t)P->maxw * P->nf;
-    P->off_V = take((size_t)(P->m + 1) * veclen * f64);
-    P->off_Z = take((size_t)P->m * veclen * f64);
     P->off_part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
-    P->off_dv = take(4096 * f64);
-    P->off_ctr = take(64 * sizeof(unsigned));
+    P->off_dv = take(512 * f64);
     P->off_tab = take((size_t)2 * (o.nx + o.ny) * f64);
-    for (int l = 0; l < P->lg.nlev; ++l) {
-        const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
-        for (int q = 0; q < 4; ++q) P->off_lev[l][q] = take(n * P->tsz);
-    }
     for (int hq = 0; hq < P->nhier; ++hq)
         for (int l = 0; l < P->lg.nlev; ++l)
             P->off_coef[hq][l] = take((size_t)P->lg.nx[l] * P->lg.ny[l] * P->tsz);
+    for (int b = 0; b < P->eb.nblocks; ++b) {
+        LaneLayout &ln = P->lane[b];
+        ln.ldv = (size_t)P->eb.width[b] * P->nf;
+        ln.V = take((size_t)(P->m + 1) * ln.ldv * f64);
+        ln.Z = take((size_t)P->m * ln.ldv * f64);
+        ln.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
+        ln.dv = take(512 * f64);
+        for (int l = 0; l < P->lg.nlev; ++l) {
+            const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
+            for (int q = 0; q < 4; ++q) ln.lev[l][q] = take(n * P->tsz);
+        }
+    }
     P->total = off;
     return IRK_OK;
 }
@@ -162,30 +175,44 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
 
 using namespace irk;
 
-// dvals slots (float64 scalars on the device)
+// slots of the float64 device scalars (per lane, and for the Newton level)
 enum {
-    DV_RES = 0,        // ||F||^2, then the squared norm of |terms of F| (DV_RES + 1)
-    DV_ABS = 1,
+    DV_RES = 0,        // ||F||^2
+    DV_ABS = 1,        // squared norm of |terms of F| (rounding scale)
     DV_K0 = 2,         // ||K0||^2
     DV_BETA = 4,       // ||r0||^2 of a block solve
-    DV_NRM = 5,        // ||w||^2 after orthogonalization
+    DV_NRM = 5,        // ||w||^2 after orthogonalization (unfused path)
     DV_SUMS = 8,       // field sums (up to 16)
     DV_MEANS = 24,     // VSF stage means (2 s)
     DV_XMEANS = 40,    // VSF matvec input means (4)
     DV_H1 = 64,        // first Gram-Schmidt coefficients (<= 64)
-    DV_H2 = 160,       // second pass (<= 64)
+    DV_H2 = 160,       // second pass (<= 64) and the norm
     DV_Y = 256,        // least-squares solution (<= 64)
 };
-enum { CTR_RED = 0 };
+#define PIN_READ 0          // per-lane pinned staging: readbacks
+#define PIN_WRITE 512       // per-lane pinned staging: uploads
+#define PIN_LANE 1024       // doubles of pinned staging per lane
+
+struct Lane {
+    int blk = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr, done = nullptr;
+    double *V = nullptr, *Z = nullptr, *part = nullptr, *dv = nullptr;
+    double *pin = nullptr;
+    size_t ldv = 0;
+    const LaneLayout *lay = nullptr;
+};
 
 struct irk_ctx {
     Plan P;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // the caller's stream (Newton level)
     unsigned char *ws = nullptr;
-    double *K, *Y, *Fh, *U, *V, *Z, *part, *dv, *tab;
-    unsigned *ctr;
+    double *K, *Y, *Fh, *U, *part, *dv, *tab;
     DeviceProblem dp;
-    double *pinned = nullptr;      // host staging, 4096 doubles
+    double *pinned = nullptr;            // host staging: Newton level + lanes
+    hipEvent_t ev_main = nullptr;
+    Lane lanes[IRK_MAX_STAGES];
+    int nlanes = 0;
     bool have_stages = false;
     // Chebyshev smoothing coefficients
     double cheb_cd[8], cheb_cr[8];
@@ -203,7 +230,7 @@ struct irk_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
 
-    template <class T> T *lev(int l, int q) { return reinterpret_cast<T *>(ws + P.off_lev[l][q]); }
+    template <class T> T *lev(const Lane &ln, int l, int q) { return reinterpret_cast<T *>(ws + ln.lay->lev[l][q]); }
     template <class T> T *coef(int h, int l) { return reinterpret_cast<T *>(ws + P.off_coef[h][l]); }
 };
 
@@ -226,7 +253,7 @@ static int prof_id(irk_ctx *c, const std::string &name) {
     return (int)c->prof_names.size() - 1;
 }
 
-// harvest the recorded event pairs (call after the stream has synchronized)
+// harvest the recorded event pairs (call after every stream has synchronized)
 static void prof_harvest(irk_ctx *c) {
     for (auto &r : c->prof_pending) {
         float ms = 0.f;
@@ -240,15 +267,15 @@ static void prof_harvest(irk_ctx *c) {
     c->ev_next = 0;
 }
 
-// time one launch site: algorithmic bytes `bytes`, `n` kernel launches
-#define PROF(c, name, bytes, n, stmt)                                                  \
+// time one launch site on stream `st`: algorithmic bytes `bytes`, `n` launches
+#define PROF(c, st, name, bytes, n, stmt)                                              \
     do {                                                                               \
         if ((c)->prof) {                                                               \
             hipEvent_t e0_ = prof_event(c);                                            \
-            if (e0_) (void)hipEventRecord(e0_, (c)->stream);                           \
+            if (e0_) (void)hipEventRecord(e0_, (st));                                  \
             stmt;                                                                      \
             hipEvent_t e1_ = prof_event(c);                                            \
-            if (e1_) (void)hipEventRecord(e1_, (c)->stream);                           \
+            if (e1_) (void)hipEventRecord(e1_, (st));                                  \
             (c)->prof_pending.push_back({prof_id(c, name), (double)(bytes), (long)(n), e0_, e1_}); \
         } else {                                                                       \
             stmt;                                                                      \
@@ -269,33 +296,53 @@ template <class T> static std::string kn(const char *base, int opk = -1) {
         if ((x) != hipSuccess) return IRK_E_DEVICE;  \
     } while (0)
 
+// IRK_DEBUG=1 in the environment traces the Newton iterations on stderr, 2
+// also every block solve.
+static int debug_level() {
+    static int lvl = -1;
+    if (lvl < 0) {
+        const char *e = getenv("IRK_DEBUG");
+        lvl = e ? atoi(e) : 0;
+    }
+    return lvl;
+}
+
 static irk_status sync_read(irk_ctx *c, const double *dev, int count) {
     HIP_TRY(hipMemcpyAsync(c->pinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return IRK_OK;
 }
 
-static irk_status write_dev(irk_ctx *c, double *dev, const double *host, int count) {
-    // staged through pinned memory; the copy is ordered on the stream and the
-    // staging area is reused only after the next synchronizing read
-    double *stage = c->pinned + 2048;
+// asynchronous readback of a lane's device scalars; completion via ln.ev
+static irk_status lane_readback(Lane &ln, int count) {
+    HIP_TRY(hipMemcpyAsync(ln.pin + PIN_READ, ln.dv, sizeof(double) * count, hipMemcpyDeviceToHost, ln.stream));
+    HIP_TRY(hipEventRecord(ln.ev, ln.stream));
+    return IRK_OK;
+}
+
+// upload through the lane's pinned staging; the staging area is only reused
+// after a later readback on the same lane has completed
+static irk_status lane_write(Lane &ln, double *dev, const double *host, int count) {
+    double *stage = ln.pin + PIN_WRITE;
     std::memcpy(stage, host, sizeof(double) * count);
-    HIP_TRY(hipMemcpyAsync(dev, stage, sizeof(double) * count, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(dev, stage, sizeof(double) * count, hipMemcpyHostToDevice, ln.stream));
     return IRK_OK;
 }
 
 // ---------------------------------------------------------------------------
-// One V-cycle on the hierarchy: tiled down sweeps on levels 0..l0-1, the rest
-// of the cycle inside one work-group, tiled up sweeps back to level 0.  The
-// finest level reads its right-hand side from float64 vectors (in) and writes
-// the float64 result (out).
+// One V-cycle on a lane's hierarchy: tiled down sweeps on levels 0..l0-1, the
+// rest of the cycle inside one work-group, tiled up sweeps back to level 0.
+// The finest level reads its right-hand side from float64 vectors (in) and
+// writes the float64 result (out).
 // ---------------------------------------------------------------------------
 template <class T>
-static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, const MgIn &in, const MgOut &out) {
+static void vcycle(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int hier, const MgIn &in,
+                   const MgOut &out) {
     const Plan &P = c->P;
     const int L = P.lg.nlev, l0 = P.l0, deg = P.opt.cheb_degree;
     const double nu = P.op.nu;
     const double ts = sizeof(T);
+    hipStream_t st = ln.stream;
     auto hl = [&](int l) { return P.op.length / P.op.nx * (double)(1 << l); };
     auto mk = [&](int l) {
         MgLevelArgs<T> a;
@@ -306,13 +353,13 @@ static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, con
         a.sigma = (T)sigma;
         a.dt = (T)dtop;
         a.coef = hier >= 0 ? c->coef<T>(hier, l) : nullptr;
-        a.b = c->lev<T>(l, 3);
-        a.x = c->lev<T>(l, 0);
-        a.xout = c->lev<T>(l, 1);
-        a.bc = l + 1 < L ? c->lev<T>(l + 1, 3) : nullptr;
+        a.b = c->lev<T>(ln, l, 3);
+        a.x = c->lev<T>(ln, l, 0);
+        a.xout = c->lev<T>(ln, l, 1);
+        a.bc = l + 1 < L ? c->lev<T>(ln, l + 1, 3) : nullptr;
         // the up sweep of level l+1 left its result in buffer 1; the
         // one-work-group sub-cycle leaves it in buffer 0
-        a.xc = l + 1 < L ? c->lev<T>(l + 1, l + 1 < l0 ? 1 : 0) : nullptr;
+        a.xc = l + 1 < L ? c->lev<T>(ln, l + 1, l + 1 < l0 ? 1 : 0) : nullptr;
         for (int k = 0; k < IRK_MAX_CHEB; ++k) {
             a.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
             a.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
@@ -326,7 +373,7 @@ static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, con
         const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
         // reads coef, b; writes x and the coarse right-hand side
         const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts) + npc * ts;
-        PROF(c, kn<T>("k_mg_down", opk), by, 1, launch_mg_down<T>(c->stream, opk, a, l == 0 ? in : MgIn{}, deg));
+        PROF(c, st, kn<T>("k_mg_down", opk), by, 1, launch_mg_down<T>(st, opk, a, l == 0 ? in : MgIn{}, deg));
     }
     {
         MgSubArgs<T> sa;
@@ -342,8 +389,8 @@ static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, con
         sa.nu = (T)nu;
         sa.sigma = (T)sigma;
         sa.dt = (T)dtop;
-        sa.b0 = c->lev<T>(l0, 3);
-        sa.x0 = c->lev<T>(l0, 0);
+        sa.b0 = c->lev<T>(ln, l0, 3);
+        sa.x0 = c->lev<T>(ln, l0, 0);
         sa.deg = deg;
         sa.coarse_iters = P.opt.coarse_iters;
         for (int k = 0; k < IRK_MAX_CHEB; ++k) {
@@ -356,28 +403,16 @@ static void vcycle(irk_ctx *c, int opk, double sigma, double dtop, int hier, con
         }
         const double np0 = (double)sa.nx[0] * sa.ny[0];
         const double by = np_all * hc * ts + np0 * ((l0 == 0 ? nin : ts) + (l0 == 0 && out.z ? 8.0 : ts));
-        PROF(c, kn<T>("k_mg_subcycle", opk), by, 1,
-             launch_mg_subcycle<T>(c->stream, opk, sa, l0 == 0 ? in : MgIn{}, l0 == 0 ? out : MgOut{}));
+        PROF(c, st, kn<T>("k_mg_subcycle", opk), by, 1,
+             launch_mg_subcycle<T>(st, opk, sa, l0 == 0 ? in : MgIn{}, l0 == 0 ? out : MgOut{}));
     }
     for (int l = l0 - 1; l >= 0; --l) {
         const MgLevelArgs<T> a = mk(l);
         const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
         // reads coef, b, x, coarse correction; writes x (float64 z on level 0)
         const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts + (l == 0 && out.z ? 8.0 : ts)) + npc * ts;
-        PROF(c, kn<T>("k_mg_up", opk), by, 1, launch_mg_up<T>(c->stream, opk, a, l == 0 ? out : MgOut{}, deg));
+        PROF(c, st, kn<T>("k_mg_up", opk), by, 1, launch_mg_up<T>(st, opk, a, l == 0 ? out : MgOut{}, deg));
     }
-    if (c->st) c->st->vcycles++;
-}
-
-// IRK_DEBUG=1 in the environment traces the Newton and FGMRES iterations
-// on stderr.
-static int debug_level() {
-    static int lvl = -1;
-    if (lvl < 0) {
-        const char *e = getenv("IRK_DEBUG");
-        lvl = e ? atoi(e) : 0;
-    }
-    return lvl;
 }
 
 static int mg_op_of(int kind) {
@@ -387,194 +422,314 @@ static int mg_op_of(int kind) {
 // z = (sigma M - dt L_hier)^{-1} (a1 v1 + a2 v2), one V-cycle, for the
 // differential variable.
 template <class T>
-static void prec_component(irk_ctx *c, double *z, const double *v1, double a1, const double *v2, double a2,
-                           double sigma, int hier) {
+static void prec_component(irk_ctx *c, Lane &ln, double *z, const double *v1, double a1, const double *v2,
+                           double a2, double sigma, int hier) {
     MgIn in;
     in.v1 = v1; in.a1 = a1; in.v2 = v2; in.a2 = a2;
     MgOut out;
     out.z = z; out.v1 = v1; out.a1 = a1; out.v2 = v2; out.a2 = a2;
-    vcycle<T>(c, mg_op_of(c->P.op.kind), sigma, c->dt, hier, in, out);
+    vcycle<T>(c, ln, mg_op_of(c->P.op.kind), sigma, c->dt, hier, in, out);
 }
 
 // VSF streamfunction row of a block: solve B psi = q, B = -dt (Lap - mean),
 // q = r_psi + dt (z_omega - mean z_omega).  The mean-free part comes from one
 // Poisson V-cycle on -dt Lap, the mean exactly: mean(psi) = mean(r_psi)/dt.
 template <class T>
-static void prec_psi(irk_ctx *c, double *zpsi, const double *rpsi, const double *zomega) {
+static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, const double *zomega) {
     const size_t npts = c->P.npts;
-    double *means = c->dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
-    PROF(c, "k_field_sums", 16.0 * npts, 2,
-         launch_field_sums(c->stream, rpsi, 0, 1, npts, 1.0 / npts, c->part, means, c->ctr + CTR_RED);
-         launch_field_sums(c->stream, zomega, 0, 1, npts, 1.0 / npts, c->part, means + 1, c->ctr + CTR_RED));
+    double *means = ln.dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
+    PROF(c, ln.stream, "k_field_sums", 16.0 * npts, 2,
+         launch_field_sums(ln.stream, rpsi, 0, 1, npts, 1.0 / npts, ln.part, means, nullptr);
+         launch_field_sums(ln.stream, zomega, 0, 1, npts, 1.0 / npts, ln.part, means + 1, nullptr));
     MgIn in;
     in.v1 = rpsi; in.a1 = 1.0; in.v2 = zomega; in.a2 = c->dt; in.mean = means;
     MgOut out;
     out.z = zpsi; out.shift = means; out.shift_scale = 1.0 / c->dt;
     out.v1 = rpsi; out.a1 = 1.0; out.v2 = zomega; out.a2 = c->dt; out.mean_in = means;
-    vcycle<T>(c, MG_POISSON, 0.0, c->dt, -1, in, out);
+    vcycle<T>(c, ln, MG_POISSON, 0.0, c->dt, -1, in, out);
 }
 
-// z = L_P^{-1} v for eigen-block blk: the block lower-triangular
+// z = L_P^{-1} v for the lane's eigen-block: the block lower-triangular
 // preconditioner of equation (Lprec) with diagonal inverses (eta M - dt L_a)
 // and the Schur complement approximation (gamma M - dt L_b) of equation
 // (schur-approx), each applied as one V-cycle; the (2,1) block of D is
-// -beta M (phi = beta in the eigenbasis).
+// -beta M (phi = beta in the eigenbasis).  Returns the number of V-cycles.
 template <class T>
-static void apply_prec(irk_ctx *c, int blk, const double *v, double *z) {
+static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
     const Plan &P = c->P;
     const EigenBlocks &eb = P.eb;
+    const int blk = ln.blk;
     const int r = eb.first[blk];
     const size_t nf = P.nf, npts = P.npts;
     const double eta = eb.eta[blk];
     const bool vsf = (P.op.kind == IRK_OP_VSF_2D);
     const int ha = P.row_hier[r];
-    prec_component<T>(c, z, v, 1.0, nullptr, 0.0, eta, ha);
-    if (vsf) prec_psi<T>(c, z + npts, v + npts, z);
+    int nvc = 0;
+    prec_component<T>(c, ln, z, v, 1.0, nullptr, 0.0, eta, ha);
+    ++nvc;
+    if (vsf) { prec_psi<T>(c, ln, z + npts, v + npts, z); ++nvc; }
     if (eb.width[blk] == 2) {
         const double beta = eb.beta[blk];
         const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eta;
         const int hb = P.row_hier[r + 1];
-        prec_component<T>(c, z + nf, v + nf, 1.0, z, beta, gam, hb);
-        if (vsf) prec_psi<T>(c, z + nf + npts, v + nf + npts, z + nf);
+        prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, beta, gam, hb);
+        ++nvc;
+        if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf); ++nvc; }
     }
-    if (c->st) c->st->prec_applications += eb.width[blk];
+    return nvc;
 }
 
 static const double *stage_field(irk_ctx *c, int stage) { return c->U + (size_t)stage * c->P.nf; }
 
-static void block_matvec(irk_ctx *c, int blk, const double *x, double *w) {
+static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
     const Plan &P = c->P;
     const EigenBlocks &eb = P.eb;
+    const int blk = ln.blk;
     const int r = eb.first[blk];
     const int width = eb.width[blk];
     const double *Ua = stage_field(c, P.hier_stage[P.row_hier[r]]);
     const double *Ub = width == 2 ? stage_field(c, P.hier_stage[P.row_hier[r + 1]]) : Ua;
     const double *xm = nullptr;
     if (P.op.kind == IRK_OP_VSF_2D) {
-        PROF(c, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
-             launch_field_sums(c->stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, c->part, c->dv + DV_XMEANS,
-                               c->ctr + CTR_RED));
-        xm = c->dv + DV_XMEANS;
+        PROF(c, ln.stream, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
+             launch_field_sums(ln.stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, ln.part, ln.dv + DV_XMEANS,
+                               nullptr));
+        xm = ln.dv + DV_XMEANS;
     }
     // reads x and writes w (width * nvar fields each), reads one linearization field per component
     const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0);
-    PROF(c, "k_block_matvec<" + std::to_string(P.op.kind) + ">", by, 1,
-         launch_block_matvec(c->stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm));
+    PROF(c, ln.stream, "k_block_matvec<" + std::to_string(P.op.kind) + ">", by, 1,
+         launch_block_matvec(ln.stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm));
 }
 
 // ---------------------------------------------------------------------------
-// Right-preconditioned FGMRES(m) on D_b y = fhat_b, y in Y (transformed rows
-// of the block), classical Gram-Schmidt with reorthogonalization, Givens QR
-// of the Hessenberg matrix on the host.
+// Right-preconditioned FGMRES(m) on D_b y = fhat_b (y in the block's rows of
+// Y), classical Gram-Schmidt with reorthogonalization, Givens QR of the
+// Hessenberg matrix on the host.  Written as a state machine driven by the
+// lane's readbacks so that several lanes can be interleaved.
 // ---------------------------------------------------------------------------
 template <class T>
-static irk_status fgmres_block(irk_ctx *c, int blk, double rtol, int maxit, int *its_out) {
-    const Plan &P = c->P;
-    const EigenBlocks &eb = P.eb;
-    const int r = eb.first[blk];
-    const size_t len = (size_t)eb.width[blk] * P.nf;
-    const size_t ldv = (size_t)P.maxw * P.nf;
-    const int m = P.m;
-    const double *rhs = c->Fh + (size_t)r * P.nf;
-    double *sol = c->Y + (size_t)r * P.nf;
-    double *V = c->V, *Z = c->Z, *dv = c->dv;
-    unsigned *ctr = c->ctr + CTR_RED;
-    irk_status stt;
-
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-    int total = 0;
-    bool first_cycle = true;
+struct Fgmres {
+    irk_ctx *c = nullptr;
+    Lane *ln = nullptr;
+    int m = 30, maxit = 200;
+    double rtol = 1e-5;
+    const double *rhs = nullptr;
+    double *sol = nullptr;
+    size_t len = 0;
+    std::vector<double> H, cs, sn, g, y;
+    int j = 0, total = 0, vcycles = 0;
+    bool first_cycle = true, converged = false, fused = true;
     double beta0 = 0.0;
-    while (true) {
-        // r0 = rhs - D sol (sol = 0 on the first cycle)
+    enum Phase { WAIT_BETA, WAIT_ITER, DONE } phase = WAIT_BETA;
+
+    void init(irk_ctx *cc, Lane *l, double rt, int mx) {
+        c = cc;
+        ln = l;
+        const Plan &P = c->P;
+        const int r = P.eb.first[ln->blk];
+        m = P.m;
+        maxit = mx;
+        rtol = rt;
+        len = (size_t)P.eb.width[ln->blk] * P.nf;
+        rhs = c->Fh + (size_t)r * P.nf;
+        sol = c->Y + (size_t)r * P.nf;
+        H.assign((size_t)(m + 1) * m, 0.0);
+        cs.assign(m, 0.0);
+        sn.assign(m, 0.0);
+        g.assign(m + 1, 0.0);
+        y.assign(m, 0.0);
+        j = total = vcycles = 0;
+        first_cycle = true;
+        converged = false;
+        beta0 = 0.0;
+    }
+
+    double *Vv(int k) { return ln->V + (size_t)k * ln->ldv; }
+    double *Zv(int k) { return ln->Z + (size_t)k * ln->ldv; }
+
+    // issue ||r0||^2 (r0 = rhs on the first cycle, rhs - D sol on restarts)
+    irk_status start() {
         if (first_cycle) {
-            PROF(c, "k_dot_multi", 8.0 * len, 1,
-                 launch_dot_multi(c->stream, V, ldv, 0, rhs, len, 1, c->part, dv + DV_BETA, ctr));
+            PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, rhs, len, 1, ln->part, ln->dv + DV_BETA, nullptr));
         } else {
-            block_matvec(c, blk, sol, V);                       // V0 <- D sol
-            PROF(c, "k_axpby", 24.0 * len, 1, launch_axpby(c->stream, V, 1.0, rhs, -1.0, V, len));
-            PROF(c, "k_dot_multi", 8.0 * len, 1,
-                 launch_dot_multi(c->stream, V, ldv, 0, V, len, 1, c->part, dv + DV_BETA, ctr));
+            block_matvec(c, *ln, sol, Vv(0));
+            PROF(c, ln->stream, "k_axpby", 24.0 * len, 1, launch_axpby(ln->stream, Vv(0), 1.0, rhs, -1.0, Vv(0), len));
+            PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, Vv(0), len, 1, ln->part, ln->dv + DV_BETA,
+                                  nullptr));
         }
-        if ((stt = sync_read(c, dv + DV_BETA, 1)) != IRK_OK) return stt;
-        const double bnorm = std::sqrt(c->pinned[0]);
-        if (!std::isfinite(bnorm)) return IRK_E_NONFINITE;
-        if (first_cycle) {
-            beta0 = bnorm;
-            if (bnorm == 0.0) {
-                launch_fill(c->stream, sol, 0.0, len);
-                *its_out = 0;
-                return IRK_OK;
-            }
+        phase = WAIT_BETA;
+        return lane_readback(*ln, DV_BETA + 1);
+    }
+
+    // one Arnoldi iteration: preconditioner, matvec, CGS2; readback of h
+    irk_status issue_iteration() {
+        double *vj = Vv(j), *zj = Zv(j), *w = Vv(j + 1);
+        vcycles += apply_prec<T>(c, *ln, vj, zj);
+        block_matvec(c, *ln, zj, w);
+        const int nv = j + 1;
+        fused = nv <= 16;
+        hipStream_t st = ln->stream;
+        double *dv = ln->dv;
+        if (fused) {
+            // classical Gram-Schmidt twice in three sweeps: h1 = V^T w;
+            // w -= V h1 with h2 = V^T w and ||w||^2 in the same sweep;
+            // w = (w - V h2) / ||.||
+            PROF(c, st, "k_dot_multi", 8.0 * len * (nv + 1), 1,
+                 launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, nullptr));
+            PROF(c, st, "k_axpy_dot", 8.0 * len * (nv + 2), 1,
+                 launch_axpy_dot(st, w, Vv(0), ln->ldv, nv, dv + DV_H1, len, ln->part, dv + DV_H2, nullptr));
+            PROF(c, st, "k_axpy_scale", 8.0 * len * (nv + 2), 1,
+                 launch_axpy_scale(st, w, Vv(0), ln->ldv, nv, dv + DV_H2, dv + DV_H2 + nv, len));
+        } else {
+            const int nch = (nv + 15) / 16;   // dot launches (16 basis vectors each)
+            PROF(c, st, "k_dot_multi", 8.0 * len * (nv + nch), nch,
+                 launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, nullptr));
+            PROF(c, st, "k_axpy_multi", 8.0 * len * (nv + 2), 1,
+                 launch_axpy_multi(st, w, Vv(0), ln->ldv, nv, dv + DV_H1, len));
+            PROF(c, st, "k_dot_multi", 8.0 * len * (nv + nch), nch,
+                 launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H2, nullptr));
+            PROF(c, st, "k_axpy_multi", 8.0 * len * (nv + 2), 1,
+                 launch_axpy_multi(st, w, Vv(0), ln->ldv, nv, dv + DV_H2, len));
+            PROF(c, st, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(st, Vv(0), ln->ldv, 0, w, len, 1, ln->part, dv + DV_NRM, nullptr));
         }
-        if (bnorm <= rtol * beta0 || total >= maxit) break;
-        PROF(c, "k_scale_copy", 16.0 * len, 1,
-             launch_scale_copy(c->stream, V, first_cycle ? rhs : V, dv + DV_BETA, len));
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = bnorm;
-        int j = 0;
-        bool converged = false;
-        for (; j < m && total < maxit; ++j) {
-            double *vj = V + (size_t)j * ldv, *zj = Z + (size_t)j * ldv, *w = V + (size_t)(j + 1) * ldv;
-            apply_prec<T>(c, blk, vj, zj);
-            block_matvec(c, blk, zj, w);
-            const int nch = (j + 1 + 15) / 16;   // dot launches (16 basis vectors each)
-            PROF(c, "k_dot_multi", 8.0 * len * (j + 1 + nch), nch,
-                 launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H1, ctr));
-            PROF(c, "k_axpy_multi", 8.0 * len * (j + 3), 1,
-                 launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H1, len));
-            PROF(c, "k_dot_multi", 8.0 * len * (j + 1 + nch), nch,
-                 launch_dot_multi(c->stream, V, ldv, j + 1, w, len, 0, c->part, dv + DV_H2, ctr));
-            PROF(c, "k_axpy_multi", 8.0 * len * (j + 3), 1,
-                 launch_axpy_multi(c->stream, w, V, ldv, j + 1, dv + DV_H2, len));
-            PROF(c, "k_dot_multi", 8.0 * len, 1,
-                 launch_dot_multi(c->stream, V, ldv, 0, w, len, 1, c->part, dv + DV_NRM, ctr));
-            if ((stt = sync_read(c, dv, DV_Y)) != IRK_OK) return stt;
-            const double *hb = c->pinned;
-            const double hn = std::sqrt(hb[DV_NRM]);
-            if (!std::isfinite(hn)) return IRK_E_NONFINITE;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[DV_H1 + i] + hb[DV_H2 + i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            // apply previous rotations, then a new one that zeroes H[j+1][j]
-            for (int i = 0; i < j; ++i) {
-                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-            }
-            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-            const double rr = std::hypot(a, b);
-            cs[j] = rr > 0 ? a / rr : 1.0;
-            sn[j] = rr > 0 ? b / rr : 0.0;
-            H[(size_t)j * m + j] = rr;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++total;
-            if (std::fabs(g[j + 1]) <= rtol * beta0 || hn <= 1e-300) { ++j; converged = true; break; }
-            PROF(c, "k_scale_copy", 16.0 * len, 1, launch_scale_copy(c->stream, w, w, dv + DV_NRM, len));
-        }
-        // y = R^{-1} g on the j x j leading block
+        phase = WAIT_ITER;
+        return lane_readback(*ln, DV_Y);
+    }
+
+    // least-squares solution of the cycle and the update of sol
+    irk_status finish_cycle() {
         for (int i = j - 1; i >= 0; --i) {
             double acc = g[i];
             for (int k = i + 1; k < j; ++k) acc -= H[(size_t)i * m + k] * y[k];
             y[i] = acc / H[(size_t)i * m + i];
         }
+        irk_status stt;
         if (first_cycle) {
-            if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
-            PROF(c, "k_lincomb", 8.0 * len * (j + 1), 1, launch_lincomb(c->stream, sol, Z, ldv, j, dv + DV_Y, len));
+            if ((stt = lane_write(*ln, ln->dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
+            PROF(c, ln->stream, "k_lincomb", 8.0 * len * (j + 1), 1,
+                 launch_lincomb(ln->stream, sol, Zv(0), ln->ldv, j, ln->dv + DV_Y, len));
         } else {
-            // sol += Z y, as sol -= Z (-y)
-            for (int i = 0; i < j; ++i) y[i] = -y[i];
-            if ((stt = write_dev(c, dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
-            PROF(c, "k_axpy_multi", 8.0 * len * (j + 2), 1,
-                 launch_axpy_multi(c->stream, sol, Z, ldv, j, dv + DV_Y, len));
+            for (int i = 0; i < j; ++i) y[i] = -y[i];        // sol += Z y as sol -= Z (-y)
+            if ((stt = lane_write(*ln, ln->dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
+            PROF(c, ln->stream, "k_axpy_multi", 8.0 * len * (j + 2), 1,
+                 launch_axpy_multi(ln->stream, sol, Zv(0), ln->ldv, j, ln->dv + DV_Y, len));
         }
         first_cycle = false;
-        if (converged || total >= maxit) break;
+        if (converged || total >= maxit) {
+            phase = DONE;
+            return IRK_OK;
+        }
+        return start();                                        // restart
     }
-    if (debug_level() > 1)
-        fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", blk, total, beta0);
-    *its_out = total;
+
+    // consume the readback that just completed
+    irk_status advance() {
+        const double *hb = ln->pin + PIN_READ;
+        if (phase == WAIT_BETA) {
+            const double bnorm = std::sqrt(hb[DV_BETA]);
+            if (!std::isfinite(bnorm)) return IRK_E_NONFINITE;
+            if (first_cycle) {
+                beta0 = bnorm;
+                if (bnorm == 0.0) {
+                    PROF(c, ln->stream, "k_fill_f64", 8.0 * len, 1, launch_fill(ln->stream, sol, 0.0, len));
+                    phase = DONE;
+                    return IRK_OK;
+                }
+            }
+            if (bnorm <= rtol * beta0 || total >= maxit) {
+                phase = DONE;
+                return IRK_OK;
+            }
+            PROF(c, ln->stream, "k_scale_copy", 16.0 * len, 1,
+                 launch_scale_copy(ln->stream, Vv(0), first_cycle ? rhs : Vv(0), ln->dv + DV_BETA, len));
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = bnorm;
+            j = 0;
+            return issue_iteration();
+        }
+        // WAIT_ITER: Hessenberg column j
+        const int nv = j + 1;
+        double hn2 = fused ? hb[DV_H2 + nv] : hb[DV_NRM];
+        if (fused)
+            for (int i = 0; i < nv; ++i) hn2 -= hb[DV_H2 + i] * hb[DV_H2 + i];
+        if (!std::isfinite(hn2)) return IRK_E_NONFINITE;
+        const double hn = std::sqrt(std::max(hn2, 0.0));
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[DV_H1 + i] + hb[DV_H2 + i];
+        H[(size_t)(j + 1) * m + j] = hn;
+        // apply previous rotations, then a new one that zeroes H[j+1][j]
+        for (int i = 0; i < j; ++i) {
+            const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+        const double rr = std::hypot(a, b);
+        cs[j] = rr > 0 ? a / rr : 1.0;
+        sn[j] = rr > 0 ? b / rr : 0.0;
+        H[(size_t)j * m + j] = rr;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++total;
+        if (std::fabs(g[j + 1]) <= rtol * beta0 || hn <= 1e-300) {
+            converged = true;
+            ++j;
+            return finish_cycle();
+        }
+        if (j + 1 >= m || total >= maxit) {
+            ++j;
+            return finish_cycle();
+        }
+        if (!fused)
+            PROF(c, ln->stream, "k_scale_copy", 16.0 * len, 1,
+                 launch_scale_copy(ln->stream, Vv(j + 1), Vv(j + 1), ln->dv + DV_NRM, len));
+        ++j;
+        return issue_iteration();
+    }
+};
+
+// All eigen-block solves of one Newton iteration, interleaved over the lanes.
+template <class T>
+static irk_status solve_blocks(irk_ctx *c, irk_stats *st) {
+    const Plan &P = c->P;
+    const int nl = c->nlanes;
+    Fgmres<T> fg[IRK_MAX_STAGES];
+    irk_status stt;
+    HIP_TRY(hipEventRecord(c->ev_main, c->stream));
+    for (int b = 0; b < nl; ++b) {
+        HIP_TRY(hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0));
+        fg[b].init(c, &c->lanes[b], P.opt.krylov_rtol, P.opt.max_krylov);
+        if ((stt = fg[b].start()) != IRK_OK) return stt;
+    }
+    int active = nl;
+    bool done[IRK_MAX_STAGES] = {false, false, false, false, false};
+    while (active > 0) {
+        for (int b = 0; b < nl; ++b) {
+            if (done[b]) continue;
+            const hipError_t q = hipEventQuery(c->lanes[b].ev);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return IRK_E_DEVICE;
+            if ((stt = fg[b].advance()) != IRK_OK) return stt;
+            if (fg[b].phase == Fgmres<T>::DONE) {
+                done[b] = true;
+                --active;
+                HIP_TRY(hipEventRecord(c->lanes[b].done, c->lanes[b].stream));
+                HIP_TRY(hipStreamWaitEvent(c->stream, c->lanes[b].done, 0));
+                if (st) {
+                    st->krylov_its += fg[b].total;
+                    st->krylov_its_block[b] += fg[b].total;
+                    st->vcycles += fg[b].vcycles;
+                    st->prec_applications += fg[b].total * P.eb.width[b];
+                }
+                if (debug_level() > 1)
+                    fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", b, fg[b].total, fg[b].beta0);
+            }
+        }
+    }
     return IRK_OK;
 }
 
@@ -605,11 +760,11 @@ static void setup_hierarchies(irk_ctx *c) {
         const double *Um = stage_field(c, P.hier_stage[hq]);
         // coefficient field of the linearization: U_m (NLDIFF, Burgers) or Psi_m (VSF)
         const double *src = P.op.kind == IRK_OP_VSF_2D ? Um + P.npts : Um;
-        PROF(c, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
+        PROF(c, c->stream, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
              launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts));
         for (int l = 0; l + 1 < P.lg.nlev; ++l) {
             const double np = (double)P.lg.nx[l] * P.lg.ny[l], npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-            PROF(c, kn<T>("k_mg_coef_restrict"), sizeof(T) * (np + npc), 1,
+            PROF(c, c->stream, kn<T>("k_mg_coef_restrict"), sizeof(T) * (np + npc), 1,
                  launch_mg_coef_restrict<T>(c->stream, P.lg.nx[l], P.lg.ny[l], c->coef<T>(hq, l),
                                             c->coef<T>(hq, l + 1)));
         }
@@ -625,24 +780,25 @@ static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double
     fill_stage_coefs(c, t_n, dt, &C);
     c->dt = dt;
     irk_status stt;
-    PROF(c, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">", 8.0 * nf * (1 + s), 1,
-         launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
+    PROF(c, c->stream, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
+         8.0 * nf * (1 + s), 1, launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
     // ||M K0|| for the absolute floor
-    PROF(c, "k_dot_multi", 8.0 * s * nf, 1,
-         launch_dot_multi(c->stream, c->V, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, c->ctr + CTR_RED));
+    PROF(c, c->stream, "k_dot_multi", 8.0 * s * nf, 1,
+         launch_dot_multi(c->stream, c->K, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, nullptr));
     double res0 = -1, thresh = 0, prev = 0;
     int fold = 0, flat = 0;
     for (int it = 0;; ++it) {
-        PROF(c, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
+        PROF(c, c->stream, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
              launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
         if (P.op.kind == IRK_OP_VSF_2D)
-            PROF(c, "k_field_sums", 8.0 * s * nf, 1,
+            PROF(c, c->stream, "k_field_sums", 8.0 * s * nf, 1,
                  launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
-                                   c->ctr + CTR_RED));
+                                   nullptr));
         // reads U and K, writes the transformed residual: 3 s fields
-        PROF(c, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">", 8.0 * nf * 3 * s, 1,
+        PROF(c, c->stream, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
+             8.0 * nf * 3 * s, 1,
              launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
-                             c->ctr + CTR_RED));
+                             nullptr));
         if ((stt = sync_read(c, c->dv, 3)) != IRK_OK) return stt;
         const double res = std::sqrt(c->pinned[DV_RES]);
         // the residual cannot be resolved below the rounding error of its own
@@ -671,14 +827,7 @@ static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double
         prev = res;
         if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return IRK_E_NOCONV;
         setup_hierarchies<T>(c);
-        for (int blk = 0; blk < P.eb.nblocks; ++blk) {
-            int its = 0;
-            if ((stt = fgmres_block<T>(c, blk, P.opt.krylov_rtol, P.opt.max_krylov, &its)) != IRK_OK) return stt;
-            if (st) {
-                st->krylov_its += its;
-                st->krylov_its_block[blk] += its;
-            }
-        }
+        if ((stt = solve_blocks<T>(c, st)) != IRK_OK) return stt;
         if (st) st->newton_its++;
         fold = 1;
     }
@@ -752,6 +901,22 @@ static void set_chebyshev(irk_ctx *c) {
     chebyshev_coefs(c->coarse_lmin, c->lmax, c->P.opt.coarse_iters, c->coarse_cd, c->coarse_cr);
 }
 
+static void release(irk_ctx *c) {
+    if (!c) return;
+    for (int b = 0; b < c->nlanes; ++b) {
+        Lane &ln = c->lanes[b];
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+        if (ln.ev) (void)hipEventDestroy(ln.ev);
+        if (ln.done) (void)hipEventDestroy(ln.done);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+    }
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
 extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,
                                  void *device_workspace, size_t workspace_bytes, void *hip_stream, irk_ctx **out) {
     if (!out) return IRK_E_ARG;
@@ -770,15 +935,35 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->Y = (double *)(c->ws + P.off_Y);
     c->Fh = (double *)(c->ws + P.off_Fh);
     c->U = (double *)(c->ws + P.off_U);
-    c->V = (double *)(c->ws + P.off_V);
-    c->Z = (double *)(c->ws + P.off_Z);
     c->part = (double *)(c->ws + P.off_part);
     c->dv = (double *)(c->ws + P.off_dv);
-    c->ctr = (unsigned *)(c->ws + P.off_ctr);
     c->tab = (double *)(c->ws + P.off_tab);
-    if (hipHostMalloc((void **)&c->pinned, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete c;
+    c->nlanes = P.eb.nblocks;
+    if (hipHostMalloc((void **)&c->pinned, (size_t)(1 + c->nlanes) * PIN_LANE * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess) {
+        release(c);
         return IRK_E_DEVICE;
+    }
+    for (int b = 0; b < c->nlanes; ++b) {
+        Lane &ln = c->lanes[b];
+        const LaneLayout &lay = P.lane[b];
+        ln.blk = b;
+        ln.lay = &c->P.lane[b];
+        ln.ldv = lay.ldv;
+        ln.V = (double *)(c->ws + lay.V);
+        ln.Z = (double *)(c->ws + lay.Z);
+        ln.part = (double *)(c->ws + lay.part);
+        ln.dv = (double *)(c->ws + lay.dv);
+        ln.pin = c->pinned + (size_t)(1 + b) * PIN_LANE;
+        // default-priority, non-blocking streams (ordering with the caller's
+        // stream is explicit, through events)
+        if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+            release(c);
+            return IRK_E_DEVICE;
+        }
     }
     set_chebyshev(c);
     // device problem descriptor and forcing tables sin/cos(2 pi x_i)
@@ -804,21 +989,24 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->dp.cosx = c->tab + nx;
     c->dp.siny = c->tab + 2 * nx;
     c->dp.cosy = c->tab + 2 * nx + ny;
-    if (hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+    if (hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
-        (void)hipHostFree(c->pinned);
-        delete c;
+        release(c);
         return IRK_E_DEVICE;
     }
-    launch_zero_u32(c->stream, c->ctr, 64);
     launch_fill(c->stream, c->Y, 0.0, (size_t)s * P.nf);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
-        (void)hipHostFree(c->pinned);
-        delete c;
+        release(c);
         return IRK_E_DEVICE;
     }
     *out = c;
     return IRK_OK;
+}
+
+static void drain(irk_ctx *c) {
+    for (int b = 0; b < c->nlanes; ++b) (void)hipStreamSynchronize(c->lanes[b].stream);
+    (void)hipStreamSynchronize(c->stream);
 }
 
 extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1,
@@ -834,12 +1022,11 @@ extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double
     if (stt == IRK_OK) {
         StageCoefs C;
         fill_stage_coefs(c, t_n, dt, &C);
-        PROF(c, "k_final_update<" + std::to_string(c->P.s) + ">", 8.0 * c->P.nf * (c->P.s + 2), 1,
+        PROF(c, c->stream, "k_final_update<" + std::to_string(c->P.s) + ">", 8.0 * c->P.nf * (c->P.s + 2), 1,
              launch_final_update(c->stream, c->P.s, c->P.nf, u_n, c->K, u_np1, C, dt));
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) stt = IRK_E_DEVICE;
-    } else {
-        (void)hipStreamSynchronize(c->stream);
     }
+    drain(c);
     c->have_stages = (stt == IRK_OK);
     c->st = nullptr;
     if (c->prof) prof_harvest(c);
@@ -883,12 +1070,10 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
     HIP_TRY(hipMemcpyAsync(c->K, K, bytes, hipMemcpyDeviceToDevice, c->stream));
     launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
     if (P.op.kind == IRK_OP_VSF_2D)
-        launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
-                          c->ctr + CTR_RED);
+        launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS, nullptr);
     // identity transform: Tinv = I gives F itself
     for (int i = 0; i < s * s; ++i) C.Tinv[i] = (i / s == i % s) ? 1.0 : 0.0;
-    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
-                    c->ctr + CTR_RED);
+    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES, nullptr);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_stages = false;
@@ -903,10 +1088,4 @@ extern "C" irk_status irk_get_stages(irk_ctx *c, double *K) {
     return IRK_OK;
 }
 
-extern "C" void irk_destroy(irk_ctx *c) {
-    if (!c) return;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->pinned) (void)hipHostFree(c->pinned);
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    delete c;
-}
+extern "C" void irk_destroy(irk_ctx *c) { release(c); }

@@ -25,6 +25,12 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, doub
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr);
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);
+// w <- w - V h1, then h2 = V^T w and ||w||^2 into out[0..nv] (nv <= 16)
+void launch_axpy_dot(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h1, size_t len,
+                     double *partials, double *out, unsigned *ctr);
+// w <- (w - V h2) / sqrt(nrm2 - |h2|^2)
+void launch_axpy_scale(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h2,
+                       const double *nrm2, size_t len);
 void launch_lincomb(hipStream_t st, double *dst, const double *V, size_t ldv, int nv, const double *c, size_t len);
 void launch_scale_copy(hipStream_t st, double *dst, const double *src, const double *nrm2, size_t len);
 void launch_axpby(hipStream_t st, double *dst, double a, const double *x, double b, const double *y, size_t len);

@@ -51,29 +51,68 @@ __device__ __forceinline__ double block_sum(double v, double *sh /* >= 4 */) {
     return r;
 }
 
-// Each work-group stores `nv` partial sums; the last one to arrive sums all
-// partials (fixed order) into out[0..nv-1] and re-arms the counter.
+// Each work-group stores its `nv` partial sums; k_reduce_partials (launched
+// right after on the same stream) adds them in a fixed order.  The kernel
+// boundary makes the partials visible: no device-scope fences, which on a
+// multi-XCD device write back L2.
 __device__ void finish_partials(const double *myvals, int nv, double *partials, double *out,
                                 unsigned *counter) {
-    __shared__ bool is_last;
-    __shared__ double sh[8];
-    if (threadIdx.x == 0) {
+    (void)out;
+    (void)counter;
+    if (threadIdx.x == 0)
         for (int k = 0; k < nv; ++k) partials[(size_t)blockIdx.x * nv + k] = myvals[k];
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x - 1);
+}
+
+// out[k] = sum over work-groups b of partials[b * nv + k], fixed order
+__global__ void __launch_bounds__(256) k_reduce_partials(const double *__restrict__ partials, int nb, int nv,
+                                                         double *__restrict__ out) {
+    __shared__ double sh[4 * 32];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < nv; ++k) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partials[(size_t)b * nv + k];
+        a = wave_sum(a);
+        if (lane == 0) sh[wid * 32 + k] = a;
     }
     __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    const volatile double *vp = partials;
-    for (int k = 0; k < nv; ++k) {
-        double acc = 0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) acc += vp[(size_t)b * nv + k];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x == 0) out[k] = acc;
+    if ((int)threadIdx.x < nv) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w * 32 + threadIdx.x];
+        out[threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// Reduce nv per-thread accumulators over the work-group: every wave reduces
+// with shuffles, wave leaders stage their sums in LDS, one barrier, and
+// thread k < nv returns value k in `mine` (fixed order: waves 0..3).
+// acc[0..nv-1] are values 0..nv-1; when with_norm, acc[NV-1] becomes value nv
+// (register arrays are only indexed with compile-time constants).
+template <int NV>
+__device__ __forceinline__ void block_reduce_multi(const double (&acc)[NV], int nv, bool with_norm,
+                                                   double *sh /* [4][NV] */, double &mine) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV - 1; ++k) {
+        if (k < nv) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0) sh[wid * NV + k] = v;
+        }
+    }
+    if (with_norm) {
+        const double v = wave_sum(acc[NV - 1]);
+        if (lane == 0) sh[wid * NV + nv] = v;
+    }
+    __syncthreads();
+    const int nout = nv + (with_norm ? 1 : 0);
+    mine = 0.0;
+    if ((int)threadIdx.x < nout)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mine += sh[w * NV + threadIdx.x];
+}
+
+// Work-group partials: thread k < nv stores value k (all in wave 0).
+template <int NV>
+__device__ __forceinline__ void finish_multi(double mine, int nv, double *partials) {
+    if ((int)threadIdx.x < nv) partials[(size_t)blockIdx.x * nv + threadIdx.x] = mine;
 }
 
 // ------------------------------------------------------------------------
@@ -348,16 +387,66 @@ __global__ void __launch_bounds__(IRK_WG) k_dot_multi(const double *__restrict__
 #pragma unroll
         for (int k = 0; k < DOT_CHUNK; ++k)
             if (k < nv) acc[k] += V[k * ldv + e] * we;
+        if (with_norm) acc[DOT_CHUNK] += we * we;
+    }
+    __shared__ double sh[4 * (DOT_CHUNK + 1)];
+    const int nout = nv + (with_norm ? 1 : 0);
+    double mine;
+    block_reduce_multi<DOT_CHUNK + 1>(acc, nv, with_norm != 0, sh, mine);
+    finish_multi<DOT_CHUNK + 1>(mine, nout, partials);
+}
+
+// Second Gram-Schmidt pass fused with the first update (one sweep over V):
+//   w <- w - sum_k h1[k] V_k ;  h2[k] = <V_k, w> ;  out[nv] = <w, w>
+// (out = h2 followed by the norm).
+__global__ void __launch_bounds__(IRK_WG) k_axpy_dot(double *__restrict__ w, const double *__restrict__ V,
+                                                     size_t ldv, int nv, const double *__restrict__ h1,
+                                                     size_t len, double *partials, double *out,
+                                                     unsigned *counter) {
+    double acc[DOT_CHUNK + 1];
+    double hk[DOT_CHUNK];
+#pragma unroll
+    for (int k = 0; k <= DOT_CHUNK; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < DOT_CHUNK; ++k) hk[k] = k < nv ? h1[k] : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double v[DOT_CHUNK];
+        double we = w[e];
+#pragma unroll
+        for (int k = 0; k < DOT_CHUNK; ++k)
+            if (k < nv) {
+                v[k] = V[k * ldv + e];
+                we -= hk[k] * v[k];
+            }
+        w[e] = we;
+#pragma unroll
+        for (int k = 0; k < DOT_CHUNK; ++k)
+            if (k < nv) acc[k] += v[k] * we;
         acc[DOT_CHUNK] += we * we;
     }
-    __shared__ double sh[8];
-    double tot[DOT_CHUNK + 1];
-    const int nout = nv + (with_norm ? 1 : 0);
-#pragma unroll
-    for (int k = 0; k < DOT_CHUNK; ++k)
-        if (k < nv) tot[k] = block_sum(acc[k], sh);
-    if (with_norm) tot[nv] = block_sum(acc[DOT_CHUNK], sh);
-    finish_partials(tot, nout, partials, out, counter);
+    __shared__ double sh[4 * (DOT_CHUNK + 1)];
+    double mine;
+    block_reduce_multi<DOT_CHUNK + 1>(acc, nv, true, sh, mine);
+    finish_multi<DOT_CHUNK + 1>(mine, nv + 1, partials);
+}
+
+// Final update and normalization of the new Arnoldi vector:
+//   w <- (w - sum_k h2[k] V_k) / sqrt(nrm2 - sum_k h2[k]^2)
+// (the norm of the twice-orthogonalized vector by Pythagoras: V orthonormal).
+__global__ void __launch_bounds__(IRK_WG) k_axpy_scale(double *__restrict__ w, const double *__restrict__ V,
+                                                       size_t ldv, int nv, const double *__restrict__ h2,
+                                                       const double *__restrict__ nrm2, size_t len) {
+    double hs = 0.0;
+    for (int k = 0; k < nv; ++k) hs += h2[k] * h2[k];
+    const double nn = *nrm2 - hs;
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double acc = w[e];
+        for (int k = 0; k < nv; ++k) acc -= h2[k] * V[k * ldv + e];
+        w[e] = acc * inv;
+    }
 }
 
 // w <- w - sum_k h[k] V_k
@@ -481,6 +570,10 @@ void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, doubl
     }
 }
 
+static void reduce_partials(hipStream_t st, const double *partials, unsigned nb, int nv, double *out) {
+    k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, out);
+}
+
 template <int S>
 static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, const double *K, double *Fh,
                        const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr) {
@@ -492,6 +585,7 @@ static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, 
         k_residual<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
     else
         k_residual<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
+    reduce_partials(st, partials, g, 2, out);
 }
 
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
@@ -539,7 +633,9 @@ void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, con
 
 void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, size_t len, double scale,
                        double *partials, double *out, unsigned *ctr) {
-    k_field_sums<<<grid_for(len, IRK_RED_BLOCKS), IRK_WG, 0, st>>>(X, ld, nfields, len, scale, partials, out, ctr);
+    const unsigned g = grid_for(len, IRK_RED_BLOCKS);
+    k_field_sums<<<g, IRK_WG, 0, st>>>(X, ld, nfields, len, scale, partials, out, ctr);
+    reduce_partials(st, partials, g, nfields, out);
 }
 
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
@@ -561,11 +657,24 @@ void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const
     do {
         const int c = (nv - done) > DOT_CHUNK ? DOT_CHUNK : (nv - done);
         const int last = (done + c == nv);
-        k_dot_multi<<<grid_for(len, IRK_RED_BLOCKS), IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len,
-                                                                       last ? with_norm : 0, partials,
-                                                                       out + done, ctr);
+        const unsigned g = grid_for(len, IRK_RED_BLOCKS);
+        const int wn = last ? with_norm : 0;
+        k_dot_multi<<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials, out + done, ctr);
+        reduce_partials(st, partials, g, c + wn, out + done);
         done += c;
     } while (done < nv);
+}
+
+void launch_axpy_dot(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h1, size_t len,
+                     double *partials, double *out, unsigned *ctr) {
+    const unsigned g = grid_for(len, IRK_RED_BLOCKS);
+    k_axpy_dot<<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials, out, ctr);
+    reduce_partials(st, partials, g, nv + 1, out);
+}
+
+void launch_axpy_scale(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h2,
+                       const double *nrm2, size_t len) {
+    k_axpy_scale<<<grid_for(len), IRK_WG, 0, st>>>(w, V, ldv, nv, h2, nrm2, len);
 }
 
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len) {

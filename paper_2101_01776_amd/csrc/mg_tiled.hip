@@ -87,13 +87,34 @@ __device__ __forceinline__ void lds_op(const T *cf, const T *x, int c, int W, T 
 }
 
 // Iterate over the sub-box of a window: columns [a0, a1), rows [b0, b1).
+// (column and row are advanced incrementally: no division per point)
 #define FOR_BOX(a0, a1, b0, b1, W, ...)                                    \
     do {                                                                   \
         const int bw_ = (a1) - (a0), bn_ = bw_ * ((b1) - (b0));            \
+        const int sx_ = (int)blockDim.x % bw_, sy_ = (int)blockDim.x / bw_; \
+        int ca_ = (int)threadIdx.x % bw_, cb_ = (int)threadIdx.x / bw_;    \
         for (int q_ = threadIdx.x; q_ < bn_; q_ += blockDim.x) {           \
-            const int ia = (a0) + q_ % bw_, ib = (b0) + q_ / bw_;          \
+            const int ia = (a0) + ca_, ib = (b0) + cb_;                    \
             const int c = ib * (W) + ia;                                   \
             __VA_ARGS__;                                                   \
+            ca_ += sx_;                                                    \
+            cb_ += sy_;                                                    \
+            if (ca_ >= bw_) { ca_ -= bw_; ++cb_; }                         \
+        }                                                                  \
+    } while (0)
+
+// Points p = j * nx + i of an nx-wide level, strided over the work-group,
+// with (i, j) advanced incrementally.
+#define FOR_PTS(np_, nx_, ...)                                             \
+    do {                                                                   \
+        const int w_ = (nx_);                                              \
+        const int sx_ = (int)blockDim.x % w_, sy_ = (int)blockDim.x / w_;  \
+        int i = (int)threadIdx.x % w_, j = (int)threadIdx.x / w_;          \
+        for (int p = threadIdx.x; p < (np_); p += blockDim.x) {            \
+            __VA_ARGS__;                                                   \
+            i += sx_;                                                      \
+            j += sy_;                                                      \
+            if (i >= w_) { i -= w_; ++j; }                                 \
         }                                                                  \
     } while (0)
 
@@ -291,6 +312,51 @@ __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
 // ---------------------------------------------------------------------------
 // The V-cycle on levels l0..L-1 in one work-group, every level in LDS.
 // ---------------------------------------------------------------------------
+// Gershgorin ratio sum_{j != i} |a_ij| / |a_ii| of row i of A = sigma M - dt L
+// on a level (periodic), from the operator's stencil coefficients.
+template <class T, int OPK>
+__device__ T row_ratio(const T *cf, int i, int j, int nx, int ny, T h, T nu, T sigma, T dt) {
+    const T inv_h2 = T(1) / (h * h);
+    if constexpr (OPK == MG_NLDIFF) {
+        const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
+        const int nb[4] = {j * nx + ip, j * nx + im, jp * nx + i, jm * nx + i};
+        const T uc = cf[j * nx + i];
+        T off = 0, ld = 0;
+        for (int q = 0; q < 4; ++q) {
+            const T un = cf[nb[q]];
+            const T kf = T(1) + T(0.5) * (uc * uc + un * un);
+            const T du = un - uc;
+            off += fabs(dt * inv_h2 * (kf + du * un));
+            ld += -kf + du * uc;
+        }
+        return off / fabs(sigma - dt * ld * inv_h2);
+    } else if constexpr (OPK == MG_BURGERS) {
+        const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
+        const T off = fabs(dt * (-cf[ip] / (T(2) * h) + nu * inv_h2)) + fabs(dt * (cf[im] / (T(2) * h) + nu * inv_h2));
+        return off / fabs(sigma + T(2) * dt * nu * inv_h2);
+    } else if constexpr (OPK == MG_VSF_OMEGA) {
+        T p[3][3], e[3][3];
+        for (int dj = 0; dj < 3; ++dj)
+            for (int di = 0; di < 3; ++di) {
+                p[dj][di] = cf[wrapm(j + dj - 1, ny) * nx + wrapm(i + di - 1, nx)];
+                e[dj][di] = T(0);
+            }
+        T off = 0;
+        for (int dj = 0; dj < 3; ++dj)
+            for (int di = 0; di < 3; ++di) {
+                if (dj == 1 && di == 1) continue;
+                e[dj][di] = T(1);
+                T cnb = arakawa9(p, e, inv_h2 / T(12));
+                if (dj == 1 || di == 1) cnb += nu * inv_h2;
+                e[dj][di] = T(0);
+                off += fabs(dt * cnb);
+            }
+        return off / fabs(sigma + T(4) * dt * nu * inv_h2);
+    } else {
+        return sigma == T(0) ? T(1) : T(4) * dt * inv_h2 / fabs(sigma + T(4) * dt * inv_h2);
+    }
+}
+
 template <class T, int OPK>
 __device__ void wg_cheb(const T *cf, T *x, const T *b, T *r, T *d, int nx, int ny, T h, T nu, T sigma, T dt,
                         const T *cd, const T *cr, int nsteps, bool from_zero) {
@@ -298,8 +364,7 @@ __device__ void wg_cheb(const T *cf, T *x, const T *b, T *r, T *d, int nx, int n
     const T inv_h2 = T(1) / (h * h);
     for (int k = 0; k < nsteps; ++k) {
         // r <- D^{-1} (b - A x)
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int i = p % nx, j = p / nx;
+        FOR_PTS(np, nx, {
             T Lx, Ld;
             T xc = from_zero && k == 0 ? T(0) : x[p];
             if (OPK == MG_VSF_OMEGA) {
@@ -318,7 +383,7 @@ __device__ void wg_cheb(const T *cf, T *x, const T *b, T *r, T *d, int nx, int n
                 level_op<T, OPK, true>(cf, x, i, j, nx, ny, h, nu, Lx, Ld);
             }
             r[p] = (b[p] - (sigma * xc - dt * Lx)) / (sigma - dt * Ld);
-        }
+        });
         __syncthreads();
         for (int p = threadIdx.x; p < np; p += blockDim.x) {
             const T dn = (k == 0 ? T(0) : cd[k] * d[p]) + cr[k] * r[p];
@@ -333,17 +398,19 @@ template <class T, int OPK>
 __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, MgOut out) {
     extern __shared__ unsigned char smem_raw[];
     T *base = reinterpret_cast<T *>(smem_raw);
-    // per level: x, b, coef; shared scratch r, d sized for the finest level
-    T *X[IRK_MAX_LEVELS], *B[IRK_MAX_LEVELS], *C[IRK_MAX_LEVELS];
-    T *ptr = base;
-    for (int l = 0; l < s.nlev; ++l) {
-        const int np = s.nx[l] * s.ny[l];
-        X[l] = ptr; ptr += np;
-        B[l] = ptr; ptr += np;
-        C[l] = ptr; ptr += np;
-    }
-    T *R = ptr;
-    T *Dv = ptr + s.nx[0] * s.ny[0];
+    // per level: x, b, coef (consecutive blocks); then shared scratch r, d
+    // sized for the finest level.  Level pointers are recomputed from the
+    // sizes (uniform scalar arithmetic) instead of being kept in an array.
+    auto lev_base = [&](int l) {
+        size_t off = 0;
+        for (int q = 0; q < l; ++q) off += 3 * (size_t)s.nx[q] * s.ny[q];
+        return base + off;
+    };
+#define X(l) (lev_base(l))
+#define B(l) (lev_base(l) + (size_t)s.nx[l] * s.ny[l])
+#define C(l) (lev_base(l) + 2 * (size_t)s.nx[l] * s.ny[l])
+    T *R = lev_base(s.nlev);
+    T *Dv = R + s.nx[0] * s.ny[0];
     const int np0 = s.nx[0] * s.ny[0];
     for (int p = threadIdx.x; p < np0; p += blockDim.x) {
         T rhs;
@@ -355,28 +422,27 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
         } else {
             rhs = s.b0[p];
         }
-        B[0][p] = rhs;
+        B(0)[p] = rhs;
     }
     for (int l = 0; l < s.nlev; ++l) {
         const int np = s.nx[l] * s.ny[l];
-        for (int p = threadIdx.x; p < np; p += blockDim.x) C[l][p] = s.coef[l] ? s.coef[l][p] : T(0);
+        for (int p = threadIdx.x; p < np; p += blockDim.x) C(l)[p] = s.coef[l] ? s.coef[l][p] : T(0);
     }
     __syncthreads();
     const int L = s.nlev;
     for (int l = 0; l < L - 1; ++l) {
         const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        wg_cheb<T, OPK>(C[l], X[l], B[l], R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, true);
-        // residual into R, then full weighting into B[l+1]
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int i = p % nx, j = p / nx;
+        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, true);
+        // residual into R, then full weighting into B(l+1)
+        FOR_PTS(np, nx, {
             T Lx, Ld;
-            level_op<T, OPK, true>(C[l], X[l], i, j, nx, ny, s.h[l], s.nu, Lx, Ld);
-            R[p] = B[l][p] - (s.sigma * X[l][p] - s.dt * Lx);
-        }
+            level_op<T, OPK, true>(C(l), X(l), i, j, nx, ny, s.h[l], s.nu, Lx, Ld);
+            R[p] = B(l)[p] - (s.sigma * X(l)[p] - s.dt * Lx);
+        });
         __syncthreads();
         const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
-        for (int q = threadIdx.x; q < nxc * nyc; q += blockDim.x) {
-            const int I = q % nxc, J = q / nxc;
+        FOR_PTS(nxc * nyc, nxc, {
+            const int I = i, J = j, q = p;
             T acc;
             if (ny > 1) {
                 acc = 0;
@@ -388,18 +454,21 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
             } else {
                 acc = T(0.5) * R[2 * I] + T(0.25) * (R[wrap_any(2 * I - 1, nx)] + R[wrap_any(2 * I + 1, nx)]);
             }
-            B[l + 1][q] = acc;
-        }
+            B(l + 1)[q] = acc;
+        });
         __syncthreads();
     }
     {
-        // coarsest level: Chebyshev iteration on [lmin, lmax]; the singular
-        // periodic Poisson operator is solved on mean-free data
+        // coarsest level: Chebyshev iteration on a Gershgorin interval
+        // [1 - rho, 1 + rho] of D^{-1} A computed here; the singular periodic
+        // Poisson operator (rho = 1) is solved on mean-free data with the
+        // interval's lower end at its smallest nonzero eigenvalue
         const int l = L - 1, nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        if (OPK == MG_POISSON && s.sigma == T(0)) {
-            __shared__ double red[16];
+        __shared__ double red[16];
+        const bool singular = (OPK == MG_POISSON && s.sigma == T(0));
+        if (singular) {
             double acc = 0;
-            for (int p = threadIdx.x; p < np; p += blockDim.x) acc += (double)B[l][p];
+            for (int p = threadIdx.x; p < np; p += blockDim.x) acc += (double)B(l)[p];
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
             __syncthreads();
@@ -407,36 +476,71 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
             const T m = (T)(tot / np);
             __syncthreads();
-            for (int p = threadIdx.x; p < np; p += blockDim.x) B[l][p] -= m;
+            for (int p = threadIdx.x; p < np; p += blockDim.x) B(l)[p] -= m;
             __syncthreads();
         }
-        wg_cheb<T, OPK>(C[l], X[l], B[l], R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.ccd, s.ccr, s.coarse_iters,
-                        true);
+        double rho = 0.0;
+        FOR_PTS(np, nx, rho = fmax(rho, (double)row_ratio<T, OPK>(C(l), i, j, nx, ny, s.h[l], s.nu, s.sigma, s.dt)));
+        for (int off = 32; off > 0; off >>= 1) rho = fmax(rho, __shfl_xor(rho, off, 64));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rho;
+        __syncthreads();
+        rho = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) rho = fmax(rho, red[w]);
+        __syncthreads();
+        double lmin = 1.0 - rho, lmax = 1.0 + rho;
+        if (singular || lmin < 0.05) {
+            const double sx = sin(3.14159265358979323846 / nx), sy = ny > 1 ? sin(3.14159265358979323846 / ny) : 1.0;
+            lmin = fmax(0.5 * fmin(sx * sx, sy * sy), 0.02);
+        }
+        // steps for a 1e-3 reduction of the Chebyshev bound 2 r^k
+        const double kap = lmax / lmin, sq = sqrt(kap);
+        const double rr = (sq - 1.0) / (sq + 1.0);
+        int iters = rr > 0.0 ? (int)ceil(log(2000.0) / -log(rr)) : 1;
+        iters = iters < 2 ? 2 : (iters > s.coarse_iters ? s.coarse_iters : iters);
+        __shared__ T ccd[IRK_MAX_COARSE_ITERS], ccr[IRK_MAX_COARSE_ITERS];
+        if (threadIdx.x == 0) {
+            const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+            const double sig1 = theta / delta;
+            double rho_k = 1.0 / sig1;
+            for (int k = 0; k < iters; ++k) {
+                if (k == 0) { ccd[0] = T(0); ccr[0] = (T)(1.0 / theta); }
+                else {
+                    const double rn = 1.0 / (2.0 * sig1 - rho_k);
+                    ccd[k] = (T)(rn * rho_k);
+                    ccr[k] = (T)(2.0 * rn / delta);
+                    rho_k = rn;
+                }
+            }
+        }
+        __syncthreads();
+        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, ccd, ccr, iters, true);
     }
     for (int l = L - 2; l >= 0; --l) {
         const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
         const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int i = p % nx, j = p / nx;
+        FOR_PTS(np, nx, {
             const int I0 = i >> 1, I1 = (i & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
             T e;
             if (ny > 1) {
                 const int J0 = j >> 1, J1 = (j & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
-                e = T(0.25) * (X[l + 1][J0 * nxc + I0] + X[l + 1][J0 * nxc + I1] + X[l + 1][J1 * nxc + I0] +
-                               X[l + 1][J1 * nxc + I1]);
+                e = T(0.25) * (X(l + 1)[J0 * nxc + I0] + X(l + 1)[J0 * nxc + I1] + X(l + 1)[J1 * nxc + I0] +
+                               X(l + 1)[J1 * nxc + I1]);
             } else {
-                e = T(0.5) * (X[l + 1][I0] + X[l + 1][I1]);
+                e = T(0.5) * (X(l + 1)[I0] + X(l + 1)[I1]);
             }
-            X[l][p] += e;
-        }
+            X(l)[p] += e;
+        });
         __syncthreads();
-        wg_cheb<T, OPK>(C[l], X[l], B[l], R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, false);
+        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, false);
     }
     for (int p = threadIdx.x; p < np0; p += blockDim.x) {
-        if (out.z) out.z[p] = (double)X[0][p] + (out.shift ? out.shift_scale * out.shift[0] : 0.0);
-        else s.x0[p] = X[0][p];
+        if (out.z) out.z[p] = (double)X(0)[p] + (out.shift ? out.shift_scale * out.shift[0] : 0.0);
+        else s.x0[p] = X(0)[p];
     }
 }
+#undef X
+#undef B
+#undef C
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -472,15 +576,15 @@ static void up_t(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int 
 template <class T, int OPK>
 static void down_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &in, int deg) {
     if (a.ny == 1) down_t<T, OPK, 256, 1>(st, a, in, deg);
-    else if (a.nx >= 256) down_t<T, OPK, 64, (sizeof(T) == 4 ? 16 : 8)>(st, a, in, deg);
-    else down_t<T, OPK, 32, 8>(st, a, in, deg);
+    else if (a.nx >= 128) down_t<T, OPK, 32, 8>(st, a, in, deg);
+    else down_t<T, OPK, 16, 8>(st, a, in, deg);
 }
 
 template <class T, int OPK>
 static void up_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int deg) {
     if (a.ny == 1) up_t<T, OPK, 256, 1>(st, a, out, deg);
-    else if (a.nx >= 256) up_t<T, OPK, 64, (sizeof(T) == 4 ? 16 : 8)>(st, a, out, deg);
-    else up_t<T, OPK, 32, 8>(st, a, out, deg);
+    else if (a.nx >= 128) up_t<T, OPK, 32, 8>(st, a, out, deg);
+    else up_t<T, OPK, 16, 8>(st, a, out, deg);
 }
 
 template <class T>
