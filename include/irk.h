@@ -208,6 +208,62 @@ irk_status irk_profile_entry(irk_ctx *ctx, int idx, char *name, int name_len, lo
 /* Release the context (not the caller's workspace).  NULL is accepted.     */
 void irk_destroy(irk_ctx *ctx);
 
+/* -------------------------------- serving -------------------------------- */
+/* Continuous batching of step-solve requests on one GPU (not in the paper).
+ * Requests are admitted first-in first-out as soon as a slot is free and
+ * their resident state fits in the caller's device arena: the solver
+ * workspace of irk_workspace_bytes plus two state fields.  Admitted requests
+ * stay resident until their last step; running requests progress
+ * concurrently, each on its own HIP streams.  A request's result is the same
+ * as irk_step's on the same problem, whatever else runs.                   */
+
+typedef struct irk_server irk_server;
+
+typedef enum irk_request_state {
+    IRK_REQ_QUEUED = 0, IRK_REQ_RUNNING = 1, IRK_REQ_DONE = 2, IRK_REQ_FAILED = 3
+} irk_request_state;
+
+typedef struct irk_request {
+    int family;             /* irk_family                                     */
+    int s;                  /* stages, 1..5                                   */
+    irk_operator op;
+    irk_options opt;        /* used when use_options != 0, else defaults      */
+    int use_options;
+    double t0, dt;          /* start time, step                               */
+    int nsteps;             /* steps to take (>= 1)                           */
+    double tol;             /* Newton tolerance (<= 0: options)               */
+    const double *u0;       /* device, initial field; read at admission; the
+                               caller keeps it valid until the request ends   */
+    double *out;            /* device, final field written at completion      */
+} irk_request;
+
+typedef struct irk_request_info {
+    int state;              /* irk_request_state                              */
+    irk_status status;      /* IRK_OK, or why the request failed              */
+    int steps_done;
+    int newton_its, krylov_its;        /* summed over the steps               */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock       */
+} irk_request_info;
+
+/* arena: caller-owned device memory (256-byte aligned) the server carves
+ * request state from; arena_bytes is the HBM admission budget; max_slots
+ * bounds the number of requests resident at once.                          */
+irk_status irk_server_create(void *arena, size_t arena_bytes, int max_slots, irk_server **out);
+/* Queue a request (nothing runs until irk_server_progress).  IRK_E_ARG for
+ * invalid requests; a request larger than the whole arena is failed with
+ * IRK_E_NOMEM when it reaches the head of the queue.                       */
+irk_status irk_server_submit(irk_server *srv, const irk_request *req, long *id);
+/* One non-blocking scheduling pass: admit what fits, advance every running
+ * request; returns the number of requests queued or running (-1 on NULL).  */
+int irk_server_progress(irk_server *srv);
+irk_status irk_server_info(irk_server *srv, long id, irk_request_info *info);
+/* Latencies (milliseconds, host clock) of every completed step so far (up to
+ * cap written), the peak number of resident requests and arena bytes.      */
+irk_status irk_server_stats(irk_server *srv, double *step_ms, int cap, int *nsteps, int *peak_running,
+                            size_t *peak_bytes);
+/* Finish or abandon everything and release the server (not the arena).     */
+void irk_server_destroy(irk_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

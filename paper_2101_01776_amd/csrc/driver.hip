@@ -203,6 +203,8 @@ struct Lane {
     const LaneLayout *lay = nullptr;
 };
 
+struct StepperBase;
+
 struct irk_ctx {
     Plan P;
     hipStream_t stream = nullptr;        // the caller's stream (Newton level)
@@ -210,7 +212,9 @@ struct irk_ctx {
     double *K, *Y, *Fh, *U, *part, *dv, *tab;
     DeviceProblem dp;
     double *pinned = nullptr;            // host staging: Newton level + lanes
-    hipEvent_t ev_main = nullptr;
+    hipEvent_t ev_main = nullptr;       // Newton level -> lanes
+    hipEvent_t ev_res = nullptr;        // Newton-level readbacks
+    StepperBase *stepper = nullptr;
     Lane lanes[IRK_MAX_STAGES];
     int nlanes = 0;
     bool have_stages = false;
@@ -692,47 +696,6 @@ struct Fgmres {
     }
 };
 
-// All eigen-block solves of one Newton iteration, interleaved over the lanes.
-template <class T>
-static irk_status solve_blocks(irk_ctx *c, irk_stats *st) {
-    const Plan &P = c->P;
-    const int nl = c->nlanes;
-    Fgmres<T> fg[IRK_MAX_STAGES];
-    irk_status stt;
-    HIP_TRY(hipEventRecord(c->ev_main, c->stream));
-    for (int b = 0; b < nl; ++b) {
-        HIP_TRY(hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0));
-        fg[b].init(c, &c->lanes[b], P.opt.krylov_rtol, P.opt.max_krylov);
-        if ((stt = fg[b].start()) != IRK_OK) return stt;
-    }
-    int active = nl;
-    bool done[IRK_MAX_STAGES] = {false, false, false, false, false};
-    while (active > 0) {
-        for (int b = 0; b < nl; ++b) {
-            if (done[b]) continue;
-            const hipError_t q = hipEventQuery(c->lanes[b].ev);
-            if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) return IRK_E_DEVICE;
-            if ((stt = fg[b].advance()) != IRK_OK) return stt;
-            if (fg[b].phase == Fgmres<T>::DONE) {
-                done[b] = true;
-                --active;
-                HIP_TRY(hipEventRecord(c->lanes[b].done, c->lanes[b].stream));
-                HIP_TRY(hipStreamWaitEvent(c->stream, c->lanes[b].done, 0));
-                if (st) {
-                    st->krylov_its += fg[b].total;
-                    st->krylov_its_block[b] += fg[b].total;
-                    st->vcycles += fg[b].vcycles;
-                    st->prec_applications += fg[b].total * P.eb.width[b];
-                }
-                if (debug_level() > 1)
-                    fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", b, fg[b].total, fg[b].beta0);
-            }
-        }
-    }
-    return IRK_OK;
-}
-
 // ---------------------------------------------------------------------------
 // One step: Algorithm 1 in the eigenbasis.
 // ---------------------------------------------------------------------------
@@ -771,23 +734,43 @@ static void setup_hierarchies(irk_ctx *c) {
     }
 }
 
+// The Newton-like loop of Algorithm 1 as a resumable state machine: every
+// host decision waits on an event instead of blocking, so irk_step can poll
+// one machine and the serving loop can poll many.
+struct StepperBase {
+    virtual ~StepperBase() {}
+    virtual void begin(const double *u_n, double t_n, double dt, double rtol, double *u_np1) = 0;
+    // advance as far as possible without blocking; true when finished
+    virtual bool poll() = 0;
+    irk_status status = IRK_OK;
+    irk_stats stats;
+};
+
 template <class T>
-static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double dt, double rtol, irk_stats *st) {
-    const Plan &P = c->P;
-    const int s = P.s;
-    const size_t nf = P.nf;
+struct Stepper : StepperBase {
+    irk_ctx *c;
+    enum Phase { RES_WAIT, BLOCKS, FINAL_WAIT, DONE } phase = DONE;
+    const double *u_n = nullptr;
+    double *u_np1 = nullptr;
+    double t_n = 0, dt = 0, rtol = 0;
     StageCoefs C;
-    fill_stage_coefs(c, t_n, dt, &C);
-    c->dt = dt;
-    irk_status stt;
-    PROF(c, c->stream, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
-         8.0 * nf * (1 + s), 1, launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
-    // ||M K0|| for the absolute floor
-    PROF(c, c->stream, "k_dot_multi", 8.0 * s * nf, 1,
-         launch_dot_multi(c->stream, c->K, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, nullptr));
+    int it = 0, fold = 0, flat = 0, active = 0;
     double res0 = -1, thresh = 0, prev = 0;
-    int fold = 0, flat = 0;
-    for (int it = 0;; ++it) {
+    Fgmres<T> fg[IRK_MAX_STAGES];
+    bool lane_done[IRK_MAX_STAGES];
+
+    explicit Stepper(irk_ctx *cc) : c(cc) {}
+
+    bool fail(irk_status e) {
+        status = e;
+        phase = DONE;
+        return true;
+    }
+
+    irk_status issue_residual() {
+        const Plan &P = c->P;
+        const int s = P.s;
+        const size_t nf = P.nf;
         PROF(c, c->stream, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
              launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
         if (P.op.kind == IRK_OP_VSF_2D)
@@ -799,40 +782,139 @@ static irk_status newton_solve(irk_ctx *c, const double *u_n, double t_n, double
              8.0 * nf * 3 * s, 1,
              launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
                              nullptr));
-        if ((stt = sync_read(c, c->dv, 3)) != IRK_OK) return stt;
+        HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipEventRecord(c->ev_res, c->stream));
+        phase = RES_WAIT;
+        return IRK_OK;
+    }
+
+    void begin(const double *un, double tn, double dtt, double rt, double *out) override {
+        const Plan &P = c->P;
+        const int s = P.s;
+        const size_t nf = P.nf;
+        u_n = un;
+        u_np1 = out;
+        t_n = tn;
+        dt = dtt;
+        rtol = rt;
+        std::memset(&stats, 0, sizeof(stats));
+        status = IRK_OK;
+        fill_stage_coefs(c, t_n, dt, &C);
+        c->dt = dt;
+        c->st = &stats;
+        it = fold = flat = 0;
+        res0 = -1;
+        thresh = prev = 0;
+        PROF(c, c->stream, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
+             8.0 * nf * (1 + s), 1, launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
+        // ||M K0|| for the absolute floor
+        PROF(c, c->stream, "k_dot_multi", 8.0 * s * nf, 1,
+             launch_dot_multi(c->stream, c->K, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, nullptr));
+        const irk_status e = issue_residual();
+        if (e != IRK_OK) fail(e);
+    }
+
+    // the residual norm has arrived: converge, fail, or start the block solves
+    bool on_residual() {
+        const Plan &P = c->P;
         const double res = std::sqrt(c->pinned[DV_RES]);
         // the residual cannot be resolved below the rounding error of its own
         // evaluation: 64 eps times the norm of the magnitudes of its terms
         const double floor_res = 64.0 * 2.220446049250313e-16 * std::sqrt(c->pinned[DV_ABS]);
-        if (!std::isfinite(res)) return IRK_E_NONFINITE;
+        if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
         if (it == 0) {
             res0 = res;
             const double k0 = std::sqrt(c->pinned[DV_K0]);
-            if (!std::isfinite(k0)) return IRK_E_NONFINITE;
+            if (!std::isfinite(k0)) return fail(IRK_E_NONFINITE);
             const double atol = P.opt.newton_atol > 0 ? P.opt.newton_atol : 1e-14 * k0;
             thresh = rtol * res0 + atol;
-            if (st) st->res0 = res0;
+            stats.res0 = res0;
         }
-        if (st) st->final_res = res;
+        stats.final_res = res;
         if (debug_level())
             fprintf(stderr, "[irk] newton it %d res %.6e thresh %.3e floor %.3e\n", it, res, thresh, floor_res);
-        if (res <= std::max(thresh, floor_res)) break;
+        bool converged = res <= std::max(thresh, floor_res);
         // stagnation within a small factor of the estimated floor: the
         // iteration has reached rounding level
-        if (it > 0 && res <= 16.0 * floor_res && res > 0.25 * prev) break;
+        if (!converged && it > 0 && res <= 16.0 * floor_res && res > 0.25 * prev) converged = true;
         // safety net: three non-decreasing iterations far below res0 mean the
         // rounding floor was underestimated
         flat = (it > 0 && res > 0.5 * prev) ? flat + 1 : 0;
-        if (flat >= 3 && res <= 1e-8 * res0) break;
+        if (!converged && flat >= 3 && res <= 1e-8 * res0) converged = true;
+        if (converged) {
+            PROF(c, c->stream, "k_final_update<" + std::to_string(P.s) + ">", 8.0 * P.nf * (P.s + 2), 1,
+                 launch_final_update(c->stream, P.s, P.nf, u_n, c->K, u_np1, C, dt));
+            if (hipEventRecord(c->ev_res, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
+            phase = FINAL_WAIT;
+            return false;
+        }
         prev = res;
-        if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return IRK_E_NOCONV;
+        if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return fail(IRK_E_NOCONV);
         setup_hierarchies<T>(c);
-        if ((stt = solve_blocks<T>(c, st)) != IRK_OK) return stt;
-        if (st) st->newton_its++;
-        fold = 1;
+        if (hipEventRecord(c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
+        active = c->nlanes;
+        for (int b = 0; b < c->nlanes; ++b) {
+            lane_done[b] = false;
+            if (hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0) != hipSuccess) return fail(IRK_E_DEVICE);
+            fg[b].init(c, &c->lanes[b], P.opt.krylov_rtol, P.opt.max_krylov);
+            const irk_status e = fg[b].start();
+            if (e != IRK_OK) return fail(e);
+        }
+        phase = BLOCKS;
+        return false;
     }
-    return IRK_OK;
-}
+
+    bool poll() override {
+        const Plan &P = c->P;
+        for (;;) {
+            if (phase == DONE) return true;
+            if (phase == RES_WAIT || phase == FINAL_WAIT) {
+                const hipError_t q = hipEventQuery(c->ev_res);
+                if (q == hipErrorNotReady) return false;
+                if (q != hipSuccess) return fail(IRK_E_DEVICE);
+                if (phase == FINAL_WAIT) {
+                    phase = DONE;
+                    return true;
+                }
+                if (on_residual()) return true;
+                continue;
+            }
+            // BLOCKS: advance every lane whose readback has landed
+            bool progressed = false;
+            for (int b = 0; b < c->nlanes; ++b) {
+                if (lane_done[b]) continue;
+                const hipError_t q = hipEventQuery(c->lanes[b].ev);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return fail(IRK_E_DEVICE);
+                progressed = true;
+                const irk_status e = fg[b].advance();
+                if (e != IRK_OK) return fail(e);
+                if (fg[b].phase == Fgmres<T>::DONE) {
+                    lane_done[b] = true;
+                    --active;
+                    if (hipEventRecord(c->lanes[b].done, c->lanes[b].stream) != hipSuccess ||
+                        hipStreamWaitEvent(c->stream, c->lanes[b].done, 0) != hipSuccess)
+                        return fail(IRK_E_DEVICE);
+                    stats.krylov_its += fg[b].total;
+                    stats.krylov_its_block[b] += fg[b].total;
+                    stats.vcycles += fg[b].vcycles;
+                    stats.prec_applications += fg[b].total * P.eb.width[b];
+                    if (debug_level() > 1)
+                        fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", b, fg[b].total, fg[b].beta0);
+                }
+            }
+            if (active == 0) {
+                stats.newton_its++;
+                fold = 1;
+                ++it;
+                const irk_status e = issue_residual();
+                if (e != IRK_OK) return fail(e);
+                continue;
+            }
+            if (!progressed) return false;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -912,6 +994,8 @@ static void release(irk_ctx *c) {
     }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->ev_res) (void)hipEventDestroy(c->ev_res);
+    delete c->stepper;
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -941,9 +1025,16 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->nlanes = P.eb.nblocks;
     if (hipHostMalloc((void **)&c->pinned, (size_t)(1 + c->nlanes) * PIN_LANE * sizeof(double),
                       hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_res, hipEventDisableTiming) != hipSuccess) {
         release(c);
         return IRK_E_DEVICE;
+    }
+    if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) Stepper<float>(c);
+    else c->stepper = new (std::nothrow) Stepper<double>(c);
+    if (!c->stepper) {
+        release(c);
+        return IRK_E_NOMEM;
     }
     for (int b = 0; b < c->nlanes; ++b) {
         Lane &ln = c->lanes[b];
@@ -1004,31 +1095,42 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     return IRK_OK;
 }
 
-static void drain(irk_ctx *c) {
+namespace irk {
+// Start one step on a context (non-blocking); poll with step_poll.
+irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1) {
+    if (!c || !u_n || !u_np1 || !(dt > 0) || !std::isfinite(t_n)) return IRK_E_ARG;
+    (void)hipGetLastError();
+    c->have_stages = false;
+    c->stepper->begin(u_n, t_n, dt, tol > 0 ? tol : c->P.opt.newton_rtol, u_np1);
+    return IRK_OK;
+}
+
+// Advance the step without blocking; returns 1 when finished (status in *st).
+int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats) {
+    if (!c->stepper->poll()) return 0;
+    irk_status s = c->stepper->status;
+    if (s == IRK_OK && hipGetLastError() != hipSuccess) s = IRK_E_DEVICE;
+    c->have_stages = (s == IRK_OK);
+    c->st = nullptr;
+    if (st) *st = s;
+    if (stats) *stats = c->stepper->stats;
+    return 1;
+}
+
+void drain_all(irk_ctx *c) {
     for (int b = 0; b < c->nlanes; ++b) (void)hipStreamSynchronize(c->lanes[b].stream);
     (void)hipStreamSynchronize(c->stream);
 }
+}  // namespace irk
 
 extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1,
                                irk_stats *stats) {
-    if (!c || !u_n || !u_np1 || !(dt > 0) || !std::isfinite(t_n)) return IRK_E_ARG;
+    irk_status stt = step_begin(c, u_n, t_n, dt, tol, u_np1);
+    if (stt != IRK_OK) return stt;
     irk_stats local;
-    std::memset(&local, 0, sizeof(local));
-    c->st = &local;
-    (void)hipGetLastError();
-    const double rtol = tol > 0 ? tol : c->P.opt.newton_rtol;
-    irk_status stt = c->P.opt.prec_fp32 ? newton_solve<float>(c, u_n, t_n, dt, rtol, &local)
-                                        : newton_solve<double>(c, u_n, t_n, dt, rtol, &local);
-    if (stt == IRK_OK) {
-        StageCoefs C;
-        fill_stage_coefs(c, t_n, dt, &C);
-        PROF(c, c->stream, "k_final_update<" + std::to_string(c->P.s) + ">", 8.0 * c->P.nf * (c->P.s + 2), 1,
-             launch_final_update(c->stream, c->P.s, c->P.nf, u_n, c->K, u_np1, C, dt));
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) stt = IRK_E_DEVICE;
+    while (!step_poll(c, &stt, &local)) {
     }
-    drain(c);
-    c->have_stages = (stt == IRK_OK);
-    c->st = nullptr;
+    drain_all(c);
     if (c->prof) prof_harvest(c);
     if (stats) *stats = local;
     return stt;

@@ -1,0 +1,284 @@
+// Serving loop for IRK step-solve requests (continuous batching on one GPU).
+//
+// Requests (operator, tableau, dt, number of steps, initial field) are
+// queued FIFO and admitted as soon as a slot is free and their resident
+// state -- the solver workspace (stage vectors, Krylov bases, multigrid
+// hierarchies) plus two state fields -- fits in the caller's device arena.
+// Admitted requests stay resident until their last step; every running
+// request is a non-blocking step state machine with its own HIP streams, and
+// one progress pass advances all of them, so requests that arrive while
+// others run start as soon as memory and a slot free up and their kernels
+// overlap on the device.  Arithmetic is exactly that of irk_step on the same
+// problem (same kernels, deterministic reductions), so a request's result
+// does not depend on what else is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "irk_internal.h"
+
+namespace irk {
+irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1);
+int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats);
+void drain_all(irk_ctx *c);
+}  // namespace irk
+
+namespace {
+
+double now_s() {
+    using clk = std::chrono::steady_clock;
+    static const clk::time_point t0 = clk::now();
+    return std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+// First-fit allocator over the caller's device arena (256-byte granules,
+// free blocks coalesced on release).
+class Arena {
+  public:
+    void init(size_t base_bytes) {
+        free_.clear();
+        free_[0] = base_bytes;
+        cap_ = base_bytes;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t capacity() const { return cap_; }
+    size_t used() const { return used_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t cap_ = 0, used_ = 0;
+};
+
+struct Req {
+    long id = 0;
+    irk_request r;
+    irk_request_info info;
+    size_t ws_bytes = 0, field_bytes = 0, off = 0, total = 0;
+    bool allocated = false;
+    irk_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    double *ua = nullptr, *ub = nullptr;      // resident state, ping-pong
+    double t = 0.0, step_t0 = 0.0;
+};
+
+}  // namespace
+
+struct irk_server {
+    unsigned char *arena = nullptr;
+    Arena alloc;
+    int max_slots = 1;
+    long next_id = 1;
+    std::deque<Req *> queue;
+    std::vector<Req *> running;
+    std::map<long, Req *> finished;
+    std::vector<double> step_ms;              // latency of every completed step
+    int peak_running = 0;
+    size_t peak_bytes = 0;
+};
+
+static size_t field_len(const irk_operator &op) {
+    const size_t n = (size_t)op.nx * op.ny;
+    return op.kind == IRK_OP_VSF_2D ? 2 * n : n;
+}
+
+static void finish(irk_server *s, Req *q, irk_status st) {
+    q->info.status = st;
+    q->info.state = st == IRK_OK ? IRK_REQ_DONE : IRK_REQ_FAILED;
+    q->info.t_done = now_s();
+    if (q->ctx) {
+        irk::drain_all(q->ctx);
+        if (st == IRK_OK && q->r.out)
+            (void)hipMemcpyAsync(q->r.out, q->ua, q->field_bytes, hipMemcpyDeviceToDevice, q->stream);
+        if (q->stream) (void)hipStreamSynchronize(q->stream);
+        irk_destroy(q->ctx);
+        q->ctx = nullptr;
+    }
+    if (q->stream) (void)hipStreamDestroy(q->stream);
+    q->stream = nullptr;
+    if (q->allocated) s->alloc.release(q->off, q->total);
+    q->allocated = false;
+    s->finished[q->id] = q;
+}
+
+// admit the queue head if a slot and memory are available
+static bool try_admit(irk_server *s) {
+    if (s->queue.empty() || (int)s->running.size() >= s->max_slots) return false;
+    Req *q = s->queue.front();
+    if (q->total > s->alloc.capacity()) {          // can never fit
+        s->queue.pop_front();
+        finish(s, q, IRK_E_NOMEM);
+        return true;
+    }
+    size_t off = 0;
+    if (!s->alloc.alloc(q->total, &off)) return false;   // FIFO: wait for memory
+    s->queue.pop_front();
+    q->off = off;
+    q->allocated = true;
+    q->info.t_admit = now_s();
+    q->info.state = IRK_REQ_RUNNING;
+    unsigned char *base = s->arena + off;
+    q->ua = (double *)base;
+    q->ub = (double *)(base + ((q->field_bytes + 255) & ~size_t(255)));
+    unsigned char *ws = base + 2 * ((q->field_bytes + 255) & ~size_t(255));
+    irk_status st = IRK_OK;
+    if (hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking) != hipSuccess) st = IRK_E_DEVICE;
+    if (st == IRK_OK &&
+        hipMemcpyAsync(q->ua, q->r.u0, q->field_bytes, hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
+        st = IRK_E_DEVICE;
+    if (st == IRK_OK && hipStreamSynchronize(q->stream) != hipSuccess) st = IRK_E_DEVICE;
+    if (st == IRK_OK)
+        st = irk_create((irk_family)q->r.family, q->r.s, &q->r.op, q->r.use_options ? &q->r.opt : nullptr, ws,
+                        q->ws_bytes, q->stream, &q->ctx);
+    q->t = q->r.t0;
+    if (st == IRK_OK) {
+        q->step_t0 = now_s();
+        st = irk::step_begin(q->ctx, q->ua, q->t, q->r.dt, q->r.tol, q->ub);
+    }
+    if (st != IRK_OK) {
+        finish(s, q, st);
+        return true;
+    }
+    s->running.push_back(q);
+    s->peak_running = std::max(s->peak_running, (int)s->running.size());
+    s->peak_bytes = std::max(s->peak_bytes, s->alloc.used());
+    return true;
+}
+
+extern "C" irk_status irk_server_create(void *arena, size_t arena_bytes, int max_slots, irk_server **out) {
+    if (!out || !arena || ((uintptr_t)arena & 255) != 0 || arena_bytes < 256 || max_slots < 1) return IRK_E_ARG;
+    irk_server *s = new (std::nothrow) irk_server();
+    if (!s) return IRK_E_NOMEM;
+    s->arena = (unsigned char *)arena;
+    s->alloc.init(arena_bytes & ~size_t(255));
+    s->max_slots = max_slots;
+    *out = s;
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_server_submit(irk_server *s, const irk_request *r, long *id) {
+    if (!s || !r || !id || !r->u0 || !r->out || r->nsteps < 1 || !(r->dt > 0)) return IRK_E_ARG;
+    const size_t ws = irk_workspace_bytes((irk_family)r->family, r->s, &r->op, r->use_options ? &r->opt : nullptr);
+    if (ws == 0) return IRK_E_ARG;
+    Req *q = new (std::nothrow) Req();
+    if (!q) return IRK_E_NOMEM;
+    q->id = s->next_id++;
+    q->r = *r;
+    std::memset(&q->info, 0, sizeof(q->info));
+    q->info.state = IRK_REQ_QUEUED;
+    q->info.t_submit = now_s();
+    q->ws_bytes = ws;
+    q->field_bytes = field_len(r->op) * sizeof(double);
+    q->total = 2 * ((q->field_bytes + 255) & ~size_t(255)) + ws;
+    s->queue.push_back(q);
+    *id = q->id;
+    return IRK_OK;
+}
+
+extern "C" int irk_server_progress(irk_server *s) {
+    if (!s) return -1;
+    while (try_admit(s)) {
+    }
+    for (size_t k = 0; k < s->running.size();) {
+        Req *q = s->running[k];
+        irk_status st = IRK_OK;
+        irk_stats stats;
+        if (!irk::step_poll(q->ctx, &st, &stats)) {
+            ++k;
+            continue;
+        }
+        const double t1 = now_s();
+        if (st == IRK_OK) {
+            s->step_ms.push_back(1e3 * (t1 - q->step_t0));
+            q->info.steps_done++;
+            q->info.newton_its += stats.newton_its;
+            q->info.krylov_its += stats.krylov_its;
+            q->t += q->r.dt;
+            std::swap(q->ua, q->ub);
+            if (q->info.steps_done < q->r.nsteps) {
+                q->step_t0 = t1;
+                st = irk::step_begin(q->ctx, q->ua, q->t, q->r.dt, q->r.tol, q->ub);
+                if (st == IRK_OK) {
+                    ++k;
+                    continue;
+                }
+            }
+        }
+        s->running.erase(s->running.begin() + k);
+        finish(s, q, st);
+        while (try_admit(s)) {
+        }
+    }
+    return (int)s->running.size() + (int)s->queue.size();
+}
+
+extern "C" irk_status irk_server_info(irk_server *s, long id, irk_request_info *info) {
+    if (!s || !info) return IRK_E_ARG;
+    auto it = s->finished.find(id);
+    if (it != s->finished.end()) {
+        *info = it->second->info;
+        return IRK_OK;
+    }
+    for (Req *q : s->running)
+        if (q->id == id) { *info = q->info; return IRK_OK; }
+    for (Req *q : s->queue)
+        if (q->id == id) { *info = q->info; return IRK_OK; }
+    return IRK_E_ARG;
+}
+
+extern "C" irk_status irk_server_stats(irk_server *s, double *step_ms, int cap, int *nsteps, int *peak_running,
+                                       size_t *peak_bytes) {
+    if (!s) return IRK_E_ARG;
+    const int n = (int)s->step_ms.size();
+    if (nsteps) *nsteps = n;
+    if (step_ms)
+        for (int k = 0; k < n && k < cap; ++k) step_ms[k] = s->step_ms[k];
+    if (peak_running) *peak_running = s->peak_running;
+    if (peak_bytes) *peak_bytes = s->peak_bytes;
+    return IRK_OK;
+}
+
+extern "C" void irk_server_destroy(irk_server *s) {
+    if (!s) return;
+    for (Req *q : s->running) finish(s, q, IRK_E_ARG);
+    s->running.clear();
+    for (Req *q : s->queue) delete q;
+    for (auto &kv : s->finished) delete kv.second;
+    delete s;
+}

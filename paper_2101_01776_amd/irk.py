@@ -61,6 +61,21 @@ class Stats(ctypes.Structure):
                 "final_res": self.final_res}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int), ("s", ctypes.c_int), ("op", Operator), ("opt", Options),
+                ("use_options", ctypes.c_int), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int), ("tol", ctypes.c_double), ("u0", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("steps_done", ctypes.c_int),
+                ("newton_its", ctypes.c_int), ("krylov_its", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
 _lib = None
 
 
@@ -98,6 +113,19 @@ def lib() -> ctypes.CDLL:
     L.irk_get_stages.argtypes = [P, P]
     L.irk_destroy.restype = None
     L.irk_destroy.argtypes = [P]
+    L.irk_server_create.restype = I
+    L.irk_server_create.argtypes = [P, Z, I, ctypes.POINTER(P)]
+    L.irk_server_submit.restype = I
+    L.irk_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_long)]
+    L.irk_server_progress.restype = I
+    L.irk_server_progress.argtypes = [P]
+    L.irk_server_info.restype = I
+    L.irk_server_info.argtypes = [P, ctypes.c_long, ctypes.POINTER(RequestInfo)]
+    L.irk_server_stats.restype = I
+    L.irk_server_stats.argtypes = [P, ctypes.POINTER(D), I, ctypes.POINTER(I), ctypes.POINTER(I),
+                                   ctypes.POINTER(Z)]
+    L.irk_server_destroy.restype = None
+    L.irk_server_destroy.argtypes = [P]
     L.irk_profile_enable.restype = I
     L.irk_profile_enable.argtypes = [P, I]
     L.irk_profile_count.restype = I
@@ -276,6 +304,110 @@ class Solver:
         if self.ctx is not None:
             irk_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------- serving -------------------------------------
+def irk_server_create(arena_ptr: int, arena_bytes: int, max_slots: int):
+    srv = ctypes.c_void_p()
+    _check(lib().irk_server_create(ctypes.c_void_p(arena_ptr), arena_bytes, max_slots, ctypes.byref(srv)),
+           "irk_server_create")
+    return srv
+
+
+def irk_server_submit(srv, req: Request) -> int:
+    rid = ctypes.c_long()
+    _check(lib().irk_server_submit(srv, ctypes.byref(req), ctypes.byref(rid)), "irk_server_submit")
+    return rid.value
+
+
+def irk_server_progress(srv) -> int:
+    return int(lib().irk_server_progress(srv))
+
+
+def irk_server_info(srv, rid: int) -> dict:
+    info = RequestInfo()
+    _check(lib().irk_server_info(srv, rid, ctypes.byref(info)), "irk_server_info")
+    return {"state": REQ_STATE[info.state], "status": STATUS.get(info.status, info.status),
+            "steps_done": info.steps_done, "newton_its": info.newton_its, "krylov_its": info.krylov_its,
+            "t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done}
+
+
+def irk_server_stats(srv) -> dict:
+    L = lib()
+    n = ctypes.c_int()
+    peak = ctypes.c_int()
+    pb = ctypes.c_size_t()
+    _check(L.irk_server_stats(srv, None, 0, ctypes.byref(n), ctypes.byref(peak), ctypes.byref(pb)),
+           "irk_server_stats")
+    buf = (ctypes.c_double * max(1, n.value))()
+    _check(L.irk_server_stats(srv, buf, n.value, ctypes.byref(n), ctypes.byref(peak), ctypes.byref(pb)),
+           "irk_server_stats")
+    return {"step_ms": list(buf)[: n.value], "peak_running": peak.value, "peak_bytes": pb.value}
+
+
+def irk_server_destroy(srv):
+    lib().irk_server_destroy(srv)
+
+
+class Server:
+    """A serving loop on a PyTorch-allocated device arena (the HBM budget)."""
+
+    def __init__(self, arena_bytes: int, max_slots: int, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        lib()
+        self._arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._arena.data_ptr() + 255) & ~255
+        self.srv = irk_server_create(ptr, arena_bytes, max_slots)
+        self._keep = {}
+
+    def submit(self, family: str, s: int, op: Operator, u0, dt: float, nsteps: int, t0: float = 0.0,
+               opt: Options = None, tol: float = 0.0, out=None) -> int:
+        torch = self.torch
+        u0 = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous()
+        if out is None:
+            out = torch.empty_like(u0)
+        req = Request()
+        req.family = FAMILY[family]
+        req.s = s
+        req.op = op
+        if opt is not None:
+            req.opt = opt
+            req.use_options = 1
+        req.t0, req.dt, req.nsteps, req.tol = t0, dt, nsteps, tol
+        req.u0 = u0.data_ptr()
+        req.out = out.data_ptr()
+        rid = irk_server_submit(self.srv, req)
+        self._keep[rid] = (u0, out)
+        return rid
+
+    def progress(self) -> int:
+        return irk_server_progress(self.srv)
+
+    def run_until_idle(self):
+        while self.progress() > 0:
+            pass
+
+    def info(self, rid: int) -> dict:
+        return irk_server_info(self.srv, rid)
+
+    def result(self, rid: int):
+        return self._keep[rid][1]
+
+    def stats(self) -> dict:
+        return irk_server_stats(self.srv)
+
+    def close(self):
+        if self.srv is not None:
+            irk_server_destroy(self.srv)
+            self.srv = None
 
     def __del__(self):
         try:

@@ -109,3 +109,27 @@ def test_create_rejects_bad_workspace_without_gpu_work():
     st = L.irk_create(irk.GAUSS, 3, ctypes.byref(op), None, ctypes.c_void_p(256), 16, None, ctypes.byref(ctx))
     assert st == -2 and not ctx.value
     L.irk_destroy(None)
+
+
+def test_server_admission_checks_without_gpu():
+    """Host-side serving logic: request validation, and a request larger than
+    the whole arena fails with IRK_E_NOMEM at admission (no device work; the
+    arena address is never dereferenced)."""
+    srv = irk.irk_server_create(256, 1 << 20, 2)
+    req = irk.Request()
+    req.family, req.s = irk.GAUSS, 3
+    req.op = irk.make_operator(irk.OP_NLDIFF_2D, 512, forcing=irk.FORCING_MMS)
+    req.t0, req.dt, req.nsteps, req.tol = 0.0, 5e-3, 2, 0.0
+    req.u0, req.out = 4096, 8192
+    rid = irk.irk_server_submit(srv, req)
+    assert irk.irk_server_progress(srv) == 0
+    info = irk.irk_server_info(srv, rid)
+    assert info["state"] == "failed" and info["status"] == "IRK_E_NOMEM"
+    bad = irk.Request()
+    bad.family, bad.s, bad.op = irk.GAUSS, 3, req.op
+    bad.dt, bad.nsteps, bad.u0, bad.out = 5e-3, 0, 4096, 8192
+    with pytest.raises(irk.IrkError):
+        irk.irk_server_submit(srv, bad)
+    st = irk.irk_server_stats(srv)
+    assert st["peak_running"] == 0 and st["peak_bytes"] == 0
+    irk.irk_server_destroy(srv)

@@ -1,0 +1,97 @@
+"""Serving: continuous batching of step-solve requests on one GPU.
+
+Every request's result in the mix equals (bitwise) the result of the same
+steps run alone with irk_step; admission respects the arena budget and the
+slot limit; a request that can never fit fails with IRK_E_NOMEM without
+disturbing the others."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu
+from paper_2101_01776_amd import inputs, irk
+
+pytestmark = gpu
+
+MIX = [  # (family, s, n, dt, nsteps, seed)
+    ("gauss", 2, 64, 4e-3, 3, 1),
+    ("radau", 3, 128, 2e-3, 2, 2),
+    ("gauss", 3, 96, 5e-3, 3, 3),
+    ("gauss", 4, 64, 1e-3, 2, 4),
+    ("radau", 2, 128, 8e-3, 2, 5),
+    ("gauss", 2, 32, 6e-3, 4, 6),
+    ("radau", 4, 64, 3e-3, 2, 7),
+    ("gauss", 3, 128, 2e-3, 2, 8),
+]
+
+
+def _alone(family, s, n, dt, nsteps, seed):
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+    sol = irk.Solver(family, s, op)
+    u = inputs.nldiff_random_u0(n, seed)
+    t = 0.0
+    for _ in range(nsteps):
+        out, _ = sol.step(u, t, dt)
+        u = out
+        t += dt
+    res = u.clone()
+    sol.close()
+    return res
+
+
+def _submit_all(srv, mix):
+    ids = []
+    for family, s, n, dt, nsteps, seed in mix:
+        op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+        ids.append(srv.submit(family, s, op, inputs.nldiff_random_u0(n, seed), dt, nsteps))
+    return ids
+
+
+def test_alone_equals_in_the_mix():
+    import torch
+    alone = [_alone(*m) for m in MIX]
+    srv = irk.Server(arena_bytes=4 << 30, max_slots=8)
+    ids = _submit_all(srv, MIX)
+    srv.run_until_idle()
+    st = srv.stats()
+    print("peak running", st["peak_running"], "steps", len(st["step_ms"]))
+    assert st["peak_running"] >= 4                 # requests really overlapped
+    for rid, ref, m in zip(ids, alone, MIX):
+        info = srv.info(rid)
+        assert info["state"] == "done" and info["steps_done"] == m[4], info
+        assert torch.equal(srv.result(rid), ref), m
+    srv.close()
+
+
+def test_budget_and_slots_bound_residency():
+    import torch
+    op_bytes = [irk.irk_workspace_bytes(f, s, irk.make_operator(irk.OP_NLDIFF_2D, n)) for f, s, n, *_ in MIX]
+    budget = int(2.2 * max(op_bytes))                # room for about two requests at a time
+    srv = irk.Server(arena_bytes=budget, max_slots=3)
+    ids = _submit_all(srv, MIX)
+    srv.run_until_idle()
+    st = srv.stats()
+    assert st["peak_running"] <= 3
+    assert st["peak_bytes"] <= budget
+    alone = [_alone(*m) for m in MIX]
+    for rid, ref in zip(ids, alone):
+        assert srv.info(rid)["state"] == "done"
+        assert torch.equal(srv.result(rid), ref)
+    # FIFO admission: admission times follow submission order
+    admits = [srv.info(r)["t_admit"] for r in ids]
+    assert admits == sorted(admits)
+    srv.close()
+
+
+def test_request_larger_than_arena_fails_alone():
+    big = irk.make_operator(irk.OP_NLDIFF_2D, 256, forcing=irk.FORCING_MMS)
+    small = irk.make_operator(irk.OP_NLDIFF_2D, 32, forcing=irk.FORCING_MMS)
+    need_small = irk.irk_workspace_bytes("gauss", 2, small)
+    srv = irk.Server(arena_bytes=4 * need_small, max_slots=4)
+    a = srv.submit("gauss", 2, small, inputs.nldiff_u0(32), 5e-3, 2)
+    b = srv.submit("gauss", 3, big, inputs.nldiff_u0(256), 5e-3, 2)
+    c = srv.submit("radau", 2, small, inputs.nldiff_u0(32), 5e-3, 2)
+    srv.run_until_idle()
+    assert srv.info(a)["state"] == "done" and srv.info(c)["state"] == "done"
+    ib = srv.info(b)
+    assert ib["state"] == "failed" and ib["status"] == "IRK_E_NOMEM"
+    srv.close()
