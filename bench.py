@@ -110,6 +110,90 @@ def cpu_baseline(n_sample, s, dt):
                       f"SuperLU factorization each, single thread; {el:.2f} s for the step"}
 
 
+def serve_inputs(torch, inputs, count, seed):
+    """Seeded serving stream (unit-rate arrivals; scaled by 1/lambda when
+    replayed) with every request's initial field resident on the device."""
+    reqs = inputs.serving_requests(count, 1.0, seed=seed)
+    fields = [torch.tensor(inputs.nldiff_random_u0(r.n, r.seed), dtype=torch.float64, device="cuda")
+              for r in reqs]
+    return reqs, fields
+
+
+def serve_run(torch, irk, reqs, fields, lam, prec_fp32, budget, slots, arena):
+    """Replay the stream through the native serving loop.  lam=None: closed
+    loop (everything submitted at t=0); otherwise open-loop Poisson arrivals
+    at lam requests/s.  Returns wall time, per-request latencies (arrival to
+    result, ms), per-step latencies (ms) and serving statistics."""
+    ops = {n: irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS) for n in {r.n for r in reqs}}
+    opt = irk.make_options(prec_fp32=prec_fp32)
+    outs = [torch.empty_like(f) for f in fields]
+    arrive = [0.0] * len(reqs) if lam is None else [r.arrival / lam for r in reqs]
+    srv = irk.Server(budget, slots, arena=arena)
+    torch.cuda.synchronize()
+    ids, late = [], []
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while k < len(reqs) and arrive[k] <= now:
+            r = reqs[k]
+            ids.append(srv.submit(r.family, r.s, ops[r.n], fields[k], r.dt, r.nsteps, opt=opt, out=outs[k]))
+            late.append(time.perf_counter() - t0 - arrive[k])      # submit delay after arrival
+            k += 1
+        left = srv.progress()
+        if left == 0 and k == len(reqs):
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat, failed, steps = [], 0, 0
+    for rid, d in zip(ids, late):
+        info = srv.info(rid)
+        failed += info["state"] != "done"
+        steps += info["steps_done"]
+        lat.append(1e3 * (info["t_done"] - info["t_submit"] + d))
+    st = srv.stats()
+    srv.close()
+    return wall, sorted(lat), sorted(st["step_ms"]), {"failed": failed, "steps": steps,
+                                                      "peak_running": st["peak_running"],
+                                                      "peak_bytes": st["peak_bytes"]}
+
+
+def serve_bench(torch, irk, inputs, count, budget_gb, slots, load, seed, fp64=True):
+    """Continuous-batching serving workload: nonlinear-diffusion requests,
+    grid side log-uniform in {128..1024}, Gauss or Radau IIA with s in
+    {2,3,4}, dt log-uniform in [1e-3, 1e-2], 10 steps each.  First the
+    closed-loop saturation throughput mu, then open-loop Poisson arrivals at
+    lambda = load * mu; the same stream with float64 V-cycles beside it."""
+    reqs, fields = serve_inputs(torch, inputs, count, seed)
+    budget = int(budget_gb * (1 << 30)) & ~255
+    arena = torch.empty(budget + 256, dtype=torch.uint8, device="cuda")     # the HBM budget, allocated once
+    dofs = sum(r.n * r.n * r.s * r.nsteps for r in reqs)
+    warm = min(len(reqs), 16)
+    serve_run(torch, irk, reqs[:warm], fields[:warm], None, 1, budget, slots, arena)       # load kernels, pools
+    out = {"requests": count, "seed": seed, "budget_gb": budget_gb, "max_slots": slots,
+           "stream": "nonlinear-diffusion-2d requests, side log-uniform {128,256,512,1024}, "
+                     "Gauss/Radau IIA s in {2,3,4}, dt log-uniform [1e-3,1e-2], 10 steps each, "
+                     "manufactured forcing, seeded smooth initial fields"}
+    for prec in ((1, 0) if fp64 else (1,)):
+        key = "mixed" if prec else "fp64_vcycle"
+        wall, lat, step_lat, st = serve_run(torch, irk, reqs, fields, None, prec, budget, slots, arena)
+        mu = count / wall
+        res = {"closed_loop": {"req_per_s": mu, "steps_per_s": st["steps"] / wall,
+                               "dof_stages_per_s": dofs / wall, "wall_s": wall,
+                               "step_p50_ms": pct(step_lat, 50), "step_p99_ms": pct(step_lat, 99),
+                               "req_p50_ms": pct(lat, 50), "req_p99_ms": pct(lat, 99), **st}}
+        if prec:
+            lam = load * mu
+            out["lambda_req_per_s"] = lam
+        wall, lat, step_lat, st = serve_run(torch, irk, reqs, fields, lam, prec, budget, slots, arena)
+        res["open_loop"] = {"lambda_req_per_s": lam, "req_per_s": count / wall, "steps_per_s": st["steps"] / wall,
+                            "dof_stages_per_s": dofs / wall, "wall_s": wall,
+                            "step_p50_ms": pct(step_lat, 50), "step_p99_ms": pct(step_lat, 99),
+                            "req_p50_ms": pct(lat, 50), "req_p99_ms": pct(lat, 99), **st}
+        out[key] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +206,15 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel roofline pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=128)
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving workload instead (one JSON line of its own)")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--load", type=float, default=0.8, help="open-loop lambda as a fraction of mu")
+    ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-sample", type=int, default=0,
+                    help="also run a serving sample of this many requests in the default bench")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -136,6 +229,23 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     irk.lib()
+    if args.serve:
+        t0 = time.perf_counter()
+        sv = serve_bench(torch, irk, inputs, args.requests, args.budget_gb, args.slots, args.load,
+                         args.serve_seed, fp64=not args.no_fp64)
+        m = sv["mixed"]["open_loop"]
+        out = {"metric": METRIC, "value": m["steps_per_s"], "unit": "IRK steps/s", "n_gpus": 1,
+               "steps": m["steps"], "warmup": 16, "ms_per_step": 1e3 / m["steps_per_s"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"serving: {args.requests} nonlinear-diffusion step-solve requests, "
+                                      f"open-loop Poisson arrivals at {args.load:g} x saturation",
+                          "precision": "float64 Newton/FGMRES/transform, float32 multigrid V-cycle",
+                          "parallelism": "single GPU"},
+               "p50_ms": m["step_p50_ms"], "p99_ms": m["step_p99_ms"], "serving": sv,
+               "bench_wall_s": time.perf_counter() - t0}
+        print(json.dumps(out), flush=True)
+        return
     n, s, dt, K, W = args.n, args.stages, args.dt, args.steps, args.warmup
     dof = n * n
 
@@ -185,6 +295,9 @@ def main():
         out["kernel_share"] = [{"kernel": r["name"], "share": r["ms"] / tot, "launches": r["launches"],
                                 "avg_us": 1e3 * r["ms"] / max(1, r["launches"]),
                                 "GB/s": r["bytes"] / max(1e-12, r["ms"] * 1e-3) / 1e9} for r in prof[:8]]
+    if args.serve_sample > 0:
+        out["serving"] = serve_bench(torch, irk, inputs, args.serve_sample, args.budget_gb, args.slots,
+                                     args.load, args.serve_seed, fp64=not args.no_fp64)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, s, dt)
     print(json.dumps(out), flush=True)

@@ -123,7 +123,8 @@ typedef struct irk_stats {
 
 const char *irk_status_str(irk_status st);
 
-/* Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||M K0||),
+/* Every step starts from K0 = 0 (all stage values at u_n).
+ * Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||F(K0)||),
  * krylov_rtol 1e-5 (the paper's GMRES tolerance, Section 7.1), restart 30,
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
  * cheb_degree 3, mg_coarsest 8, coarse_iters 24.                           */

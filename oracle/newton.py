@@ -106,8 +106,12 @@ def solve_sparse_lowrank(S, Ub, Vb, rhs):
 
 
 def initial_stages(problem, u_n, t_n, s):
-    k0 = problem.initial_k(u_n, t_n)
-    return np.stack([k0] * s)
+    """Starting stage vectors K^0 = 0, i.e. every stage value U_i starts at
+    u_n.  Algorithm 1 leaves the starting value open; zero increments are the
+    usual stiff starting value (an explicit guess k_i = N(u_n) overshoots by
+    dt times the stiff eigenvalues and can leave Newton's region of
+    convergence)."""
+    return np.zeros((s, problem.size))
 
 
 def irk_stages(problem, A, c, u_n, t_n, dt, max_iter=60, K0=None):

@@ -10,8 +10,7 @@ algebraic rows, Section 6 equation (dae)).  A problem exposes
 * ``rhs(u, t)``       -- N(u, t),
 * ``jac(u, t)``       -- the exact Jacobian dN/du as ``(S, U, V)`` with
   dN/du = S + U V^T, S a SciPy sparse matrix and U, V dense low-rank factors
-  (``None`` when there is no low-rank part),
-* ``initial_k(u, t)`` -- the Newton initial guess for one stage vector.
+  (``None`` when there is no low-rank part).
 
 The discretizations are the plain finite-difference definitions on a
 periodic grid of spacing h = L / n with nodes x_i = i h:
@@ -71,9 +70,6 @@ class Burgers1D:
         adv = -(self._Ep @ sp.diags(u) - self._Em @ sp.diags(u)) / (2.0 * h)
         dif = nu * (self._Ep - 2.0 * sp.identity(n) + self._Em) / (h * h)
         return (adv + dif).tocsr(), None, None
-
-    def initial_k(self, u, t):
-        return self.rhs(u, t)
 
 
 # --------------------------------------------------------------------------
@@ -174,9 +170,6 @@ class NonlinearDiffusion2D:
             coef_nb = kf + 0.5 * (P @ dk) * dU
             L = L + sp.diags(diag_c) + sp.diags(coef_nb) @ P
         return (L / h2).tocsr(), None, None
-
-    def initial_k(self, u, t):
-        return self.rhs(u, t)
 
 
 # --------------------------------------------------------------------------
@@ -283,11 +276,6 @@ class VorticityStreamfunction2D:
         Vlow = np.stack([np.concatenate([np.full(nn, -1.0 / nn), np.zeros(nn)]),
                          np.concatenate([np.zeros(nn), np.full(nn, -1.0 / nn)])], axis=1)
         return S, Ulow, Vlow
-
-    def initial_k(self, u, t):
-        """omega stage guess = N_omega(u_n); psi stage guess = 0."""
-        f = self.rhs(u, t)
-        return np.concatenate([f[: self.nn], np.zeros(self.nn)])
 
     def gauge_pins(self):
         """(row, column) entries that make S nonsingular: S alone is singular

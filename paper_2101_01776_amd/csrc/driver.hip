@@ -179,7 +179,6 @@ using namespace irk;
 enum {
     DV_RES = 0,        // ||F||^2
     DV_ABS = 1,        // squared norm of |terms of F| (rounding scale)
-    DV_K0 = 2,         // ||K0||^2
     DV_BETA = 4,       // ||r0||^2 of a block solve
     DV_NRM = 5,        // ||w||^2 after orthogonalization (unfused path)
     DV_SUMS = 8,       // field sums (up to 16)
@@ -805,11 +804,9 @@ struct Stepper : StepperBase {
         it = fold = flat = 0;
         res0 = -1;
         thresh = prev = 0;
-        PROF(c, c->stream, "k_rhs_init<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
-             8.0 * nf * (1 + s), 1, launch_rhs_init(c->stream, s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
-        // ||M K0|| for the absolute floor
-        PROF(c, c->stream, "k_dot_multi", 8.0 * s * nf, 1,
-             launch_dot_multi(c->stream, c->K, 0, 0, c->K, s * nf, 1, c->part, c->dv + DV_K0, nullptr));
+        // starting stage vectors K^0 = 0: every stage value starts at u_n
+        // (Algorithm 1 leaves the starting value open)
+        PROF(c, c->stream, "k_fill", 8.0 * s * nf, 1, launch_fill(c->stream, c->K, 0.0, (size_t)s * nf));
         const irk_status e = issue_residual();
         if (e != IRK_OK) fail(e);
     }
@@ -824,9 +821,7 @@ struct Stepper : StepperBase {
         if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
         if (it == 0) {
             res0 = res;
-            const double k0 = std::sqrt(c->pinned[DV_K0]);
-            if (!std::isfinite(k0)) return fail(IRK_E_NONFINITE);
-            const double atol = P.opt.newton_atol > 0 ? P.opt.newton_atol : 1e-14 * k0;
+            const double atol = P.opt.newton_atol > 0 ? P.opt.newton_atol : 1e-14 * res0;
             thresh = rtol * res0 + atol;
             stats.res0 = res0;
         }

@@ -48,12 +48,16 @@ def nldiff_random_u0(n: int, seed: int, amplitude: float = 1.0) -> np.ndarray:
     should not coincide with the manufactured solution."""
     rng = np.random.Generator(np.random.PCG64(seed))
     g = np.arange(n) / n
-    X, Y = np.meshgrid(g, g)
     u = np.zeros((n, n))
     for _ in range(6):
         kx, ky = rng.integers(1, 4, size=2)
         ph = rng.uniform(0.0, 2.0 * np.pi, size=2)
-        u += rng.uniform(-1.0, 1.0) * np.sin(2 * np.pi * kx * X + ph[0]) * np.cos(2 * np.pi * ky * Y + ph[1])
+        a = rng.uniform(-1.0, 1.0)
+        # separable mode a sin(2 pi kx x + ph0) cos(2 pi ky y + ph1), evaluated
+        # from 1-D factors (same values as the 2-D evaluation, O(n) sin/cos)
+        sx = np.sin(2 * np.pi * kx * g + ph[0])
+        cy = np.cos(2 * np.pi * ky * g + ph[1])
+        u += (a * sx)[None, :] * cy[:, None]
     return amplitude * u / max(1.0, float(np.abs(u).max()))
 
 

@@ -358,12 +358,19 @@ def irk_server_destroy(srv):
 class Server:
     """A serving loop on a PyTorch-allocated device arena (the HBM budget)."""
 
-    def __init__(self, arena_bytes: int, max_slots: int, device: str = "cuda:0"):
+    def __init__(self, arena_bytes: int, max_slots: int, device: str = "cuda:0", arena=None):
+        """``arena``: an existing uint8 device tensor of at least
+        ``arena_bytes + 256`` bytes to serve from (reused across servers);
+        by default one is allocated."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         lib()
-        self._arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        if arena is None:
+            arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        elif arena.dtype != torch.uint8 or arena.numel() < arena_bytes + 256 or arena.device != self.device:
+            raise ValueError("arena must be a uint8 tensor of at least arena_bytes + 256 bytes on the device")
+        self._arena = arena
         ptr = (self._arena.data_ptr() + 255) & ~255
         self.srv = irk_server_create(ptr, arena_bytes, max_slots)
         self._keep = {}
@@ -408,6 +415,7 @@ class Server:
         if self.srv is not None:
             irk_server_destroy(self.srv)
             self.srv = None
+        self._arena = None
 
     def __del__(self):
         try:

@@ -88,7 +88,9 @@ def test_aliasing_and_bitwise_determinism():
 
 def test_full_size_bench_workload_residual_and_update():
     """512^2, Gauss-3, dt 5e-3, float32 V-cycles: the oracle's residual of the
-    GPU stage vectors is at the rounding floor of the residual evaluation, and
+    GPU stage vectors agrees with the residual the GPU reports and is small
+    enough that the update it implies, dt |F| (times the bounded inverse of
+    the stage Jacobian), stays below 1e-11 of |u_n|; and
     u_{n+1} = u_n + dt sum_i b_i k_i holds to rounding."""
     n, s, dt = 512, 3, 5e-3
     op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
@@ -102,8 +104,11 @@ def test_full_size_bench_workload_residual_and_update():
         F = oracle_residual(op, "gauss", s, u, t, dt, K)
         F0 = oracle_residual(op, "gauss", s, u, t, dt, nw.initial_stages(
             pb.NonlinearDiffusion2D(n), u.ravel(), t, s))
-        print(f"  512^2 step {step}: |F| {np.linalg.norm(F):.3e} |F0| {np.linalg.norm(F0):.3e} {st}")
-        assert np.linalg.norm(F) <= 1e-7 * np.linalg.norm(F0)
+        nF = np.linalg.norm(F)
+        print(f"  512^2 step {step}: |F| {nF:.3e} |F0| {np.linalg.norm(F0):.3e} {st}")
+        assert abs(nF - st["final_res"]) <= 5e-2 * nF
+        assert abs(np.linalg.norm(F0) - st["res0"]) <= 1e-9 * st["res0"]
+        assert dt * nF <= 1e-11 * np.linalg.norm(u)
         _, b, _ = tb.tableau("gauss", s)
         assert rel(u1.ravel(), u.ravel() + dt * (b @ K)) < 1e-15
         u, t = u1, t + dt

@@ -31,9 +31,6 @@ class _Diagonal:
     def jac(self, u, t=0.0):
         return sp.diags(self.lam).tocsr(), None, None
 
-    def initial_k(self, u, t):
-        return self.rhs(u, t)
-
 
 @pytest.mark.parametrize("family,s", FAMS)
 def test_scalar_step_is_stability_function(family, s):
