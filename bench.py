@@ -35,10 +35,34 @@ METRIC = "IRK steps/sec & DOF·stages/s vs plain FP64 on same GPU; p50/p99 step 
 HBM_PEAK_GBS = 8000.0
 
 
-def run_job(torch, irk, inputs, n, s, dt, steps, warmup, prec_fp32, profile=False):
-    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
-    solver = irk.Solver("gauss", s, op, irk.make_options(prec_fp32=prec_fp32))
-    u0 = torch.tensor(inputs.nldiff_u0(n), dtype=torch.float64, device="cuda")
+WORKLOADS = {
+    # name: (problem, grid side, family, stages, dt, steps, nu)
+    "nldiff512-gauss3": ("nldiff", 512, "gauss", 3, 5e-3, 50, 0.0),
+    "vsf1024-radau3": ("vsf", 1024, "radau", 3, 2e-3, 20, 1e-3),
+    "nldiff1024-gauss5": ("nldiff", 1024, "gauss", 5, 1e-2, 20, 0.0),
+}
+
+
+def describe(problem, n, family, s, dt, steps, nu):
+    fam = "Gauss" if family == "gauss" else "Radau IIA"
+    if problem == "vsf":
+        return (f"vorticity-streamfunction 2-D DAE periodic {n}x{n}, nu={nu:g}, 32 seeded Gaussian vortices, "
+                f"{fam} s={s}, dt={dt:g}, {steps} steps from t=0")
+    return (f"nonlinear-diffusion-2d periodic {n}x{n}, {fam} s={s}, dt={dt:g}, {steps} steps from t=0, "
+            f"manufactured forcing")
+
+
+def make_problem(irk, inputs, problem, n, nu):
+    if problem == "vsf":
+        return irk.make_operator(irk.OP_VSF_2D, n, nu=nu), inputs.vsf_state0(n, 0, 32), 2 * n * n
+    return irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS), inputs.nldiff_u0(n), n * n
+
+
+def run_job(torch, irk, inputs, wl, steps, warmup, prec_fp32, profile=False):
+    problem, n, family, s, dt, _, nu = wl
+    op, u_init, _ = make_problem(irk, inputs, problem, n, nu)
+    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=prec_fp32))
+    u0 = torch.tensor(u_init, dtype=torch.float64, device="cuda")
     a = u0.clone()
     b = torch.empty_like(a)
     t = 0.0
@@ -81,7 +105,7 @@ def pct(sorted_vals, q):
     return sorted_vals[k]
 
 
-def cpu_baseline(n_sample, s, dt):
+def cpu_baseline(wl, n_sample):
     """The oracle as it stands (full Newton, SuperLU) on one step of the same
     workload at a reduced grid, single-threaded."""
     try:
@@ -92,22 +116,28 @@ def cpu_baseline(n_sample, s, dt):
     from oracle import problems as pb
     from oracle import tableau as tb
     from paper_2101_01776_amd import inputs
-    A, b, c = tb.tableau("gauss", s)
-    prob = pb.NonlinearDiffusion2D(n_sample, forcing="continuous")
-    u0 = inputs.nldiff_u0(n_sample).ravel()
+    problem, _, family, s, dt, _, nu = wl
+    A, b, c = tb.tableau(family, s)
+    if problem == "vsf":
+        prob = pb.VorticityStreamfunction2D(n_sample, nu=nu)
+        u0 = inputs.vsf_state0(n_sample, 0, 32).ravel()
+        dof = 2 * n_sample * n_sample
+    else:
+        prob = pb.NonlinearDiffusion2D(n_sample, forcing="continuous")
+        u0 = inputs.nldiff_u0(n_sample).ravel()
+        dof = n_sample * n_sample
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         t0 = time.perf_counter()
         _, _, info = nw.irk_step(prob, A, b, c, u0, 0.0, dt)
         el = time.perf_counter() - t0
     finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
-    dof = n_sample * n_sample
+        if ctx is not None and hasattr(ctx, "unregister"):
+            ctx.unregister()
     return {"value": dof * s / el, "unit": "DOF*stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"one Gauss-{s} step (dt={dt}) of the same nonlinear-diffusion workload on a "
-                      f"{n_sample}x{n_sample} grid: full Newton ({info.newton_its} iterations) with a "
-                      f"SuperLU factorization each, single thread; {el:.2f} s for the step"}
+            "sample": f"one {family} s={s} step (dt={dt:g}) of the same workload on a {n_sample}x{n_sample} "
+                      f"grid: full Newton ({info.newton_its} iterations) with a SuperLU factorization each, "
+                      f"single thread; {el:.2f} s for the step"}
 
 
 def serve_inputs(torch, inputs, count, seed):
@@ -197,15 +227,21 @@ def serve_bench(torch, irk, inputs, count, budget_gb, slots, load, seed, fp64=Tr
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's job)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=512, help="grid side (default 512)")
-    ap.add_argument("--stages", type=int, default=3)
-    ap.add_argument("--dt", type=float, default=5e-3)
+    ap.add_argument("--workload", default="nldiff512-gauss3", choices=sorted(WORKLOADS),
+                    help="nldiff512-gauss3 (default): 2-D nonlinear diffusion 512^2, Gauss-3, dt 5e-3, "
+                         "50 steps; vsf1024-radau3: vorticity-streamfunction DAE 1024^2, Radau IIA-3, "
+                         "dt 2e-3, 20 steps; nldiff1024-gauss5: nonlinear diffusion 1024^2, Gauss-5, "
+                         "dt 1e-2, 20 steps")
+    ap.add_argument("--n", type=int, default=None, help="override the grid side")
+    ap.add_argument("--stages", type=int, default=None, help="override s")
+    ap.add_argument("--dt", type=float, default=None, help="override dt")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64-V-cycle comparison run")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel roofline pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=128)
+    ap.add_argument("--cpu-sample-n", type=int, default=None,
+                    help="grid side of the oracle sample (default 128; 32 for the DAE, 96 for Gauss-5)")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving workload instead (one JSON line of its own)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -246,10 +282,16 @@ def main():
                "bench_wall_s": time.perf_counter() - t0}
         print(json.dumps(out), flush=True)
         return
-    n, s, dt, K, W = args.n, args.stages, args.dt, args.steps, args.warmup
-    dof = n * n
+    problem, n, family, s, dt, K, nu = WORKLOADS[args.workload]
+    n = args.n or n
+    s = args.stages or s
+    dt = args.dt or dt
+    K = args.steps or K
+    W = args.warmup
+    wl = (problem, n, family, s, dt, K, nu)
+    dof = n * n * (2 if problem == "vsf" else 1)
 
-    wall, lat, stats, _, _ = run_job(torch, irk, inputs, n, s, dt, K, W, prec_fp32=1)
+    wall, lat, stats, _, _ = run_job(torch, irk, inputs, wl, K, W, prec_fp32=1)
     value = dof * s * K / wall
     out = {
         "metric": METRIC,
@@ -264,9 +306,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"nonlinear-diffusion-2d periodic {n}x{n}, Gauss s={s}, dt={dt}, "
-                               f"{K} steps from t=0, manufactured forcing",
-                   "grid": n, "stages": s, "dt": dt,
+        "config": {"workload": describe(problem, n, family, s, dt, K, nu),
+                   "grid": n, "family": family, "stages": s, "dt": dt, "dof_per_stage": dof,
                    "precision": "float64 Newton/FGMRES/transform, float32 multigrid V-cycle",
                    "parallelism": "single GPU"},
         "steps_per_s": K / wall,
@@ -277,13 +318,14 @@ def main():
         "prec_applications_per_step": sum(x["prec_applications"] for x in stats) / K,
     }
     if not args.no_fp64:
-        w64, lat64, st64, _, _ = run_job(torch, irk, inputs, n, s, dt, K, W, prec_fp32=0)
+        w64, lat64, st64, _, _ = run_job(torch, irk, inputs, wl, K, W, prec_fp32=0)
         out["fp64_vcycle"] = {"value": dof * s * K / w64, "ms_per_step": 1e3 * w64 / K,
                               "steps_per_s": K / w64, "p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99),
                               "krylov_its_per_step": sum(x["krylov_its"] for x in st64) / K}
         out["mixed_speedup_vs_fp64"] = w64 / wall
     if not args.no_profile:
-        _, _, _, prof, _ = run_job(torch, irk, inputs, n, s, dt, min(K, 10), 1, prec_fp32=1, profile=True)
+        kp = min(K, 10)
+        wp, _, _, prof, _ = run_job(torch, irk, inputs, wl, kp, 1, prec_fp32=1, profile=True)
         prof.sort(key=lambda r: -r["ms"])
         top = prof[0]
         achieved = top["bytes"] / (top["ms"] * 1e-3) / 1e9
@@ -292,6 +334,11 @@ def main():
                            "launches": top["launches"], "avg_us": 1e3 * top["ms"] / max(1, top["launches"]),
                            "avg_bytes": top["bytes"] / max(1, top["launches"])}
         tot = sum(r["ms"] for r in prof)
+        step_bytes = sum(r["bytes"] for r in prof) / kp
+        out["step_traffic"] = {"algorithmic_MB_per_step": step_bytes / 1e6,
+                               "GB_per_s_over_step": step_bytes / (wall / K) / 1e9,
+                               "frac_of_peak": step_bytes / (wall / K) / 1e9 / HBM_PEAK_GBS,
+                               "kernel_ms_per_step": tot / kp}
         out["kernel_share"] = [{"kernel": r["name"], "share": r["ms"] / tot, "launches": r["launches"],
                                 "avg_us": 1e3 * r["ms"] / max(1, r["launches"]),
                                 "GB/s": r["bytes"] / max(1e-12, r["ms"] * 1e-3) / 1e9} for r in prof[:8]]
@@ -299,7 +346,8 @@ def main():
         out["serving"] = serve_bench(torch, irk, inputs, args.serve_sample, args.budget_gb, args.slots,
                                      args.load, args.serve_seed, fp64=not args.no_fp64)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, s, dt)
+        ns = args.cpu_sample_n or {"vsf1024-radau3": 32, "nldiff1024-gauss5": 96}.get(args.workload, 128)
+        out["cpu_baseline"] = cpu_baseline(wl, ns)
     print(json.dumps(out), flush=True)
 
 

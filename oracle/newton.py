@@ -105,19 +105,24 @@ def solve_sparse_lowrank(S, Ub, Vb, rhs):
     return x - SU @ np.linalg.solve(small, Vb.T @ x)
 
 
-def initial_stages(problem, u_n, t_n, s):
-    """Starting stage vectors K^0 = 0, i.e. every stage value U_i starts at
-    u_n.  Algorithm 1 leaves the starting value open; zero increments are the
-    usual stiff starting value (an explicit guess k_i = N(u_n) overshoots by
-    dt times the stiff eigenvalues and can leave Newton's region of
-    convergence)."""
-    return np.zeros((s, problem.size))
+def initial_stages(problem, A, c, u_n, t_n, dt):
+    """Starting stage vectors K^0.  Algorithm 1 leaves them open; of the two
+    natural candidates -- K = 0 (every stage value U_i at u_n, the usual stiff
+    start) and the explicit k_i = M^{-1} N(u_n, t_n) on differential rows, 0
+    on algebraic rows (good for smooth, non-stiff motion) -- take the one with
+    the smaller stage residual of equation (stages), zero on ties."""
+    s = len(c)
+    zero = np.zeros((s, problem.size))
+    explicit = np.stack([problem.rhs(u_n, t_n) * problem.mass] * s)
+    r_zero = np.linalg.norm(stage_residual(problem, A, c, u_n, t_n, dt, zero))
+    r_expl = np.linalg.norm(stage_residual(problem, A, c, u_n, t_n, dt, explicit))
+    return explicit if r_expl < r_zero else zero
 
 
 def irk_stages(problem, A, c, u_n, t_n, dt, max_iter=60, K0=None):
     """Stage vectors K (shape (s, N)) solving equation (stages) to roundoff."""
     s = len(c)
-    K = initial_stages(problem, u_n, t_n, s) if K0 is None else K0.copy()
+    K = initial_stages(problem, A, c, u_n, t_n, dt) if K0 is None else K0.copy()
     corr, res = [], []
     prev = np.inf
     for it in range(1, max_iter + 1):

@@ -121,13 +121,20 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     if (!level_geometry(o, P->opt.mg_coarsest, &P->lg)) return IRK_E_ARG;
     P->tsz = P->opt.prec_fp32 ? sizeof(float) : sizeof(double);
     // levels from l0 down run inside one work-group with everything in LDS
-    // (at most 60 KiB and 4096 points on its finest level)
+    // (at most 64 KiB, 4096 points on its finest level and IRK_MAX_SUB_LEVELS
+    // levels)
     P->l0 = P->lg.nlev - 1;
-    for (int l = 0; l < P->lg.nlev; ++l) {
-        size_t sum = 0;
-        for (int q = l; q < P->lg.nlev; ++q) sum += (size_t)P->lg.nx[q] * P->lg.ny[q];
-        const size_t top = (size_t)P->lg.nx[l] * P->lg.ny[l];
-        if ((3 * sum + 2 * top) * P->tsz <= 60 * 1024 && top <= 4096) { P->l0 = l; break; }
+    {
+        const int opk = o.kind == IRK_OP_NLDIFF_2D ? MG_NLDIFF : (o.kind == IRK_OP_BURGERS_1D ? MG_BURGERS : MG_VSF_OMEGA);
+        for (int l = 0; l < P->lg.nlev; ++l) {
+            const size_t top = (size_t)P->lg.nx[l] * P->lg.ny[l];
+            const int nl = P->lg.nlev - l;
+            if (top <= 4096 && nl <= IRK_MAX_SUB_LEVELS &&
+                mg_subcycle_lds_bytes(opk, nl, P->lg.nx + l, P->lg.ny + l, P->tsz) <= 64 * 1024) {
+                P->l0 = l;
+                break;
+            }
+        }
     }
 
     // linearization stage of every transformed row (Newton-like (0) or (1))
@@ -755,6 +762,10 @@ struct Stepper : StepperBase {
     StageCoefs C;
     int it = 0, fold = 0, flat = 0, active = 0;
     double res0 = -1, thresh = 0, prev = 0;
+    // starting stage vectors: K = 0 is evaluated first, then the explicit
+    // k_i = N(u_n, t_n); the one with the smaller residual starts Newton
+    enum Start { START_ZERO, START_EXPLICIT, START_CHOSEN } start = START_CHOSEN;
+    double res_zero = 0;
     Fgmres<T> fg[IRK_MAX_STAGES];
     bool lane_done[IRK_MAX_STAGES];
 
@@ -804,8 +815,9 @@ struct Stepper : StepperBase {
         it = fold = flat = 0;
         res0 = -1;
         thresh = prev = 0;
-        // starting stage vectors K^0 = 0: every stage value starts at u_n
-        // (Algorithm 1 leaves the starting value open)
+        // starting stage vectors (Algorithm 1 leaves them open): first K = 0,
+        // every stage value at u_n
+        start = START_ZERO;
         PROF(c, c->stream, "k_fill", 8.0 * s * nf, 1, launch_fill(c->stream, c->K, 0.0, (size_t)s * nf));
         const irk_status e = issue_residual();
         if (e != IRK_OK) fail(e);
@@ -818,6 +830,27 @@ struct Stepper : StepperBase {
         // the residual cannot be resolved below the rounding error of its own
         // evaluation: 64 eps times the norm of the magnitudes of its terms
         const double floor_res = 64.0 * 2.220446049250313e-16 * std::sqrt(c->pinned[DV_ABS]);
+        if (start == START_ZERO) {
+            // K = 0 evaluated; now the explicit candidate k_i = N(u_n, t_n)
+            if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
+            res_zero = res;
+            start = START_EXPLICIT;
+            PROF(c, c->stream, "k_rhs_init<" + std::to_string(P.s) + "," + std::to_string(P.op.kind) + ">",
+                 8.0 * P.nf * (1 + P.s), 1,
+                 launch_rhs_init(c->stream, P.s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
+            const irk_status e = issue_residual();
+            return e != IRK_OK ? fail(e) : false;
+        }
+        if (start == START_EXPLICIT) {
+            start = START_CHOSEN;
+            if (!(res < res_zero)) {
+                // zero wins (ties included): back to K = 0
+                PROF(c, c->stream, "k_fill", 8.0 * P.s * P.nf, 1,
+                     launch_fill(c->stream, c->K, 0.0, (size_t)P.s * P.nf));
+                const irk_status e = issue_residual();
+                return e != IRK_OK ? fail(e) : false;
+            }
+        }
         if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
         if (it == 0) {
             res0 = res;

@@ -3,6 +3,7 @@
 //   stage_prep      k <- k + (T Lambda (x) I) y ;  U_i = u_n + dt sum_j a_ij k_j
 //   residual        F_i = M k_i - N(U_i, t_n + c_i dt) ; fhat = (T^{-1} (x) I) F ;
 //                   ||F||^2 (Algorithm 1, equations (stages), (dae_stage))
+//   rhs_init        k_i = N(u_n, t_n) (explicit starting candidate)
 //   final_update    u_{n+1} = u_n + dt sum_i b_i k_i (equation (update))
 //   block_matvec    w = D_b x for a 1x1 or 2x2 eigen-block (equation (diag_blocks))
 //   dot / axpy      Arnoldi (classical Gram-Schmidt, two passes)
@@ -254,6 +255,41 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
     tot[0] = block_sum(sumsq, sh);
     tot[1] = block_sum(abssq, sh);
     finish_partials(tot, 2, partials, out, counter);
+}
+
+// k_i <- N(u_n, t_n) on differential rows, 0 on algebraic rows (explicit candidate for the
+// starting stage vectors)
+template <int S, int OP>
+__global__ void __launch_bounds__(IRK_WG) k_rhs_init(DeviceProblem P, const double *__restrict__ un,
+                                                     double *__restrict__ K, double st_n, double ct_n) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double N;
+        if constexpr (OP == IRK_OP_NLDIFF_2D) {
+            const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
+            N = nldiff_flux5(un[p], un[j * nx + ip], un[j * nx + im], un[jp * nx + i], un[jm * nx + i], inv_h2);
+            if (P.forcing != IRK_FORCING_NONE) N += mms_forcing(P, i, j, st_n, ct_n);
+        } else if constexpr (OP == IRK_OP_BURGERS_1D) {
+            const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
+            N = -(un[ip] * un[ip] - un[im] * un[im]) / (4.0 * h) + P.g.nu * (un[ip] - 2.0 * un[p] + un[im]) * inv_h2;
+        } else {
+            double w[3][3], ps[3][3];
+            load3x3(un, i, j, nx, ny, w);
+            load3x3(un + npts, i, j, nx, ny, ps);
+            N = arakawa9(ps, w, inv_h2 / 12.0) + P.g.nu * lap5(w, inv_h2);
+        }
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            K[st * nf + p] = N;
+            if constexpr (NV == 2) K[st * nf + npts + p] = 0.0;
+        }
+    }
 }
 
 template <int S>
@@ -562,6 +598,26 @@ void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double
         case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
         case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
         case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+    }
+}
+
+template <int S>
+static void rhs_init_s(hipStream_t st, const DeviceProblem &P, const double *un, double *K, double s_n, double c_n) {
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const unsigned g = grid_for(npts);
+    if (P.kind == IRK_OP_NLDIFF_2D) k_rhs_init<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+    else if (P.kind == IRK_OP_BURGERS_1D) k_rhs_init<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+    else k_rhs_init<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, un, K, s_n, c_n);
+}
+
+void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
+                     double cos_tn) {
+    switch (s) {
+        case 1: rhs_init_s<1>(st, P, un, K, sin_tn, cos_tn); break;
+        case 2: rhs_init_s<2>(st, P, un, K, sin_tn, cos_tn); break;
+        case 3: rhs_init_s<3>(st, P, un, K, sin_tn, cos_tn); break;
+        case 4: rhs_init_s<4>(st, P, un, K, sin_tn, cos_tn); break;
+        case 5: rhs_init_s<5>(st, P, un, K, sin_tn, cos_tn); break;
     }
 }
 

@@ -9,6 +9,7 @@ namespace irk {
 
 #define IRK_MAX_CHEB 8
 #define IRK_MAX_COARSE_ITERS 64
+#define IRK_MAX_SUB_LEVELS 8       // levels of the one-work-group sub-cycle
 
 // One level of a V-cycle: geometry, operator parameters, buffers.
 template <class T>
@@ -69,7 +70,7 @@ template <class T>
 void launch_mg_up(hipStream_t st, int opk, const MgLevelArgs<T> &a, const MgOut &out, int deg);
 template <class T>
 void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const MgIn &in, const MgOut &out);
-template <class T>
-size_t mg_subcycle_lds_bytes(const MgSubArgs<T> &s);
+// LDS bytes of the one-work-group sub-cycle over levels nx[0..nlev-1]
+size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, size_t tsz);
 
 }  // namespace irk

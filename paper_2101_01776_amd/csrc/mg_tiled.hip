@@ -17,6 +17,14 @@
 // The finest level reads its right-hand side directly from the float64
 // Krylov vector(s) and writes the float64 preconditioned vector, so the
 // precision casts cost no launches.
+//
+// Each kernel first turns the level's linearization field into the explicit
+// stencil of A on its LDS window, scaled by the Jacobi diagonal:
+// a~_q = A_q / A_c for the NS off-diagonal neighbours q, A_c, and
+// b~ = b / A_c.  A Chebyshev step is then d <- cd d + cr (b~ - x - sum_q
+// a~_q x_q), x <- x + d: a few fused multiply-adds per point instead of
+// re-deriving the nonlinear face coefficients and dividing by the diagonal in
+// every sweep (the sweeps are bound by vector-ALU issue, not by memory).
 #include <hip/hip_runtime.h>
 
 #include "irk_internal.h"
@@ -26,10 +34,8 @@
 
 namespace irk {
 
-__device__ __forceinline__ int wrap_any(int i, int n) {
-    i %= n;
-    return i < 0 ? i + n : i;
-}
+// index wrap for i in [-n, 2n)
+__device__ __forceinline__ int wrap2(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ __forceinline__ int xcd_tile() {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -37,53 +43,102 @@ __device__ __forceinline__ int xcd_tile() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Level operator on an LDS window: neighbours at +-1 (x) and +-W (y); the
-// window is already periodically unwrapped, so no index wrapping.
-template <class T, int OPK, bool HAS_X>
-__device__ __forceinline__ void lds_op(const T *cf, const T *x, int c, int W, T inv_h2, T h, T nu, T &Lx,
-                                       T &Ld) {
+// Off-diagonal neighbours of the level stencils: 5-point operators use
+// E, W, N, S; 1-D Burgers E, W; the vorticity operator (Arakawa Jacobian +
+// viscous Laplacian) all eight.
+template <int OPK>
+struct StencilShape {
+    static constexpr int NS = (OPK == MG_VSF_OMEGA) ? 8 : (OPK == MG_BURGERS ? 2 : 4);
+};
+
+// neighbour q at (di, dj): E(+1,0) W(-1,0) N(0,+1) S(0,-1) NE NW SE SW
+__device__ __forceinline__ int nb_off(int q, int W) {
+    switch (q) {
+        case 0: return 1;
+        case 1: return -1;
+        case 2: return W;
+        case 3: return -W;
+        case 4: return W + 1;
+        case 5: return W - 1;
+        case 6: return -W + 1;
+        default: return -W - 1;
+    }
+}
+
+// Stencil of A = sigma M - dt L at point c of an array with row stride W
+// (neighbours at c + nb_off(q, W) must exist): off-diagonals a[q], diagonal ac.
+template <class T, int OPK>
+__device__ __forceinline__ void build_stencil(const T *cf, int c, int W, T inv_h2, T h, T nu, T sigma, T dt,
+                                              T (&a)[StencilShape<OPK>::NS], T &ac) {
     if constexpr (OPK == MG_NLDIFF) {
-        const int nb[4] = {c + 1, c - 1, c + W, c - W};
+        // L x = h^-2 sum_f [kf (x_nb - x_c) + (u_nb - u_c)(u_c x_c + u_nb x_nb)],
+        // kf = 1 + (u_c^2 + u_nb^2)/2: coefficient of x_nb is kf + du u_nb, of
+        // x_c the sum of -kf + du u_c
         const T uc = cf[c];
-        const T xc = HAS_X ? x[c] : T(0);
-        T lx = 0, ld = 0;
+        T ld = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T un = cf[nb[q]];
+            const T un = cf[c + nb_off(q, W)];
             const T kf = T(1) + T(0.5) * (uc * uc + un * un);
             const T du = un - uc;
-            if (HAS_X) {
-                const T xn = x[nb[q]];
-                lx += kf * (xn - xc) + du * (uc * xc + un * xn);
-            }
+            a[q] = -dt * inv_h2 * (kf + du * un);
             ld += -kf + du * uc;
         }
-        Lx = lx * inv_h2;
-        Ld = ld * inv_h2;
+        ac = sigma - dt * inv_h2 * ld;
     } else if constexpr (OPK == MG_BURGERS) {
-        Lx = HAS_X ? (-(cf[c + 1] * x[c + 1] - cf[c - 1] * x[c - 1]) / (T(2) * h) +
-                      nu * (x[c + 1] - T(2) * x[c] + x[c - 1]) * inv_h2)
-                   : T(0);
-        Ld = T(-2) * nu * inv_h2;
+        const T i2h = T(0.5) / h;
+        a[0] = -dt * (-cf[c + 1] * i2h + nu * inv_h2);
+        a[1] = -dt * (cf[c - 1] * i2h + nu * inv_h2);
+        ac = sigma + T(2) * dt * nu * inv_h2;
     } else if constexpr (OPK == MG_VSF_OMEGA) {
-        if (HAS_X) {
-            T p[3][3], w[3][3];
+        // coefficients of x in J_A(psi, x) (the three second-order forms of
+        // Arakawa's Jacobian, divided by 12 h^2) plus nu times the 5-point
+        // Laplacian; psi(di, dj) = cf[c + dj W + di]
+#define PS(dj, di) cf[c + (dj) * W + (di)]
+        const T k = inv_h2 / T(12), v = nu * inv_h2;
+        T L[8];
+        L[0] = (-(PS(1, 0) - PS(-1, 0)) - (PS(1, 1) - PS(-1, 1))) * k + v;      // E
+        L[1] = ((PS(1, 0) - PS(-1, 0)) + (PS(1, -1) - PS(-1, -1))) * k + v;     // W
+        L[2] = ((PS(0, 1) - PS(0, -1)) + (PS(1, 1) - PS(1, -1))) * k + v;       // N
+        L[3] = (-(PS(0, 1) - PS(0, -1)) - (PS(-1, 1) - PS(-1, -1))) * k + v;    // S
+        L[4] = (PS(0, 1) - PS(1, 0)) * k;                                       // NE
+        L[5] = (PS(1, 0) - PS(0, -1)) * k;                                      // NW
+        L[6] = (PS(-1, 0) - PS(0, 1)) * k;                                      // SE
+        L[7] = (PS(0, -1) - PS(-1, 0)) * k;                                     // SW
+#undef PS
 #pragma unroll
-            for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-                for (int di = 0; di < 3; ++di) {
-                    p[dj][di] = cf[c + (dj - 1) * W + (di - 1)];
-                    w[dj][di] = x[c + (dj - 1) * W + (di - 1)];
-                }
-            Lx = arakawa9(p, w, inv_h2 / T(12)) + nu * lap5(w, inv_h2);
-        } else {
-            Lx = T(0);
-        }
-        Ld = T(-4) * nu * inv_h2;
+        for (int q = 0; q < 8; ++q) a[q] = -dt * L[q];
+        ac = sigma + T(4) * dt * v;
     } else {
-        Lx = HAS_X ? (x[c + 1] + x[c - 1] + x[c + W] + x[c - W] - T(4) * x[c]) * inv_h2 : T(0);
-        Ld = T(-4) * inv_h2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = -dt * inv_h2;
+        ac = sigma + T(4) * dt * inv_h2;
     }
+}
+
+// Build the scaled stencil at point c: A~[q][c] = a_q / ac, Ac[c] = ac,
+// bt[c] <- bt[c] / ac (arrays of stride npl between the NS coefficients).
+template <class T, int OPK>
+__device__ __forceinline__ void store_stencil(const T *cf, int c, int W, T inv_h2, T h, T nu, T sigma, T dt,
+                                              T *At, int npl, T *Ac, T *bt) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    T a[NS], ac;
+    build_stencil<T, OPK>(cf, c, W, inv_h2, h, nu, sigma, dt, a, ac);
+    const T inv = T(1) / ac;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) At[q * npl + c] = a[q] * inv;
+    if (Ac) Ac[c] = ac;
+    bt[c] *= inv;
+}
+
+// D^{-1} (b - A x) at c from the scaled stencil
+template <class T, int OPK>
+__device__ __forceinline__ T jacobi_res(const T *At, int npl, const T *bt, const T *x, int c, int W) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    T r = bt[c] - x[c];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) r -= At[q * npl + c] * x[c + nb_off(q, W)];
+    return r;
 }
 
 // Iterate over the sub-box of a window: columns [a0, a1), rows [b0, b1).
@@ -118,22 +173,97 @@ __device__ __forceinline__ void lds_op(const T *cf, const T *x, int c, int W, T 
         }                                                                  \
     } while (0)
 
+// The window points a thread loads: q = threadIdx.x + 256 k, k < NPT, with
+// their periodic global coordinates (clamped to a valid point when q lies
+// past the window, so every address is in bounds).
+template <int NPT>
+struct WindowIndex {
+    int gi[NPT], gj[NPT];
+    size_t gidx[NPT];
+    int npl_;
+    template <int W, int H>
+    __device__ __forceinline__ void init(int npl, int i0, int j0, int nx, int ny, bool two_d) {
+        npl_ = npl;
+        const int hy = two_d ? H : 0;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int qq = q(k) < npl ? q(k) : 0;
+            const int ia = qq % W, ib = qq / W;
+            gi[k] = wrap2(i0 - H + ia, nx);
+            gj[k] = two_d ? wrap2(j0 - hy + ib, ny) : 0;
+            gidx[k] = (size_t)gj[k] * nx + gi[k];
+        }
+    }
+    __device__ __forceinline__ int q(int k) const { return (int)threadIdx.x + 256 * k; }
+    __device__ __forceinline__ bool ok(int k) const { return q(k) < npl_; }
+};
+
+template <int NPT, class T>
+__device__ __forceinline__ void load_field(const T *f, const WindowIndex<NPT> &wi, T (&v)[NPT]) {
+    if (f) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) v[k] = f[wi.gidx[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) v[k] = T(0);
+    }
+}
+
+// right-hand side a1 v1 + a2 v2 - (a1 mean[0] + a2 mean[1]) from float64
+// vectors (v2 and mean optional), or the level's own b when v1 is null
+template <class T, int NPT>
+__device__ __forceinline__ void load_rhs(const double *v1, double a1, const double *v2, double a2,
+                                         const double *mean, const T *b, const WindowIndex<NPT> &wi,
+                                         T (&rv)[NPT]) {
+    if (v1) {
+        double v[NPT], w[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) v[k] = v1[wi.gidx[k]];
+        if (v2) {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) w[k] = v2[wi.gidx[k]];
+        }
+        const double m = mean ? a1 * mean[0] + (v2 ? a2 * mean[1] : 0.0) : 0.0;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            double t = a1 * v[k];
+            if (v2) t += a2 * w[k];
+            rv[k] = (T)(t - m);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) rv[k] = b[wi.gidx[k]];
+    }
+}
+
+// LDS layout of a tiled kernel's window (npl = window points): NS scaled
+// off-diagonals, A_c, b~, two iterates, and cf/d sharing one array (the
+// linearization field is needed only to build the stencil).
+template <class T, int OPK>
+__host__ __device__ constexpr int window_arrays() {
+    return StencilShape<OPK>::NS + 5;
+}
+
 // ---------------------------------------------------------------------------
 // Down: pre-smoothing from x = 0, residual, restriction.
 // ---------------------------------------------------------------------------
 template <class T, int OPK, int TX, int TY, int D>
 __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
+    constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D + 2;                                   // halo of the window
     const bool two_d = g.ny > 1;
     const int hy = two_d ? H : 0;
     constexpr int W = TX + 2 * H;
     const int Hh = (two_d ? TY : 1) + 2 * hy;
+    const int npl = W * Hh;
     extern __shared__ unsigned char smem_raw[];
-    T *cf = reinterpret_cast<T *>(smem_raw);
-    T *bb = cf + W * Hh;
-    T *xa = bb + W * Hh;
-    T *xb = xa + W * Hh;
-    T *dd = xb + W * Hh;
+    T *At = reinterpret_cast<T *>(smem_raw);
+    T *Ac = At + NS * npl;
+    T *bt = Ac + npl;
+    T *xa = bt + npl;
+    T *xb = xa + npl;
+    T *dd = xb + npl;
+    T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tile = xcd_tile();
@@ -142,22 +272,28 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
     const int nx = g.nx, ny = g.ny;
     const T inv_h2 = T(1) / (g.h * g.h);
 
-    // load coefficient (full window) and right-hand side (window minus 1)
-    FOR_BOX(0, W, 0, Hh, W, {
-        const int gi = wrap_any(i0 - H + ia, nx), gj = two_d ? wrap_any(j0 - hy + ib, ny) : 0;
-        const size_t gidx = (size_t)gj * nx + gi;
-        cf[c] = g.coef ? g.coef[gidx] : T(0);
-        T rhs;
-        if (in.v1) {
-            double v = in.a1 * in.v1[gidx];
-            if (in.v2) v += in.a2 * in.v2[gidx];
-            if (in.mean) v -= in.a1 * in.mean[0] + (in.v2 ? in.a2 * in.mean[1] : 0.0);
-            rhs = (T)v;
-        } else {
-            rhs = g.b[gidx];
+    // load the linearization field and the right-hand side on the window:
+    // every load of the thread is issued before the first one is used
+    constexpr int NPT = (W * (TY + 2 * H) + 255) / 256;
+    WindowIndex<NPT> wi;
+    wi.template init<W, H>(npl, i0, j0, nx, ny, two_d);
+    {
+        T cfv[NPT];
+        load_field<NPT>(g.coef, wi, cfv);
+        T rv[NPT];
+        load_rhs<T, NPT>(in.v1, in.a1, in.v2, in.a2, in.mean, g.b, wi, rv);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (wi.ok(k)) {
+                cf[wi.q(k)] = cfv[k];
+                bt[wi.q(k)] = rv[k];
+            }
         }
-        bb[c] = rhs;
-    });
+    }
+    __syncthreads();
+    // scaled stencil on the window minus its outer ring
+    FOR_BOX(1, W - 1, two_d ? 1 : 0, two_d ? Hh - 1 : 1, W,
+            store_stencil<T, OPK>(cf, c, W, inv_h2, g.h, g.nu, g.sigma, g.dt, At, npl, Ac, bt));
     __syncthreads();
 
     // D Chebyshev steps on shrinking regions R(D+1) ... R(2)
@@ -169,23 +305,15 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
         const T cd = g.cd[k], cr = g.cr[k];
         if (k == 0) {
             FOR_BOX(ax0, ax1, by0, by1, W, {
-                T Lx, Ld;
-                lds_op<T, OPK, false>(cf, nullptr, c, W, inv_h2, g.h, g.nu, Lx, Ld);
-                const T diag = g.sigma - g.dt * Ld;
-                const T dn = cr * bb[c] / diag;
+                const T dn = cr * bt[c];
                 dd[c] = dn;
                 xnext[c] = dn;
             });
         } else {
             FOR_BOX(ax0, ax1, by0, by1, W, {
-                T Lx, Ld;
-                lds_op<T, OPK, true>(cf, xcur, c, W, inv_h2, g.h, g.nu, Lx, Ld);
-                const T xc = xcur[c];
-                const T rr = bb[c] - (g.sigma * xc - g.dt * Lx);
-                const T diag = g.sigma - g.dt * Ld;
-                const T dn = cd * dd[c] + cr * rr / diag;
+                const T dn = cd * dd[c] + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
                 dd[c] = dn;
-                xnext[c] = xc + dn;
+                xnext[c] = xcur[c] + dn;
             });
         }
         __syncthreads();
@@ -193,18 +321,15 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
         xcur = xnext;
         xnext = t;
     }
-    // write the smoothed iterate on the tile
+    // write the smoothed iterate on the tile; residual b - A x on R(1)
     FOR_BOX(H, H + TX, hy, hy + (two_d ? TY : 1), W, {
         const int gi = i0 + (ia - H), gj = j0 + (ib - hy);
         if (gi < nx && gj < ny) g.x[(size_t)gj * nx + gi] = xcur[c];
     });
-    // residual on R(1) into dd
-    FOR_BOX(H - 1, H + TX + 1, two_d ? hy - 1 : 0, two_d ? hy + TY + 1 : 1, W, {
-        T Lx, Ld;
-        lds_op<T, OPK, true>(cf, xcur, c, W, inv_h2, g.h, g.nu, Lx, Ld);
-        dd[c] = bb[c] - (g.sigma * xcur[c] - g.dt * Lx);
-    });
+    FOR_BOX(H - 1, H + TX + 1, two_d ? hy - 1 : 0, two_d ? hy + TY + 1 : 1, W,
+            xnext[c] = Ac[c] * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W));
     __syncthreads();
+    const T *rr = xnext;
     // full-weighting restriction to coarse points whose fine node lies in the tile
     const int nxc = nx / 2, nyc = two_d ? ny / 2 : 1;
     constexpr int CX = TX / 2;
@@ -216,11 +341,11 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
         const int c = cb * W + ca;
         T acc;
         if (two_d) {
-            acc = T(0.25) * dd[c] +
-                  T(0.125) * (dd[c - 1] + dd[c + 1] + dd[c - W] + dd[c + W]) +
-                  T(0.0625) * (dd[c - W - 1] + dd[c - W + 1] + dd[c + W - 1] + dd[c + W + 1]);
+            acc = T(0.25) * rr[c] +
+                  T(0.125) * (rr[c - 1] + rr[c + 1] + rr[c - W] + rr[c + W]) +
+                  T(0.0625) * (rr[c - W - 1] + rr[c - W + 1] + rr[c + W - 1] + rr[c + W + 1]);
         } else {
-            acc = T(0.5) * dd[c] + T(0.25) * (dd[c - 1] + dd[c + 1]);
+            acc = T(0.5) * rr[c] + T(0.25) * (rr[c - 1] + rr[c + 1]);
         }
         g.bc[(size_t)J * nxc + I] = acc;
     }
@@ -231,17 +356,20 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
 // ---------------------------------------------------------------------------
 template <class T, int OPK, int TX, int TY, int D>
 __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
+    constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D;                                       // halo of the window
     const bool two_d = g.ny > 1;
     const int hy = two_d ? H : 0;
     constexpr int W = TX + 2 * H;
     const int Hh = (two_d ? TY : 1) + 2 * hy;
+    const int npl = W * Hh;
     extern __shared__ unsigned char smem_raw[];
-    T *cf = reinterpret_cast<T *>(smem_raw);
-    T *bb = cf + W * Hh;
-    T *xa = bb + W * Hh;
-    T *xb = xa + W * Hh;
-    T *dd = xb + W * Hh;
+    T *At = reinterpret_cast<T *>(smem_raw);
+    T *bt = At + NS * npl;
+    T *xa = bt + npl;
+    T *xb = xa + npl;
+    T *dd = xb + npl;
+    T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tile = xcd_tile();
@@ -251,32 +379,40 @@ __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
     const int nxc = nx / 2, nyc = two_d ? ny / 2 : 1;
     const T inv_h2 = T(1) / (g.h * g.h);
 
-    FOR_BOX(0, W, 0, Hh, W, {
-        const int gi = wrap_any(i0 - H + ia, nx), gj = two_d ? wrap_any(j0 - hy + ib, ny) : 0;
-        const size_t gidx = (size_t)gj * nx + gi;
-        cf[c] = g.coef ? g.coef[gidx] : T(0);
-        T rhs;
-        if (out.v1) {
-            double v = out.a1 * out.v1[gidx];
-            if (out.v2) v += out.a2 * out.v2[gidx];
-            if (out.mean_in) v -= out.a1 * out.mean_in[0] + (out.v2 ? out.a2 * out.mean_in[1] : 0.0);
-            rhs = (T)v;
-        } else {
-            rhs = g.b[gidx];
+    constexpr int NPT = (W * (TY + 2 * H) + 255) / 256;
+    WindowIndex<NPT> wi;
+    wi.template init<W, H>(npl, i0, j0, nx, ny, two_d);
+    {
+        T cfv[NPT], xv[NPT], ev[NPT];
+        load_field<NPT>(g.coef, wi, cfv);
+        load_field<NPT>(g.x, wi, xv);
+        // prolongation of the coarse correction: coarse node I sits at fine 2I
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int gi = wi.gi[k], gj = wi.gj[k];
+            const int I0 = gi >> 1, I1 = (gi & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
+            if (two_d) {
+                const int J0 = gj >> 1, J1 = (gj & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
+                ev[k] = T(0.25) * (g.xc[(size_t)J0 * nxc + I0] + g.xc[(size_t)J0 * nxc + I1] +
+                                   g.xc[(size_t)J1 * nxc + I0] + g.xc[(size_t)J1 * nxc + I1]);
+            } else {
+                ev[k] = T(0.5) * (g.xc[I0] + g.xc[I1]);
+            }
         }
-        bb[c] = rhs;
-        // prolongation: coarse node I sits at fine 2I
-        const int I0 = gi >> 1, I1 = (gi & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
-        T e;
-        if (two_d) {
-            const int J0 = gj >> 1, J1 = (gj & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
-            e = T(0.25) * (g.xc[(size_t)J0 * nxc + I0] + g.xc[(size_t)J0 * nxc + I1] +
-                           g.xc[(size_t)J1 * nxc + I0] + g.xc[(size_t)J1 * nxc + I1]);
-        } else {
-            e = T(0.5) * (g.xc[I0] + g.xc[I1]);
+        T rv[NPT];
+        load_rhs<T, NPT>(out.v1, out.a1, out.v2, out.a2, out.mean_in, g.b, wi, rv);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (wi.ok(k)) {
+                cf[wi.q(k)] = cfv[k];
+                bt[wi.q(k)] = rv[k];
+                xa[wi.q(k)] = xv[k] + ev[k];
+            }
         }
-        xa[c] = g.x[gidx] + e;
-    });
+    }
+    __syncthreads();
+    FOR_BOX(1, W - 1, two_d ? 1 : 0, two_d ? Hh - 1 : 1, W,
+            store_stencil<T, OPK>(cf, c, W, inv_h2, g.h, g.nu, g.sigma, g.dt, At, npl, (T *)nullptr, bt));
     __syncthreads();
     T *xcur = xa, *xnext = xb;
     for (int k = 0; k < D; ++k) {
@@ -285,14 +421,9 @@ __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
         const int by0 = two_d ? hy - r : 0, by1 = two_d ? hy + TY + r : 1;
         const T cd = g.cd[k], cr = g.cr[k];
         FOR_BOX(ax0, ax1, by0, by1, W, {
-            T Lx, Ld;
-            lds_op<T, OPK, true>(cf, xcur, c, W, inv_h2, g.h, g.nu, Lx, Ld);
-            const T xc = xcur[c];
-            const T rr = bb[c] - (g.sigma * xc - g.dt * Lx);
-            const T diag = g.sigma - g.dt * Ld;
-            const T dn = (k == 0 ? T(0) : cd * dd[c]) + cr * rr / diag;
+            const T dn = (k == 0 ? T(0) : cd * dd[c]) + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
             dd[c] = dn;
-            xnext[c] = xc + dn;
+            xnext[c] = xcur[c] + dn;
         });
         __syncthreads();
         T *t = xcur;
@@ -312,157 +443,219 @@ __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
 // ---------------------------------------------------------------------------
 // The V-cycle on levels l0..L-1 in one work-group, every level in LDS.
 // ---------------------------------------------------------------------------
-// Gershgorin ratio sum_{j != i} |a_ij| / |a_ii| of row i of A = sigma M - dt L
-// on a level (periodic), from the operator's stencil coefficients.
-template <class T, int OPK>
-__device__ T row_ratio(const T *cf, int i, int j, int nx, int ny, T h, T nu, T sigma, T dt) {
-    const T inv_h2 = T(1) / (h * h);
-    if constexpr (OPK == MG_NLDIFF) {
-        const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
-        const int nb[4] = {j * nx + ip, j * nx + im, jp * nx + i, jm * nx + i};
-        const T uc = cf[j * nx + i];
-        T off = 0, ld = 0;
-        for (int q = 0; q < 4; ++q) {
-            const T un = cf[nb[q]];
-            const T kf = T(1) + T(0.5) * (uc * uc + un * un);
-            const T du = un - uc;
-            off += fabs(dt * inv_h2 * (kf + du * un));
-            ld += -kf + du * uc;
-        }
-        return off / fabs(sigma - dt * ld * inv_h2);
-    } else if constexpr (OPK == MG_BURGERS) {
-        const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx);
-        const T off = fabs(dt * (-cf[ip] / (T(2) * h) + nu * inv_h2)) + fabs(dt * (cf[im] / (T(2) * h) + nu * inv_h2));
-        return off / fabs(sigma + T(2) * dt * nu * inv_h2);
-    } else if constexpr (OPK == MG_VSF_OMEGA) {
-        T p[3][3], e[3][3];
-        for (int dj = 0; dj < 3; ++dj)
-            for (int di = 0; di < 3; ++di) {
-                p[dj][di] = cf[wrapm(j + dj - 1, ny) * nx + wrapm(i + di - 1, nx)];
-                e[dj][di] = T(0);
-            }
-        T off = 0;
-        for (int dj = 0; dj < 3; ++dj)
-            for (int di = 0; di < 3; ++di) {
-                if (dj == 1 && di == 1) continue;
-                e[dj][di] = T(1);
-                T cnb = arakawa9(p, e, inv_h2 / T(12));
-                if (dj == 1 || di == 1) cnb += nu * inv_h2;
-                e[dj][di] = T(0);
-                off += fabs(dt * cnb);
-            }
-        return off / fabs(sigma + T(4) * dt * nu * inv_h2);
+// Periodic neighbour indices of point (i, j) on an nx x ny level, in the
+// order of nb_off.
+template <int OPK>
+__device__ __forceinline__ void nb_index(int i, int j, int nx, int ny, int (&idx)[StencilShape<OPK>::NS]) {
+    const int ip = wrap2(i + 1, nx), im = wrap2(i - 1, nx);
+    if constexpr (OPK == MG_BURGERS) {
+        idx[0] = ip;
+        idx[1] = im;
     } else {
-        return sigma == T(0) ? T(1) : T(4) * dt * inv_h2 / fabs(sigma + T(4) * dt * inv_h2);
+        const int jp = wrap2(j + 1, ny), jm = wrap2(j - 1, ny);
+        idx[0] = j * nx + ip;
+        idx[1] = j * nx + im;
+        idx[2] = jp * nx + i;
+        idx[3] = jm * nx + i;
+        if constexpr (StencilShape<OPK>::NS == 8) {
+            idx[4] = jp * nx + ip;
+            idx[5] = jp * nx + im;
+            idx[6] = jm * nx + ip;
+            idx[7] = jm * nx + im;
+        }
     }
 }
 
+// Scaled stencil row p of a periodic level from its padded field (point c
+// of the padded array); b~ scaled too when bl is given.
 template <class T, int OPK>
-__device__ void wg_cheb(const T *cf, T *x, const T *b, T *r, T *d, int nx, int ny, T h, T nu, T sigma, T dt,
-                        const T *cd, const T *cr, int nsteps, bool from_zero) {
+__device__ __forceinline__ void store_level_stencil(const T *pad, int c, int pw, T inv_h2, T h, T nu, T sigma, T dt,
+                                                    T *at, int np, int p, T *acl, T *bl) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    T a[NS], ac;
+    build_stencil<T, OPK>(pad, c, pw, inv_h2, h, nu, sigma, dt, a, ac);
+    const T inv = T(1) / ac;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) at[q * np + p] = a[q] * inv;
+    acl[p] = ac;
+    if (bl) bl[p] *= inv;
+}
+
+// D^{-1}(b - A x) at point p of a periodic level
+template <class T, int OPK>
+__device__ __forceinline__ T level_jres(const T *At, int np, const T *bt, const T *x, int p, int i, int j, int nx,
+                                        int ny) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    int idx[NS];
+    nb_index<OPK>(i, j, nx, ny, idx);
+    T r = bt[p] - x[p];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) r -= At[q * np + p] * x[idx[q]];
+    return r;
+}
+
+// nsteps Chebyshev steps on a level; x and xn alternate (one barrier per
+// step), the result is left in x.
+template <class T, int OPK>
+__device__ void wg_cheb(const T *At, const T *bt, T *x, T *xn, T *d, int nx, int ny, const T *cd, const T *cr,
+                        int nsteps, bool from_zero) {
     const int np = nx * ny;
-    const T inv_h2 = T(1) / (h * h);
+    T *xc = x, *xo = xn;
     for (int k = 0; k < nsteps; ++k) {
-        // r <- D^{-1} (b - A x)
-        FOR_PTS(np, nx, {
-            T Lx, Ld;
-            T xc = from_zero && k == 0 ? T(0) : x[p];
-            if (OPK == MG_VSF_OMEGA) {
-                T pp[3][3], ww[3][3];
-                for (int dj = 0; dj < 3; ++dj)
-                    for (int di = 0; di < 3; ++di) {
-                        const int q = wrap_any(j + dj - 1, ny) * nx + wrap_any(i + di - 1, nx);
-                        pp[dj][di] = cf[q];
-                        ww[dj][di] = (from_zero && k == 0) ? T(0) : x[q];
-                    }
-                Lx = arakawa9(pp, ww, inv_h2 / T(12)) + nu * lap5(ww, inv_h2);
-                Ld = T(-4) * nu * inv_h2;
-            } else if (from_zero && k == 0) {
-                level_op<T, OPK, false>(cf, x, i, j, nx, ny, h, nu, Lx, Ld);
-            } else {
-                level_op<T, OPK, true>(cf, x, i, j, nx, ny, h, nu, Lx, Ld);
+        if (from_zero && k == 0) {
+            for (int p = threadIdx.x; p < np; p += blockDim.x) {
+                const T dn = cr[0] * bt[p];
+                d[p] = dn;
+                xo[p] = dn;
             }
-            r[p] = (b[p] - (sigma * xc - dt * Lx)) / (sigma - dt * Ld);
-        });
-        __syncthreads();
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const T dn = (k == 0 ? T(0) : cd[k] * d[p]) + cr[k] * r[p];
-            d[p] = dn;
-            x[p] = (from_zero && k == 0 ? T(0) : x[p]) + dn;
+        } else {
+            FOR_PTS(np, nx, {
+                const T dn = (k == 0 ? T(0) : cd[k] * d[p]) + cr[k] * level_jres<T, OPK>(At, np, bt, xc, p, i, j, nx, ny);
+                d[p] = dn;
+                xo[p] = xc[p] + dn;
+            });
         }
+        __syncthreads();
+        T *t = xc;
+        xc = xo;
+        xo = t;
+    }
+    if (xc != x) {
+        for (int p = threadIdx.x; p < np; p += blockDim.x) x[p] = xc[p];
         __syncthreads();
     }
 }
 
 template <class T, int OPK>
 __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, MgOut out) {
+    constexpr int NS = StencilShape<OPK>::NS;
     extern __shared__ unsigned char smem_raw[];
     T *base = reinterpret_cast<T *>(smem_raw);
-    // per level: x, b, coef (consecutive blocks); then shared scratch r, d
-    // sized for the finest level.  Level pointers are recomputed from the
-    // sizes (uniform scalar arithmetic) instead of being kept in an array.
+    // per level: x, b~, A_c, then NS scaled off-diagonals; after the levels:
+    // scratch R and Dv sized for the first level, and a padded copy of a
+    // level's linearization field for building its stencil.  Level pointers
+    // are recomputed from the sizes (uniform scalar arithmetic).
     auto lev_base = [&](int l) {
         size_t off = 0;
-        for (int q = 0; q < l; ++q) off += 3 * (size_t)s.nx[q] * s.ny[q];
+        for (int q = 0; q < l; ++q) off += (3 + NS) * (size_t)s.nx[q] * s.ny[q];
         return base + off;
     };
+    auto npts = [&](int l) { return s.nx[l] * s.ny[l]; };
 #define X(l) (lev_base(l))
-#define B(l) (lev_base(l) + (size_t)s.nx[l] * s.ny[l])
-#define C(l) (lev_base(l) + 2 * (size_t)s.nx[l] * s.ny[l])
+#define B(l) (lev_base(l) + npts(l))
+#define AC(l) (lev_base(l) + 2 * npts(l))
+#define AT(l) (lev_base(l) + 3 * npts(l))
+    const int np0 = npts(0);
     T *R = lev_base(s.nlev);
-    T *Dv = R + s.nx[0] * s.ny[0];
-    const int np0 = s.nx[0] * s.ny[0];
-    for (int p = threadIdx.x; p < np0; p += blockDim.x) {
-        T rhs;
-        if (in.v1) {
-            double v = in.a1 * in.v1[p];
-            if (in.v2) v += in.a2 * in.v2[p];
-            if (in.mean) v -= in.a1 * in.mean[0] + (in.v2 ? in.a2 * in.mean[1] : 0.0);
-            rhs = (T)v;
-        } else {
-            rhs = s.b0[p];
+    T *Dv = R + np0;
+    T *Pad = Dv + np0;            // per-level padded fields, consecutive
+    const int L = s.nlev;
+    const bool two_d = s.ny[0] > 1;
+    // padded level l: (nx + 2) x (ny + 2) (2-D) or nx + 2 points, periodic
+    // ring; offsets recomputed from the sizes (no private arrays)
+    auto pad_size = [&](int l) { return (s.nx[l] + 2) * (two_d ? s.ny[l] + 2 : 1); };
+    auto pad_off = [&](int l) {
+        int off = 0;
+        for (int q = 0; q < l; ++q) off += pad_size(q);
+        return off;
+    };
+    const int ptot = pad_off(L);
+    // every global load is issued before its value is used: the first
+    // level's right-hand side, then the linearization fields of all levels
+    // in batches of SB points per thread
+    constexpr int SB = 4;
+    T bv[SB];
+    {
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int p0 = (int)threadIdx.x + k * (int)blockDim.x;
+            const int p = p0 < np0 ? p0 : 0;
+            if (in.v1) {
+                double v = in.a1 * in.v1[p];
+                if (in.v2) v += in.a2 * in.v2[p];
+                if (in.mean) v -= in.a1 * in.mean[0] + (in.v2 ? in.a2 * in.mean[1] : 0.0);
+                bv[k] = (T)v;
+            } else {
+                bv[k] = s.b0[p];
+            }
         }
-        B(0)[p] = rhs;
     }
-    for (int l = 0; l < s.nlev; ++l) {
-        const int np = s.nx[l] * s.ny[l];
-        for (int p = threadIdx.x; p < np; p += blockDim.x) C(l)[p] = s.coef[l] ? s.coef[l][p] : T(0);
+    for (int base = 0; base < ptot; base += SB * (int)blockDim.x) {
+        T v[SB];
+        int dst[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int q = base + (int)threadIdx.x + k * (int)blockDim.x;
+            dst[k] = q < ptot ? q : -1;
+            // level of q (compile-time indexed search: no private arrays)
+            int nx = s.nx[0], ny = s.ny[0], off = 0, offm = 0;
+            const T *cl = s.coef[0];
+#pragma unroll
+            for (int m = 0; m < IRK_MAX_SUB_LEVELS; ++m) {
+                if (m < L && q >= offm) {
+                    nx = s.nx[m];
+                    ny = s.ny[m];
+                    off = offm;
+                    cl = s.coef[m];
+                }
+                if (m < L) offm += pad_size(m);
+            }
+            const int pw = nx + 2;
+            const int loc = q < ptot ? q - off : 0;
+            const int gi = wrap2(loc % pw - 1, nx), gj = two_d ? wrap2(loc / pw - 1, ny) : 0;
+            v[k] = cl ? cl[gj * nx + gi] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k)
+            if (dst[k] >= 0) Pad[dst[k]] = v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < SB; ++k) {
+        const int p = (int)threadIdx.x + k * (int)blockDim.x;
+        if (p < np0) B(0)[p] = bv[k];
     }
     __syncthreads();
-    const int L = s.nlev;
+    // scaled stencils of every level (levels are independent: one barrier)
+    for (int l = 0; l < L; ++l) {
+        const int nx = s.nx[l], ny = s.ny[l];
+        const int pw = nx + 2;
+        const T inv_h2 = T(1) / (s.h[l] * s.h[l]);
+        T *at = AT(l), *acl = AC(l), *bl = B(l);
+        const T *pad = Pad + pad_off(l);
+        const int np = nx * ny;
+        FOR_PTS(np, nx, store_level_stencil<T, OPK>(pad, (two_d ? (j + 1) * pw : 0) + i + 1, pw, inv_h2, s.h[l],
+                                                      s.nu, s.sigma, s.dt, at, np, p, acl, l == 0 ? bl : nullptr));
+    }
+    __syncthreads();
     for (int l = 0; l < L - 1; ++l) {
         const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, true);
-        // residual into R, then full weighting into B(l+1)
-        FOR_PTS(np, nx, {
-            T Lx, Ld;
-            level_op<T, OPK, true>(C(l), X(l), i, j, nx, ny, s.h[l], s.nu, Lx, Ld);
-            R[p] = B(l)[p] - (s.sigma * X(l)[p] - s.dt * Lx);
-        });
+        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, s.cd, s.cr, s.deg, true);
+        // residual b - A x into R, then full weighting into the next b~
+        FOR_PTS(np, nx, R[p] = AC(l)[p] * level_jres<T, OPK>(AT(l), np, B(l), X(l), p, i, j, nx, ny));
         __syncthreads();
         const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
+        const T *acc_c = AC(l + 1);
+        T *bc = B(l + 1);
         FOR_PTS(nxc * nyc, nxc, {
-            const int I = i, J = j, q = p;
             T acc;
             if (ny > 1) {
-                acc = 0;
-                for (int bj = -1; bj <= 1; ++bj)
-                    for (int ai = -1; ai <= 1; ++ai) {
-                        const T w = (ai == 0 ? T(0.5) : T(0.25)) * (bj == 0 ? T(0.5) : T(0.25));
-                        acc += w * R[wrap_any(2 * J + bj, ny) * nx + wrap_any(2 * I + ai, nx)];
-                    }
+                const int im = wrap2(2 * i - 1, nx), ip = 2 * i + 1, jm = wrap2(2 * j - 1, ny), jp = 2 * j + 1;
+                acc = T(0.25) * R[2 * j * nx + 2 * i] +
+                      T(0.125) * (R[2 * j * nx + im] + R[2 * j * nx + ip] + R[jm * nx + 2 * i] + R[jp * nx + 2 * i]) +
+                      T(0.0625) * (R[jm * nx + im] + R[jm * nx + ip] + R[jp * nx + im] + R[jp * nx + ip]);
             } else {
-                acc = T(0.5) * R[2 * I] + T(0.25) * (R[wrap_any(2 * I - 1, nx)] + R[wrap_any(2 * I + 1, nx)]);
+                acc = T(0.5) * R[2 * i] + T(0.25) * (R[wrap2(2 * i - 1, nx)] + R[2 * i + 1]);
             }
-            B(l + 1)[q] = acc;
+            bc[p] = acc / acc_c[p];
         });
         __syncthreads();
     }
     {
-        // coarsest level: Chebyshev iteration on a Gershgorin interval
-        // [1 - rho, 1 + rho] of D^{-1} A computed here; the singular periodic
-        // Poisson operator (rho = 1) is solved on mean-free data with the
-        // interval's lower end at its smallest nonzero eigenvalue
+        // coarsest level: Chebyshev iteration on the Gershgorin interval
+        // [1 - rho, 1 + rho] of D^{-1} A (rho = max row sum of |a~_q|); the
+        // singular periodic Poisson operator (rho = 1) is solved on mean-free
+        // data with the interval's lower end at its smallest nonzero
+        // eigenvalue
         const int l = L - 1, nx = s.nx[l], ny = s.ny[l], np = nx * ny;
         __shared__ double red[16];
         const bool singular = (OPK == MG_POISSON && s.sigma == T(0));
@@ -480,7 +673,12 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
             __syncthreads();
         }
         double rho = 0.0;
-        FOR_PTS(np, nx, rho = fmax(rho, (double)row_ratio<T, OPK>(C(l), i, j, nx, ny, s.h[l], s.nu, s.sigma, s.dt)));
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            double rs = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) rs += fabs((double)AT(l)[q * np + p]);
+            rho = fmax(rho, rs);
+        }
         for (int off = 32; off > 0; off >>= 1) rho = fmax(rho, __shfl_xor(rho, off, 64));
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rho;
         __syncthreads();
@@ -489,7 +687,12 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
         __syncthreads();
         double lmin = 1.0 - rho, lmax = 1.0 + rho;
         if (singular || lmin < 0.05) {
-            const double sx = sin(3.14159265358979323846 / nx), sy = ny > 1 ? sin(3.14159265358979323846 / ny) : 1.0;
+            // sin(pi / n) from its Taylor series (a heuristic lower end only)
+            auto sin_pi_over = [](int n) {
+                const double x = 3.14159265358979323846 / n, x2 = x * x;
+                return x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0)));
+            };
+            const double sx = sin_pi_over(nx), sy = ny > 1 ? sin_pi_over(ny) : 1.0;
             lmin = fmax(0.5 * fmin(sx * sx, sy * sy), 0.02);
         }
         // steps for a 1e-3 reduction of the Chebyshev bound 2 r^k
@@ -513,25 +716,26 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
             }
         }
         __syncthreads();
-        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, ccd, ccr, iters, true);
+        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, ccd, ccr, iters, true);
     }
     for (int l = L - 2; l >= 0; --l) {
         const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
         const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
+        const T *xcl = X(l + 1);
+        T *xl = X(l);
         FOR_PTS(np, nx, {
             const int I0 = i >> 1, I1 = (i & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
             T e;
             if (ny > 1) {
                 const int J0 = j >> 1, J1 = (j & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
-                e = T(0.25) * (X(l + 1)[J0 * nxc + I0] + X(l + 1)[J0 * nxc + I1] + X(l + 1)[J1 * nxc + I0] +
-                               X(l + 1)[J1 * nxc + I1]);
+                e = T(0.25) * (xcl[J0 * nxc + I0] + xcl[J0 * nxc + I1] + xcl[J1 * nxc + I0] + xcl[J1 * nxc + I1]);
             } else {
-                e = T(0.5) * (X(l + 1)[I0] + X(l + 1)[I1]);
+                e = T(0.5) * (xcl[I0] + xcl[I1]);
             }
-            X(l)[p] += e;
+            xl[p] += e;
         });
         __syncthreads();
-        wg_cheb<T, OPK>(C(l), X(l), B(l), R, Dv, nx, ny, s.h[l], s.nu, s.sigma, s.dt, s.cd, s.cr, s.deg, false);
+        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, s.cd, s.cr, s.deg, false);
     }
     for (int p = threadIdx.x; p < np0; p += blockDim.x) {
         if (out.z) out.z[p] = (double)X(0)[p] + (out.shift ? out.shift_scale * out.shift[0] : 0.0);
@@ -540,7 +744,8 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
 }
 #undef X
 #undef B
-#undef C
+#undef AC
+#undef AT
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -549,7 +754,8 @@ template <class T, int OPK, int TX, int TY>
 static void down_t(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &in, int deg) {
     const int tiles = ((a.nx + TX - 1) / TX) * (a.ny > 1 ? (a.ny + TY - 1) / TY : 1);
     const int H = deg + 2;
-    const size_t shm = (size_t)5 * (TX + 2 * H) * ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
+    const size_t shm = (size_t)window_arrays<T, OPK>() * (TX + 2 * H) *
+                       ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
     switch (deg) {
         case 1: k_mg_down<T, OPK, TX, TY, 1><<<tiles, 256, shm, st>>>(a, in); break;
         case 2: k_mg_down<T, OPK, TX, TY, 2><<<tiles, 256, shm, st>>>(a, in); break;
@@ -562,7 +768,9 @@ template <class T, int OPK, int TX, int TY>
 static void up_t(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int deg) {
     const int tiles = ((a.nx + TX - 1) / TX) * (a.ny > 1 ? (a.ny + TY - 1) / TY : 1);
     const int H = deg;
-    const size_t shm = (size_t)5 * (TX + 2 * H) * ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
+    // no A_c array on the way up
+    const size_t shm = (size_t)(window_arrays<T, OPK>() - 1) * (TX + 2 * H) *
+                       ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
     switch (deg) {
         case 1: k_mg_up<T, OPK, TX, TY, 1><<<tiles, 256, shm, st>>>(a, out); break;
         case 2: k_mg_up<T, OPK, TX, TY, 2><<<tiles, 256, shm, st>>>(a, out); break;
@@ -573,18 +781,37 @@ static void up_t(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int 
 
 // tile shape per level size: wide tiles on big levels, small tiles (more
 // work-groups) on small ones; 1-D levels use 256-point strips
+// The window loads wrap indices once (wrap2), valid when the window of
+// every tile stays within [-n, 2n): tiles * T + halo <= 2 n and halo <= n.
+static bool window_fits(int n, int t, int halo) {
+    const int tiles = (n + t - 1) / t;
+    return halo <= n && tiles * t + halo <= 2 * n;
+}
+
 template <class T, int OPK>
 static void down_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &in, int deg) {
-    if (a.ny == 1) down_t<T, OPK, 256, 1>(st, a, in, deg);
-    else if (a.nx >= 128) down_t<T, OPK, 32, 8>(st, a, in, deg);
-    else down_t<T, OPK, 16, 8>(st, a, in, deg);
+    const int H = (deg > 4 ? 4 : deg) + 2;
+    if (a.ny == 1) {
+        if (window_fits(a.nx, 256, H)) down_t<T, OPK, 256, 1>(st, a, in, deg);
+        else down_t<T, OPK, 64, 1>(st, a, in, deg);
+    } else if (a.nx >= 128 && window_fits(a.nx, 32, H) && window_fits(a.ny, 8, H)) {
+        down_t<T, OPK, 32, 8>(st, a, in, deg);
+    } else {
+        down_t<T, OPK, 16, 8>(st, a, in, deg);
+    }
 }
 
 template <class T, int OPK>
 static void up_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int deg) {
-    if (a.ny == 1) up_t<T, OPK, 256, 1>(st, a, out, deg);
-    else if (a.nx >= 128) up_t<T, OPK, 32, 8>(st, a, out, deg);
-    else up_t<T, OPK, 16, 8>(st, a, out, deg);
+    const int H = deg > 4 ? 4 : deg;
+    if (a.ny == 1) {
+        if (window_fits(a.nx, 256, H)) up_t<T, OPK, 256, 1>(st, a, out, deg);
+        else up_t<T, OPK, 64, 1>(st, a, out, deg);
+    } else if (a.nx >= 128 && window_fits(a.nx, 32, H) && window_fits(a.ny, 8, H)) {
+        up_t<T, OPK, 32, 8>(st, a, out, deg);
+    } else {
+        up_t<T, OPK, 16, 8>(st, a, out, deg);
+    }
 }
 
 template <class T>
@@ -607,17 +834,21 @@ void launch_mg_up(hipStream_t st, int opk, const MgLevelArgs<T> &a, const MgOut 
     }
 }
 
-template <class T>
-size_t mg_subcycle_lds_bytes(const MgSubArgs<T> &s) {
+static int stencil_ns(int opk) {
+    return opk == MG_VSF_OMEGA ? 8 : (opk == MG_BURGERS ? 2 : 4);
+}
+
+size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, size_t tsz) {
     size_t n = 0;
-    for (int l = 0; l < s.nlev; ++l) n += 3 * (size_t)s.nx[l] * s.ny[l];
-    n += 2 * (size_t)s.nx[0] * s.ny[0];
-    return n * sizeof(T);
+    for (int l = 0; l < nlev; ++l) n += (size_t)(3 + stencil_ns(opk)) * nx[l] * ny[l];
+    n += 2 * (size_t)nx[0] * ny[0];
+    for (int l = 0; l < nlev; ++l) n += (size_t)(nx[l] + 2) * (ny[0] > 1 ? ny[l] + 2 : 1);
+    return n * tsz;
 }
 
 template <class T>
 void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const MgIn &in, const MgOut &out) {
-    const size_t shm = mg_subcycle_lds_bytes(s);
+    const size_t shm = mg_subcycle_lds_bytes(opk, s.nlev, s.nx, s.ny, sizeof(T));
     const int np0 = s.nx[0] * s.ny[0];
     const unsigned nt = np0 >= 1024 ? 1024 : ((np0 + 63) / 64) * 64;
     switch (opk) {
@@ -634,7 +865,5 @@ template void launch_mg_up<float>(hipStream_t, int, const MgLevelArgs<float> &, 
 template void launch_mg_up<double>(hipStream_t, int, const MgLevelArgs<double> &, const MgOut &, int);
 template void launch_mg_subcycle<float>(hipStream_t, int, const MgSubArgs<float> &, const MgIn &, const MgOut &);
 template void launch_mg_subcycle<double>(hipStream_t, int, const MgSubArgs<double> &, const MgIn &, const MgOut &);
-template size_t mg_subcycle_lds_bytes<float>(const MgSubArgs<float> &);
-template size_t mg_subcycle_lds_bytes<double>(const MgSubArgs<double> &);
 
 }  // namespace irk

@@ -161,15 +161,4 @@ __device__ __forceinline__ void poisson_lin(const T *x, int i, int j, int nx, in
     Ld = T(-4) * inv_h2;
 }
 
-// Rediscretized level operator of a multigrid hierarchy (periodic wrap),
-// its action on x and its diagonal.
-template <class T, int OPK, bool HAS_X>
-__device__ __forceinline__ void level_op(const T *coef, const T *x, int i, int j, int nx, int ny, T h, T nu,
-                                         T &Lx, T &Ld) {
-    if constexpr (OPK == MG_NLDIFF) nldiff_lin<T, HAS_X>(coef, x, i, j, nx, ny, T(1) / (h * h), Lx, Ld);
-    else if constexpr (OPK == MG_BURGERS) burgers_lin<T, HAS_X>(coef, x, i, nx, h, nu, Lx, Ld);
-    else if constexpr (OPK == MG_VSF_OMEGA) vsf_omega_lin<T, HAS_X>(coef, x, i, j, nx, ny, h, nu, Lx, Ld);
-    else poisson_lin<T, HAS_X>(x, i, j, nx, ny, h, Lx, Ld);
-}
-
 }  // namespace irk

@@ -68,7 +68,7 @@ def test_matches_minpack_root(family, s):
     for prob, u0, dt in ((pb.Burgers1D(32, 0.01), inputs.burgers_u0(32, 1), 1e-2),
                          (pb.NonlinearDiffusion2D(8), inputs.nldiff_u0(8).ravel(), 5e-3)):
         K, _ = nw.irk_stages(prob, A, c, u0, 0.2, dt)
-        K0 = nw.initial_stages(prob, u0, 0.2, s)
+        K0 = nw.initial_stages(prob, A, c, u0, 0.2, dt)
         sol = so.root(lambda z: nw.stage_residual(prob, A, c, u0, 0.2, dt, z.reshape(K.shape)).ravel(),
                       K0.ravel(), method="hybr", options={"xtol": 1e-15, "maxfev": 200000})
         Kr = sol.x.reshape(K.shape)
@@ -167,3 +167,33 @@ def test_radau_update_equals_last_stage():
     u1, K, _ = nw.irk_step(prob, A, b, c, u0, 0.0, 5e-3)
     Us = nw.stage_values(A, u0, 5e-3, K)[-1]
     assert np.max(np.abs(u1 - Us)) < 1e-15 * max(1.0, np.abs(u1).max()) * 10
+
+
+def test_starting_vectors_choice_and_independence():
+    """The starting stage vectors are the better of K = 0 and the explicit
+    k_i = N(u_n, t_n): the explicit one for smooth motion resolved by the
+    grid (the manufactured solution at t = 0.2 on 256^2), zero for a stiff
+    decaying transient (modes up to 3 per direction at dt = 5e-3, where
+    dt * lambda ~ 4 makes the explicit guess overshoot).  Either start
+    converges to the same stage vectors."""
+    A, b, c = tb.tableau("gauss", 3)
+    fine = pb.NonlinearDiffusion2D(256)
+    u_f = inputs.nldiff_u0(256).ravel() * np.cos(0.2)        # u*(t = 0.2)
+    K0 = nw.initial_stages(fine, A, c, u_f, 0.2, 5e-3)
+    np.testing.assert_array_equal(K0[2], fine.rhs(u_f, 0.2))
+    smooth = pb.NonlinearDiffusion2D(16)
+    u_s = inputs.nldiff_u0(16).ravel()
+    stiff = pb.NonlinearDiffusion2D(32)
+    u_r = inputs.nldiff_random_u0(32, 579470083).ravel()
+    K0 = nw.initial_stages(stiff, A, c, u_r, 0.0, 5e-3)
+    assert not np.any(K0)
+    for prob, u in ((smooth, u_s), (stiff, u_r)):
+        Ka, _ = nw.irk_stages(prob, A, c, u, 0.0, 5e-3, K0=np.zeros((3, prob.size)))
+        Kb, _ = nw.irk_stages(prob, A, c, u, 0.0, 5e-3, K0=np.stack([prob.rhs(u, 0.0)] * 3))
+        assert np.linalg.norm(Ka - Kb) <= 1e-12 * np.linalg.norm(Ka)
+    # algebraic rows of the DAE start at zero in the explicit candidate
+    vsf = pb.VorticityStreamfunction2D(12, nu=1e-3)
+    x = inputs.vsf_state0(12, 3, 6).ravel()
+    Ar, br, cr = tb.tableau("radau", 2)
+    K0 = nw.initial_stages(vsf, Ar, cr, x, 0.0, 1e-3)
+    assert not np.any(K0[:, vsf.size // 2:])
