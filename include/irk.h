@@ -206,6 +206,16 @@ int irk_profile_count(irk_ctx *ctx);
 irk_status irk_profile_entry(irk_ctx *ctx, int idx, char *name, int name_len, long *launches,
                              double *total_ms, double *total_bytes);
 
+/* Back-to-back timing of one kernel group: while recording, the context
+ * keeps the most recent launches of every group (at most 32, all on one
+ * stream, with their arguments).  This re-issues them reps times in a row on
+ * that stream between two HIP events and returns the average duration of one
+ * launch in milliseconds (and the average algorithmic bytes of one launch),
+ * free of the per-launch event overhead of irk_profile_entry.  The replays
+ * overwrite the context's internal buffers: call it only between steps.
+ * IRK_E_ARG if nothing of that name was recorded.                          */
+irk_status irk_profile_replay(irk_ctx *ctx, const char *name, int reps, double *avg_ms, double *avg_bytes);
+
 /* Release the context (not the caller's workspace).  NULL is accepted.     */
 void irk_destroy(irk_ctx *ctx);
 

@@ -19,6 +19,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -239,6 +241,10 @@ struct irk_ctx {
     std::vector<Rec> prof_pending;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
+    // the most recent launches (at most 32, all on one stream) of every
+    // kernel group, kept for back-to-back replay timing (irk_profile_replay)
+    struct Replay { hipStream_t strm = nullptr; std::vector<std::function<void()>> f; std::vector<double> nbytes; };
+    std::map<std::string, Replay> prof_rep;
 
     template <class T> T *lev(const Lane &ln, int l, int q) { return reinterpret_cast<T *>(ws + ln.lay->lev[l][q]); }
     template <class T> T *coef(int h, int l) { return reinterpret_cast<T *>(ws + P.off_coef[h][l]); }
@@ -287,6 +293,11 @@ static void prof_harvest(irk_ctx *c) {
             hipEvent_t e1_ = prof_event(c);                                            \
             if (e1_) (void)hipEventRecord(e1_, (st));                                  \
             (c)->prof_pending.push_back({prof_id(c, name), (double)(bytes), (long)(n), e0_, e1_}); \
+            auto &rp_ = (c)->prof_rep[name];                                           \
+            if (rp_.strm != (st)) { rp_.strm = (st); rp_.f.clear(); rp_.nbytes.clear(); }   \
+            if (rp_.f.size() >= 32) { rp_.f.erase(rp_.f.begin()); rp_.nbytes.erase(rp_.nbytes.begin()); } \
+            rp_.f.push_back([=]() { stmt; });                                          \
+            rp_.nbytes.push_back((double)(bytes));                                      \
         } else {                                                                       \
             stmt;                                                                      \
         }                                                                              \
@@ -1172,7 +1183,40 @@ extern "C" irk_status irk_profile_enable(irk_ctx *c, int enable) {
     c->prof_bytes.clear();
     c->prof_launches.clear();
     c->prof_pending.clear();
+    c->prof_rep.clear();
     c->ev_next = 0;
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_profile_replay(irk_ctx *c, const char *name, int reps, double *avg_ms,
+                                         double *avg_bytes) {
+    if (!c || !name || reps < 1 || !avg_ms) return IRK_E_ARG;
+    auto it = c->prof_rep.find(name);
+    if (it == c->prof_rep.end() || it->second.f.empty()) return IRK_E_ARG;
+    auto &rp = it->second;
+    HIP_TRY(hipDeviceSynchronize());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return IRK_E_DEVICE;
+    }
+    for (auto &f : rp.f) f();                      // warm
+    irk_status st = IRK_OK;
+    if (hipEventRecord(e0, rp.strm) != hipSuccess) st = IRK_E_DEVICE;
+    for (int r = 0; r < reps && st == IRK_OK; ++r)
+        for (auto &f : rp.f) f();
+    float ms = 0.f;
+    if (st == IRK_OK && (hipEventRecord(e1, rp.strm) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess))
+        st = IRK_E_DEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != IRK_OK) return st;
+    double by = 0;
+    for (double b : rp.nbytes) by += b;
+    *avg_ms = ms / ((double)reps * rp.f.size());
+    if (avg_bytes) *avg_bytes = by / rp.f.size();
     return IRK_OK;
 }
 

@@ -700,19 +700,27 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
         const double rr = (sq - 1.0) / (sq + 1.0);
         int iters = rr > 0.0 ? (int)ceil(log(2000.0) / -log(rr)) : 1;
         iters = iters < 2 ? 2 : (iters > s.coarse_iters ? s.coarse_iters : iters);
+        // Chebyshev step coefficients, one per thread from the closed form of
+        // the recurrence rho_k = 1 / (2 sigma1 - rho_{k-1}), rho_0 = 1/sigma1:
+        // rho_k = T_k(sigma1) / T_{k+1}(sigma1)
+        //       = e^{-a} (1 + e^{-2ka}) / (1 + e^{-2(k+1)a}),  a = acosh(sigma1);
+        // step k: d <- rho_k rho_{k-1} d + (2 rho_k / delta) r  (k = 0: r / theta)
         __shared__ T ccd[IRK_MAX_COARSE_ITERS], ccr[IRK_MAX_COARSE_ITERS];
-        if (threadIdx.x == 0) {
-            const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+        if ((int)threadIdx.x < iters) {
+            const int k = threadIdx.x;
+            const double theta = 0.5 * (lmax + lmin), delta = fmax(0.5 * (lmax - lmin), 1e-12 * theta);
             const double sig1 = theta / delta;
-            double rho_k = 1.0 / sig1;
-            for (int k = 0; k < iters; ++k) {
-                if (k == 0) { ccd[0] = T(0); ccr[0] = (T)(1.0 / theta); }
-                else {
-                    const double rn = 1.0 / (2.0 * sig1 - rho_k);
-                    ccd[k] = (T)(rn * rho_k);
-                    ccr[k] = (T)(2.0 * rn / delta);
-                    rho_k = rn;
-                }
+            const double a = log(sig1 + sqrt(sig1 * sig1 - 1.0));
+            auto rho = [&](int m) {
+                return exp(-a) * (1.0 + exp(-2.0 * m * a)) / (1.0 + exp(-2.0 * (m + 1) * a));
+            };
+            if (k == 0) {
+                ccd[0] = T(0);
+                ccr[0] = (T)(1.0 / theta);
+            } else {
+                const double rk = rho(k);
+                ccd[k] = (T)(rk * rho(k - 1));
+                ccr[k] = (T)(2.0 * rk / delta);
             }
         }
         __syncthreads();
@@ -849,8 +857,11 @@ size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, si
 template <class T>
 void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const MgIn &in, const MgOut &out) {
     const size_t shm = mg_subcycle_lds_bytes(opk, s.nlev, s.nx, s.ny, sizeof(T));
+    // threads: about half a point per thread on a 32^2 first level, one per
+    // point below (measured fastest); at least np0 / 4 (the first level's
+    // right-hand side is loaded four points per thread)
     const int np0 = s.nx[0] * s.ny[0];
-    const unsigned nt = np0 >= 1024 ? 1024 : ((np0 + 63) / 64) * 64;
+    const unsigned nt = np0 >= 2048 ? 1024 : (np0 >= 1024 ? 512 : (unsigned)(((np0 + 63) / 64) * 64));
     switch (opk) {
         case MG_NLDIFF: k_mg_subcycle<T, MG_NLDIFF><<<1, nt, shm, st>>>(s, in, out); break;
         case MG_BURGERS: k_mg_subcycle<T, MG_BURGERS><<<1, nt, shm, st>>>(s, in, out); break;

@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
     L.irk_profile_entry.restype = I
     L.irk_profile_entry.argtypes = [P, I, ctypes.c_char_p, I, ctypes.POINTER(ctypes.c_long),
                                     ctypes.POINTER(D), ctypes.POINTER(D)]
+    L.irk_profile_replay.restype = I
+    L.irk_profile_replay.argtypes = [P, ctypes.c_char_p, I, ctypes.POINTER(D), ctypes.POINTER(D)]
     _lib = L
     return L
 
@@ -245,6 +247,16 @@ def irk_profile_read(ctx) -> list:
                "irk_profile_entry")
         out.append({"name": buf.value.decode(), "launches": n.value, "ms": ms.value, "bytes": by.value})
     return out
+
+
+def irk_profile_replay(ctx, name: str, reps: int = 20) -> dict:
+    """Average duration (ms) and algorithmic bytes of one launch of a kernel
+    group, from back-to-back replays of its most recent recorded launches."""
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(lib().irk_profile_replay(ctx, name.encode(), reps, ctypes.byref(ms), ctypes.byref(by)),
+           "irk_profile_replay")
+    return {"ms": ms.value, "bytes": by.value}
 
 
 class Solver:
