@@ -104,6 +104,40 @@ def run_job(torch, irk, inputs, wl, steps, warmup, prec_fp32, profile=False):
     return wall, lat_ms, stats, prof, final
 
 
+def ablation(torch, irk, inputs, wl, steps):
+    """Preconditioner variants of the paper's solver study on the same job:
+    gamma* = eta + beta^2/eta vs gamma = eta in the 2x2 Schur approximation
+    (Table 4's comparison), and Newton-like (1) (each block linearized at its
+    largest-weight stage) vs (0) (last stage).  Preconditioner applications
+    are the paper's cost unit."""
+    problem, n, family, s, dt, _, nu = wl
+    op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
+    res = []
+    for gm, nl in ((0, 1), (1, 1), (0, 0), (1, 0)):
+        solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl))
+        u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(u)
+        t = 0.0
+        stats = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = solver.step(u, t, dt, out=b)
+            stats.append(st)
+            u, b = b, u
+            t += dt
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        solver.close()
+        res.append({"gamma": "gamma*" if gm == 0 else "eta", "newton_like": nl, "ms_per_step": 1e3 * wall / steps,
+                    "newton_its_per_step": sum(x["newton_its"] for x in stats) / steps,
+                    "krylov_its_per_step": sum(x["krylov_its"] for x in stats) / steps,
+                    "krylov_its_per_block": [sum(x["krylov_its_block"][k] for x in stats) / steps
+                                             for k in range(5)],
+                    "prec_applications_per_step": sum(x["prec_applications"] for x in stats) / steps})
+    return res
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a plain
@@ -282,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=None,
                     help="grid side of the oracle sample (default 128; 32 for the DAE, 96 for Gauss-5)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also compare gamma* vs eta and Newton-like (1) vs (0) on the workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -392,6 +428,8 @@ def main():
         out["kernel_share"] = [{"kernel": r["name"], "share": r["ms"] / tot, "launches": r["launches"],
                                 "avg_us": 1e3 * r["ms"] / max(1, r["launches"]),
                                 "GB/s": r["bytes"] / max(1e-12, r["ms"] * 1e-3) / 1e9} for r in prof[:8]]
+    if args.ablation:
+        out["ablation"] = ablation(torch, irk, inputs, wl, min(K, 20))
     if args.serve_sample > 0:
         out["serving"] = serve_bench(torch, irk, inputs, args.serve_sample, args.budget_gb, args.slots,
                                      args.load, args.serve_seed, fp64=not args.no_fp64)
