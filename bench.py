@@ -138,6 +138,45 @@ def ablation(torch, irk, inputs, wl, steps):
     return res
 
 
+def sdirk_compare(torch, irk, inputs, wl, steps):
+    """The paper's comparison on the same kernels: fully implicit Gauss /
+    Radau IIA against SDIRK of equal order on the same job (same dt, same
+    preconditioner: one V-cycle per real block or per diagonal of a 2x2
+    block), with the error at the end of the job against a Gauss-3 run at
+    dt/4 of the same semi-discrete system."""
+    problem, n, _, _, dt, _, nu = wl
+    op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
+
+    def job(family, s, dtt, nsteps):
+        solver = irk.Solver(family, s, op)
+        u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(u)
+        t, stats = 0.0, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            _, st = solver.step(u, t, dtt, out=b)
+            stats.append(st)
+            u, b = b, u
+            t += dtt
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        solver.close()
+        return u, wall, stats
+
+    ref, _, _ = job("gauss", 3, dt / 4, 4 * steps)
+    out = []
+    for order, fam, s in ((2, "gauss", 1), (2, "sdirk", 2), (3, "radau", 2), (3, "sdirk", 3),
+                          (4, "gauss", 2), (4, "sdirk", 5)):
+        u, wall, stats = job(fam, s, dt, steps)
+        err = float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
+        out.append({"order": order, "method": f"{fam}-{s}", "ms_per_step": 1e3 * wall / steps,
+                    "newton_its_per_step": sum(x["newton_its"] for x in stats) / steps,
+                    "prec_applications_per_step": sum(x["prec_applications"] for x in stats) / steps,
+                    "rel_error_at_end": err})
+    return {"dt": dt, "steps": steps, "reference": "gauss-3 at dt/4", "runs": out}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a plain
@@ -316,6 +355,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=None,
                     help="grid side of the oracle sample (default 128; 32 for the DAE, 96 for Gauss-5)")
+    ap.add_argument("--sdirk-compare", action="store_true",
+                    help="also compare Gauss/Radau IIA with SDIRK of equal order on the workload")
     ap.add_argument("--ablation", action="store_true",
                     help="also compare gamma* vs eta and Newton-like (1) vs (0) on the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -430,6 +471,8 @@ def main():
                                 "GB/s": r["bytes"] / max(1e-12, r["ms"] * 1e-3) / 1e9} for r in prof[:8]]
     if args.ablation:
         out["ablation"] = ablation(torch, irk, inputs, wl, min(K, 20))
+    if args.sdirk_compare:
+        out["sdirk_compare"] = sdirk_compare(torch, irk, inputs, wl, K)
     if args.serve_sample > 0:
         out["serving"] = serve_bench(torch, irk, inputs, args.serve_sample, args.budget_gb, args.slots,
                                      args.load, args.serve_seed, fp64=not args.no_fp64)

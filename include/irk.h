@@ -56,7 +56,14 @@ typedef enum irk_status {
 
 typedef enum irk_family {
     IRK_GAUSS = 0,          /* s-stage Gauss, order 2s                       */
-    IRK_RADAU_IIA = 1       /* s-stage Radau IIA, order 2s-1                 */
+    IRK_RADAU_IIA = 1,      /* s-stage Radau IIA, order 2s-1                 */
+    IRK_LOBATTO_IIIC = 2,   /* s-stage Lobatto IIIC, order 2s-2, s >= 2      */
+    IRK_SDIRK = 3           /* published L-stable SDIRK methods (comparison
+                               class): s = 1 backward Euler, 2 Alexander
+                               order 2, 3 Alexander order 3, 5 Hairer-Wanner
+                               order 4; the stages are solved one after
+                               another, each as a single real block with the
+                               same preconditioner (eta = 1/gamma)          */
 } irk_family;
 
 typedef enum irk_op_kind {
@@ -143,7 +150,8 @@ irk_status irk_tableau(irk_family family, int s, double *A, double *b, double *c
  * Blocks are ordered real first, then pairs by decreasing beta.  Host
  * outputs: T, Tinv (s x s row-major), nblocks, and per block its width
  * (1 or 2), eta, beta, gamma_* = eta + beta^2/eta (equation (gamma*)) and the
- * first transformed row it covers.  Arrays sized IRK_MAX_STAGES suffice.   */
+ * first transformed row it covers.  Arrays sized IRK_MAX_STAGES suffice.
+ * IRK_E_ARG for IRK_SDIRK (its stages are solved one after another).     */
 irk_status irk_eigen_blocks(irk_family family, int s, double *T, double *Tinv,
                             int *nblocks, int *width, double *eta, double *beta,
                             double *gamma_star, int *first_row);
@@ -182,12 +190,12 @@ irk_status irk_step(irk_ctx *ctx, const double *u_n, double t_n, double dt,
 /* Stage residual F_i(K) = M k_i - N(u_n + dt sum_j a_ij k_j, t_n + c_i dt)
  * (equation (stages) / (dae_stage)) for caller stage vectors K (device,
  * [s][field]) into F (device, [s][field]).  Evaluates exactly the residual
- * the Newton loop of irk_step uses.                                        */
+ * the Newton loop of irk_step uses.  IRK_E_UNSUPPORTED for IRK_SDIRK.    */
 irk_status irk_eval_residual(irk_ctx *ctx, const double *u_n, double t_n,
                              double dt, const double *K, double *F);
 
 /* Copy the stage vectors K of the last successful irk_step (device, [s][field])
- * into the caller's device buffer.                                          */
+ * into the caller's device buffer (for IRK_SDIRK the s stage derivatives). */
 irk_status irk_get_stages(irk_ctx *ctx, double *K);
 
 /* ------------------------------ measurement ------------------------------ */

@@ -9,6 +9,20 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
   a_ij = int_0^{c_i} l_j and b_j = int_0^1 l_j for the Lagrange basis l_j on c.
   Roots and integrals are computed with mpmath at 60 digits and rounded to
   float64 once, at the end.
+* Lobatto IIIC (named with Gauss and Radau IIA in Section 2.2 and Table 1)
+  has the Lobatto nodes c_1 = 0, c_s = 1 and the interior roots of the
+  derivative of P_{s-1}(2x-1), the Lobatto quadrature weights b_j =
+  int_0^1 l_j, and the A with first column a_i1 = b_1 that satisfies the
+  simplifying conditions C(s-1): sum_j a_ij c_j^{k-1} = c_i^k / k,
+  k = 1..s-1 (Chipman's construction); order 2s-2, stability function the
+  (s-2, s) Pade approximant.  s >= 2.
+* SDIRK (singly diagonally implicit, the paper's comparison class): the
+  paper prints no tableau, so the published L-stable methods are used:
+  s = 1 backward Euler; s = 2 Alexander's two-stage order-2 method
+  (gamma = 1 - 1/sqrt 2); s = 3 Alexander's three-stage order-3 method
+  (gamma the root of x^3 - 3x^2 + 3x/2 - 1/6 in (1/3, 1/2)); s = 5 the
+  five-stage order-4 method of Hairer and Wanner (gamma = 1/4).  All are
+  stiffly accurate (b = last row of A).
 * ``inverse_eigs`` gives the eigenvalues eta +- i beta of A0^{-1}
   (Section 3), ``gamma_star`` equation (gamma*), ``kappa_bound`` equation
   (kappa_gamma*_L1=L2) as tabulated in Table 1, and ``d_weights`` the vectors
@@ -60,6 +74,14 @@ def nodes(family: str, s: int) -> list:
                 return [mp.mpf(1)]
             pm = _shifted_legendre(s - 1) + [mp.mpf(0)]
             poly = [a - b for a, b in zip(ps, pm)]
+        elif family == "lobatto":
+            if s < 2:
+                raise ValueError("Lobatto IIIC needs s >= 2")
+            if s == 2:
+                return [mp.mpf(0), mp.mpf(1)]
+            q = _shifted_legendre(s - 1)
+            dq = [k * q[k] for k in range(1, len(q))]       # d/dx P_{s-1}(2x-1)
+            return [mp.mpf(0)] + _poly_roots_real(dq) + [mp.mpf(1)]
         else:
             raise ValueError(f"unknown family {family!r}")
         roots = _poly_roots_real(poly)
@@ -94,15 +116,59 @@ def tableau_mp(family: str, s: int):
     with mp.workdps(_DPS):
         c = nodes(family, s)
         basis = [_lagrange_coeffs(c, j) for j in range(s)]
-        A = [[_integral_0_to(basis[j], c[i]) for j in range(s)] for i in range(s)]
         b = [_integral_0_to(basis[j], mp.mpf(1)) for j in range(s)]
+        if family == "lobatto":
+            # a_i1 = b_1; the remaining s-1 entries of row i from C(s-1):
+            # sum_{j>=2} a_ij c_j^{k-1} = c_i^k / k - b_1 [k = 1], k = 1..s-1
+            V = mp.matrix(s - 1, s - 1)
+            for k in range(1, s):
+                for j in range(1, s):
+                    V[k - 1, j - 1] = c[j] ** (k - 1)
+            A = []
+            for i in range(s):
+                rhs = mp.matrix([c[i] ** k / k - (b[0] if k == 1 else 0) for k in range(1, s)])
+                x = mp.lu_solve(V, rhs)
+                A.append([b[0]] + [x[j] for j in range(s - 1)])
+        else:
+            A = [[_integral_0_to(basis[j], c[i]) for j in range(s)] for i in range(s)]
+    return A, b, c
+
+
+def _sdirk_mp(s: int):
+    """SDIRK tableaux of the published methods listed in the module notes."""
+    with mp.workdps(_DPS):
+        F = mp.mpf
+        if s == 1:
+            A = [[F(1)]]
+        elif s == 2:
+            g = 1 - 1 / mp.sqrt(2)
+            A = [[g, F(0)], [1 - g, g]]
+        elif s == 3:
+            g = mp.findroot(lambda x: x ** 3 - 3 * x ** 2 + F(3) / 2 * x - F(1) / 6, F("0.4358665"))
+            t2 = (1 + g) / 2
+            b1 = -(6 * g ** 2 - 16 * g + 1) / 4
+            b2 = (6 * g ** 2 - 20 * g + 5) / 4
+            A = [[g, F(0), F(0)], [t2 - g, g, F(0)], [b1, b2, g]]
+        elif s == 5:
+            q = mp.mpf
+            A = [[q(1) / 4, 0, 0, 0, 0],
+                 [q(1) / 2, q(1) / 4, 0, 0, 0],
+                 [q(17) / 50, -q(1) / 25, q(1) / 4, 0, 0],
+                 [q(371) / 1360, -q(137) / 2720, q(15) / 544, q(1) / 4, 0],
+                 [q(25) / 24, -q(49) / 48, q(125) / 16, -q(85) / 12, q(1) / 4]]
+            A = [[mp.mpf(v) for v in row] for row in A]
+        else:
+            raise ValueError("SDIRK methods are provided for s in {1, 2, 3, 5}")
+        b = list(A[-1])
+        c = [sum(row) for row in A]
     return A, b, c
 
 
 def tableau(family: str, s: int):
-    """Butcher tableau (A0, b0, c0) of the s-stage Gauss or Radau IIA method,
-    rounded to float64 from the extended-precision construction."""
-    A, b, c = tableau_mp(family, s)
+    """Butcher tableau (A0, b0, c0) of the s-stage Gauss, Radau IIA or
+    Lobatto IIIC method, rounded to float64 from the extended-precision
+    construction."""
+    A, b, c = _sdirk_mp(s) if family == "sdirk" else tableau_mp(family, s)
     return (np.array([[float(v) for v in row] for row in A]),
             np.array([float(v) for v in b]),
             np.array([float(v) for v in c]))

@@ -83,6 +83,11 @@ struct Plan {
     size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
     LaneLayout lane[IRK_MAX_STAGES];
+    // SDIRK: the method's own tableau; the machinery above runs one stage at
+    // a time as a 1-stage method (s = 1, A = [gamma], c = [c_i])
+    int sd_s = 0;
+    double sd_A[IRK_MAX_STAGES * IRK_MAX_STAGES], sd_b[IRK_MAX_STAGES], sd_c[IRK_MAX_STAGES];
+    size_t off_Ksd = 0, off_Uin = 0, off_Uout = 0;
     size_t total = 0;
 };
 
@@ -96,7 +101,8 @@ static bool valid_options(const irk_options &o) {
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
     if (!op || s < 1 || s > IRK_MAX_STAGES) return IRK_E_ARG;
-    if (family != IRK_GAUSS && family != IRK_RADAU_IIA) return IRK_E_ARG;
+    if (family != IRK_GAUSS && family != IRK_RADAU_IIA && family != IRK_LOBATTO_IIIC && family != IRK_SDIRK)
+        return IRK_E_ARG;
     P->op = *op;
     if (opt) P->opt = *opt; else irk_default_options(&P->opt);
     if (!valid_options(P->opt)) return IRK_E_ARG;
@@ -111,7 +117,18 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     } else {
         return IRK_E_ARG;
     }
-    if (!build_eigen_blocks(family, s, &P->eb)) return IRK_E_ARG;
+    const int s_sd = s;
+    if (family == IRK_SDIRK) {
+        long double A[IRK_MAX_STAGES * IRK_MAX_STAGES], b[IRK_MAX_STAGES], c[IRK_MAX_STAGES];
+        if (!build_tableau_ld(family, s, A, b, c)) return IRK_E_ARG;
+        P->sd_s = s;
+        for (int i = 0; i < s * s; ++i) P->sd_A[i] = (double)A[i];
+        for (int i = 0; i < s; ++i) { P->sd_b[i] = (double)b[i]; P->sd_c[i] = (double)c[i]; }
+        build_sdirk_stage_block(P->sd_A[0], P->sd_c[0], &P->eb);
+        s = 1;
+    } else if (!build_eigen_blocks(family, s, &P->eb)) {
+        return IRK_E_ARG;
+    }
     for (int k = 0; k < P->eb.nblocks; ++k)
         if (!(P->eb.eta[k] > 0)) return IRK_E_UNSUPPORTED;     // Assumption 1
     P->family = family;
@@ -175,6 +192,11 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
             const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
             for (int q = 0; q < 4; ++q) ln.lev[l][q] = take(n * P->tsz);
         }
+    }
+    if (family == IRK_SDIRK) {
+        P->off_Ksd = take((size_t)s_sd * P->nf * f64);
+        P->off_Uin = take(P->nf * f64);
+        P->off_Uout = take(P->nf * f64);
     }
     P->total = off;
     return IRK_OK;
@@ -854,6 +876,8 @@ struct Stepper : StepperBase {
         }
         if (start == START_EXPLICIT) {
             start = START_CHOSEN;
+            if (debug_level())
+                fprintf(stderr, "[irk] start candidates: |F(0)| %.6e |F(explicit)| %.6e\n", res_zero, res);
             if (!(res < res_zero)) {
                 // zero wins (ties included): back to K = 0
                 PROF(c, c->stream, "k_fill", 8.0 * P.s * P.nf, 1,
@@ -951,6 +975,102 @@ struct Stepper : StepperBase {
                 continue;
             }
             if (!progressed) return false;
+        }
+    }
+};
+
+// SDIRK (the comparison class): the stages are solved one after another.
+// Stage i is the 1-stage problem k_i = N(u' + dt gamma k_i, t_n + c_i dt)
+// with u' = u_n + dt sum_{j<i} a_ij k_j, i.e. the machinery above with
+// A = [gamma], c = [c_i] on the state u' (one real block, eta = 1/gamma);
+// then u_{n+1} = u_n + dt sum_i b_i k_i.
+template <class T>
+struct SdirkStepper : StepperBase {
+    irk_ctx *c;
+    Stepper<T> inner;
+    enum Phase { STAGE, FINAL_WAIT, DONE } phase = DONE;
+    const double *u_n = nullptr;
+    double *u_np1 = nullptr;
+    double t_n = 0, dt = 0, rtol = 0;
+    int stage = 0;
+
+    explicit SdirkStepper(irk_ctx *cc) : c(cc), inner(cc) {}
+
+    double *Ksd() { return reinterpret_cast<double *>(c->ws + c->P.off_Ksd); }
+
+    bool fail(irk_status e) {
+        status = e;
+        phase = DONE;
+        return true;
+    }
+
+    void start_stage() {
+        Plan &P = c->P;
+        P.eb.c[0] = P.sd_c[stage];
+        const double *u_in = u_n;
+        if (stage > 0) {
+            StageCoefs C;
+            std::memset(&C, 0, sizeof(C));
+            for (int j = 0; j < stage; ++j) C.b[j] = P.sd_A[stage * P.sd_s + j];
+            double *uin = reinterpret_cast<double *>(c->ws + P.off_Uin);
+            PROF(c, c->stream, "k_final_update<" + std::to_string(stage) + ">", 8.0 * P.nf * (stage + 2), 1,
+                 launch_final_update(c->stream, stage, P.nf, u_n, Ksd(), uin, C, dt));
+            u_in = uin;
+        }
+        inner.begin(u_in, t_n, dt, rtol, reinterpret_cast<double *>(c->ws + P.off_Uout));
+    }
+
+    void begin(const double *un, double tn, double dtt, double rt, double *out) override {
+        u_n = un;
+        u_np1 = out;
+        t_n = tn;
+        dt = dtt;
+        rtol = rt;
+        stage = 0;
+        std::memset(&stats, 0, sizeof(stats));
+        status = IRK_OK;
+        phase = STAGE;
+        start_stage();
+    }
+
+    bool poll() override {
+        const Plan &P = c->P;
+        for (;;) {
+            if (phase == DONE) return true;
+            if (phase == FINAL_WAIT) {
+                const hipError_t q = hipEventQuery(c->ev_res);
+                if (q == hipErrorNotReady) return false;
+                if (q != hipSuccess) return fail(IRK_E_DEVICE);
+                phase = DONE;
+                return true;
+            }
+            if (!inner.poll()) return false;
+            const irk_stats &is = inner.stats;
+            stats.newton_its += is.newton_its;
+            stats.krylov_its += is.krylov_its;
+            stats.krylov_its_block[stage] += is.krylov_its;
+            stats.vcycles += is.vcycles;
+            stats.prec_applications += is.prec_applications;
+            stats.res0 = std::max(stats.res0, is.res0);
+            stats.final_res = std::max(stats.final_res, is.final_res);
+            if (inner.status != IRK_OK) return fail(inner.status);
+            if (debug_level())
+                fprintf(stderr, "[irk] sdirk stage %d done: newton %d krylov %d res0 %.3e final %.3e\n", stage,
+                        is.newton_its, is.krylov_its, is.res0, is.final_res);
+            if (hipMemcpyAsync(Ksd() + (size_t)stage * P.nf, c->K, P.nf * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream) != hipSuccess)
+                return fail(IRK_E_DEVICE);
+            if (++stage < P.sd_s) {
+                start_stage();
+                continue;
+            }
+            StageCoefs C;
+            std::memset(&C, 0, sizeof(C));
+            for (int i = 0; i < P.sd_s; ++i) C.b[i] = P.sd_b[i];
+            PROF(c, c->stream, "k_final_update<" + std::to_string(P.sd_s) + ">", 8.0 * P.nf * (P.sd_s + 2), 1,
+                 launch_final_update(c->stream, P.sd_s, P.nf, u_n, Ksd(), u_np1, C, dt));
+            if (hipEventRecord(c->ev_res, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
+            phase = FINAL_WAIT;
         }
     }
 };
@@ -1069,8 +1189,13 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         release(c);
         return IRK_E_DEVICE;
     }
-    if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) Stepper<float>(c);
-    else c->stepper = new (std::nothrow) Stepper<double>(c);
+    if (c->P.sd_s > 0) {
+        if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) SdirkStepper<float>(c);
+        else c->stepper = new (std::nothrow) SdirkStepper<double>(c);
+    } else {
+        if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) Stepper<float>(c);
+        else c->stepper = new (std::nothrow) Stepper<double>(c);
+    }
     if (!c->stepper) {
         release(c);
         return IRK_E_NOMEM;
@@ -1125,7 +1250,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         release(c);
         return IRK_E_DEVICE;
     }
-    launch_fill(c->stream, c->Y, 0.0, (size_t)s * P.nf);
+    launch_fill(c->stream, c->Y, 0.0, (size_t)P.s * P.nf);   // the plan's s (1 for SDIRK)
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         release(c);
         return IRK_E_DEVICE;
@@ -1235,6 +1360,7 @@ extern "C" irk_status irk_profile_entry(irk_ctx *c, int idx, char *name, int nam
 extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_n, double dt, const double *K,
                                         double *F) {
     if (!c || !u_n || !K || !F || !(dt > 0)) return IRK_E_ARG;
+    if (c->P.sd_s > 0) return IRK_E_UNSUPPORTED;        // stages are solved one at a time
     const Plan &P = c->P;
     const int s = P.s;
     const size_t bytes = (size_t)s * P.nf * sizeof(double);
@@ -1257,7 +1383,9 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
 extern "C" irk_status irk_get_stages(irk_ctx *c, double *K) {
     if (!c || !K) return IRK_E_ARG;
     if (!c->have_stages) return IRK_E_ARG;
-    HIP_TRY(hipMemcpyAsync(K, c->K, (size_t)c->P.s * c->P.nf * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    const double *src = c->P.sd_s > 0 ? reinterpret_cast<const double *>(c->ws + c->P.off_Ksd) : c->K;
+    const int ns = c->P.sd_s > 0 ? c->P.sd_s : c->P.s;
+    HIP_TRY(hipMemcpyAsync(K, src, (size_t)ns * c->P.nf * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return IRK_OK;
 }

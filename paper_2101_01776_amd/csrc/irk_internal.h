@@ -28,6 +28,7 @@ struct EigenBlocks {
 
 bool build_tableau_ld(int family, int s, long double *A, long double *b, long double *c);
 bool build_eigen_blocks(int family, int s, EigenBlocks *eb);
+void build_sdirk_stage_block(double gamma, double ci, EigenBlocks *eb);
 
 // Small constant blocks passed to kernels by value.
 struct StageCoefs {

@@ -96,8 +96,49 @@ static ld integrate0(const std::vector<ld> &p, ld x) {
     return s;
 }
 
+// Published L-stable SDIRK methods (lower triangular A with constant
+// diagonal gamma, stiffly accurate: b = last row, c = row sums).
+static bool sdirk_tableau(int s, ld *A, ld *b, ld *c) {
+    for (int i = 0; i < s * s; ++i) A[i] = 0;
+    if (s == 1) {
+        A[0] = 1;                                   // backward Euler
+    } else if (s == 2) {                            // Alexander, order 2
+        const ld g = 1.0L - 1.0L / sqrtl(2.0L);
+        A[0] = g;
+        A[2] = 1.0L - g; A[3] = g;
+    } else if (s == 3) {                            // Alexander, order 3
+        // gamma: root of x^3 - 3x^2 + 3x/2 - 1/6 in (1/3, 1/2), by Newton
+        ld g = 0.4358665L;
+        for (int it = 0; it < 20; ++it)
+            g -= (g * g * g - 3 * g * g + 1.5L * g - 1.0L / 6) / (3 * g * g - 6 * g + 1.5L);
+        const ld t2 = 0.5L * (1 + g);
+        const ld b1 = -(6 * g * g - 16 * g + 1) / 4, b2 = (6 * g * g - 20 * g + 5) / 4;
+        A[0] = g;
+        A[3] = t2 - g; A[4] = g;
+        A[6] = b1; A[7] = b2; A[8] = g;
+    } else if (s == 5) {                            // Hairer-Wanner, order 4
+        const ld r[5][5] = {{1.0L / 4, 0, 0, 0, 0},
+                            {1.0L / 2, 1.0L / 4, 0, 0, 0},
+                            {17.0L / 50, -1.0L / 25, 1.0L / 4, 0, 0},
+                            {371.0L / 1360, -137.0L / 2720, 15.0L / 544, 1.0L / 4, 0},
+                            {25.0L / 24, -49.0L / 48, 125.0L / 16, -85.0L / 12, 1.0L / 4}};
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) A[i * 5 + j] = r[i][j];
+    } else {
+        return false;
+    }
+    for (int i = 0; i < s; ++i) {
+        ld sum = 0;
+        for (int j = 0; j < s; ++j) sum += A[i * s + j];
+        c[i] = sum;
+        b[i] = A[(s - 1) * s + i];
+    }
+    return true;
+}
+
 bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
     if (s < 1 || s > IRK_MAX_STAGES) return false;
+    if (family == IRK_SDIRK) return sdirk_tableau(s, A, b, c);
     std::vector<ld> nodes;
     if (family == IRK_GAUSS) {
         nodes = roots_unit_interval(shifted_legendre(s), s);
@@ -115,6 +156,17 @@ bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
             nodes = roots_unit_interval(d, s - 1);
             nodes.push_back(1.0L);
         }
+    } else if (family == IRK_LOBATTO_IIIC) {
+        // nodes 0, the roots of d/dx P_{s-1}(2x-1), 1
+        if (s < 2) return false;
+        nodes.push_back(0.0L);
+        if (s > 2) {
+            std::vector<ld> q = shifted_legendre(s - 1), dq(s - 1);
+            for (int k = 1; k < s; ++k) dq[k - 1] = k * q[k];
+            std::vector<ld> r = roots_unit_interval(dq, s - 2);
+            nodes.insert(nodes.end(), r.begin(), r.end());
+        }
+        nodes.push_back(1.0L);
     } else {
         return false;
     }
@@ -124,6 +176,32 @@ bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
         std::vector<ld> l = lagrange(nodes, j);
         for (int i = 0; i < s; ++i) A[i * s + j] = integrate0(l, nodes[i]);
         b[j] = integrate0(l, 1.0L);
+    }
+    if (family == IRK_LOBATTO_IIIC) {
+        // a_i1 = b_1 and the simplifying conditions C(s-1) for the other
+        // entries of each row: sum_{j>=2} a_ij c_j^{k-1} = c_i^k/k - b_1 [k=1]
+        const int m = s - 1;
+        for (int i = 0; i < s; ++i) {
+            ld M[IRK_MAX_STAGES][IRK_MAX_STAGES + 1];
+            for (int k = 1; k <= m; ++k) {
+                for (int j = 1; j < s; ++j) M[k - 1][j - 1] = powl(nodes[j], (ld)(k - 1));
+                M[k - 1][m] = powl(nodes[i], (ld)k) / k - (k == 1 ? b[0] : 0.0L);
+            }
+            for (int col = 0; col < m; ++col) {             // Gaussian elimination, partial pivoting
+                int piv = col;
+                for (int r = col + 1; r < m; ++r)
+                    if (fabsl(M[r][col]) > fabsl(M[piv][col])) piv = r;
+                for (int q = 0; q <= m; ++q) std::swap(M[col][q], M[piv][q]);
+                if (M[col][col] == 0) return false;
+                for (int r = 0; r < m; ++r) {
+                    if (r == col) continue;
+                    const ld f = M[r][col] / M[col][col];
+                    for (int q = col; q <= m; ++q) M[r][q] -= f * M[col][q];
+                }
+            }
+            A[i * s] = b[0];
+            for (int j = 1; j < s; ++j) A[i * s + j] = M[j - 1][m] / M[j - 1][j - 1];
+        }
     }
     for (int i = 0; i < s; ++i) c[i] = nodes[i];
     return true;
@@ -253,7 +331,28 @@ static std::vector<cld> null_vector(int n, const ld *M, cld lam) {
     return v;
 }
 
+// One SDIRK stage as a 1-stage method: A = [gamma], b = [1], c = [c_i];
+// one real block, eta = 1/gamma.
+void build_sdirk_stage_block(double gamma, double ci, EigenBlocks *eb) {
+    *eb = EigenBlocks();
+    eb->s = 1;
+    eb->nblocks = 1;
+    eb->A[0] = gamma;
+    eb->Ainv[0] = 1.0 / gamma;
+    eb->b[0] = 1.0;
+    eb->c[0] = ci;
+    eb->T[0] = eb->Tinv[0] = 1.0;
+    eb->TLam[0] = 1.0 / gamma;
+    eb->width[0] = 1;
+    eb->first[0] = 0;
+    eb->eta[0] = 1.0 / gamma;
+    eb->beta[0] = 0.0;
+    eb->gamma_star[0] = 1.0 / gamma;
+    eb->argmax_stage[0] = 0;
+}
+
 bool build_eigen_blocks(int family, int s, EigenBlocks *eb) {
+    if (family == IRK_SDIRK) return false;         // stages are sequential, no eigenbasis
     ld A[IRK_MAX_STAGES * IRK_MAX_STAGES], b[IRK_MAX_STAGES], c[IRK_MAX_STAGES];
     if (!build_tableau_ld(family, s, A, b, c)) return false;
     ld Ai[IRK_MAX_STAGES * IRK_MAX_STAGES];

@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libirk.so")
 
 IRK_MAX_STAGES = 5
 
-GAUSS, RADAU_IIA = 0, 1
+GAUSS, RADAU_IIA, LOBATTO_IIIC, SDIRK = 0, 1, 2, 3
 OP_BURGERS_1D, OP_NLDIFF_2D, OP_VSF_2D = 0, 1, 2
 FORCING_NONE, FORCING_MMS, FORCING_MMS_DISCRETE = 0, 1, 2
 
 STATUS = {0: "IRK_OK", -1: "IRK_E_ARG", -2: "IRK_E_NOMEM", -3: "IRK_E_NOCONV",
           -4: "IRK_E_NONFINITE", -5: "IRK_E_DEVICE", -6: "IRK_E_UNSUPPORTED", -7: "IRK_E_BUSY"}
 
-FAMILY = {"gauss": GAUSS, "radau": RADAU_IIA}
+FAMILY = {"gauss": GAUSS, "radau": RADAU_IIA, "lobatto": LOBATTO_IIIC, "sdirk": SDIRK}
 
 
 class IrkError(RuntimeError):

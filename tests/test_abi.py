@@ -31,6 +31,32 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
 
 
+def test_lobatto_needs_two_stages():
+    import ctypes
+    A = (ctypes.c_double * 1)()
+    b = (ctypes.c_double * 1)()
+    c = (ctypes.c_double * 1)()
+    assert irk.lib().irk_tableau(irk.LOBATTO_IIIC, 1, A, b, c) == -1
+    assert irk.irk_workspace_bytes("lobatto", 1, irk.make_operator(irk.OP_NLDIFF_2D, 32)) == 0
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 5])
+def test_host_sdirk_tableau_matches_oracle(s):
+    A, b, c = irk.irk_tableau("sdirk", s)
+    Ao, bo, co = tb.tableau("sdirk", s)
+    assert np.max(np.abs(np.asarray(A) - Ao)) < 2e-16 * max(1.0, np.abs(Ao).max())
+    assert np.max(np.abs(np.asarray(b) - bo)) < 2e-16 * max(1.0, np.abs(bo).max())
+    assert np.max(np.abs(np.asarray(c) - co)) < 2e-16
+
+
+def test_sdirk_shapes_and_unsupported_calls():
+    op = irk.make_operator(irk.OP_NLDIFF_2D, 64)
+    assert irk.irk_workspace_bytes("sdirk", 4, op) == 0          # no 4-stage method provided
+    assert irk.irk_workspace_bytes("sdirk", 5, op) > irk.irk_workspace_bytes("sdirk", 1, op)
+    with pytest.raises(irk.IrkError):
+        irk.irk_eigen_blocks("sdirk", 2)
+
+
 def test_status_strings_and_defaults():
     L = irk.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
@@ -40,8 +66,8 @@ def test_status_strings_and_defaults():
     assert o.prec_fp32 == 1 and o.cheb_degree == 3 and o.newton_like == 1 and o.gamma_mode == 0
 
 
-@pytest.mark.parametrize("family", ["gauss", "radau"])
-@pytest.mark.parametrize("s", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("family,s", [(f, s) for f in ("gauss", "radau", "lobatto") for s in (1, 2, 3, 4, 5)
+                                      if not (f == "lobatto" and s == 1)])
 def test_host_tableau_matches_oracle(family, s):
     A, b, c = irk.irk_tableau(family, s)
     A2, b2, c2 = tb.tableau(family, s)
@@ -49,8 +75,8 @@ def test_host_tableau_matches_oracle(family, s):
     assert np.max(np.abs(c - c2)) <= 1e-16
 
 
-@pytest.mark.parametrize("family", ["gauss", "radau"])
-@pytest.mark.parametrize("s", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("family,s", [(f, s) for f in ("gauss", "radau", "lobatto") for s in (1, 2, 3, 4, 5)
+                                      if not (f == "lobatto" and s == 1)])
 def test_host_eigenbasis(family, s):
     """A0^{-1} = T Lambda T^{-1} with Lambda in the real block form, eigenvalues
     and gamma_* equal to the oracle's."""

@@ -19,6 +19,7 @@ RES_CASES = [
     ("burgers-ragged", irk.make_operator(irk.OP_BURGERS_1D, 250, nu=0.01), "radau", 3),
     ("vsf", irk.make_operator(irk.OP_VSF_2D, 48, nu=1e-3), "radau", 3),
     ("vsf-ragged", irk.make_operator(irk.OP_VSF_2D, 30, nu=1e-3), "gauss", 2),
+    ("nldiff-lobatto4", irk.make_operator(irk.OP_NLDIFF_2D, 36, forcing=irk.FORCING_MMS), "lobatto", 4),
 ]
 
 
@@ -53,6 +54,21 @@ STEP_CASES = [
     ("burgers-radau3", irk.make_operator(irk.OP_BURGERS_1D, 128, nu=0.01), "radau", 3, 1e-2),
     ("vsf-radau3", irk.make_operator(irk.OP_VSF_2D, 32, nu=1e-3), "radau", 3, 2e-3),
     ("vsf-gauss2", irk.make_operator(irk.OP_VSF_2D, 24, nu=1e-3), "gauss", 2, 2e-3),
+    ("nldiff-lobatto2", irk.make_operator(irk.OP_NLDIFF_2D, 32, forcing=irk.FORCING_MMS), "lobatto", 2, 5e-3),
+    ("nldiff-lobatto3-96", irk.make_operator(irk.OP_NLDIFF_2D, 96, forcing=irk.FORCING_MMS), "lobatto", 3, 5e-3),
+    ("burgers-lobatto4", irk.make_operator(irk.OP_BURGERS_1D, 128, nu=0.01), "lobatto", 4, 1e-2),
+    ("vsf-lobatto3", irk.make_operator(irk.OP_VSF_2D, 24, nu=1e-3), "lobatto", 3, 2e-3),
+    # SDIRK comparison methods: stages solved one after another on the same
+    # kernels (one real block per stage)
+    ("nldiff-sdirk2", irk.make_operator(irk.OP_NLDIFF_2D, 48, forcing=irk.FORCING_MMS), "sdirk", 2, 5e-3),
+    ("nldiff-sdirk3-96", irk.make_operator(irk.OP_NLDIFF_2D, 96, forcing=irk.FORCING_MMS), "sdirk", 3, 5e-3),
+    ("nldiff-sdirk4", irk.make_operator(irk.OP_NLDIFF_2D, 40, forcing=irk.FORCING_MMS), "sdirk", 5, 5e-3),
+    # 96^2: large enough that a context-setup fill sized by the method's s
+    # instead of the solver's would reach the forcing tables
+    ("nldiff-sdirk4-96", irk.make_operator(irk.OP_NLDIFF_2D, 96, forcing=irk.FORCING_MMS), "sdirk", 5, 5e-3),
+    ("burgers-sdirk3", irk.make_operator(irk.OP_BURGERS_1D, 128, nu=0.01), "sdirk", 3, 1e-2),
+    ("vsf-sdirk4", irk.make_operator(irk.OP_VSF_2D, 24, nu=1e-3), "sdirk", 5, 2e-3),
+    ("nldiff-backward-euler", irk.make_operator(irk.OP_NLDIFF_2D, 32, forcing=irk.FORCING_MMS), "sdirk", 1, 5e-3),
 ]
 
 

@@ -14,7 +14,8 @@ from oracle import problems as pb
 from oracle import tableau as tb
 from paper_2101_01776_amd import inputs
 
-FAMS = [("gauss", s) for s in (1, 2, 3, 4, 5)] + [("radau", s) for s in (1, 2, 3, 4, 5)]
+FAMS = ([("gauss", s) for s in (1, 2, 3, 4, 5)] + [("radau", s) for s in (1, 2, 3, 4, 5)] +
+        [("lobatto", s) for s in (2, 3, 4, 5)] + [("sdirk", s) for s in (1, 2, 3, 5)])
 
 
 class _Diagonal:
@@ -40,7 +41,9 @@ def test_scalar_step_is_stability_function(family, s):
     dt = 0.1
     u1, _, _ = nw.irk_step(_Diagonal(lam), A, b, c, u0, 0.0, dt)
     want = np.array([tb.stability_function(A, b, dt * l).real for l in lam]) * u0
-    assert np.max(np.abs(u1 - want) / np.maximum(np.abs(want), 1e-300)) < 1e-13
+    # relative to the value, plus a rounding allowance on the input scale for
+    # the strongly damped stiff mode (L-stable methods: R(-300) ~ 1e-5)
+    assert np.all(np.abs(u1 - want) <= 1e-13 * np.abs(want) + 4e-15 * np.abs(u0))
 
 
 @pytest.mark.parametrize("family,s", [("gauss", 3), ("radau", 3), ("gauss", 5)])
@@ -76,9 +79,12 @@ def test_matches_minpack_root(family, s):
 
 
 @pytest.mark.parametrize("family,s", [("gauss", 1), ("gauss", 2), ("gauss", 3),
-                                      ("radau", 1), ("radau", 2), ("radau", 3)])
+                                      ("radau", 1), ("radau", 2), ("radau", 3),
+                                      ("lobatto", 2), ("lobatto", 3), ("lobatto", 4),
+                                      ("sdirk", 2), ("sdirk", 3), ("sdirk", 5)])
 def test_order_of_accuracy(family, s):
-    """Observed order 2s (Gauss) / 2s-1 (Radau IIA) on 1-D Burgers (n=32),
+    """Observed order 2s (Gauss) / 2s-1 (Radau IIA) / 2s-2 (Lobatto IIIC) /
+    2, 3, 4 (the SDIRK methods with 2, 3, 5 stages) on 1-D Burgers (n=32),
     against an explicit DOP853 reference at rtol 1e-13."""
     n, nu, T = 32, 0.01, 0.4
     prob = pb.Burgers1D(n, nu)
@@ -86,7 +92,7 @@ def test_order_of_accuracy(family, s):
     ref = si.solve_ivp(lambda t, u: prob.rhs(u, t), (0, T), u0, method="DOP853",
                        rtol=1e-13, atol=1e-15).y[:, -1]
     A, b, c = tb.tableau(family, s)
-    p = 2 * s if family == "gauss" else 2 * s - 1
+    p = {"gauss": 2 * s, "radau": 2 * s - 1, "lobatto": 2 * s - 2, "sdirk": {2: 2, 3: 3, 5: 4}.get(s)}[family]
     dts = [0.1, 0.05, 0.025] if p >= 5 else [0.05, 0.025, 0.0125]
     errs = []
     for dt in dts:
