@@ -58,10 +58,13 @@ def make_problem(irk, inputs, problem, n, nu):
     return irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS), inputs.nldiff_u0(n), n * n
 
 
+BATCH_MG = 0      # shared V-cycle launches (irk_options.batch_mg), off by default
+
+
 def run_job(torch, irk, inputs, wl, steps, warmup, prec_fp32, profile=False):
     problem, n, family, s, dt, _, nu = wl
     op, u_init, _ = make_problem(irk, inputs, problem, n, nu)
-    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=prec_fp32))
+    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=prec_fp32, batch_mg=BATCH_MG))
     u0 = torch.tensor(u_init, dtype=torch.float64, device="cuda")
     a = u0.clone()
     b = torch.empty_like(a)
@@ -268,7 +271,7 @@ def serve_run(torch, irk, reqs, fields, lam, prec_fp32, budget, slots, arena):
     at lam requests/s.  Returns wall time, per-request latencies (arrival to
     result, ms), per-step latencies (ms) and serving statistics."""
     ops = {n: irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS) for n in {r.n for r in reqs}}
-    opt = irk.make_options(prec_fp32=prec_fp32)
+    opt = irk.make_options(prec_fp32=prec_fp32, batch_mg=BATCH_MG)
     outs = [torch.empty_like(f) for f in fields]
     arrive = [0.0] * len(reqs) if lam is None else [r.arrival / lam for r in reqs]
     srv = irk.Server(budget, slots, arena=arena)
@@ -359,6 +362,8 @@ def main():
                     help="also compare Gauss/Radau IIA with SDIRK of equal order on the workload")
     ap.add_argument("--ablation", action="store_true",
                     help="also compare gamma* vs eta and Newton-like (1) vs (0) on the workload")
+    ap.add_argument("--batch-mg", action="store_true",
+                    help="run the V-cycles of blocks/requests that wait together as shared launches")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -384,6 +389,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     irk.lib()
+    global BATCH_MG
+    BATCH_MG = 1 if args.batch_mg else 0
     if args.copy_probe:
         copy_probe(torch)
     if args.serve:

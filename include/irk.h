@@ -111,6 +111,10 @@ typedef struct irk_options {
     int cheb_degree;        /* Chebyshev pre- and post-smoothing degree       */
     int mg_coarsest;        /* coarsest grid side of the V-cycle hierarchy    */
     int coarse_iters;       /* Chebyshev iterations on the coarsest level     */
+    int batch_mg;           /* 1: V-cycles of blocks (and, in a server, of
+                               requests) waiting at the same time run in
+                               shared launches; 0: one launch sequence per
+                               V-cycle on its block's stream                 */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -134,7 +138,9 @@ const char *irk_status_str(irk_status st);
  * Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||F(K0)||),
  * krylov_rtol 1e-5 (the paper's GMRES tolerance, Section 7.1), restart 30,
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
- * cheb_degree 3, mg_coarsest 8, coarse_iters 24.                           */
+ * cheb_degree 3, mg_coarsest 8, coarse_iters 24, batch_mg 0 (shared
+ * launches couple the blocks' progress and were measured slower on the
+ * bench workloads; see the option).                                         */
 void irk_default_options(irk_options *opt);
 
 /* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,

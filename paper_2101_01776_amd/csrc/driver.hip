@@ -96,7 +96,7 @@ static bool valid_options(const irk_options &o) {
            (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
-           o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0;
+           o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -227,6 +227,7 @@ struct Lane {
     int blk = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr, done = nullptr;
+    hipEvent_t ev_prec = nullptr;       // lane work before a shared V-cycle batch
     double *V = nullptr, *Z = nullptr, *part = nullptr, *dv = nullptr;
     double *pin = nullptr;
     size_t ldv = 0;
@@ -245,13 +246,16 @@ struct irk_ctx {
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
     hipEvent_t ev_res = nullptr;        // Newton-level readbacks
     StepperBase *stepper = nullptr;
+    // V-cycle batching: a broker of the context's precision (PrecBroker<T>),
+    // private (owned, batches this context's blocks) or a server's (shared)
+    void *broker = nullptr;
+    bool broker_owned = false;
     Lane lanes[IRK_MAX_STAGES];
     int nlanes = 0;
     bool have_stages = false;
     // Chebyshev smoothing coefficients
     double cheb_cd[8], cheb_cr[8];
-    double coarse_cd[64], coarse_cr[64];
-    double lmax = 2.0, lmin = 0.5, coarse_lmin = 0.1;
+    double lmax = 2.0, lmin = 0.5;
     irk_stats *st = nullptr;
     double dt = 0;
     // optional per-kernel timing with HIP events (irk_profile_enable)
@@ -376,19 +380,39 @@ static irk_status lane_write(Lane &ln, double *dev, const double *host, int coun
 // One V-cycle on a lane's hierarchy: tiled down sweeps on levels 0..l0-1, the
 // rest of the cycle inside one work-group, tiled up sweeps back to level 0.
 // The finest level reads its right-hand side from float64 vectors (in) and
-// writes the float64 result (out).
+// writes the float64 result (out).  A V-cycle is first described as a job
+// (all kernel arguments), then either launched on its lane's stream or
+// batched with the V-cycles of other lanes (and of other contexts).
 // ---------------------------------------------------------------------------
 template <class T>
-static void vcycle(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int hier, const MgIn &in,
-                   const MgOut &out) {
+struct VcJob {
+    int opk = 0, l0 = 0, deg = 3;
+    hipStream_t st = nullptr;
+    MgLevelArgs<T> lev[IRK_MAX_LEVELS];
+    MgSubArgs<T> sub;
+    MgIn in;
+    MgOut out;
+    double by_down[IRK_MAX_LEVELS], by_up[IRK_MAX_LEVELS], by_sub = 0;   // algorithmic bytes
+};
+
+template <class T>
+static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int hier, const MgIn &in,
+                       const MgOut &out, VcJob<T> *J) {
     const Plan &P = c->P;
     const int L = P.lg.nlev, l0 = P.l0, deg = P.opt.cheb_degree;
     const double nu = P.op.nu;
     const double ts = sizeof(T);
-    hipStream_t st = ln.stream;
+    J->opk = opk;
+    J->l0 = l0;
+    J->deg = deg;
+    J->st = ln.stream;
+    J->in = in;
+    J->out = out;
     auto hl = [&](int l) { return P.op.length / P.op.nx * (double)(1 << l); };
-    auto mk = [&](int l) {
-        MgLevelArgs<T> a;
+    const double hc = hier >= 0 ? 1.0 : 0.0;
+    const double nin = in.v1 ? (in.v2 ? 16.0 : 8.0) : ts;      // bytes per point of the finest b
+    for (int l = 0; l < l0; ++l) {
+        MgLevelArgs<T> &a = J->lev[l];
         a.nx = P.lg.nx[l];
         a.ny = P.lg.ny[l];
         a.h = (T)hl(l);
@@ -407,55 +431,123 @@ static void vcycle(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int
             a.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
             a.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
         }
-        return a;
-    };
-    const double hc = hier >= 0 ? 1.0 : 0.0;
-    const double nin = in.v1 ? (in.v2 ? 16.0 : 8.0) : ts;      // bytes per point of the finest b
-    for (int l = 0; l < l0; ++l) {
-        const MgLevelArgs<T> a = mk(l);
         const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-        // reads coef, b; writes x and the coarse right-hand side
-        const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts) + npc * ts;
-        PROF(c, st, kn<T>("k_mg_down", opk), by, 1, launch_mg_down<T>(st, opk, a, l == 0 ? in : MgIn{}, deg));
+        // down: reads coef, b; writes x and the coarse right-hand side
+        J->by_down[l] = np * (hc * ts + (l == 0 ? nin : ts) + ts) + npc * ts;
+        // up: reads coef, b, x, coarse correction; writes x (float64 z on level 0)
+        J->by_up[l] = np * (hc * ts + (l == 0 ? nin : ts) + ts + (l == 0 && out.z ? 8.0 : ts)) + npc * ts;
+    }
+    MgSubArgs<T> &sa = J->sub;
+    sa.nlev = L - l0;
+    double np_all = 0;
+    for (int q = 0; q < sa.nlev; ++q) {
+        sa.nx[q] = P.lg.nx[l0 + q];
+        sa.ny[q] = P.lg.ny[l0 + q];
+        sa.h[q] = (T)hl(l0 + q);
+        sa.coef[q] = hier >= 0 ? c->coef<T>(hier, l0 + q) : nullptr;
+        np_all += (double)sa.nx[q] * sa.ny[q];
+    }
+    sa.nu = (T)nu;
+    sa.sigma = (T)sigma;
+    sa.dt = (T)dtop;
+    sa.b0 = c->lev<T>(ln, l0, 3);
+    sa.x0 = c->lev<T>(ln, l0, 0);
+    sa.deg = deg;
+    sa.coarse_iters = P.opt.coarse_iters;
+    for (int k = 0; k < IRK_MAX_CHEB; ++k) {
+        sa.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
+        sa.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
+    }
+    const double np0 = (double)sa.nx[0] * sa.ny[0];
+    J->by_sub = np_all * hc * ts + np0 * ((l0 == 0 ? nin : ts) + (l0 == 0 && out.z ? 8.0 : ts));
+}
+
+// one job, launched on its lane's stream
+template <class T>
+static void run_vcjob(irk_ctx *c, const VcJob<T> &J) {
+    const int l0 = J.l0, opk = J.opk, deg = J.deg;
+    hipStream_t st = J.st;
+    for (int l = 0; l < l0; ++l) {
+        const MgLevelArgs<T> a = J.lev[l];
+        const MgIn in = l == 0 ? J.in : MgIn{};
+        PROF(c, st, kn<T>("k_mg_down", opk), J.by_down[l], 1, launch_mg_down<T>(st, opk, a, in, deg));
     }
     {
-        MgSubArgs<T> sa;
-        sa.nlev = L - l0;
-        double np_all = 0;
-        for (int q = 0; q < sa.nlev; ++q) {
-            sa.nx[q] = P.lg.nx[l0 + q];
-            sa.ny[q] = P.lg.ny[l0 + q];
-            sa.h[q] = (T)hl(l0 + q);
-            sa.coef[q] = hier >= 0 ? c->coef<T>(hier, l0 + q) : nullptr;
-            np_all += (double)sa.nx[q] * sa.ny[q];
-        }
-        sa.nu = (T)nu;
-        sa.sigma = (T)sigma;
-        sa.dt = (T)dtop;
-        sa.b0 = c->lev<T>(ln, l0, 3);
-        sa.x0 = c->lev<T>(ln, l0, 0);
-        sa.deg = deg;
-        sa.coarse_iters = P.opt.coarse_iters;
-        for (int k = 0; k < IRK_MAX_CHEB; ++k) {
-            sa.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
-            sa.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
-        }
-        for (int k = 0; k < IRK_MAX_COARSE_ITERS; ++k) {
-            sa.ccd[k] = (T)c->coarse_cd[k];
-            sa.ccr[k] = (T)c->coarse_cr[k];
-        }
-        const double np0 = (double)sa.nx[0] * sa.ny[0];
-        const double by = np_all * hc * ts + np0 * ((l0 == 0 ? nin : ts) + (l0 == 0 && out.z ? 8.0 : ts));
-        PROF(c, st, kn<T>("k_mg_subcycle", opk), by, 1,
-             launch_mg_subcycle<T>(st, opk, sa, l0 == 0 ? in : MgIn{}, l0 == 0 ? out : MgOut{}));
+        const MgSubArgs<T> sa = J.sub;
+        const MgIn in = l0 == 0 ? J.in : MgIn{};
+        const MgOut out = l0 == 0 ? J.out : MgOut{};
+        PROF(c, st, kn<T>("k_mg_subcycle", opk), J.by_sub, 1, launch_mg_subcycle<T>(st, opk, sa, in, out));
     }
     for (int l = l0 - 1; l >= 0; --l) {
-        const MgLevelArgs<T> a = mk(l);
-        const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-        // reads coef, b, x, coarse correction; writes x (float64 z on level 0)
-        const double by = np * (hc * ts + (l == 0 ? nin : ts) + ts + (l == 0 && out.z ? 8.0 : ts)) + npc * ts;
-        PROF(c, st, kn<T>("k_mg_up", opk), by, 1, launch_mg_up<T>(st, opk, a, l == 0 ? out : MgOut{}, deg));
+        const MgLevelArgs<T> a = J.lev[l];
+        const MgOut out = l == 0 ? J.out : MgOut{};
+        PROF(c, st, kn<T>("k_mg_up", opk), J.by_up[l], 1, launch_mg_up<T>(st, opk, a, out, deg));
     }
+}
+
+// several independent jobs of one operator and degree, one launch per
+// V-cycle phase on stream st: down sweeps by depth from the finest level,
+// all sub-cycles (one work-group each), up sweeps by depth back to the finest
+template <class T>
+static void run_vcjobs_batched(irk_ctx *c, hipStream_t st, const std::vector<const VcJob<T> *> &jobs) {
+    if (jobs.empty()) return;
+    const int opk = jobs[0]->opk, deg = jobs[0]->deg;
+    int maxl0 = 0;
+    for (auto *J : jobs) maxl0 = std::max(maxl0, J->l0);
+    std::vector<MgLevelArgs<T>> g;
+    std::vector<MgIn> ins;
+    std::vector<MgOut> outs;
+    std::vector<MgSubArgs<T>> subs;
+    for (int d = 0; d < maxl0; ++d) {
+        g.clear();
+        ins.clear();
+        double by = 0;
+        for (auto *J : jobs)
+            if (J->l0 > d) {
+                g.push_back(J->lev[d]);
+                ins.push_back(d == 0 ? J->in : MgIn{});
+                by += J->by_down[d];
+            }
+        const int n = (int)g.size();
+        PROF(c, st, kn<T>("k_mg_down", opk), by, 1,
+             launch_mg_down_batch<T>(st, opk, g.data(), ins.data(), n, deg));
+    }
+    {
+        subs.clear();
+        ins.clear();
+        outs.clear();
+        double by = 0;
+        for (auto *J : jobs) {
+            subs.push_back(J->sub);
+            ins.push_back(J->l0 == 0 ? J->in : MgIn{});
+            outs.push_back(J->l0 == 0 ? J->out : MgOut{});
+            by += J->by_sub;
+        }
+        const int n = (int)subs.size();
+        PROF(c, st, kn<T>("k_mg_subcycle", opk), by, 1,
+             launch_mg_subcycle_batch<T>(st, opk, subs.data(), ins.data(), outs.data(), n));
+    }
+    for (int d = maxl0 - 1; d >= 0; --d) {
+        g.clear();
+        outs.clear();
+        double by = 0;
+        for (auto *J : jobs)
+            if (J->l0 > d) {
+                g.push_back(J->lev[d]);
+                outs.push_back(d == 0 ? J->out : MgOut{});
+                by += J->by_up[d];
+            }
+        const int n = (int)g.size();
+        PROF(c, st, kn<T>("k_mg_up", opk), by, 1, launch_mg_up_batch<T>(st, opk, g.data(), outs.data(), n, deg));
+    }
+}
+
+template <class T>
+static void vcycle(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int hier, const MgIn &in,
+                   const MgOut &out) {
+    VcJob<T> J;
+    make_vcjob<T>(c, ln, opk, sigma, dtop, hier, in, out, &J);
+    run_vcjob<T>(c, J);
 }
 
 static int mg_op_of(int kind) {
@@ -552,6 +644,34 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
 // lane's readbacks so that several lanes can be interleaved.
 // ---------------------------------------------------------------------------
 template <class T>
+struct Fgmres;
+
+// V-cycles of lanes that wait for their preconditioner at the same time
+// (the blocks of one step, or the blocks of many requests in a server),
+// run as shared launches on the broker's stream; flush() orders them after
+// each lane's preceding work, runs the first (and, for 2x2 blocks, second)
+// diagonal V-cycles of all of them, and resumes every lane.
+template <class T>
+struct PrecBroker {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr, done1 = nullptr;     // after all rounds; after round 1
+    std::vector<Fgmres<T> *> pending;
+    bool init() {
+        return hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&done1, hipEventDisableTiming) == hipSuccess;
+    }
+    ~PrecBroker() {
+        if (st) (void)hipStreamSynchronize(st);
+        if (done) (void)hipEventDestroy(done);
+        if (done1) (void)hipEventDestroy(done1);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    void forget(const irk_ctx *c);
+    int flush();            // number of lanes resumed
+};
+
+template <class T>
 struct Fgmres {
     irk_ctx *c = nullptr;
     Lane *ln = nullptr;
@@ -564,7 +684,9 @@ struct Fgmres {
     int j = 0, total = 0, vcycles = 0;
     bool first_cycle = true, converged = false, fused = true;
     double beta0 = 0.0;
-    enum Phase { WAIT_BETA, WAIT_ITER, DONE } phase = WAIT_BETA;
+    enum Phase { WAIT_BETA, WAIT_PREC, WAIT_ITER, DONE } phase = WAIT_BETA;
+    double *pend_v = nullptr, *pend_z = nullptr;    // preconditioner input/output waiting in a broker
+    irk_status deferred = IRK_OK;                    // error raised while resumed by a broker
 
     void init(irk_ctx *cc, Lane *l, double rt, int mx) {
         c = cc;
@@ -607,10 +729,54 @@ struct Fgmres {
         return lane_readback(*ln, DV_BETA + 1);
     }
 
-    // one Arnoldi iteration: preconditioner, matvec, CGS2; readback of h
+    // one Arnoldi iteration: preconditioner, matvec, CGS2; readback of h.
+    // With a broker the preconditioner waits for a shared V-cycle batch.
     irk_status issue_iteration() {
-        double *vj = Vv(j), *zj = Zv(j), *w = Vv(j + 1);
+        double *vj = Vv(j), *zj = Zv(j);
+        if (c->broker && c->P.op.kind != IRK_OP_VSF_2D) {
+            pend_v = vj;
+            pend_z = zj;
+            phase = WAIT_PREC;
+            static_cast<PrecBroker<T> *>(c->broker)->pending.push_back(this);
+            return IRK_OK;
+        }
         vcycles += apply_prec<T>(c, *ln, vj, zj);
+        return issue_after_prec();
+    }
+
+    // the broker's jobs for this lane: round 1 the first diagonal V-cycle,
+    // round 2 (2x2 blocks) the second, which reads the first's output
+    void prec_jobs(int round, std::vector<VcJob<T>> &jobs) {
+        const Plan &P = c->P;
+        const EigenBlocks &eb = P.eb;
+        const int blk = ln->blk, r = eb.first[blk];
+        const size_t nf = P.nf;
+        const int opk = mg_op_of(P.op.kind);
+        MgIn in;
+        MgOut out;
+        if (round == 1) {
+            in.v1 = pend_v; in.a1 = 1.0;
+            out.z = pend_z; out.v1 = pend_v; out.a1 = 1.0;
+            jobs.emplace_back();
+            make_vcjob<T>(c, *ln, opk, eb.eta[blk], c->dt, P.row_hier[r], in, out, &jobs.back());
+        } else if (eb.width[blk] == 2) {
+            const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eb.eta[blk];
+            in.v1 = pend_v + nf; in.a1 = 1.0; in.v2 = pend_z; in.a2 = eb.beta[blk];
+            out.z = pend_z + nf; out.v1 = pend_v + nf; out.a1 = 1.0; out.v2 = pend_z; out.a2 = eb.beta[blk];
+            jobs.emplace_back();
+            make_vcjob<T>(c, *ln, opk, gam, c->dt, P.row_hier[r + 1], in, out, &jobs.back());
+        }
+    }
+
+    // continue after the broker ran this lane's V-cycles
+    void resume() {
+        vcycles += c->P.eb.width[ln->blk];
+        const irk_status e = issue_after_prec();
+        if (e != IRK_OK) deferred = e;
+    }
+
+    irk_status issue_after_prec() {
+        double *zj = Zv(j), *w = Vv(j + 1);
         block_matvec(c, *ln, zj, w);
         const int nv = j + 1;
         fused = nv <= 16;
@@ -735,6 +901,60 @@ struct Fgmres {
     }
 };
 
+template <class T>
+void PrecBroker<T>::forget(const irk_ctx *c) {
+    pending.erase(std::remove_if(pending.begin(), pending.end(), [c](Fgmres<T> *f) { return f->c == c; }),
+                  pending.end());
+}
+
+template <class T>
+int PrecBroker<T>::flush() {
+    if (pending.empty()) return 0;
+    std::vector<Fgmres<T> *> batch;
+    batch.swap(pending);
+    // order after every lane's preceding work
+    for (Fgmres<T> *f : batch) {
+        if (hipEventRecord(f->ln->ev_prec, f->ln->stream) != hipSuccess ||
+            hipStreamWaitEvent(st, f->ln->ev_prec, 0) != hipSuccess)
+            f->deferred = IRK_E_DEVICE;
+    }
+    bool two_rounds = false;
+    for (int round = 1; round <= 2; ++round) {
+        std::vector<VcJob<T>> jobs;
+        jobs.reserve(batch.size());
+        for (Fgmres<T> *f : batch) f->prec_jobs(round, jobs);
+        if (jobs.empty()) continue;
+        if (round == 2) {
+            // lanes of 1x1 blocks are done after round 1: let them go on
+            two_rounds = true;
+            const bool ok1 = hipEventRecord(done1, st) == hipSuccess;
+            for (Fgmres<T> *f : batch) {
+                if (f->c->P.eb.width[f->ln->blk] != 1) continue;
+                if (!ok1 || hipStreamWaitEvent(f->ln->stream, done1, 0) != hipSuccess) f->deferred = IRK_E_DEVICE;
+            }
+        }
+        // one batched sequence per operator kind and smoothing degree
+        std::vector<bool> used(jobs.size(), false);
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            if (used[i]) continue;
+            std::vector<const VcJob<T> *> grp;
+            for (size_t k = i; k < jobs.size(); ++k)
+                if (!used[k] && jobs[k].opk == jobs[i].opk && jobs[k].deg == jobs[i].deg) {
+                    grp.push_back(&jobs[k]);
+                    used[k] = true;
+                }
+            run_vcjobs_batched<T>(batch[0]->c, st, grp);
+        }
+    }
+    const bool ok = hipEventRecord(done, st) == hipSuccess;
+    for (Fgmres<T> *f : batch) {
+        const bool waited1 = two_rounds && f->c->P.eb.width[f->ln->blk] == 1;
+        if (!waited1 && (!ok || hipStreamWaitEvent(f->ln->stream, done, 0) != hipSuccess)) f->deferred = IRK_E_DEVICE;
+        f->resume();
+    }
+    return (int)batch.size();
+}
+
 // ---------------------------------------------------------------------------
 // One step: Algorithm 1 in the eigenbasis.
 // ---------------------------------------------------------------------------
@@ -807,6 +1027,7 @@ struct Stepper : StepperBase {
     bool fail(irk_status e) {
         status = e;
         phase = DONE;
+        if (c->broker) static_cast<PrecBroker<T> *>(c->broker)->forget(c);   // lanes left waiting in a batch
         return true;
     }
 
@@ -946,6 +1167,8 @@ struct Stepper : StepperBase {
             bool progressed = false;
             for (int b = 0; b < c->nlanes; ++b) {
                 if (lane_done[b]) continue;
+                if (fg[b].deferred != IRK_OK) return fail(fg[b].deferred);
+                if (fg[b].phase == Fgmres<T>::WAIT_PREC) continue;      // in a broker batch
                 const hipError_t q = hipEventQuery(c->lanes[b].ev);
                 if (q == hipErrorNotReady) continue;
                 if (q != hipSuccess) return fail(IRK_E_DEVICE);
@@ -965,6 +1188,13 @@ struct Stepper : StepperBase {
                     if (debug_level() > 1)
                         fprintf(stderr, "[irk]   block %d fgmres its %d beta0 %.3e\n", b, fg[b].total, fg[b].beta0);
                 }
+            }
+            // this context's own broker: run the V-cycles of the blocks that
+            // wait now as shared launches (a server flushes its shared one)
+            if (c->broker_owned && static_cast<PrecBroker<T> *>(c->broker)->flush() > 0) {
+                for (int b = 0; b < c->nlanes; ++b)
+                    if (!lane_done[b] && fg[b].deferred != IRK_OK) return fail(fg[b].deferred);
+                progressed = true;
             }
             if (active == 0) {
                 stats.newton_its++;
@@ -1106,6 +1336,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->cheb_degree = 3;
     o->mg_coarsest = 8;
     o->coarse_iters = 24;
+    o->batch_mg = 0;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
@@ -1136,19 +1367,27 @@ static void chebyshev_coefs(double lmin, double lmax, int n, double *cd, double 
 static void set_chebyshev(irk_ctx *c) {
     std::memset(c->cheb_cd, 0, sizeof(c->cheb_cd));
     std::memset(c->cheb_cr, 0, sizeof(c->cheb_cr));
-    std::memset(c->coarse_cd, 0, sizeof(c->coarse_cd));
-    std::memset(c->coarse_cr, 0, sizeof(c->coarse_cr));
     chebyshev_coefs(c->lmin, c->lmax, c->P.opt.cheb_degree, c->cheb_cd, c->cheb_cr);
-    chebyshev_coefs(c->coarse_lmin, c->lmax, c->P.opt.coarse_iters, c->coarse_cd, c->coarse_cr);
 }
 
 static void release(irk_ctx *c) {
     if (!c) return;
+    if (c->broker) {
+        if (c->P.opt.prec_fp32) {
+            auto *b = static_cast<PrecBroker<float> *>(c->broker);
+            if (c->broker_owned) delete b; else b->forget(c);
+        } else {
+            auto *b = static_cast<PrecBroker<double> *>(c->broker);
+            if (c->broker_owned) delete b; else b->forget(c);
+        }
+        c->broker = nullptr;
+    }
     for (int b = 0; b < c->nlanes; ++b) {
         Lane &ln = c->lanes[b];
         if (ln.stream) (void)hipStreamSynchronize(ln.stream);
         if (ln.ev) (void)hipEventDestroy(ln.ev);
         if (ln.done) (void)hipEventDestroy(ln.done);
+        if (ln.ev_prec) (void)hipEventDestroy(ln.ev_prec);
         if (ln.stream) (void)hipStreamDestroy(ln.stream);
     }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -1215,7 +1454,26 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         // stream is explicit, through events)
         if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.ev_prec, hipEventDisableTiming) != hipSuccess) {
+            release(c);
+            return IRK_E_DEVICE;
+        }
+    }
+    // a private broker batches the V-cycles of this context's blocks
+    if (c->P.opt.batch_mg && c->nlanes > 1 && c->P.op.kind != IRK_OP_VSF_2D) {
+        bool ok;
+        if (c->P.opt.prec_fp32) {
+            auto *b = new (std::nothrow) PrecBroker<float>();
+            ok = b && b->init();
+            c->broker = b;
+        } else {
+            auto *b = new (std::nothrow) PrecBroker<double>();
+            ok = b && b->init();
+            c->broker = b;
+        }
+        c->broker_owned = c->broker != nullptr;
+        if (!ok) {
             release(c);
             return IRK_E_DEVICE;
         }
@@ -1284,6 +1542,41 @@ int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats) {
 void drain_all(irk_ctx *c) {
     for (int b = 0; b < c->nlanes; ++b) (void)hipStreamSynchronize(c->lanes[b].stream);
     (void)hipStreamSynchronize(c->stream);
+}
+
+// Shared V-cycle brokers for a server: one per precision (fp32 = 1: float).
+void *broker_create(int fp32) {
+    if (fp32) {
+        auto *b = new (std::nothrow) PrecBroker<float>();
+        if (b && !b->init()) { delete b; b = nullptr; }
+        return b;
+    }
+    auto *b = new (std::nothrow) PrecBroker<double>();
+    if (b && !b->init()) { delete b; b = nullptr; }
+    return b;
+}
+
+void broker_destroy(void *b, int fp32) {
+    if (fp32) delete static_cast<PrecBroker<float> *>(b);
+    else delete static_cast<PrecBroker<double> *>(b);
+}
+
+int broker_flush(void *b, int fp32) {
+    if (!b) return 0;
+    return fp32 ? static_cast<PrecBroker<float> *>(b)->flush() : static_cast<PrecBroker<double> *>(b)->flush();
+}
+
+// Let a context's blocks join a shared broker (replacing its private one);
+// false when the context does not batch (option off, or the DAE operator).
+bool attach_broker(irk_ctx *c, void *fp32_broker, void *fp64_broker) {
+    if (!c->P.opt.batch_mg || c->P.op.kind == IRK_OP_VSF_2D) return false;
+    if (c->broker_owned) {
+        if (c->P.opt.prec_fp32) delete static_cast<PrecBroker<float> *>(c->broker);
+        else delete static_cast<PrecBroker<double> *>(c->broker);
+    }
+    c->broker = c->P.opt.prec_fp32 ? fp32_broker : fp64_broker;
+    c->broker_owned = false;
+    return c->broker != nullptr;
 }
 }  // namespace irk
 

@@ -53,15 +53,32 @@ struct MgOut {
 template <class T>
 struct MgSubArgs {
     int nlev;
-    int nx[IRK_MAX_LEVELS], ny[IRK_MAX_LEVELS];
-    T h[IRK_MAX_LEVELS];
+    int nx[IRK_MAX_SUB_LEVELS], ny[IRK_MAX_SUB_LEVELS];
+    T h[IRK_MAX_SUB_LEVELS];
     T nu, sigma, dt;
-    const T *coef[IRK_MAX_LEVELS];
+    const T *coef[IRK_MAX_SUB_LEVELS];
     const T *b0;         // right-hand side of the first level (when MgIn has none)
     T *x0;               // result of the first level (when MgOut has no z)
     int deg, coarse_iters;
     T cd[IRK_MAX_CHEB], cr[IRK_MAX_CHEB];
-    T ccd[IRK_MAX_COARSE_ITERS], ccr[IRK_MAX_COARSE_ITERS];
+};
+
+// Several jobs of one kernel in one launch (at most IRK_MG_BATCH; the
+// argument block stays below the 4 KiB kernel-argument limit).
+#define IRK_MG_BATCH 6
+template <class T>
+struct MgLevelBatch {
+    int n;
+    int prefix[IRK_MG_BATCH + 1];       // first work-group of each job; prefix[n] = grid
+    MgLevelArgs<T> g[IRK_MG_BATCH];
+    MgIn in[IRK_MG_BATCH];
+    MgOut out[IRK_MG_BATCH];
+};
+template <class T>
+struct MgSubBatch {
+    MgSubArgs<T> s[IRK_MG_BATCH];
+    MgIn in[IRK_MG_BATCH];
+    MgOut out[IRK_MG_BATCH];
 };
 
 template <class T>
@@ -70,6 +87,16 @@ template <class T>
 void launch_mg_up(hipStream_t st, int opk, const MgLevelArgs<T> &a, const MgOut &out, int deg);
 template <class T>
 void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const MgIn &in, const MgOut &out);
+
+// Batched launches: n jobs of one kernel (n >= 1; split into launches of at
+// most IRK_MG_BATCH jobs of one tile shape each).  Jobs must be independent.
+template <class T>
+void launch_mg_down_batch(hipStream_t st, int opk, const MgLevelArgs<T> *g, const MgIn *in, int n, int deg);
+template <class T>
+void launch_mg_up_batch(hipStream_t st, int opk, const MgLevelArgs<T> *g, const MgOut *out, int n, int deg);
+template <class T>
+void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, const MgIn *in, const MgOut *out,
+                              int n);
 // LDS bytes of the one-work-group sub-cycle over levels nx[0..nlev-1]
 size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, size_t tsz);
 

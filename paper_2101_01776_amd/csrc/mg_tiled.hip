@@ -27,6 +27,9 @@
 // every sweep (the sweeps are bound by vector-ALU issue, not by memory).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "irk_internal.h"
 #include "kernels.h"
 #include "mg_tiled.h"
@@ -248,7 +251,7 @@ __host__ __device__ constexpr int window_arrays() {
 // Down: pre-smoothing from x = 0, residual, restriction.
 // ---------------------------------------------------------------------------
 template <class T, int OPK, int TX, int TY, int D>
-__global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
+__device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn &in, const int tile) {
     constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D + 2;                                   // halo of the window
     const bool two_d = g.ny > 1;
@@ -266,7 +269,6 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
     T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
-    const int tile = xcd_tile();
     const int ty = tile / tiles_x, tx = tile % tiles_x;
     const int i0 = tx * TX, j0 = ty * (two_d ? TY : 1);
     const int nx = g.nx, ny = g.ny;
@@ -355,7 +357,7 @@ __global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
 // Up: prolongation of the coarse correction, then post-smoothing.
 // ---------------------------------------------------------------------------
 template <class T, int OPK, int TX, int TY, int D>
-__global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
+__device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut &out, const int tile) {
     constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D;                                       // halo of the window
     const bool two_d = g.ny > 1;
@@ -372,7 +374,6 @@ __global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
     T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
-    const int tile = xcd_tile();
     const int ty = tile / tiles_x, tx = tile % tiles_x;
     const int i0 = tx * TX, j0 = ty * (two_d ? TY : 1);
     const int nx = g.nx, ny = g.ny;
@@ -527,7 +528,7 @@ __device__ void wg_cheb(const T *At, const T *bt, T *x, T *xn, T *d, int nx, int
 }
 
 template <class T, int OPK>
-__global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, MgOut out) {
+__device__ __forceinline__ void mg_subcycle_body(const MgSubArgs<T> &s, const MgIn &in, const MgOut &out) {
     constexpr int NS = StencilShape<OPK>::NS;
     extern __shared__ unsigned char smem_raw[];
     T *base = reinterpret_cast<T *>(smem_raw);
@@ -756,8 +757,73 @@ __global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, M
 #undef AT
 
 // ---------------------------------------------------------------------------
+// kernels: one job per launch, or a batch of jobs (same operator, precision
+// and tile shape; different grids, shifts, linearizations and vectors) in
+// one launch -- work-group b runs tile b - prefix[e] of job e.  Job fields
+// are selected with compile-time indices (no dynamically indexed copies).
+// ---------------------------------------------------------------------------
+template <class T, int OPK, int TX, int TY, int D>
+__global__ void __launch_bounds__(256) k_mg_down(MgLevelArgs<T> g, MgIn in) {
+    mg_down_body<T, OPK, TX, TY, D>(g, in, xcd_tile());
+}
+
+template <class T, int OPK, int TX, int TY, int D>
+__global__ void __launch_bounds__(256) k_mg_up(MgLevelArgs<T> g, MgOut out) {
+    mg_up_body<T, OPK, TX, TY, D>(g, out, xcd_tile());
+}
+
+template <class T, int OPK>
+__global__ void __launch_bounds__(1024) k_mg_subcycle(MgSubArgs<T> s, MgIn in, MgOut out) {
+    mg_subcycle_body<T, OPK>(s, in, out);
+}
+
+// job of global tile t: largest e with prefix[e] <= t (uniform)
+__device__ __forceinline__ int batch_job(const int (&prefix)[IRK_MG_BATCH + 1], int n, int t) {
+    int e = 0;
+#pragma unroll
+    for (int q = 1; q < IRK_MG_BATCH; ++q)
+        if (q < n && t >= prefix[q]) e = q;
+    return e;
+}
+
+template <class T, int OPK, int TX, int TY, int D>
+__global__ void __launch_bounds__(256) k_mg_down_batch(MgLevelBatch<T> b) {
+    const int t = xcd_tile();
+    const int e = batch_job(b.prefix, b.n, t);
+    MgLevelArgs<T> g = b.g[0];
+    MgIn in = b.in[0];
+    int p0 = b.prefix[0];
+#pragma unroll
+    for (int q = 1; q < IRK_MG_BATCH; ++q)
+        if (q == e) { g = b.g[q]; in = b.in[q]; p0 = b.prefix[q]; }
+    mg_down_body<T, OPK, TX, TY, D>(g, in, t - p0);
+}
+
+template <class T, int OPK, int TX, int TY, int D>
+__global__ void __launch_bounds__(256) k_mg_up_batch(MgLevelBatch<T> b) {
+    const int t = xcd_tile();
+    const int e = batch_job(b.prefix, b.n, t);
+    MgLevelArgs<T> g = b.g[0];
+    MgOut out = b.out[0];
+    int p0 = b.prefix[0];
+#pragma unroll
+    for (int q = 1; q < IRK_MG_BATCH; ++q)
+        if (q == e) { g = b.g[q]; out = b.out[q]; p0 = b.prefix[q]; }
+    mg_up_body<T, OPK, TX, TY, D>(g, out, t - p0);
+}
+
+template <class T, int OPK>
+__global__ void __launch_bounds__(1024) k_mg_subcycle_batch(MgSubBatch<T> b) {
+    // job = work-group; its arguments are read in place (uniform index into
+    // the kernel arguments)
+    const int e = blockIdx.x;
+    mg_subcycle_body<T, OPK>(b.s[e], b.in[e], b.out[e]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static unsigned subcycle_threads(int np0);
 template <class T, int OPK, int TX, int TY>
 static void down_t(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &in, int deg) {
     const int tiles = ((a.nx + TX - 1) / TX) * (a.ny > 1 ? (a.ny + TY - 1) / TY : 1);
@@ -857,11 +923,7 @@ size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, si
 template <class T>
 void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const MgIn &in, const MgOut &out) {
     const size_t shm = mg_subcycle_lds_bytes(opk, s.nlev, s.nx, s.ny, sizeof(T));
-    // threads: about half a point per thread on a 32^2 first level, one per
-    // point below (measured fastest); at least np0 / 4 (the first level's
-    // right-hand side is loaded four points per thread)
-    const int np0 = s.nx[0] * s.ny[0];
-    const unsigned nt = np0 >= 2048 ? 1024 : (np0 >= 1024 ? 512 : (unsigned)(((np0 + 63) / 64) * 64));
+    const unsigned nt = subcycle_threads(s.nx[0] * s.ny[0]);
     switch (opk) {
         case MG_NLDIFF: k_mg_subcycle<T, MG_NLDIFF><<<1, nt, shm, st>>>(s, in, out); break;
         case MG_BURGERS: k_mg_subcycle<T, MG_BURGERS><<<1, nt, shm, st>>>(s, in, out); break;
@@ -870,6 +932,138 @@ void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const Mg
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched launchers
+// ---------------------------------------------------------------------------
+// tile shape class of a level (the one launch_mg_down/up would use):
+// 0 = 32x8 (2-D) or 256-point strips (1-D), 1 = 16x8 or 64-point strips
+template <class T>
+static int shape_class(const MgLevelArgs<T> &a, int halo) {
+    if (a.ny == 1) return window_fits(a.nx, 256, halo) ? 0 : 1;
+    return (a.nx >= 128 && window_fits(a.nx, 32, halo) && window_fits(a.ny, 8, halo)) ? 0 : 1;
+}
+
+template <class T, int OPK, int TX, int TY, bool DOWN>
+static void level_batch_t(hipStream_t st, MgLevelBatch<T> &b, int deg) {
+    const bool two_d = b.g[0].ny > 1;
+    int acc = 0;
+    for (int e = 0; e < b.n; ++e) {
+        b.prefix[e] = acc;
+        acc += ((b.g[e].nx + TX - 1) / TX) * (two_d ? (b.g[e].ny + TY - 1) / TY : 1);
+    }
+    for (int e = b.n; e <= IRK_MG_BATCH; ++e) b.prefix[e] = acc;
+    const int H = DOWN ? deg + 2 : deg;
+    const int arrays = DOWN ? window_arrays<T, OPK>() : window_arrays<T, OPK>() - 1;
+    const size_t shm = (size_t)arrays * (TX + 2 * H) * ((two_d ? TY : 1) + (two_d ? 2 * H : 0)) * sizeof(T);
+    if (DOWN) {
+        switch (deg) {
+            case 1: k_mg_down_batch<T, OPK, TX, TY, 1><<<acc, 256, shm, st>>>(b); break;
+            case 2: k_mg_down_batch<T, OPK, TX, TY, 2><<<acc, 256, shm, st>>>(b); break;
+            case 3: k_mg_down_batch<T, OPK, TX, TY, 3><<<acc, 256, shm, st>>>(b); break;
+            default: k_mg_down_batch<T, OPK, TX, TY, 4><<<acc, 256, shm, st>>>(b); break;
+        }
+    } else {
+        switch (deg) {
+            case 1: k_mg_up_batch<T, OPK, TX, TY, 1><<<acc, 256, shm, st>>>(b); break;
+            case 2: k_mg_up_batch<T, OPK, TX, TY, 2><<<acc, 256, shm, st>>>(b); break;
+            case 3: k_mg_up_batch<T, OPK, TX, TY, 3><<<acc, 256, shm, st>>>(b); break;
+            default: k_mg_up_batch<T, OPK, TX, TY, 4><<<acc, 256, shm, st>>>(b); break;
+        }
+    }
+}
+
+template <class T, int OPK, bool DOWN>
+static void level_batch_dispatch(hipStream_t st, const MgLevelArgs<T> *g, const MgIn *in, const MgOut *out, int n,
+                                 int deg) {
+    const int halo = DOWN ? (deg > 4 ? 4 : deg) + 2 : (deg > 4 ? 4 : deg);
+    for (int cls = 0; cls < 2; ++cls) {
+        MgLevelBatch<T> b;
+        std::memset(&b, 0, sizeof(b));
+        b.n = 0;
+        auto flush = [&]() {
+            if (b.n == 0) return;
+            const bool one_d = b.g[0].ny == 1;
+            if (cls == 0) {
+                if (one_d) level_batch_t<T, OPK, 256, 1, DOWN>(st, b, deg);
+                else level_batch_t<T, OPK, 32, 8, DOWN>(st, b, deg);
+            } else {
+                if (one_d) level_batch_t<T, OPK, 64, 1, DOWN>(st, b, deg);
+                else level_batch_t<T, OPK, 16, 8, DOWN>(st, b, deg);
+            }
+            std::memset(&b, 0, sizeof(b));
+            b.n = 0;
+        };
+        for (int i = 0; i < n; ++i) {
+            if (shape_class(g[i], halo) != cls) continue;
+            b.g[b.n] = g[i];
+            if (in) b.in[b.n] = in[i];
+            if (out) b.out[b.n] = out[i];
+            if (++b.n == IRK_MG_BATCH) flush();
+        }
+        flush();
+    }
+}
+
+template <class T>
+void launch_mg_down_batch(hipStream_t st, int opk, const MgLevelArgs<T> *g, const MgIn *in, int n, int deg) {
+    switch (opk) {
+        case MG_NLDIFF: level_batch_dispatch<T, MG_NLDIFF, true>(st, g, in, nullptr, n, deg); break;
+        case MG_BURGERS: level_batch_dispatch<T, MG_BURGERS, true>(st, g, in, nullptr, n, deg); break;
+        case MG_VSF_OMEGA: level_batch_dispatch<T, MG_VSF_OMEGA, true>(st, g, in, nullptr, n, deg); break;
+        default: level_batch_dispatch<T, MG_POISSON, true>(st, g, in, nullptr, n, deg); break;
+    }
+}
+
+template <class T>
+void launch_mg_up_batch(hipStream_t st, int opk, const MgLevelArgs<T> *g, const MgOut *out, int n, int deg) {
+    switch (opk) {
+        case MG_NLDIFF: level_batch_dispatch<T, MG_NLDIFF, false>(st, g, nullptr, out, n, deg); break;
+        case MG_BURGERS: level_batch_dispatch<T, MG_BURGERS, false>(st, g, nullptr, out, n, deg); break;
+        case MG_VSF_OMEGA: level_batch_dispatch<T, MG_VSF_OMEGA, false>(st, g, nullptr, out, n, deg); break;
+        default: level_batch_dispatch<T, MG_POISSON, false>(st, g, nullptr, out, n, deg); break;
+    }
+}
+
+// threads of a sub-cycle work-group: about half a point per thread on a
+// 32^2 first level, one per point below (measured fastest); at least np0 / 4
+// (the first level's right-hand side is loaded four points per thread)
+static unsigned subcycle_threads(int np0) {
+    return np0 >= 2048 ? 1024 : (np0 >= 1024 ? 512 : (unsigned)(((np0 + 63) / 64) * 64));
+}
+
+template <class T>
+void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, const MgIn *in, const MgOut *out,
+                              int n) {
+    for (int i0 = 0; i0 < n; i0 += IRK_MG_BATCH) {
+        const int cnt = std::min(IRK_MG_BATCH, n - i0);
+        MgSubBatch<T> b;
+        std::memset(&b, 0, sizeof(b));
+        size_t shm = 0;
+        unsigned nt = 64;
+        for (int e = 0; e < cnt; ++e) {
+            b.s[e] = s[i0 + e];
+            b.in[e] = in[i0 + e];
+            b.out[e] = out[i0 + e];
+            shm = std::max(shm, mg_subcycle_lds_bytes(opk, s[i0 + e].nlev, s[i0 + e].nx, s[i0 + e].ny, sizeof(T)));
+            nt = std::max(nt, subcycle_threads(s[i0 + e].nx[0] * s[i0 + e].ny[0]));
+        }
+        switch (opk) {
+            case MG_NLDIFF: k_mg_subcycle_batch<T, MG_NLDIFF><<<cnt, nt, shm, st>>>(b); break;
+            case MG_BURGERS: k_mg_subcycle_batch<T, MG_BURGERS><<<cnt, nt, shm, st>>>(b); break;
+            case MG_VSF_OMEGA: k_mg_subcycle_batch<T, MG_VSF_OMEGA><<<cnt, nt, shm, st>>>(b); break;
+            default: k_mg_subcycle_batch<T, MG_POISSON><<<cnt, nt, shm, st>>>(b); break;
+        }
+    }
+}
+
+template void launch_mg_down_batch<float>(hipStream_t, int, const MgLevelArgs<float> *, const MgIn *, int, int);
+template void launch_mg_down_batch<double>(hipStream_t, int, const MgLevelArgs<double> *, const MgIn *, int, int);
+template void launch_mg_up_batch<float>(hipStream_t, int, const MgLevelArgs<float> *, const MgOut *, int, int);
+template void launch_mg_up_batch<double>(hipStream_t, int, const MgLevelArgs<double> *, const MgOut *, int, int);
+template void launch_mg_subcycle_batch<float>(hipStream_t, int, const MgSubArgs<float> *, const MgIn *,
+                                              const MgOut *, int);
+template void launch_mg_subcycle_batch<double>(hipStream_t, int, const MgSubArgs<double> *, const MgIn *,
+                                               const MgOut *, int);
 template void launch_mg_down<float>(hipStream_t, int, const MgLevelArgs<float> &, const MgIn &, int);
 template void launch_mg_down<double>(hipStream_t, int, const MgLevelArgs<double> &, const MgIn &, int);
 template void launch_mg_up<float>(hipStream_t, int, const MgLevelArgs<float> &, const MgOut &, int);

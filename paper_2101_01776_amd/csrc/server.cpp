@@ -27,6 +27,10 @@ namespace irk {
 irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1);
 int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats);
 void drain_all(irk_ctx *c);
+void *broker_create(int fp32);
+void broker_destroy(void *b, int fp32);
+int broker_flush(void *b, int fp32);
+bool attach_broker(irk_ctx *c, void *fp32_broker, void *fp64_broker);
 }  // namespace irk
 
 namespace {
@@ -102,6 +106,9 @@ struct Req {
 
 struct irk_server {
     unsigned char *arena = nullptr;
+    // shared V-cycle brokers: the preconditioner V-cycles of all running
+    // requests that wait at the same time run as shared launches
+    void *brk32 = nullptr, *brk64 = nullptr;
     Arena alloc;
     int max_slots = 1;
     long next_id = 1;
@@ -163,9 +170,15 @@ static bool try_admit(irk_server *s) {
         hipMemcpyAsync(q->ua, q->r.u0, q->field_bytes, hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
         st = IRK_E_DEVICE;
     if (st == IRK_OK && hipStreamSynchronize(q->stream) != hipSuccess) st = IRK_E_DEVICE;
+    // the shared brokers are created with the first admitted request (they
+    // own a stream and an event each)
+    if (st == IRK_OK && !s->brk32) s->brk32 = irk::broker_create(1);
+    if (st == IRK_OK && !s->brk64) s->brk64 = irk::broker_create(0);
+    if (st == IRK_OK && (!s->brk32 || !s->brk64)) st = IRK_E_DEVICE;
     if (st == IRK_OK)
         st = irk_create((irk_family)q->r.family, q->r.s, &q->r.op, q->r.use_options ? &q->r.opt : nullptr, ws,
                         q->ws_bytes, q->stream, &q->ctx);
+    if (st == IRK_OK) (void)irk::attach_broker(q->ctx, s->brk32, s->brk64);
     q->t = q->r.t0;
     if (st == IRK_OK) {
         q->step_t0 = now_s();
@@ -211,10 +224,21 @@ extern "C" irk_status irk_server_submit(irk_server *s, const irk_request *r, lon
     return IRK_OK;
 }
 
+static void poll_running(irk_server *s);
+
 extern "C" int irk_server_progress(irk_server *s) {
     if (!s) return -1;
     while (try_admit(s)) {
     }
+    poll_running(s);
+    // V-cycles that requests left waiting in this pass run as shared
+    // launches; the resumed lanes continue at the next poll
+    irk::broker_flush(s->brk32, 1);
+    irk::broker_flush(s->brk64, 0);
+    return (int)s->running.size() + (int)s->queue.size();
+}
+
+static void poll_running(irk_server *s) {
     for (size_t k = 0; k < s->running.size();) {
         Req *q = s->running[k];
         irk_status st = IRK_OK;
@@ -245,7 +269,6 @@ extern "C" int irk_server_progress(irk_server *s) {
         while (try_admit(s)) {
         }
     }
-    return (int)s->running.size() + (int)s->queue.size();
 }
 
 extern "C" irk_status irk_server_info(irk_server *s, long id, irk_request_info *info) {
@@ -280,5 +303,7 @@ extern "C" void irk_server_destroy(irk_server *s) {
     s->running.clear();
     for (Req *q : s->queue) delete q;
     for (auto &kv : s->finished) delete kv.second;
+    if (s->brk32) irk::broker_destroy(s->brk32, 1);
+    if (s->brk64) irk::broker_destroy(s->brk64, 0);
     delete s;
 }

@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("max_krylov", ctypes.c_int), ("max_newton", ctypes.c_int),
                 ("newton_like", ctypes.c_int), ("gamma_mode", ctypes.c_int),
                 ("prec_fp32", ctypes.c_int), ("cheb_degree", ctypes.c_int),
-                ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int)]
+                ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("batch_mg", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

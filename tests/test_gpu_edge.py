@@ -175,3 +175,28 @@ def test_stats_accounting():
     assert st["krylov_its"] == sum(st["krylov_its_block"])
     assert st["vcycles"] == want          # one V-cycle per diagonal inverse
     sol.close()
+
+
+def test_shared_vcycle_launches_change_nothing():
+    """With batch_mg = 1 the V-cycles of blocks that wait at the same time run
+    as shared launches; with batch_mg = 0 (the default) each V-cycle runs
+    alone on its block's stream.  Same kernels, same arithmetic: bitwise-equal steps
+    (Gauss-3: one real block and one pair; Gauss-5 at a size with tiled
+    levels: three blocks; float32 and float64 V-cycles)."""
+    import torch
+    for n, s, dt in ((96, 3, 5e-3), (128, 5, 1e-2)):
+        op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+        u0 = torch.tensor(inputs.nldiff_random_u0(n, 3, 0.5), dtype=torch.float64, device="cuda")
+        for prec in (1, 0):
+            res = []
+            for batch in (1, 0):
+                sol = _solver(op, "gauss", s, prec_fp32=prec, batch_mg=batch)
+                u, t = u0.clone(), 0.0
+                for _ in range(2):
+                    u, st = sol.step(u, t, dt)
+                    t += dt
+                res.append((u, st))
+                sol.close()
+            print(f"  n {n} s {s} prec {prec}: {res[0][1]['krylov_its']} / {res[1][1]['krylov_its']} Krylov its")
+            assert torch.equal(res[0][0], res[1][0])
+            assert res[0][1]["krylov_its"] == res[1][1]["krylov_its"]

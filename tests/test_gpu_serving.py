@@ -1,9 +1,10 @@
 """Serving: continuous batching of step-solve requests on one GPU.
 
 Every request's result in the mix equals (bitwise) the result of the same
-steps run alone with irk_step; admission respects the arena budget and the
-slot limit; a request that can never fit fails with IRK_E_NOMEM without
-disturbing the others."""
+steps run alone with irk_step -- in the mix the preconditioner V-cycles of
+all requests that wait at the same time run as shared launches; admission
+respects the arena budget and the slot limit; a request that can never fit
+fails with IRK_E_NOMEM without disturbing the others."""
 import numpy as np
 import pytest
 
@@ -38,28 +39,30 @@ def _alone(family, s, n, dt, nsteps, seed):
     return res
 
 
-def _submit_all(srv, mix):
+def _submit_all(srv, mix, batch=0):
     ids = []
     for family, s, n, dt, nsteps, seed in mix:
         op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
-        ids.append(srv.submit(family, s, op, inputs.nldiff_random_u0(n, seed), dt, nsteps))
+        ids.append(srv.submit(family, s, op, inputs.nldiff_random_u0(n, seed), dt, nsteps,
+                              opt=irk.make_options(batch_mg=batch)))
     return ids
 
 
 def test_alone_equals_in_the_mix():
     import torch
     alone = [_alone(*m) for m in MIX]
-    srv = irk.Server(arena_bytes=4 << 30, max_slots=8)
-    ids = _submit_all(srv, MIX)
-    srv.run_until_idle()
-    st = srv.stats()
-    print("peak running", st["peak_running"], "steps", len(st["step_ms"]))
-    assert st["peak_running"] >= 4                 # requests really overlapped
-    for rid, ref, m in zip(ids, alone, MIX):
-        info = srv.info(rid)
-        assert info["state"] == "done" and info["steps_done"] == m[4], info
-        assert torch.equal(srv.result(rid), ref), m
-    srv.close()
+    for batch in (0, 1):                            # separate or shared V-cycle launches
+        srv = irk.Server(arena_bytes=4 << 30, max_slots=8)
+        ids = _submit_all(srv, MIX, batch)
+        srv.run_until_idle()
+        st = srv.stats()
+        print("batch_mg", batch, "peak running", st["peak_running"], "steps", len(st["step_ms"]))
+        assert st["peak_running"] >= 4                 # requests really overlapped
+        for rid, ref, m in zip(ids, alone, MIX):
+            info = srv.info(rid)
+            assert info["state"] == "done" and info["steps_done"] == m[4], info
+            assert torch.equal(srv.result(rid), ref), m
+        srv.close()
 
 
 def test_budget_and_slots_bound_residency():
