@@ -59,12 +59,13 @@ def make_problem(irk, inputs, problem, n, nu):
 
 
 BATCH_MG = 0      # shared V-cycle launches (irk_options.batch_mg), off by default
+MG_OPTS = {}      # multigrid option overrides (--cheb-degree, --mg-coarsest)
 
 
 def run_job(torch, irk, inputs, wl, steps, warmup, prec_fp32, profile=False):
     problem, n, family, s, dt, _, nu = wl
     op, u_init, _ = make_problem(irk, inputs, problem, n, nu)
-    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=prec_fp32, batch_mg=BATCH_MG))
+    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=prec_fp32, batch_mg=BATCH_MG, **MG_OPTS))
     u0 = torch.tensor(u_init, dtype=torch.float64, device="cuda")
     a = u0.clone()
     b = torch.empty_like(a)
@@ -279,8 +280,12 @@ def serve_run(torch, irk, reqs, fields, lam, prec_fp32, budget, slots, arena):
     ids, late = [], []
     k = 0
     t0 = time.perf_counter()
+    t_note = 20.0
     while True:
         now = time.perf_counter() - t0
+        if now > t_note:                     # progress note for long runs
+            print(f"serve: {now:.0f} s, {k} of {len(reqs)} submitted", file=sys.stderr, flush=True)
+            t_note += 20.0
         while k < len(reqs) and arrive[k] <= now:
             r = reqs[k]
             ids.append(srv.submit(r.family, r.s, ops[r.n], fields[k], r.dt, r.nsteps, opt=opt, out=outs[k]))
@@ -362,6 +367,8 @@ def main():
                     help="also compare Gauss/Radau IIA with SDIRK of equal order on the workload")
     ap.add_argument("--ablation", action="store_true",
                     help="also compare gamma* vs eta and Newton-like (1) vs (0) on the workload")
+    ap.add_argument("--cheb-degree", type=int, default=None, help="Chebyshev smoothing degree (default 3)")
+    ap.add_argument("--mg-coarsest", type=int, default=None, help="coarsest multigrid side (default 8)")
     ap.add_argument("--batch-mg", action="store_true",
                     help="run the V-cycles of blocks/requests that wait together as shared launches")
     ap.add_argument("--copy-probe", action="store_true",
@@ -389,8 +396,12 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     irk.lib()
-    global BATCH_MG
+    global BATCH_MG, MG_OPTS
     BATCH_MG = 1 if args.batch_mg else 0
+    if args.cheb_degree:
+        MG_OPTS["cheb_degree"] = args.cheb_degree
+    if args.mg_coarsest:
+        MG_OPTS["mg_coarsest"] = args.mg_coarsest
     if args.copy_probe:
         copy_probe(torch)
     if args.serve:
