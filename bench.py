@@ -385,8 +385,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the request-level sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py: one GPU only; runs on several GPUs are not supported (requests are independent "
+              "and would shard over GPUs with one admission ledger per GPU, which is not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -654,7 +654,7 @@ struct Fgmres;
 template <class T>
 struct PrecBroker {
     hipStream_t st = nullptr;
-    hipEvent_t done = nullptr, done1 = nullptr;     // after all rounds; after round 1
+    hipEvent_t done = nullptr, done1 = nullptr;     // after both passes; after the first
     std::vector<Fgmres<T> *> pending;
     bool init() {
         return hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
@@ -744,9 +744,9 @@ struct Fgmres {
         return issue_after_prec();
     }
 
-    // the broker's jobs for this lane: round 1 the first diagonal V-cycle,
-    // round 2 (2x2 blocks) the second, which reads the first's output
-    void prec_jobs(int round, std::vector<VcJob<T>> &jobs) {
+    // the broker's jobs for this lane: pass 1 the first diagonal V-cycle,
+    // pass 2 (2x2 blocks) the second, which reads the first's output
+    void prec_jobs(int pass, std::vector<VcJob<T>> &jobs) {
         const Plan &P = c->P;
         const EigenBlocks &eb = P.eb;
         const int blk = ln->blk, r = eb.first[blk];
@@ -754,7 +754,7 @@ struct Fgmres {
         const int opk = mg_op_of(P.op.kind);
         MgIn in;
         MgOut out;
-        if (round == 1) {
+        if (pass == 1) {
             in.v1 = pend_v; in.a1 = 1.0;
             out.z = pend_z; out.v1 = pend_v; out.a1 = 1.0;
             jobs.emplace_back();
@@ -918,15 +918,15 @@ int PrecBroker<T>::flush() {
             hipStreamWaitEvent(st, f->ln->ev_prec, 0) != hipSuccess)
             f->deferred = IRK_E_DEVICE;
     }
-    bool two_rounds = false;
-    for (int round = 1; round <= 2; ++round) {
+    bool two_passes = false;
+    for (int pass = 1; pass <= 2; ++pass) {
         std::vector<VcJob<T>> jobs;
         jobs.reserve(batch.size());
-        for (Fgmres<T> *f : batch) f->prec_jobs(round, jobs);
+        for (Fgmres<T> *f : batch) f->prec_jobs(pass, jobs);
         if (jobs.empty()) continue;
-        if (round == 2) {
-            // lanes of 1x1 blocks are done after round 1: let them go on
-            two_rounds = true;
+        if (pass == 2) {
+            // lanes of 1x1 blocks are done after the first pass: let them go on
+            two_passes = true;
             const bool ok1 = hipEventRecord(done1, st) == hipSuccess;
             for (Fgmres<T> *f : batch) {
                 if (f->c->P.eb.width[f->ln->blk] != 1) continue;
@@ -948,7 +948,7 @@ int PrecBroker<T>::flush() {
     }
     const bool ok = hipEventRecord(done, st) == hipSuccess;
     for (Fgmres<T> *f : batch) {
-        const bool waited1 = two_rounds && f->c->P.eb.width[f->ln->blk] == 1;
+        const bool waited1 = two_passes && f->c->P.eb.width[f->ln->blk] == 1;
         if (!waited1 && (!ok || hipStreamWaitEvent(f->ln->stream, done, 0) != hipSuccess)) f->deferred = IRK_E_DEVICE;
         f->resume();
     }
