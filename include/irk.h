@@ -115,6 +115,12 @@ typedef struct irk_options {
                                requests) waiting at the same time run in
                                shared launches; 0: one launch sequence per
                                V-cycle on its block's stream                 */
+    int start_extrapolate;  /* 1: when a step continues the context's
+                               previous one (u_n is that step's output
+                               buffer and t_n its end time), the previous
+                               stage vectors extrapolated along their
+                               interpolating polynomial are a third starting
+                               candidate; 0: zero and explicit only         */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -128,19 +134,26 @@ typedef struct irk_stats {
     int prec_applications;
     double res0;                /* ||F(K0)||_2                                */
     double final_res;           /* ||F(K)||_2 at acceptance                   */
+    int start;                  /* starting stage vectors Newton began from:
+                                   0 zero, 1 explicit, 2 extrapolated       */
 } irk_stats;
 
 /* ---------------- host-only entry points (no GPU needed) ---------------- */
 
 const char *irk_status_str(irk_status st);
 
-/* Every step starts from K0 = 0 (all stage values at u_n).
+/* Starting stage vectors K0 (Algorithm 1 leaves them open): the candidates
+ * K = 0 (every stage value at u_n), the explicit k_i = N(u_n, t_n) on
+ * differential rows (0 on algebraic rows) and, with start_extrapolate on a
+ * continued step, k_i = sum_j l_j(1 + c_i dt / dt_prev) k_j^prev (l_j the
+ * Lagrange basis on the nodes c) are evaluated in that order; Newton starts
+ * from the one with the smallest stage residual, the earlier one on ties.
  * Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||F(K0)||),
  * krylov_rtol 1e-5 (the paper's GMRES tolerance, Section 7.1), restart 30,
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
  * cheb_degree 3, mg_coarsest 8, coarse_iters 24, batch_mg 0 (shared
  * launches couple the blocks' progress and were measured slower on the
- * bench workloads; see the option).                                         */
+ * bench workloads; see the option), start_extrapolate 1.                   */
 void irk_default_options(irk_options *opt);
 
 /* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,

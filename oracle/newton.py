@@ -105,24 +105,51 @@ def solve_sparse_lowrank(S, Ub, Vb, rhs):
     return x - SU @ np.linalg.solve(small, Vb.T @ x)
 
 
-def initial_stages(problem, A, c, u_n, t_n, dt):
-    """Starting stage vectors K^0.  Algorithm 1 leaves them open; of the two
-    natural candidates -- K = 0 (every stage value U_i at u_n, the usual stiff
-    start) and the explicit k_i = M^{-1} N(u_n, t_n) on differential rows, 0
-    on algebraic rows (good for smooth, non-stiff motion) -- take the one with
-    the smaller stage residual of equation (stages), zero on ties."""
+def extrapolated_stages(c, K_prev, dt_prev, dt):
+    """Previous step's stage vectors carried along their interpolating
+    polynomial: k_j^prev sits at the previous step's node c_j (in units of
+    dt_prev), the new stage i at 1 + c_i dt / dt_prev, so
+    k_i = sum_j l_j(1 + c_i dt/dt_prev) k_j^prev with l_j the Lagrange basis
+    on the nodes c.  For collocation methods the k_j are the derivative of the
+    collocation polynomial at the nodes, and this is its continuation."""
+    c = np.asarray(c, dtype=np.float64)
     s = len(c)
-    zero = np.zeros((s, problem.size))
-    explicit = np.stack([problem.rhs(u_n, t_n) * problem.mass] * s)
-    r_zero = np.linalg.norm(stage_residual(problem, A, c, u_n, t_n, dt, zero))
-    r_expl = np.linalg.norm(stage_residual(problem, A, c, u_n, t_n, dt, explicit))
-    return explicit if r_expl < r_zero else zero
+    W = np.ones((s, s))
+    for i in range(s):
+        x = 1.0 + c[i] * dt / dt_prev
+        for j in range(s):
+            for m in range(s):
+                if m != j:
+                    W[i, j] *= (x - c[m]) / (c[j] - c[m])
+    return W @ K_prev
 
 
-def irk_stages(problem, A, c, u_n, t_n, dt, max_iter=60, K0=None):
-    """Stage vectors K (shape (s, N)) solving equation (stages) to roundoff."""
+def initial_stages(problem, A, c, u_n, t_n, dt, prev=None):
+    """Starting stage vectors K^0.  Algorithm 1 leaves them open.  Candidates,
+    in this order: K = 0 (every stage value U_i at u_n, the usual stiff
+    start); the explicit k_i = M^{-1} N(u_n, t_n) on differential rows, 0 on
+    algebraic rows (good for smooth, non-stiff motion); and, when the step
+    continues a previous one (``prev`` = (K_prev, dt_prev)), the previous
+    stage vectors extrapolated (``extrapolated_stages``).  The one with the
+    smallest stage residual of equation (stages) is taken, the earlier one on
+    ties.  Returns (K0, index of the candidate)."""
     s = len(c)
-    K = initial_stages(problem, A, c, u_n, t_n, dt) if K0 is None else K0.copy()
+    cands = [np.zeros((s, problem.size)), np.stack([problem.rhs(u_n, t_n) * problem.mass] * s)]
+    if prev is not None:
+        cands.append(extrapolated_stages(c, prev[0], prev[1], dt))
+    res = [np.linalg.norm(stage_residual(problem, A, c, u_n, t_n, dt, K)) for K in cands]
+    best = 0
+    for k in range(1, len(cands)):
+        if res[k] < res[best]:
+            best = k
+    return cands[best], best
+
+
+def irk_stages(problem, A, c, u_n, t_n, dt, max_iter=60, K0=None, prev=None):
+    """Stage vectors K (shape (s, N)) solving equation (stages) to roundoff.
+    ``prev`` = (K_prev, dt_prev) of the step this one continues, if any."""
+    s = len(c)
+    K = initial_stages(problem, A, c, u_n, t_n, dt, prev)[0] if K0 is None else K0.copy()
     corr, res = [], []
     prev = np.inf
     for it in range(1, max_iter + 1):
@@ -139,7 +166,7 @@ def irk_stages(problem, A, c, u_n, t_n, dt, max_iter=60, K0=None):
     raise RuntimeError(f"oracle Newton did not converge in {max_iter} iterations: {corr}")
 
 
-def irk_step(problem, A, b, c, u_n, t_n, dt, max_iter=60):
+def irk_step(problem, A, b, c, u_n, t_n, dt, max_iter=60, prev=None):
     """u_{n+1} = u_n + dt sum_i b_i k_i with K from ``irk_stages``."""
-    K, info = irk_stages(problem, A, c, u_n, t_n, dt, max_iter=max_iter)
+    K, info = irk_stages(problem, A, c, u_n, t_n, dt, max_iter=max_iter, prev=prev)
     return u_n + dt * (b @ K), K, info

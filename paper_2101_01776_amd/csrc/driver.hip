@@ -96,7 +96,8 @@ static bool valid_options(const irk_options &o) {
            (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
-           o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1);
+           o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
+           (o.start_extrapolate == 0 || o.start_extrapolate == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -253,6 +254,12 @@ struct irk_ctx {
     Lane lanes[IRK_MAX_STAGES];
     int nlanes = 0;
     bool have_stages = false;
+    // the last successful step's output buffer and end time: a step from
+    // there continues it, and K (still the previous stages) extrapolates
+    const double *next_u = nullptr;
+    double next_t = 0, prev_dt = 0;
+    bool extrap = false;                  // this step has the third candidate
+    double extrap_ratio = 1.0;            // dt / previous dt
     // Chebyshev smoothing coefficients
     double cheb_cd[8], cheb_cr[8];
     double lmax = 2.0, lmin = 0.5;
@@ -1017,8 +1024,8 @@ struct Stepper : StepperBase {
     double res0 = -1, thresh = 0, prev = 0;
     // starting stage vectors: K = 0 is evaluated first, then the explicit
     // k_i = N(u_n, t_n); the one with the smaller residual starts Newton
-    enum Start { START_ZERO, START_EXPLICIT, START_CHOSEN } start = START_CHOSEN;
-    double res_zero = 0;
+    enum Start { START_ZERO, START_EXPLICIT, START_EXTRAP, START_CHOSEN } start = START_CHOSEN;
+    double res_zero = 0, res_expl = 0;
     Fgmres<T> fg[IRK_MAX_STAGES];
     bool lane_done[IRK_MAX_STAGES];
 
@@ -1070,7 +1077,25 @@ struct Stepper : StepperBase {
         res0 = -1;
         thresh = prev = 0;
         // starting stage vectors (Algorithm 1 leaves them open): first K = 0,
-        // every stage value at u_n
+        // every stage value at u_n.  On a continued step the previous stage
+        // vectors are first carried along their interpolating polynomial
+        // into Y (not read before the first Newton correction):
+        // k_i = sum_j l_j(1 + c_i dt / dt_prev) k_j^prev
+        if (c->extrap) {
+            StageCoefs W;
+            std::memset(&W, 0, sizeof(W));
+            for (int i = 0; i < s; ++i) {
+                const double x = 1.0 + P.eb.c[i] * c->extrap_ratio;
+                for (int j = 0; j < s; ++j) {
+                    double l = 1.0;
+                    for (int m = 0; m < s; ++m)
+                        if (m != j) l *= (x - P.eb.c[m]) / (P.eb.c[j] - P.eb.c[m]);
+                    W.A[i * s + j] = l;
+                }
+            }
+            PROF(c, c->stream, "k_stage_extrap<" + std::to_string(s) + ">", 8.0 * nf * 2 * s, 1,
+                 launch_stage_extrap(c->stream, s, nf, c->K, c->Y, W));
+        }
         start = START_ZERO;
         PROF(c, c->stream, "k_fill", 8.0 * s * nf, 1, launch_fill(c->stream, c->K, 0.0, (size_t)s * nf));
         const irk_status e = issue_residual();
@@ -1095,12 +1120,42 @@ struct Stepper : StepperBase {
             const irk_status e = issue_residual();
             return e != IRK_OK ? fail(e) : false;
         }
-        if (start == START_EXPLICIT) {
+        if (start == START_EXPLICIT || start == START_EXTRAP) {
+            // candidates in order zero, explicit, extrapolated: the smallest
+            // residual wins, the earlier one on ties (NaN never wins)
+            if (start == START_EXPLICIT) {
+                res_expl = res;
+                if (c->extrap) {
+                    start = START_EXTRAP;
+                    if (hipMemcpyAsync(c->K, c->Y, (size_t)P.s * P.nf * sizeof(double), hipMemcpyDeviceToDevice,
+                                       c->stream) != hipSuccess)
+                        return fail(IRK_E_DEVICE);
+                    const irk_status e = issue_residual();
+                    return e != IRK_OK ? fail(e) : false;
+                }
+            }
+            const bool had_extrap = start == START_EXTRAP;
             start = START_CHOSEN;
             if (debug_level())
-                fprintf(stderr, "[irk] start candidates: |F(0)| %.6e |F(explicit)| %.6e\n", res_zero, res);
-            if (!(res < res_zero)) {
-                // zero wins (ties included): back to K = 0
+                fprintf(stderr, "[irk] start candidates: |F(0)| %.6e |F(explicit)| %.6e |F(extrapolated)| %.6e\n",
+                        res_zero, res_expl, had_extrap ? res : -1.0);
+            const bool expl_beats_zero = res_expl < res_zero;
+            const double best = expl_beats_zero ? res_expl : res_zero;
+            if (had_extrap && res < best) {
+                stats.start = 2;
+            } else if (expl_beats_zero) {
+                stats.start = 1;
+                if (had_extrap) {
+                    // back to the explicit candidate
+                    PROF(c, c->stream, "k_rhs_init<" + std::to_string(P.s) + "," + std::to_string(P.op.kind) + ">",
+                         8.0 * P.nf * (1 + P.s), 1,
+                         launch_rhs_init(c->stream, P.s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
+                    const irk_status e = issue_residual();
+                    return e != IRK_OK ? fail(e) : false;
+                }
+            } else {
+                // zero wins: back to K = 0
+                stats.start = 0;
                 PROF(c, c->stream, "k_fill", 8.0 * P.s * P.nf, 1,
                      launch_fill(c->stream, c->K, 0.0, (size_t)P.s * P.nf));
                 const irk_status e = issue_residual();
@@ -1337,6 +1392,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->mg_coarsest = 8;
     o->coarse_iters = 24;
     o->batch_mg = 0;
+    o->start_extrapolate = 1;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
@@ -1522,7 +1578,15 @@ namespace irk {
 irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1) {
     if (!c || !u_n || !u_np1 || !(dt > 0) || !std::isfinite(t_n)) return IRK_E_ARG;
     (void)hipGetLastError();
+    // a step from the previous step's output buffer at its end time
+    // continues it: its stage vectors (still in K) give a third candidate
+    c->extrap = c->have_stages && c->P.sd_s == 0 && c->P.opt.start_extrapolate && u_n == c->next_u &&
+                t_n == c->next_t;
+    c->extrap_ratio = c->extrap ? dt / c->prev_dt : 1.0;
     c->have_stages = false;
+    c->next_u = u_np1;
+    c->next_t = t_n + dt;
+    c->prev_dt = dt;
     c->stepper->begin(u_n, t_n, dt, tol > 0 ? tol : c->P.opt.newton_rtol, u_np1);
     return IRK_OK;
 }

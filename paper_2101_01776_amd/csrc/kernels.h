@@ -16,6 +16,8 @@ void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double
                      const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr);
 void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
                      double cos_tn);
+// Kx_i = sum_j W.A[i][j] K_j (s stage fields of length nf; Kx must not alias K)
+void launch_stage_extrap(hipStream_t st, int s, size_t nf, const double *K, double *Kx, const StageCoefs &W);
 void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, const double *K, double *out,
                          const StageCoefs &C, double dt);
 void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, size_t len, double scale,

@@ -305,6 +305,26 @@ __global__ void __launch_bounds__(IRK_WG) k_final_update(size_t nf, const double
     }
 }
 
+// Kx_i = sum_j W_ij K_j over the s stage fields (the extrapolated starting
+// stage vectors; W row-major s x s, passed in StageCoefs.A)
+template <int S>
+__global__ void __launch_bounds__(IRK_WG) k_stage_extrap(size_t nf, const double *__restrict__ K,
+                                                         double *__restrict__ Kx, StageCoefs W) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < nf; e += stride) {
+        double k[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) k[j] = K[j * nf + e];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double acc = 0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc += W.A[i * S + j] * k[j];
+            Kx[i * nf + e] = acc;
+        }
+    }
+}
+
 // sums of `nfields` consecutive fields of length len (VSF means)
 __global__ void __launch_bounds__(IRK_WG) k_field_sums(const double *__restrict__ X, size_t ld, int nfields,
                                                        size_t len, double scale, double *partials, double *out,
@@ -630,6 +650,17 @@ void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, con
         case 3: k_final_update<3><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
         case 4: k_final_update<4><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
         case 5: k_final_update<5><<<g, IRK_WG, 0, st>>>(nf, un, K, out, C, dt); break;
+    }
+}
+
+void launch_stage_extrap(hipStream_t st, int s, size_t nf, const double *K, double *Kx, const StageCoefs &W) {
+    const unsigned g = grid_for(nf);
+    switch (s) {
+        case 1: k_stage_extrap<1><<<g, IRK_WG, 0, st>>>(nf, K, Kx, W); break;
+        case 2: k_stage_extrap<2><<<g, IRK_WG, 0, st>>>(nf, K, Kx, W); break;
+        case 3: k_stage_extrap<3><<<g, IRK_WG, 0, st>>>(nf, K, Kx, W); break;
+        case 4: k_stage_extrap<4><<<g, IRK_WG, 0, st>>>(nf, K, Kx, W); break;
+        case 5: k_stage_extrap<5><<<g, IRK_WG, 0, st>>>(nf, K, Kx, W); break;
     }
 }
 

@@ -95,24 +95,30 @@ def test_full_size_bench_workload_residual_and_update():
     n, s, dt = 512, 3, 5e-3
     op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
     sol = _solver(op)
+    import torch
     u = inputs.nldiff_u0(n)
+    u_dev = torch.tensor(u, dtype=torch.float64, device="cuda")
     t = 0.0
-    for step in range(2):
-        out, st = sol.step(u, t, dt)
+    A, b, c = tb.tableau("gauss", s)
+    K_prev = None
+    for step in range(3):
+        # each step continues the previous one (its output buffer, its end
+        # time): from the second on the extrapolated stages are a candidate
+        out, st = sol.step(u_dev, t, dt)
         K = sol.stages().cpu().numpy().reshape(s, -1)
         u1 = out.cpu().numpy()
         F = oracle_residual(op, "gauss", s, u, t, dt, K)
-        A, _, c = tb.tableau("gauss", s)
-        F0 = oracle_residual(op, "gauss", s, u, t, dt, nw.initial_stages(
-            pb.NonlinearDiffusion2D(n), A, c, u.ravel(), t, dt))
+        K0, pick = nw.initial_stages(pb.NonlinearDiffusion2D(n), A, c, u.ravel(), t, dt,
+                                     prev=None if K_prev is None else (K_prev, dt))
+        F0 = oracle_residual(op, "gauss", s, u, t, dt, K0)
         nF = np.linalg.norm(F)
-        print(f"  512^2 step {step}: |F| {nF:.3e} |F0| {np.linalg.norm(F0):.3e} {st}")
+        print(f"  512^2 step {step}: |F| {nF:.3e} |F0| {np.linalg.norm(F0):.3e} start {pick} {st}")
+        assert st["start"] == pick
         assert abs(nF - st["final_res"]) <= 5e-2 * nF
         assert abs(np.linalg.norm(F0) - st["res0"]) <= 1e-9 * st["res0"]
         assert dt * nF <= 1e-11 * np.linalg.norm(u)
-        _, b, _ = tb.tableau("gauss", s)
         assert rel(u1.ravel(), u.ravel() + dt * (b @ K)) < 1e-15
-        u, t = u1, t + dt
+        u, u_dev, t, K_prev = u1, out, t + dt, K
     sol.close()
 
 
@@ -139,6 +145,52 @@ def test_trajectory_discrete_manufactured_solution():
         eg, eo = rel(ug, exact), rel(uo, exact)
         assert abs(eg - eo) <= 1e-3 * eo
         sol.close()
+
+
+@pytest.mark.parametrize("family,s", [("gauss", 3), ("radau", 3), ("gauss", 5)])
+def test_extrapolated_start_on_continued_steps(family, s):
+    """Continued steps (input = the previous output buffer, t_n = its end
+    time) start from the extrapolated stage vectors when their residual is
+    the smallest: on the semi-discrete manufactured solution that is every
+    step after the first, with fewer Newton iterations than without the
+    candidate and the same trajectory (float64 V-cycles: 1e-10, the parity
+    bar).  The oracle, fed the same history, picks the same candidate at
+    every step.  A step that does not continue (same input again, or a
+    different time) does not use it."""
+    import torch
+    n, dt, nsteps = 64, 5e-3, 6
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS_DISCRETE)
+    prob = pb.NonlinearDiffusion2D(n, forcing="discrete")
+    A, b, c = tb.tableau(family, s)
+    runs = {}
+    for ex in (1, 0):
+        sol = _solver(op, family, s, prec_fp32=0, start_extrapolate=ex)
+        u = torch.tensor(inputs.nldiff_u0(n), dtype=torch.float64, device="cuda")
+        t, its, picks, K_prev = 0.0, 0, [], None
+        for k in range(nsteps):
+            un = u.cpu().numpy().ravel()
+            u, st = sol.step(u, t, dt)
+            if ex:
+                _, pick = nw.initial_stages(prob, A, c, un, t, dt,
+                                            prev=None if K_prev is None else (K_prev, dt))
+                assert st["start"] == pick, (k, st, pick)
+                K_prev = sol.stages().cpu().numpy().reshape(s, -1)
+            picks.append(st["start"])
+            its += st["newton_its"]
+            t += dt
+        runs[ex] = (u.cpu().numpy(), its, picks)
+        if ex:
+            # not a continuation: the same input again, and a shifted time
+            again, st = sol.step(u, t - dt, dt)
+            assert st["start"] != 2
+            _, st = sol.step(again, t + 1.0, dt)
+            assert st["start"] != 2
+        sol.close()
+    print(f"  {family}-{s}: Newton its {runs[1][1]} (extrapolated start) vs {runs[0][1]}; picks {runs[1][2]}")
+    assert runs[1][2][1:] == [2] * (nsteps - 1)
+    assert 2 not in runs[0][2]
+    assert runs[1][1] < runs[0][1]
+    assert rel(runs[1][0], runs[0][0]) < 1e-10
 
 
 def test_gauss_conserves_invariants_on_gpu():
