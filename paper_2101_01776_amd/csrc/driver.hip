@@ -141,8 +141,9 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     if (!level_geometry(o, P->opt.mg_coarsest, &P->lg)) return IRK_E_ARG;
     P->tsz = P->opt.prec_fp32 ? sizeof(float) : sizeof(double);
     // levels from l0 down run inside one work-group with everything in LDS
-    // (at most 64 KiB, 4096 points on its finest level and IRK_MAX_SUB_LEVELS
-    // levels)
+    // (at most 60 KiB of dynamic LDS -- the kernel's few KiB of static LDS
+    // come on top of it --, 4096 points on its finest level and
+    // IRK_MAX_SUB_LEVELS levels)
     P->l0 = P->lg.nlev - 1;
     {
         const int opk = o.kind == IRK_OP_NLDIFF_2D ? MG_NLDIFF : (o.kind == IRK_OP_BURGERS_1D ? MG_BURGERS : MG_VSF_OMEGA);
@@ -150,7 +151,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
             const size_t top = (size_t)P->lg.nx[l] * P->lg.ny[l];
             const int nl = P->lg.nlev - l;
             if (top <= 4096 && nl <= IRK_MAX_SUB_LEVELS &&
-                mg_subcycle_lds_bytes(opk, nl, P->lg.nx + l, P->lg.ny + l, P->tsz) <= 64 * 1024) {
+                mg_subcycle_lds_bytes(opk, nl, P->lg.nx + l, P->lg.ny + l, P->tsz) <= 60 * 1024) {
                 P->l0 = l;
                 break;
             }
@@ -461,6 +462,7 @@ static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop,
     sa.x0 = c->lev<T>(ln, l0, 0);
     sa.deg = deg;
     sa.coarse_iters = P.opt.coarse_iters;
+    sa.wave_pts = IRK_SUB_WAVE_PTS;
     for (int k = 0; k < IRK_MAX_CHEB; ++k) {
         sa.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
         sa.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);

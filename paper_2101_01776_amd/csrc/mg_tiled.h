@@ -10,6 +10,7 @@ namespace irk {
 #define IRK_MAX_CHEB 8
 #define IRK_MAX_COARSE_ITERS 64
 #define IRK_MAX_SUB_LEVELS 8       // levels of the one-work-group sub-cycle
+#define IRK_SUB_WAVE_PTS 64        // sub-cycle levels this small run on one wave
 
 // One level of a V-cycle: geometry, operator parameters, buffers.
 template <class T>
@@ -60,6 +61,7 @@ struct MgSubArgs {
     const T *b0;         // right-hand side of the first level (when MgIn has none)
     T *x0;               // result of the first level (when MgOut has no z)
     int deg, coarse_iters;
+    int wave_pts;        // levels of at most this many points run on one wave
     T cd[IRK_MAX_CHEB], cr[IRK_MAX_CHEB];
 };
 

@@ -161,13 +161,24 @@ __device__ __forceinline__ T jacobi_res(const T *At, int npl, const T *bt, const
         }                                                                  \
     } while (0)
 
+// (t / w, t % w) for 0 <= t < 2^20, 1 <= w <= 2^16 with a float reciprocal
+// (the quotient estimate is off by at most one; one correction each way)
+// instead of the integer division sequence
+__device__ __forceinline__ void divmod_small(int t, int w, int &q, int &r) {
+    q = (int)((float)t * __builtin_amdgcn_rcpf((float)w));
+    r = t - q * w;
+    if (r < 0) { r += w; --q; }
+    if (r >= w) { r -= w; ++q; }
+}
+
 // Points p = j * nx + i of an nx-wide level, strided over the work-group,
 // with (i, j) advanced incrementally.
 #define FOR_PTS(np_, nx_, ...)                                             \
     do {                                                                   \
         const int w_ = (nx_);                                              \
         const int sx_ = (int)blockDim.x % w_, sy_ = (int)blockDim.x / w_;  \
-        int i = (int)threadIdx.x % w_, j = (int)threadIdx.x / w_;          \
+        int i, j;                                                          \
+        divmod_small((int)threadIdx.x, w_, j, i);                          \
         for (int p = threadIdx.x; p < (np_); p += blockDim.x) {            \
             __VA_ARGS__;                                                   \
             i += sx_;                                                      \
@@ -313,9 +324,12 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
             });
         } else {
             FOR_BOX(ax0, ax1, by0, by1, W, {
+                // x read before d is stored (d may alias x for the compiler:
+                // a read after the store would cost another LDS round trip)
+                const T xv = xcur[c];
                 const T dn = cd * dd[c] + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
                 dd[c] = dn;
-                xnext[c] = xcur[c] + dn;
+                xnext[c] = xv + dn;
             });
         }
         __syncthreads();
@@ -422,9 +436,10 @@ __device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut 
         const int by0 = two_d ? hy - r : 0, by1 = two_d ? hy + TY + r : 1;
         const T cd = g.cd[k], cr = g.cr[k];
         FOR_BOX(ax0, ax1, by0, by1, W, {
+            const T xv = xcur[c];
             const T dn = (k == 0 ? T(0) : cd * dd[c]) + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
             dd[c] = dn;
-            xnext[c] = xcur[c] + dn;
+            xnext[c] = xv + dn;
         });
         __syncthreads();
         T *t = xcur;
@@ -495,36 +510,216 @@ __device__ __forceinline__ T level_jres(const T *At, int np, const T *bt, const 
     return r;
 }
 
-// nsteps Chebyshev steps on a level; x and xn alternate (one barrier per
+// A crew runs one level's sweeps: the whole work-group (separated by
+// barriers), or its first wave alone, whose lanes run in lockstep so that
+// wave-scope fences order its LDS accesses (no barrier, no idle waves to
+// wait for on levels of at most a few hundred points).
+struct CrewGroup {
+    static constexpr bool size_is_wave = false;
+    static __device__ __forceinline__ int tid() { return (int)threadIdx.x; }
+    static __device__ __forceinline__ int size() { return (int)blockDim.x; }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct CrewWave {
+    static constexpr bool size_is_wave = true;
+    static __device__ __forceinline__ int tid() { return (int)(threadIdx.x & 63); }
+    static __device__ __forceinline__ int size() { return 64; }
+    static __device__ __forceinline__ void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+// FOR_PTS over the members of a crew
+#define FOR_PTS_C(C_, np_, nx_, ...)                                       \
+    do {                                                                   \
+        const int w_ = (nx_), n_ = C_::size(), t_ = C_::tid();             \
+        const int sx_ = n_ % w_, sy_ = n_ / w_;                            \
+        int i, j;                                                          \
+        divmod_small(t_, w_, j, i);                                        \
+        for (int p = t_; p < (np_); p += n_) {                             \
+            __VA_ARGS__;                                                   \
+            i += sx_;                                                      \
+            j += sy_;                                                      \
+            if (i >= w_) { i -= w_; ++j; }                                 \
+        }                                                                  \
+    } while (0)
+
+// sum / max over a crew, result in every member (red: >= 16 doubles of LDS)
+template <class C>
+__device__ __forceinline__ double crew_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if constexpr (C::size_is_wave) {
+        return v;
+    } else {
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        __syncthreads();
+        return t;
+    }
+}
+template <class C>
+__device__ __forceinline__ double crew_max(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if constexpr (C::size_is_wave) {
+        return v;
+    } else {
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
+        __syncthreads();
+        return t;
+    }
+}
+
+// nsteps Chebyshev steps on a level; x and xn alternate (one crew sync per
 // step), the result is left in x.
-template <class T, int OPK>
+template <class T, int OPK, class C>
 __device__ void wg_cheb(const T *At, const T *bt, T *x, T *xn, T *d, int nx, int ny, const T *cd, const T *cr,
                         int nsteps, bool from_zero) {
     const int np = nx * ny;
     T *xc = x, *xo = xn;
     for (int k = 0; k < nsteps; ++k) {
         if (from_zero && k == 0) {
-            for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            for (int p = C::tid(); p < np; p += C::size()) {
                 const T dn = cr[0] * bt[p];
                 d[p] = dn;
                 xo[p] = dn;
             }
         } else {
-            FOR_PTS(np, nx, {
+            FOR_PTS_C(C, np, nx, {
+                const T xv = xc[p];
                 const T dn = (k == 0 ? T(0) : cd[k] * d[p]) + cr[k] * level_jres<T, OPK>(At, np, bt, xc, p, i, j, nx, ny);
                 d[p] = dn;
-                xo[p] = xc[p] + dn;
+                xo[p] = xv + dn;
             });
         }
-        __syncthreads();
+        C::sync();
         T *t = xc;
         xc = xo;
         xo = t;
     }
     if (xc != x) {
-        for (int p = threadIdx.x; p < np; p += blockDim.x) x[p] = xc[p];
-        __syncthreads();
+        for (int p = C::tid(); p < np; p += C::size()) x[p] = xc[p];
+        C::sync();
     }
+}
+
+// one sub-cycle level on the way down: pre-smoothing from zero, residual,
+// full weighting into the next level's scaled right-hand side
+template <class T, int OPK, class C>
+__device__ void sub_down(const MgSubArgs<T> &s, int l, const T *At, const T *Ac, const T *bt, T *x, T *R, T *Dv,
+                         const T *acc_c, T *bc) {
+    const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
+    wg_cheb<T, OPK, C>(At, bt, x, R, Dv, nx, ny, s.cd, s.cr, s.deg, true);
+    FOR_PTS_C(C, np, nx, R[p] = Ac[p] * level_jres<T, OPK>(At, np, bt, x, p, i, j, nx, ny));
+    C::sync();
+    const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
+    FOR_PTS_C(C, nxc * nyc, nxc, {
+        T acc;
+        if (ny > 1) {
+            const int im = wrap2(2 * i - 1, nx), ip = 2 * i + 1, jm = wrap2(2 * j - 1, ny), jp = 2 * j + 1;
+            acc = T(0.25) * R[2 * j * nx + 2 * i] +
+                  T(0.125) * (R[2 * j * nx + im] + R[2 * j * nx + ip] + R[jm * nx + 2 * i] + R[jp * nx + 2 * i]) +
+                  T(0.0625) * (R[jm * nx + im] + R[jm * nx + ip] + R[jp * nx + im] + R[jp * nx + ip]);
+        } else {
+            acc = T(0.5) * R[2 * i] + T(0.25) * (R[wrap2(2 * i - 1, nx)] + R[2 * i + 1]);
+        }
+        bc[p] = acc / acc_c[p];
+    });
+    C::sync();
+}
+
+// one sub-cycle level on the way up: add the (bi)linear interpolation of the
+// coarse correction, post-smooth
+template <class T, int OPK, class C>
+__device__ void sub_up(const MgSubArgs<T> &s, int l, const T *At, const T *bt, T *xl, const T *xcl, T *R, T *Dv) {
+    const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
+    const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
+    FOR_PTS_C(C, np, nx, {
+        const int I0 = i >> 1, I1 = (i & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
+        T e;
+        if (ny > 1) {
+            const int J0 = j >> 1, J1 = (j & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
+            e = T(0.25) * (xcl[J0 * nxc + I0] + xcl[J0 * nxc + I1] + xcl[J1 * nxc + I0] + xcl[J1 * nxc + I1]);
+        } else {
+            e = T(0.5) * (xcl[I0] + xcl[I1]);
+        }
+        xl[p] += e;
+    });
+    C::sync();
+    wg_cheb<T, OPK, C>(At, bt, xl, R, Dv, nx, ny, s.cd, s.cr, s.deg, false);
+}
+
+// coarsest level: Chebyshev iteration on the Gershgorin interval
+// [1 - rho, 1 + rho] of D^{-1} A (rho = max row sum of |a~_q|); the
+// singular periodic Poisson operator (rho = 1) is solved on mean-free data
+// with the interval's lower end at its smallest nonzero eigenvalue
+template <class T, int OPK, class C>
+__device__ void sub_coarse(const MgSubArgs<T> &s, int l, const T *At, T *bt, T *x, T *R, T *Dv) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
+    __shared__ double red[16];
+    const bool singular = (OPK == MG_POISSON && s.sigma == T(0));
+    if (singular) {
+        double acc = 0;
+        for (int p = C::tid(); p < np; p += C::size()) acc += (double)bt[p];
+        const T m = (T)(crew_sum<C>(acc, red) / np);
+        for (int p = C::tid(); p < np; p += C::size()) bt[p] -= m;
+        C::sync();
+    }
+    double rho = 0.0;
+    for (int p = C::tid(); p < np; p += C::size()) {
+        double rs = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) rs += fabs((double)At[q * np + p]);
+        rho = fmax(rho, rs);
+    }
+    rho = crew_max<C>(rho, red);
+    double lmin = 1.0 - rho, lmax = 1.0 + rho;
+    if (singular || lmin < 0.05) {
+        // sin(pi / n) from its Taylor series (a heuristic lower end only)
+        auto sin_pi_over = [](int n) {
+            const double x = 3.14159265358979323846 / n, x2 = x * x;
+            return x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0)));
+        };
+        const double sx = sin_pi_over(nx), sy = ny > 1 ? sin_pi_over(ny) : 1.0;
+        lmin = fmax(0.5 * fmin(sx * sx, sy * sy), 0.02);
+    }
+    // steps for a 1e-3 reduction of the Chebyshev bound 2 r^k
+    const double kap = lmax / lmin, sq = sqrt(kap);
+    const double rr = (sq - 1.0) / (sq + 1.0);
+    int iters = rr > 0.0 ? (int)ceil(log(2000.0) / -log(rr)) : 1;
+    iters = iters < 2 ? 2 : (iters > s.coarse_iters ? s.coarse_iters : iters);
+    // Chebyshev step coefficients, one per member from the closed form of
+    // the recurrence rho_k = 1 / (2 sigma1 - rho_{k-1}), rho_0 = 1/sigma1:
+    // rho_k = T_k(sigma1) / T_{k+1}(sigma1)
+    //       = e^{-a} (1 + e^{-2ka}) / (1 + e^{-2(k+1)a}),  a = acosh(sigma1);
+    // step k: d <- rho_k rho_{k-1} d + (2 rho_k / delta) r  (k = 0: r / theta)
+    __shared__ T ccd[IRK_MAX_COARSE_ITERS], ccr[IRK_MAX_COARSE_ITERS];
+    if (C::tid() < iters) {
+        const int k = C::tid();
+        const double theta = 0.5 * (lmax + lmin), delta = fmax(0.5 * (lmax - lmin), 1e-12 * theta);
+        const double sig1 = theta / delta;
+        const double a = log(sig1 + sqrt(sig1 * sig1 - 1.0));
+        auto rho_k = [&](int m) {
+            return exp(-a) * (1.0 + exp(-2.0 * m * a)) / (1.0 + exp(-2.0 * (m + 1) * a));
+        };
+        if (k == 0) {
+            ccd[0] = T(0);
+            ccr[0] = (T)(1.0 / theta);
+        } else {
+            const double rk = rho_k(k);
+            ccd[k] = (T)(rk * rho_k(k - 1));
+            ccr[k] = (T)(2.0 * rk / delta);
+        }
+    }
+    C::sync();
+    wg_cheb<T, OPK, C>(At, bt, x, R, Dv, nx, ny, ccd, ccr, iters, true);
 }
 
 template <class T, int OPK>
@@ -628,124 +823,26 @@ __device__ __forceinline__ void mg_subcycle_body(const MgSubArgs<T> &s, const Mg
                                                       s.nu, s.sigma, s.dt, at, np, p, acl, l == 0 ? bl : nullptr));
     }
     __syncthreads();
-    for (int l = 0; l < L - 1; ++l) {
-        const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, s.cd, s.cr, s.deg, true);
-        // residual b - A x into R, then full weighting into the next b~
-        FOR_PTS(np, nx, R[p] = AC(l)[p] * level_jres<T, OPK>(AT(l), np, B(l), X(l), p, i, j, nx, ny));
+    // levels of at most s.wave_pts points (and everything coarser) run on
+    // the first wave alone; the larger ones on the whole work-group
+    int lw = L - 1;
+    while (lw > 0 && npts(lw - 1) <= s.wave_pts) --lw;
+    if (npts(lw) > s.wave_pts) lw = L;
+    const int lg = lw < L - 1 ? lw : L - 1;        // levels 0..lg-1 go down as a group
+    for (int l = 0; l < lg; ++l)
+        sub_down<T, OPK, CrewGroup>(s, l, AT(l), AC(l), B(l), X(l), R, Dv, AC(l + 1), B(l + 1));
+    if (lw < L) {
+        if (threadIdx.x < 64) {
+            for (int l = lw; l < L - 1; ++l)
+                sub_down<T, OPK, CrewWave>(s, l, AT(l), AC(l), B(l), X(l), R, Dv, AC(l + 1), B(l + 1));
+            sub_coarse<T, OPK, CrewWave>(s, L - 1, AT(L - 1), B(L - 1), X(L - 1), R, Dv);
+            for (int l = L - 2; l >= lw; --l) sub_up<T, OPK, CrewWave>(s, l, AT(l), B(l), X(l), X(l + 1), R, Dv);
+        }
         __syncthreads();
-        const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
-        const T *acc_c = AC(l + 1);
-        T *bc = B(l + 1);
-        FOR_PTS(nxc * nyc, nxc, {
-            T acc;
-            if (ny > 1) {
-                const int im = wrap2(2 * i - 1, nx), ip = 2 * i + 1, jm = wrap2(2 * j - 1, ny), jp = 2 * j + 1;
-                acc = T(0.25) * R[2 * j * nx + 2 * i] +
-                      T(0.125) * (R[2 * j * nx + im] + R[2 * j * nx + ip] + R[jm * nx + 2 * i] + R[jp * nx + 2 * i]) +
-                      T(0.0625) * (R[jm * nx + im] + R[jm * nx + ip] + R[jp * nx + im] + R[jp * nx + ip]);
-            } else {
-                acc = T(0.5) * R[2 * i] + T(0.25) * (R[wrap2(2 * i - 1, nx)] + R[2 * i + 1]);
-            }
-            bc[p] = acc / acc_c[p];
-        });
-        __syncthreads();
+    } else {
+        sub_coarse<T, OPK, CrewGroup>(s, L - 1, AT(L - 1), B(L - 1), X(L - 1), R, Dv);
     }
-    {
-        // coarsest level: Chebyshev iteration on the Gershgorin interval
-        // [1 - rho, 1 + rho] of D^{-1} A (rho = max row sum of |a~_q|); the
-        // singular periodic Poisson operator (rho = 1) is solved on mean-free
-        // data with the interval's lower end at its smallest nonzero
-        // eigenvalue
-        const int l = L - 1, nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        __shared__ double red[16];
-        const bool singular = (OPK == MG_POISSON && s.sigma == T(0));
-        if (singular) {
-            double acc = 0;
-            for (int p = threadIdx.x; p < np; p += blockDim.x) acc += (double)B(l)[p];
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-            __syncthreads();
-            double tot = 0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
-            const T m = (T)(tot / np);
-            __syncthreads();
-            for (int p = threadIdx.x; p < np; p += blockDim.x) B(l)[p] -= m;
-            __syncthreads();
-        }
-        double rho = 0.0;
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            double rs = 0.0;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) rs += fabs((double)AT(l)[q * np + p]);
-            rho = fmax(rho, rs);
-        }
-        for (int off = 32; off > 0; off >>= 1) rho = fmax(rho, __shfl_xor(rho, off, 64));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rho;
-        __syncthreads();
-        rho = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) rho = fmax(rho, red[w]);
-        __syncthreads();
-        double lmin = 1.0 - rho, lmax = 1.0 + rho;
-        if (singular || lmin < 0.05) {
-            // sin(pi / n) from its Taylor series (a heuristic lower end only)
-            auto sin_pi_over = [](int n) {
-                const double x = 3.14159265358979323846 / n, x2 = x * x;
-                return x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0)));
-            };
-            const double sx = sin_pi_over(nx), sy = ny > 1 ? sin_pi_over(ny) : 1.0;
-            lmin = fmax(0.5 * fmin(sx * sx, sy * sy), 0.02);
-        }
-        // steps for a 1e-3 reduction of the Chebyshev bound 2 r^k
-        const double kap = lmax / lmin, sq = sqrt(kap);
-        const double rr = (sq - 1.0) / (sq + 1.0);
-        int iters = rr > 0.0 ? (int)ceil(log(2000.0) / -log(rr)) : 1;
-        iters = iters < 2 ? 2 : (iters > s.coarse_iters ? s.coarse_iters : iters);
-        // Chebyshev step coefficients, one per thread from the closed form of
-        // the recurrence rho_k = 1 / (2 sigma1 - rho_{k-1}), rho_0 = 1/sigma1:
-        // rho_k = T_k(sigma1) / T_{k+1}(sigma1)
-        //       = e^{-a} (1 + e^{-2ka}) / (1 + e^{-2(k+1)a}),  a = acosh(sigma1);
-        // step k: d <- rho_k rho_{k-1} d + (2 rho_k / delta) r  (k = 0: r / theta)
-        __shared__ T ccd[IRK_MAX_COARSE_ITERS], ccr[IRK_MAX_COARSE_ITERS];
-        if ((int)threadIdx.x < iters) {
-            const int k = threadIdx.x;
-            const double theta = 0.5 * (lmax + lmin), delta = fmax(0.5 * (lmax - lmin), 1e-12 * theta);
-            const double sig1 = theta / delta;
-            const double a = log(sig1 + sqrt(sig1 * sig1 - 1.0));
-            auto rho = [&](int m) {
-                return exp(-a) * (1.0 + exp(-2.0 * m * a)) / (1.0 + exp(-2.0 * (m + 1) * a));
-            };
-            if (k == 0) {
-                ccd[0] = T(0);
-                ccr[0] = (T)(1.0 / theta);
-            } else {
-                const double rk = rho(k);
-                ccd[k] = (T)(rk * rho(k - 1));
-                ccr[k] = (T)(2.0 * rk / delta);
-            }
-        }
-        __syncthreads();
-        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, ccd, ccr, iters, true);
-    }
-    for (int l = L - 2; l >= 0; --l) {
-        const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-        const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
-        const T *xcl = X(l + 1);
-        T *xl = X(l);
-        FOR_PTS(np, nx, {
-            const int I0 = i >> 1, I1 = (i & 1) ? (I0 + 1 == nxc ? 0 : I0 + 1) : I0;
-            T e;
-            if (ny > 1) {
-                const int J0 = j >> 1, J1 = (j & 1) ? (J0 + 1 == nyc ? 0 : J0 + 1) : J0;
-                e = T(0.25) * (xcl[J0 * nxc + I0] + xcl[J0 * nxc + I1] + xcl[J1 * nxc + I0] + xcl[J1 * nxc + I1]);
-            } else {
-                e = T(0.5) * (xcl[I0] + xcl[I1]);
-            }
-            xl[p] += e;
-        });
-        __syncthreads();
-        wg_cheb<T, OPK>(AT(l), B(l), X(l), R, Dv, nx, ny, s.cd, s.cr, s.deg, false);
-    }
+    for (int l = lg - 1; l >= 0; --l) sub_up<T, OPK, CrewGroup>(s, l, AT(l), B(l), X(l), X(l + 1), R, Dv);
     for (int p = threadIdx.x; p < np0; p += blockDim.x) {
         if (out.z) out.z[p] = (double)X(0)[p] + (out.shift ? out.shift_scale * out.shift[0] : 0.0);
         else s.x0[p] = X(0)[p];
