@@ -18,8 +18,13 @@ whose fixed point is the solution of the stage equations):
   or stops decreasing, so the result is the stage solution to roundoff;
 * update, equation (update): u_{n+1} = u_n + dt sum_i b_i k_i.
 
-The initial guess is the same for every stage, k_i = M^+ N(u_n, t_n) on the
-differential rows and 0 on algebraic rows (the paper leaves it open).
+The initial guess is the best (smallest residual) of K = 0, the explicit
+k_i = M^+ N(u_n, t_n) on differential rows and 0 on algebraic rows, and on a
+continued step the previous stages extrapolated (the paper leaves it open).
+
+``block_operator`` writes out the Krylov operator of one eigen-block under
+each Newton-like truncation of Section 3.2 (the definition those iterations
+are built from; used to pin the GPU's block operators).
 """
 from __future__ import annotations
 
@@ -170,3 +175,48 @@ def irk_step(problem, A, b, c, u_n, t_n, dt, max_iter=60, prev=None):
     """u_{n+1} = u_n + dt sum_i b_i k_i with K from ``irk_stages``."""
     K, info = irk_stages(problem, A, c, u_n, t_n, dt, max_iter=max_iter, prev=prev)
     return u_n + dt * (b @ K), K, info
+
+
+def block_operator(problem, A, c, u_n, t_n, dt, K, T, block, variant):
+    """Krylov operator D_b of one eigen-block (equation (diag_blocks)) as a
+    sparse matrix on the block's transformed components.  With the stage
+    Jacobians L_k = L(U_k) and d weights d_{r,q,k} = (T^{-1})_{r k} T_{k q}
+    (equation (Q0approx) for the similarity T), row a of the block (transformed
+    row r_a = first + a) is
+      Lambda_{ab} M - dt sum_k W_{a b k} L_k
+    with the truncations of Section 3.2 written in the eigenbasis:
+      0: W_{aak} = [k = s-1] (every row linearized at the last stage),
+      1: W_{aak} = [k = argmax_k |d_{r_a r_a k}|] (lumped to the largest
+         weight),
+      2: W_{aak} = d_{r_a r_a k} (the diagonal weights, not lumped),
+      3: W_{abk} = d_{r_a r_b k} for both rows of the block (the truncation to
+         the block sparsity of R0; in the eigenbasis R0 is block diagonal).
+    ``block`` = (first_row, width, eta, beta); ODE operators only (M = I or
+    the problem's mass, no low-rank Jacobian part)."""
+    first, width, eta, beta = block
+    s = len(c)
+    U = stage_values(A, u_n, dt, K)
+    L = []
+    for k in range(s):
+        S, Ul, _ = problem.jac(U[k], t_n + c[k] * dt)
+        assert Ul is None
+        L.append(S)
+    Ti = np.linalg.inv(T)
+    W = np.zeros((width, width, s))
+    for a in range(width):
+        r = first + a
+        dr = Ti[r, :] * T[:, r]
+        if variant == 0:
+            W[a, a, s - 1] = 1.0
+        elif variant == 1:
+            W[a, a, int(np.argmax(np.abs(dr)))] = 1.0
+        elif variant == 2:
+            W[a, a, :] = dr
+        else:
+            for b2 in range(width):
+                W[a, b2, :] = Ti[r, :] * T[:, first + b2]
+    Lam = np.array([[eta]]) if width == 1 else np.array([[eta, beta], [-beta, eta]])
+    M = sp.diags(problem.mass)
+    blocks = [[Lam[a, b2] * M - dt * sum(W[a, b2, k] * L[k] for k in range(s)) for b2 in range(width)]
+              for a in range(width)]
+    return sp.bmat(blocks, format="csr")

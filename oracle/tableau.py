@@ -30,6 +30,10 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 * ``real_schur_standard`` is the real Schur form A0^{-1} = Q0 R0 Q0^T with
   each 2x2 diagonal block standardized to equal diagonal entries (the form
   the worked example of equation (Gauss4Radau3_example) uses).
+* ``real_eigenbasis`` is the real eigenbasis A0^{-1} = T Lambda T^{-1}
+  (Section 3.1 with phi = beta): one column per real eigenvalue and the pair
+  (Re v, Im v) per conjugate pair, normalized so that the transformed blocks
+  and their d weights are unique (see the function).
 """
 from __future__ import annotations
 
@@ -251,3 +255,41 @@ def real_schur_standard(Ainv: np.ndarray):
         else:
             i += 1
     return Q, R
+
+
+def real_eigenbasis(A: np.ndarray):
+    """Real eigenbasis of A0^{-1}: A0^{-1} = T Lambda T^{-1}, Lambda block
+    diagonal with eta for a real eigenvalue and [[eta, beta], [-beta, eta]]
+    for a pair eta +- i beta (beta > 0): if A0^{-1} v = (eta + i beta) v with
+    v = a + i b, then A0^{-1} [a b] = [a b] [[eta, beta], [-beta, eta]].
+    Blocks: real eigenvalues first (ascending), then pairs by decreasing beta.
+    Normalization: unit vectors; for a pair the phase of v that makes a
+    orthogonal to b with |a| >= |b| (it maximizes |a|^2 - |b|^2); the entry of
+    largest magnitude of a (of v, for a real eigenvalue) positive.  Returns
+    (T, blocks) with blocks a list of (first_row, width, eta, beta)."""
+    s = A.shape[0]
+    lam, V = np.linalg.eig(np.linalg.inv(A))
+    reals = sorted((float(lam[k].real), k) for k in range(s) if abs(lam[k].imag) < 1e-12)
+    ups = sorted(((float(lam[k].imag), k) for k in range(s) if lam[k].imag > 1e-12), reverse=True)
+    T = np.zeros((s, s))
+    blocks = []
+    row = 0
+    for eta, k in reals:
+        v = np.real(V[:, k])
+        v = v / np.linalg.norm(v)
+        if v[np.argmax(np.abs(v))] < 0:
+            v = -v
+        T[:, row] = v
+        blocks.append((row, 1, eta, 0.0))
+        row += 1
+    for beta, k in ups:
+        v = V[:, k] / np.linalg.norm(V[:, k])
+        a, b = v.real, v.imag
+        th = 0.5 * math.atan2(-2.0 * float(a @ b), float(a @ a - b @ b))
+        v = v * np.exp(1j * th)
+        if v.real[np.argmax(np.abs(v.real))] < 0:
+            v = -v
+        T[:, row], T[:, row + 1] = v.real, v.imag
+        blocks.append((row, 2, float(lam[k].real), beta))
+        row += 2
+    return T, blocks
