@@ -104,8 +104,17 @@ typedef struct irk_options {
     int restart;            /* FGMRES restart length (1..IRK_MAX_RESTART)     */
     int max_krylov;         /* FGMRES iteration cap per block solve           */
     int max_newton;         /* Newton-like iteration cap                      */
-    int newton_like;        /* 0: simplified Newton (last-stage Jacobian),
-                               1: lump each block to its argmax |d_kk| stage  */
+    int newton_like;        /* Section 3.2 in the eigenbasis, d_rq,k =
+                               (T^{-1})_rk T_kq:
+                               0: simplified Newton (last-stage Jacobian),
+                               1: lump each row to its argmax |d_rr,k| stage,
+                               2: each row its weighted sum_k d_rr,k L(U_k),
+                               3: as 2 plus the coupling sum_k d_rq,k L(U_k)
+                                  between the two rows of a pair (the
+                                  truncation to the blocks of Lambda; exact
+                                  Newton for 2-stage methods).  (2), (3):
+                               each row's V-cycle is built at
+                               sum_k d_rr,k U_k; (3) is never batched       */
     int gamma_mode;         /* 0: gamma_* = eta + beta^2/eta, 1: gamma = eta  */
     int prec_fp32;          /* 1: V-cycles in float32, 0: float64            */
     int cheb_degree;        /* Chebyshev pre- and post-smoothing degree       */
@@ -212,6 +221,15 @@ irk_status irk_step(irk_ctx *ctx, const double *u_n, double t_n, double dt,
  * the Newton loop of irk_step uses.  IRK_E_UNSUPPORTED for IRK_SDIRK.    */
 irk_status irk_eval_residual(irk_ctx *ctx, const double *u_n, double t_n,
                              double dt, const double *K, double *F);
+
+/* y = D_b x: the Krylov operator of eigen-block `block` (0 <= block <
+ * nblocks of irk_eigen_blocks; equation (diag_blocks) under the context's
+ * Newton-like truncation, Section 3.2) at the stage values of the last
+ * irk_eval_residual call or successful irk_step.  x, y: device
+ * [width][field] (the block's transformed components, one after the
+ * other), not aliased.  Errors: IRK_E_ARG (no stage values yet, bad block),
+ * IRK_E_UNSUPPORTED for IRK_SDIRK, IRK_E_DEVICE.                           */
+irk_status irk_apply_block(irk_ctx *ctx, int block, const double *x, double *y);
 
 /* Copy the stage vectors K of the last successful irk_step (device, [s][field])
  * into the caller's device buffer (for IRK_SDIRK the s stage derivatives). */

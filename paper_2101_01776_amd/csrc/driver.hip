@@ -62,6 +62,7 @@ static bool level_geometry(const irk_operator &op, int coarsest, LevelGeom *lg) 
 // Workspace offsets of one lane (one eigen-block's concurrent solve).
 struct LaneLayout {
     size_t V, Z, part, dv;
+    size_t tmp;                         // one float64 field (Newton-like (3) pairs), else 0
     size_t lev[IRK_MAX_LEVELS][4];
     size_t ldv;                         // Krylov vector length (block width * field)
 };
@@ -80,6 +81,12 @@ struct Plan {
     int nhier = 0;                      // distinct linearization stages
     int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
     int row_hier[IRK_MAX_STAGES];       // transformed row -> hierarchy
+    // Newton-like (2), (3): every transformed row r linearizes at the stage
+    // weights d_rr (its own hierarchy, built from sum_k d_rr,k U_k) and the
+    // block operators carry the weights blk_w
+    bool weighted = false;
+    double hier_w[IRK_MAX_STAGES][IRK_MAX_STAGES];
+    BlockWeights blk_w[IRK_MAX_STAGES];
     size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
     LaneLayout lane[IRK_MAX_STAGES];
@@ -93,7 +100,7 @@ struct Plan {
 
 static bool valid_options(const irk_options &o) {
     return o.restart >= 1 && o.restart <= IRK_MAX_RESTART && o.max_krylov >= 1 && o.max_newton >= 1 &&
-           (o.newton_like == 0 || o.newton_like == 1) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
+           (o.newton_like >= 0 && o.newton_like <= 3) && (o.gamma_mode == 0 || o.gamma_mode == 1) &&
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
@@ -158,15 +165,41 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         }
     }
 
-    // linearization stage of every transformed row (Newton-like (0) or (1))
+    // linearization of every transformed row (Section 3.2, written in the
+    // eigenbasis with d_rq,k = (T^{-1})_rk T_kq): Newton-like (0) the last
+    // stage, (1) the stage of the largest |d_rr,k|, each shared by the rows
+    // that use it; (2) the weights d_rr of the row itself, (3) also the
+    // weights d_rq coupling the two rows of a pair.  A 1-stage problem (and
+    // every SDIRK stage) has a single weight 1: all four coincide.
     P->nhier = 0;
-    for (int r = 0; r < s; ++r) {
-        const int stage = P->opt.newton_like == 1 ? P->eb.argmax_stage[r] : s - 1;
-        int hidx = -1;
-        for (int q = 0; q < P->nhier; ++q)
-            if (P->hier_stage[q] == stage) hidx = q;
-        if (hidx < 0) { hidx = P->nhier++; P->hier_stage[hidx] = stage; }
-        P->row_hier[r] = hidx;
+    std::memset(P->hier_w, 0, sizeof(P->hier_w));
+    std::memset(P->blk_w, 0, sizeof(P->blk_w));
+    P->weighted = P->opt.newton_like >= 2 && family != IRK_SDIRK && s > 1;
+    if (P->weighted) {
+        const double *T = P->eb.T, *Ti = P->eb.Tinv;
+        for (int r = 0; r < s; ++r) {
+            P->row_hier[r] = r;
+            P->hier_stage[r] = P->eb.argmax_stage[r];
+            for (int k = 0; k < s; ++k) P->hier_w[r][k] = Ti[r * s + k] * T[k * s + r];
+        }
+        P->nhier = s;
+        for (int b = 0; b < P->eb.nblocks; ++b) {
+            const int f = P->eb.first[b], w = P->eb.width[b];
+            for (int a = 0; a < w; ++a)
+                for (int q = 0; q < w; ++q)
+                    if (P->opt.newton_like == 3 || a == q)
+                        for (int k = 0; k < s; ++k) P->blk_w[b].w[a][q][k] = Ti[(f + a) * s + k] * T[k * s + f + q];
+        }
+    } else {
+        for (int r = 0; r < s; ++r) {
+            const int stage = P->opt.newton_like == 1 ? P->eb.argmax_stage[r] : s - 1;
+            int hidx = -1;
+            for (int q = 0; q < P->nhier; ++q)
+                if (P->hier_stage[q] == stage) hidx = q;
+            if (hidx < 0) { hidx = P->nhier++; P->hier_stage[hidx] = stage; }
+            P->row_hier[r] = hidx;
+        }
+        for (int q = 0; q < P->nhier; ++q) P->hier_w[q][P->hier_stage[q]] = 1.0;
     }
 
     // workspace layout
@@ -190,6 +223,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         ln.Z = take((size_t)P->m * ln.ldv * f64);
         ln.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
         ln.dv = take(512 * f64);
+        ln.tmp = (P->weighted && P->opt.newton_like == 3 && P->eb.width[b] == 2) ? take(P->nf * f64) : 0;
         for (int l = 0; l < P->lg.nlev; ++l) {
             const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
             for (int q = 0; q < 4; ++q) ln.lev[l][q] = take(n * P->tsz);
@@ -231,6 +265,7 @@ struct Lane {
     hipEvent_t ev = nullptr, done = nullptr;
     hipEvent_t ev_prec = nullptr;       // lane work before a shared V-cycle batch
     double *V = nullptr, *Z = nullptr, *part = nullptr, *dv = nullptr;
+    double *tmp = nullptr;              // the (2,1) coupling of Newton-like (3) pairs
     double *pin = nullptr;
     size_t ldv = 0;
     const LaneLayout *lay = nullptr;
@@ -255,6 +290,7 @@ struct irk_ctx {
     Lane lanes[IRK_MAX_STAGES];
     int nlanes = 0;
     bool have_stages = false;
+    bool have_U = false;                 // U holds the stage values of some K
     // the last successful step's output buffer and end time: a step from
     // there continues it, and K (still the previous stages) extrapolates
     const double *next_u = nullptr;
@@ -597,7 +633,8 @@ static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, con
 // preconditioner of equation (Lprec) with diagonal inverses (eta M - dt L_a)
 // and the Schur complement approximation (gamma M - dt L_b) of equation
 // (schur-approx), each applied as one V-cycle; the (2,1) block of D is
-// -beta M (phi = beta in the eigenbasis).  Returns the number of V-cycles.
+// -beta M (phi = beta in the eigenbasis), and with Newton-like (3) also
+// -dt sum_k d_21,k L_k.  Returns the number of V-cycles.
 template <class T>
 static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
     const Plan &P = c->P;
@@ -616,7 +653,17 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
         const double beta = eb.beta[blk];
         const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eta;
         const int hb = P.row_hier[r + 1];
-        prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, beta, gam, hb);
+        if (ln.tmp) {
+            // Newton-like (3): the (2,1) block of D is -beta M - dt sum_k
+            // d_21,k L_k; its negation applied to z1 joins the right-hand side
+            PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">",
+                 8.0 * P.npts * (2.0 + P.s * P.nvar), 1,
+                 launch_block_matvec_w(ln.stream, c->dp, P.s, 1, 0.0, beta, c->dt, c->U, P.blk_w[blk], z, ln.tmp,
+                                       nullptr, 1));
+            prec_component<T>(c, ln, z + nf, v + nf, 1.0, ln.tmp, 1.0, gam, hb);
+        } else {
+            prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, beta, gam, hb);
+        }
         ++nvc;
         if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf); ++nvc; }
     }
@@ -639,6 +686,14 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
              launch_field_sums(ln.stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, ln.part, ln.dv + DV_XMEANS,
                                nullptr));
         xm = ln.dv + DV_XMEANS;
+    }
+    if (P.weighted) {
+        // reads x, w (width * nvar fields each) and the s stage fields
+        const double byw = 8.0 * P.npts * (2.0 * width * P.nvar + P.s * P.nvar);
+        PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">", byw, 1,
+             launch_block_matvec_w(ln.stream, c->dp, P.s, width, eb.eta[blk], eb.beta[blk], c->dt, c->U,
+                                   P.blk_w[blk], x, w, xm, 0));
+        return;
     }
     // reads x and writes w (width * nvar fields each), reads one linearization field per component
     const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0);
@@ -988,11 +1043,18 @@ template <class T>
 static void setup_hierarchies(irk_ctx *c) {
     const Plan &P = c->P;
     for (int hq = 0; hq < P.nhier; ++hq) {
-        const double *Um = stage_field(c, P.hier_stage[hq]);
-        // coefficient field of the linearization: U_m (NLDIFF, Burgers) or Psi_m (VSF)
-        const double *src = P.op.kind == IRK_OP_VSF_2D ? Um + P.npts : Um;
-        PROF(c, c->stream, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
-             launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts));
+        // coefficient field of the linearization: U_m (NLDIFF, Burgers) or
+        // Psi_m (VSF) of the hierarchy's stage, or (Newton-like (2), (3)) the
+        // row's weighted combination sum_k d_rr,k U_k
+        const size_t off = P.op.kind == IRK_OP_VSF_2D ? P.npts : 0;
+        if (P.weighted) {
+            PROF(c, c->stream, kn<T>("k_mix_cast"), (double)P.npts * (8.0 * P.s + sizeof(T)), 1,
+                 launch_mix_cast<T>(c->stream, c->coef<T>(hq, 0), c->U, P.nf, off, P.s, P.hier_w[hq], P.npts));
+        } else {
+            const double *src = stage_field(c, P.hier_stage[hq]) + off;
+            PROF(c, c->stream, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
+                 launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts));
+        }
         for (int l = 0; l + 1 < P.lg.nlev; ++l) {
             const double np = (double)P.lg.nx[l] * P.lg.ny[l], npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
             PROF(c, c->stream, kn<T>("k_mg_coef_restrict"), sizeof(T) * (np + npc), 1,
@@ -1507,6 +1569,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         ln.Z = (double *)(c->ws + lay.Z);
         ln.part = (double *)(c->ws + lay.part);
         ln.dv = (double *)(c->ws + lay.dv);
+        ln.tmp = lay.tmp ? (double *)(c->ws + lay.tmp) : nullptr;
         ln.pin = c->pinned + (size_t)(1 + b) * PIN_LANE;
         // default-priority, non-blocking streams (ordering with the caller's
         // stream is explicit, through events)
@@ -1519,7 +1582,9 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         }
     }
     // a private broker batches the V-cycles of this context's blocks
-    if (c->P.opt.batch_mg && c->nlanes > 1 && c->P.op.kind != IRK_OP_VSF_2D) {
+    // (Newton-like (3) pairs apply an operator between their two V-cycles:
+    // they are not batched)
+    if (c->P.opt.batch_mg && c->nlanes > 1 && c->P.op.kind != IRK_OP_VSF_2D && c->P.opt.newton_like != 3) {
         bool ok;
         if (c->P.opt.prec_fp32) {
             auto *b = new (std::nothrow) PrecBroker<float>();
@@ -1586,6 +1651,7 @@ irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, doub
                 t_n == c->next_t;
     c->extrap_ratio = c->extrap ? dt / c->prev_dt : 1.0;
     c->have_stages = false;
+    c->have_U = false;
     c->next_u = u_np1;
     c->next_t = t_n + dt;
     c->prev_dt = dt;
@@ -1599,6 +1665,7 @@ int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats) {
     irk_status s = c->stepper->status;
     if (s == IRK_OK && hipGetLastError() != hipSuccess) s = IRK_E_DEVICE;
     c->have_stages = (s == IRK_OK);
+    c->have_U = c->have_stages && c->P.sd_s == 0;
     c->st = nullptr;
     if (st) *st = s;
     if (stats) *stats = c->stepper->stats;
@@ -1635,7 +1702,7 @@ int broker_flush(void *b, int fp32) {
 // Let a context's blocks join a shared broker (replacing its private one);
 // false when the context does not batch (option off, or the DAE operator).
 bool attach_broker(irk_ctx *c, void *fp32_broker, void *fp64_broker) {
-    if (!c->P.opt.batch_mg || c->P.op.kind == IRK_OP_VSF_2D) return false;
+    if (!c->P.opt.batch_mg || c->P.op.kind == IRK_OP_VSF_2D || c->P.opt.newton_like == 3) return false;
     if (c->broker_owned) {
         if (c->P.opt.prec_fp32) delete static_cast<PrecBroker<float> *>(c->broker);
         else delete static_cast<PrecBroker<double> *>(c->broker);
@@ -1725,6 +1792,8 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
     const size_t bytes = (size_t)s * P.nf * sizeof(double);
     StageCoefs C;
     fill_stage_coefs(c, t_n, dt, &C);
+    c->dt = dt;
+    c->have_U = false;
     (void)hipGetLastError();
     HIP_TRY(hipMemcpyAsync(c->K, K, bytes, hipMemcpyDeviceToDevice, c->stream));
     launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
@@ -1736,6 +1805,22 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_stages = false;
+    c->have_U = true;
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_apply_block(irk_ctx *c, int block, const double *x, double *y) {
+    if (!c || !x || !y) return IRK_E_ARG;
+    if (c->P.sd_s > 0) return IRK_E_UNSUPPORTED;
+    if (!c->have_U || block < 0 || block >= c->nlanes) return IRK_E_ARG;
+    Lane &ln = c->lanes[block];
+    (void)hipGetLastError();
+    // the stage values were written on the context's stream
+    HIP_TRY(hipEventRecord(c->ev_main, c->stream));
+    HIP_TRY(hipStreamWaitEvent(ln.stream, c->ev_main, 0));
+    block_matvec(c, ln, x, y);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ln.stream));
     return IRK_OK;
 }
 

@@ -40,6 +40,12 @@ struct StageCoefs {
     double sin_t[IRK_MAX_STAGES], cos_t[IRK_MAX_STAGES];
 };
 
+// Stage weights of an eigen-block's operator under Newton-like (2), (3):
+// row a of the block applies sum_b sum_k w[a][b][k] L(U_k) to component b.
+struct BlockWeights {
+    double w[2][2][IRK_MAX_STAGES];
+};
+
 // Geometry and physical parameters of one grid level.
 struct Grid {
     int nx, ny;

@@ -24,6 +24,16 @@ void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, 
                        double *partials, double *out, unsigned *ctr);
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
+// Eigen-block operator with stage-weighted linearizations (U: the s stage
+// fields); coupling = 1 gives beta M x_0 + dt sum_k W[1][0][k] L(U_k) x_0 on
+// the differential variable instead
+void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+                           double dt, const double *U, const BlockWeights &W, const double *x, double *w,
+                           const double *xmeans, int coupling);
+// dst = (T) sum_k wts[k] U[k * nf + off + e], e < len (wts: host, s values)
+template <class T>
+void launch_mix_cast(hipStream_t st, T *dst, const double *U, size_t nf, size_t off, int s, const double *wts,
+                     size_t len);
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr);
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);

@@ -16,6 +16,8 @@
 // fixed order.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "irk_internal.h"
 #include "kernels.h"
 #include "stencils.h"
@@ -392,6 +394,84 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int wi
     }
 }
 
+// Eigen-block operator with stage-weighted linearizations (Newton-like (2),
+// (3)): L_kb = L(U_k) x_b at the point for every stage k and component b,
+//   coupling = 0:  w_a = eta M x_a (+ beta M x_1 | - beta M x_0)
+//                        - dt sum_b sum_k W[a][b][k] L_kb
+//                  (the algebraic rows of the DAE as in k_block_matvec);
+//   coupling = 1:  w = beta M x_0 + dt sum_k W[1][0][k] L_k0 on the
+//                  differential variable only (the negated (2,1) block of the
+//                  pair applied to x_0: the second row's right-hand side of
+//                  the block-triangular preconditioner).
+template <int OP, int S>
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int width, double eta, double beta,
+                                                           double dt, const double *__restrict__ U,
+                                                           BlockWeights W, const double *__restrict__ x,
+                                                           double *__restrict__ w,
+                                                           const double *__restrict__ xmeans, int coupling) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const int nin = coupling ? 1 : width;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double acc[2] = {0.0, 0.0}, xc[2] = {0.0, 0.0};
+        for (int b = 0; b < nin; ++b) {
+            const double *xx = x + b * nf;
+            xc[b] = xx[p];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const double *Uk = U + (size_t)k * nf;
+                double lx, ld;
+                if constexpr (OP == IRK_OP_NLDIFF_2D) nldiff_lin<double, true>(Uk, xx, i, j, nx, ny, inv_h2, lx, ld);
+                else if constexpr (OP == IRK_OP_BURGERS_1D) burgers_lin<double, true>(Uk, xx, i, nx, h, P.g.nu, lx, ld);
+                else vsf_omega_lin<double, true>(Uk + npts, xx, i, j, nx, ny, h, P.g.nu, lx, ld);
+                if (coupling) {
+                    acc[0] += W.w[1][0][k] * lx;
+                } else {
+                    acc[0] += W.w[0][b][k] * lx;
+                    if (width == 2) acc[1] += W.w[1][b][k] * lx;
+                }
+            }
+        }
+        if (coupling) {
+            w[p] = beta * xc[0] + dt * acc[0];
+            continue;
+        }
+        if (width == 1) {
+            w[p] = eta * xc[0] - dt * acc[0];
+        } else {
+            w[p] = eta * xc[0] + beta * xc[1] - dt * acc[0];
+            w[nf + p] = -beta * xc[0] + eta * xc[1] - dt * acc[1];
+        }
+        if constexpr (NV == 2) {
+            for (int comp = 0; comp < width; ++comp) {
+                const double *xx = x + comp * nf;
+                double lp, ld;
+                poisson_lin<double, true>(xx + npts, i, j, nx, ny, h, lp, ld);
+                const double mw = xmeans[2 * comp], mp = xmeans[2 * comp + 1];
+                w[comp * nf + npts + p] = -dt * ((xc[comp] - mw) + lp - mp);
+            }
+        }
+    }
+}
+
+// dst = (T) sum_k wts.b[k] U_k[off + e], e < len (the linearization field of
+// a hierarchy built from stage-weighted stage values)
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mix_cast(T *__restrict__ dst, const double *__restrict__ U, size_t nf,
+                                                     size_t off, int s, StageCoefs wts, size_t len) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double acc = 0.0;
+        for (int k = 0; k < s; ++k) acc += wts.b[k] * U[(size_t)k * nf + off + e];
+        dst[e] = (T)acc;
+    }
+}
+
 // ------------------------------------------------------------------------
 // Arnoldi kernels
 // ------------------------------------------------------------------------
@@ -683,6 +763,40 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, doub
         k_block_matvec<IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
 }
 
+template <int OP>
+static void block_matvec_w_op(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+                              double dt, const double *U, const BlockWeights &W, const double *x, double *w,
+                              const double *xmeans, int coupling) {
+    const unsigned g = grid_for((size_t)P.g.nx * P.g.ny);
+    switch (s) {
+        case 1: k_block_matvec_w<OP, 1><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+        case 2: k_block_matvec_w<OP, 2><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+        case 3: k_block_matvec_w<OP, 3><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+        case 4: k_block_matvec_w<OP, 4><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+        case 5: k_block_matvec_w<OP, 5><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+    }
+}
+
+void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+                           double dt, const double *U, const BlockWeights &W, const double *x, double *w,
+                           const double *xmeans, int coupling) {
+    if (P.kind == IRK_OP_NLDIFF_2D)
+        block_matvec_w_op<IRK_OP_NLDIFF_2D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+    else if (P.kind == IRK_OP_BURGERS_1D)
+        block_matvec_w_op<IRK_OP_BURGERS_1D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+    else
+        block_matvec_w_op<IRK_OP_VSF_2D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+}
+
+template <class T>
+void launch_mix_cast(hipStream_t st, T *dst, const double *U, size_t nf, size_t off, int s, const double *wts,
+                     size_t len) {
+    StageCoefs C;
+    std::memset(&C, 0, sizeof(C));
+    for (int k = 0; k < s; ++k) C.b[k] = wts[k];
+    k_mix_cast<T><<<grid_for(len), IRK_WG, 0, st>>>(dst, U, nf, off, s, C, len);
+}
+
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr) {
     // chunks of DOT_CHUNK vectors; the norm (if any) rides on the last chunk
@@ -760,7 +874,8 @@ void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len) {
     template void launch_mg_cast_in<T>(hipStream_t, T *, const double *, double, const double *, double,           \
                                        const double *, size_t);                                                    \
     template void launch_mg_cast_out<T>(hipStream_t, double *, const T *, double, const double *, double, size_t); \
-    template void launch_cast_coef<T>(hipStream_t, T *, const double *, size_t);
+    template void launch_cast_coef<T>(hipStream_t, T *, const double *, size_t);                                     \
+    template void launch_mix_cast<T>(hipStream_t, T *, const double *, size_t, size_t, int, const double *, size_t);
 INST(float)
 INST(double)
 #undef INST

@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.irk_eval_residual.argtypes = [P, P, D, D, P, P]
     L.irk_get_stages.restype = I
     L.irk_get_stages.argtypes = [P, P]
+    L.irk_apply_block.restype = I
+    L.irk_apply_block.argtypes = [P, I, P, P]
     L.irk_destroy.restype = None
     L.irk_destroy.argtypes = [P]
     L.irk_server_create.restype = I
@@ -227,6 +229,10 @@ def irk_get_stages(ctx, K_ptr: int):
     _check(lib().irk_get_stages(ctx, ctypes.c_void_p(K_ptr)), "irk_get_stages")
 
 
+def irk_apply_block(ctx, block: int, x_ptr: int, y_ptr: int):
+    _check(lib().irk_apply_block(ctx, block, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr)), "irk_apply_block")
+
+
 def irk_destroy(ctx):
     lib().irk_destroy(ctx)
 
@@ -307,6 +313,14 @@ class Solver:
         F = self.torch.empty_like(K)
         irk_eval_residual(self.ctx, u.data_ptr(), t_n, dt, K.data_ptr(), F.data_ptr())
         return F
+
+    def apply_block(self, block: int, x):
+        """D_b x for eigen-block ``block`` at the last evaluated stage values;
+        x: (width,) + field shape."""
+        x = self._dev(x)
+        y = self.torch.empty_like(x)
+        irk_apply_block(self.ctx, block, x.data_ptr(), y.data_ptr())
+        return y
 
     def stages(self):
         K = self.torch.empty((self.s,) + self.field_shape, dtype=self.torch.float64, device=self.device)
