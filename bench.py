@@ -111,14 +111,16 @@ def run_job(torch, irk, inputs, wl, steps, warmup, prec_fp32, profile=False):
 def ablation(torch, irk, inputs, wl, steps):
     """Preconditioner variants of the paper's solver study on the same job:
     gamma* = eta + beta^2/eta vs gamma = eta in the 2x2 Schur approximation
-    (Table 4's comparison), and Newton-like (1) (each block linearized at its
-    largest-weight stage) vs (0) (last stage).  Preconditioner applications
+    (Table 4's comparison), and the Newton-like truncations (0) last stage,
+    (1) lumped to the largest stage weight, (2) the row's stage weights,
+    (3) plus the coupling of the rows of a pair; and the adaptive Krylov
+    tolerance against the paper's fixed one.  Preconditioner applications
     are the paper's cost unit."""
     problem, n, family, s, dt, _, nu = wl
     op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
     res = []
-    for gm, nl in ((0, 1), (1, 1), (0, 0), (1, 0)):
-        solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl))
+    for gm, nl, ka in ((0, 1, 1), (0, 1, 0), (1, 1, 1), (0, 0, 1), (0, 2, 1), (0, 3, 1)):
+        solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl, krylov_adaptive=ka))
         u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
         b = torch.empty_like(u)
         t = 0.0
@@ -133,7 +135,8 @@ def ablation(torch, irk, inputs, wl, steps):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         solver.close()
-        res.append({"gamma": "gamma*" if gm == 0 else "eta", "newton_like": nl, "ms_per_step": 1e3 * wall / steps,
+        res.append({"gamma": "gamma*" if gm == 0 else "eta", "newton_like": nl,
+                    "krylov_tol": "adaptive" if ka else "fixed", "ms_per_step": 1e3 * wall / steps,
                     "newton_its_per_step": sum(x["newton_its"] for x in stats) / steps,
                     "krylov_its_per_step": sum(x["krylov_its"] for x in stats) / steps,
                     "krylov_its_per_block": [sum(x["krylov_its_block"][k] for x in stats) / steps
@@ -152,9 +155,10 @@ def sdirk_compare(torch, irk, inputs, wl, steps):
     op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
 
     def job(family, s, dtt, nsteps):
-        # both classes start every step the same way (zero or explicit): the
-        # extrapolated start is a property of the fully implicit stages only
-        solver = irk.Solver(family, s, op, irk.make_options(start_extrapolate=0))
+        # both classes start every step the same way (zero or explicit; the
+        # extrapolated start is a property of the fully implicit stages only)
+        # and solve every block to the paper's fixed Krylov tolerance
+        solver = irk.Solver(family, s, op, irk.make_options(start_extrapolate=0, krylov_adaptive=0))
         u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
         b = torch.empty_like(u)
         t, stats = 0.0, []

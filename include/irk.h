@@ -130,6 +130,11 @@ typedef struct irk_options {
                                stage vectors extrapolated along their
                                interpolating polynomial are a third starting
                                candidate; 0: zero and explicit only         */
+    int krylov_adaptive;    /* 1: the block solves of a Newton iteration stop
+                               at max(krylov_rtol, 0.1 target / ||F||), at
+                               most 0.1, target = the acceptance threshold
+                               (never solving further than the outer test
+                               can use); 0: krylov_rtol always             */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -162,7 +167,7 @@ const char *irk_status_str(irk_status st);
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
  * cheb_degree 3, mg_coarsest 8, coarse_iters 24, batch_mg 0 (shared
  * launches couple the blocks' progress and were measured slower on the
- * bench workloads; see the option), start_extrapolate 1.                   */
+ * bench workloads; see the option), start_extrapolate 1, krylov_adaptive 1.*/
 void irk_default_options(irk_options *opt);
 
 /* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,

@@ -104,7 +104,7 @@ static bool valid_options(const irk_options &o) {
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
-           (o.start_extrapolate == 0 || o.start_extrapolate == 1);
+           (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -1256,10 +1256,16 @@ struct Stepper : StepperBase {
         setup_hierarchies<T>(c);
         if (hipEventRecord(c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
         active = c->nlanes;
+        // relative Krylov tolerance of the block solves: the fixed one, or
+        // (krylov_adaptive) never tighter than a tenth of the reduction the
+        // acceptance test still asks of this residual (an inexact Newton
+        // forcing term: solving further cannot change the accepted stages)
+        double ktol = P.opt.krylov_rtol;
+        if (P.opt.krylov_adaptive) ktol = std::min(0.1, std::max(ktol, 0.1 * std::max(thresh, floor_res) / res));
         for (int b = 0; b < c->nlanes; ++b) {
             lane_done[b] = false;
             if (hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0) != hipSuccess) return fail(IRK_E_DEVICE);
-            fg[b].init(c, &c->lanes[b], P.opt.krylov_rtol, P.opt.max_krylov);
+            fg[b].init(c, &c->lanes[b], ktol, P.opt.max_krylov);
             const irk_status e = fg[b].start();
             if (e != IRK_OK) return fail(e);
         }
@@ -1457,6 +1463,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->coarse_iters = 24;
     o->batch_mg = 0;
     o->start_extrapolate = 1;
+    o->krylov_adaptive = 1;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {

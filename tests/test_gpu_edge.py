@@ -193,6 +193,29 @@ def test_extrapolated_start_on_continued_steps(family, s):
     assert rel(runs[1][0], runs[0][0]) < 1e-10
 
 
+@pytest.mark.parametrize("family,s,n", [("gauss", 3, 128), ("radau", 3, 128), ("gauss", 5, 64)])
+def test_adaptive_krylov_tolerance(family, s, n):
+    """The adaptive block-solve tolerance (never tighter than the acceptance
+    test can use) reaches the same steps as the fixed 1e-5 (float64
+    V-cycles: within the parity bar 1e-10) with no more Krylov iterations."""
+    import torch
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+    out = {}
+    for ka in (1, 0):
+        sol = _solver(op, family, s, prec_fp32=0, krylov_adaptive=ka)
+        u = torch.tensor(inputs.nldiff_u0(n), dtype=torch.float64, device="cuda")
+        t, its = 0.0, 0
+        for _ in range(8):
+            u, st = sol.step(u, t, 5e-3)
+            its += st["krylov_its"]
+            t += 5e-3
+        out[ka] = (u.cpu().numpy(), its)
+        sol.close()
+    print(f"  {family}-{s} {n}^2: Krylov its adaptive {out[1][1]} fixed {out[0][1]}")
+    assert rel(out[1][0], out[0][0]) < 1e-10
+    assert out[1][1] <= out[0][1]
+
+
 def test_gauss_conserves_invariants_on_gpu():
     """nu = 0: enstrophy sum(omega^2) and energy sum(psi omega) are conserved
     by Gauss-2 to solver tolerance; Radau IIA-2 dissipates enstrophy."""
