@@ -119,47 +119,6 @@ __device__ __forceinline__ void build_stencil(const T *cf, int c, int W, T inv_h
     }
 }
 
-// Build the scaled stencil at point c: A~[q][c] = a_q / ac, Ac[c] = ac,
-// bt[c] <- bt[c] / ac (arrays of stride npl between the NS coefficients).
-template <class T, int OPK>
-__device__ __forceinline__ void store_stencil(const T *cf, int c, int W, T inv_h2, T h, T nu, T sigma, T dt,
-                                              T *At, int npl, T *Ac, T *bt) {
-    constexpr int NS = StencilShape<OPK>::NS;
-    T a[NS], ac;
-    build_stencil<T, OPK>(cf, c, W, inv_h2, h, nu, sigma, dt, a, ac);
-    const T inv = T(1) / ac;
-#pragma unroll
-    for (int q = 0; q < NS; ++q) At[q * npl + c] = a[q] * inv;
-    if (Ac) Ac[c] = ac;
-    bt[c] *= inv;
-}
-
-// D^{-1} (b - A x) at c from the scaled stencil
-template <class T, int OPK>
-__device__ __forceinline__ T jacobi_res(const T *At, int npl, const T *bt, const T *x, int c, int W) {
-    constexpr int NS = StencilShape<OPK>::NS;
-    T r = bt[c] - x[c];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) r -= At[q * npl + c] * x[c + nb_off(q, W)];
-    return r;
-}
-
-// Iterate over the sub-box of a window: columns [a0, a1), rows [b0, b1).
-// (column and row are advanced incrementally: no division per point)
-#define FOR_BOX(a0, a1, b0, b1, W, ...)                                    \
-    do {                                                                   \
-        const int bw_ = (a1) - (a0), bn_ = bw_ * ((b1) - (b0));            \
-        const int sx_ = (int)blockDim.x % bw_, sy_ = (int)blockDim.x / bw_; \
-        int ca_ = (int)threadIdx.x % bw_, cb_ = (int)threadIdx.x / bw_;    \
-        for (int q_ = threadIdx.x; q_ < bn_; q_ += blockDim.x) {           \
-            const int ia = (a0) + ca_, ib = (b0) + cb_;                    \
-            const int c = ib * (W) + ia;                                   \
-            __VA_ARGS__;                                                   \
-            ca_ += sx_;                                                    \
-            cb_ += sy_;                                                    \
-            if (ca_ >= bw_) { ca_ -= bw_; ++cb_; }                         \
-        }                                                                  \
-    } while (0)
 
 // (t / w, t % w) for 0 <= t < 2^20, 1 <= w <= 2^16 with a float reciprocal
 // (the quotient estimate is off by at most one; one correction each way)
@@ -250,12 +209,46 @@ __device__ __forceinline__ void load_rhs(const double *v1, double a1, const doub
     }
 }
 
-// LDS layout of a tiled kernel's window (npl = window points): NS scaled
-// off-diagonals, A_c, b~, two iterates, and cf/d sharing one array (the
-// linearization field is needed only to build the stencil).
-template <class T, int OPK>
-__host__ __device__ constexpr int window_arrays() {
-    return StencilShape<OPK>::NS + 5;
+// LDS of a tiled kernel's window (npl = window points): the linearization
+// field (later the residual) and two iterates.  Everything else a point
+// needs -- its scaled stencil, b~ and the Chebyshev direction -- stays in
+// the registers of the thread that owns the point (window point q belongs
+// to thread q mod 256, the same thread that loaded it).
+__host__ __device__ constexpr int tile_arrays() { return 3; }
+
+// Scaled stencil rows of a thread's window points (all but the outer ring
+// of the window): a~_q = A_q / A_c in a, A_c in ac, b~ = b / A_c in bv.
+template <class T, int OPK, int NPT, int W>
+__device__ __forceinline__ void own_stencils(const T *cf, const WindowIndex<NPT> &wi, int Hh, bool two_d,
+                                             const MgLevelArgs<T> &g, T inv_h2,
+                                             T (&a)[NPT][StencilShape<OPK>::NS], T (&ac)[NPT], T (&bv)[NPT]) {
+    constexpr int NS = StencilShape<OPK>::NS;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = wi.q(k), ia = q % W, ib = q / W;
+        const bool inner = wi.ok(k) && ia >= 1 && ia < W - 1 && (!two_d || (ib >= 1 && ib < Hh - 1));
+        if (inner) {
+            build_stencil<T, OPK>(cf, q, W, inv_h2, g.h, g.nu, g.sigma, g.dt, a[k], ac[k]);
+            const T inv = T(1) / ac[k];
+#pragma unroll
+            for (int m = 0; m < NS; ++m) a[k][m] *= inv;
+            bv[k] *= inv;
+        } else {
+#pragma unroll
+            for (int m = 0; m < NS; ++m) a[k][m] = T(0);
+            ac[k] = T(1);
+        }
+    }
+}
+
+// b~ - x - sum_q a~_q x_q at window point c (D^{-1}(b - A x))
+template <class T, int OPK, int W>
+__device__ __forceinline__ T own_jres(const T (&a)[StencilShape<OPK>::NS], T bv, const T *x, int c, T xv) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    T r = bv - xv;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) r -= a[m] * x[c + nb_off(m, W)];
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -271,13 +264,9 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
     const int Hh = (two_d ? TY : 1) + 2 * hy;
     const int npl = W * Hh;
     extern __shared__ unsigned char smem_raw[];
-    T *At = reinterpret_cast<T *>(smem_raw);
-    T *Ac = At + NS * npl;
-    T *bt = Ac + npl;
-    T *xa = bt + npl;
+    T *cf = reinterpret_cast<T *>(smem_raw);
+    T *xa = cf + npl;
     T *xb = xa + npl;
-    T *dd = xb + npl;
-    T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int ty = tile / tiles_x, tx = tile % tiles_x;
@@ -290,47 +279,43 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
     constexpr int NPT = (W * (TY + 2 * H) + 255) / 256;
     WindowIndex<NPT> wi;
     wi.template init<W, H>(npl, i0, j0, nx, ny, two_d);
+    T bv[NPT];
     {
         T cfv[NPT];
         load_field<NPT>(g.coef, wi, cfv);
-        T rv[NPT];
-        load_rhs<T, NPT>(in.v1, in.a1, in.v2, in.a2, in.mean, g.b, wi, rv);
+        load_rhs<T, NPT>(in.v1, in.a1, in.v2, in.a2, in.mean, g.b, wi, bv);
 #pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            if (wi.ok(k)) {
-                cf[wi.q(k)] = cfv[k];
-                bt[wi.q(k)] = rv[k];
-            }
-        }
+        for (int k = 0; k < NPT; ++k)
+            if (wi.ok(k)) cf[wi.q(k)] = cfv[k];
     }
     __syncthreads();
-    // scaled stencil on the window minus its outer ring
-    FOR_BOX(1, W - 1, two_d ? 1 : 0, two_d ? Hh - 1 : 1, W,
-            store_stencil<T, OPK>(cf, c, W, inv_h2, g.h, g.nu, g.sigma, g.dt, At, npl, Ac, bt));
-    __syncthreads();
+    T a[NPT][NS], ac[NPT];
+    own_stencils<T, OPK, NPT, W>(cf, wi, Hh, two_d, g, inv_h2, a, ac, bv);
 
-    // D Chebyshev steps on shrinking regions R(D+1) ... R(2)
+    // D Chebyshev steps on shrinking regions R(D+1) ... R(2) (the thread's
+    // own points inside the region)
+    T dv[NPT];
     T *xcur = xa, *xnext = xb;
-    for (int k = 0; k < D; ++k) {
-        const int r = D + 1 - k;                 // region half-width added to the tile
+    for (int st = 0; st < D; ++st) {
+        const int r = D + 1 - st;                // region half-width added to the tile
         const int ax0 = H - r, ax1 = H + TX + r;
         const int by0 = two_d ? hy - r : 0, by1 = two_d ? hy + TY + r : 1;
-        const T cd = g.cd[k], cr = g.cr[k];
-        if (k == 0) {
-            FOR_BOX(ax0, ax1, by0, by1, W, {
-                const T dn = cr * bt[c];
-                dd[c] = dn;
-                xnext[c] = dn;
-            });
-        } else {
-            FOR_BOX(ax0, ax1, by0, by1, W, {
-                // x read before d is stored (d may alias x for the compiler:
-                // a read after the store would cost another LDS round trip)
-                const T xv = xcur[c];
-                const T dn = cd * dd[c] + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
-                dd[c] = dn;
-                xnext[c] = xv + dn;
-            });
+        const T cd = g.cd[st], cr = g.cr[st];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int c = wi.q(k), ia = c % W, ib = c / W;
+            if (wi.ok(k) && ia >= ax0 && ia < ax1 && ib >= by0 && ib < by1) {
+                if (st == 0) {
+                    const T dn = cr * bv[k];
+                    dv[k] = dn;
+                    xnext[c] = dn;
+                } else {
+                    const T xv = xcur[c];
+                    const T dn = cd * dv[k] + cr * own_jres<T, OPK, W>(a[k], bv[k], xcur, c, xv);
+                    dv[k] = dn;
+                    xnext[c] = xv + dn;
+                }
+            }
         }
         __syncthreads();
         T *t = xcur;
@@ -338,12 +323,18 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
         xnext = t;
     }
     // write the smoothed iterate on the tile; residual b - A x on R(1)
-    FOR_BOX(H, H + TX, hy, hy + (two_d ? TY : 1), W, {
-        const int gi = i0 + (ia - H), gj = j0 + (ib - hy);
-        if (gi < nx && gj < ny) g.x[(size_t)gj * nx + gi] = xcur[c];
-    });
-    FOR_BOX(H - 1, H + TX + 1, two_d ? hy - 1 : 0, two_d ? hy + TY + 1 : 1, W,
-            xnext[c] = Ac[c] * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W));
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int c = wi.q(k), ia = c % W, ib = c / W;
+        if (!wi.ok(k)) continue;
+        const T xv = xcur[c];
+        if (ia >= H && ia < H + TX && ib >= hy && ib < hy + (two_d ? TY : 1)) {
+            const int gi = i0 + (ia - H), gj = j0 + (ib - hy);
+            if (gi < nx && gj < ny) g.x[(size_t)gj * nx + gi] = xv;
+        }
+        if (ia >= H - 1 && ia < H + TX + 1 && (!two_d || (ib >= hy - 1 && ib < hy + TY + 1)))
+            xnext[c] = ac[k] * own_jres<T, OPK, W>(a[k], bv[k], xcur, c, xv);
+    }
     __syncthreads();
     const T *rr = xnext;
     // full-weighting restriction to coarse points whose fine node lies in the tile
@@ -380,12 +371,9 @@ __device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut 
     const int Hh = (two_d ? TY : 1) + 2 * hy;
     const int npl = W * Hh;
     extern __shared__ unsigned char smem_raw[];
-    T *At = reinterpret_cast<T *>(smem_raw);
-    T *bt = At + NS * npl;
-    T *xa = bt + npl;
+    T *cf = reinterpret_cast<T *>(smem_raw);
+    T *xa = cf + npl;
     T *xb = xa + npl;
-    T *dd = xb + npl;
-    T *cf = dd;
 
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int ty = tile / tiles_x, tx = tile % tiles_x;
@@ -397,6 +385,7 @@ __device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut 
     constexpr int NPT = (W * (TY + 2 * H) + 255) / 256;
     WindowIndex<NPT> wi;
     wi.template init<W, H>(npl, i0, j0, nx, ny, two_d);
+    T bv[NPT];
     {
         T cfv[NPT], xv[NPT], ev[NPT];
         load_field<NPT>(g.coef, wi, cfv);
@@ -414,46 +403,51 @@ __device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut 
                 ev[k] = T(0.5) * (g.xc[I0] + g.xc[I1]);
             }
         }
-        T rv[NPT];
-        load_rhs<T, NPT>(out.v1, out.a1, out.v2, out.a2, out.mean_in, g.b, wi, rv);
+        load_rhs<T, NPT>(out.v1, out.a1, out.v2, out.a2, out.mean_in, g.b, wi, bv);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (wi.ok(k)) {
                 cf[wi.q(k)] = cfv[k];
-                bt[wi.q(k)] = rv[k];
                 xa[wi.q(k)] = xv[k] + ev[k];
             }
         }
     }
     __syncthreads();
-    FOR_BOX(1, W - 1, two_d ? 1 : 0, two_d ? Hh - 1 : 1, W,
-            store_stencil<T, OPK>(cf, c, W, inv_h2, g.h, g.nu, g.sigma, g.dt, At, npl, (T *)nullptr, bt));
-    __syncthreads();
+    T a[NPT][NS], ac[NPT];
+    own_stencils<T, OPK, NPT, W>(cf, wi, Hh, two_d, g, inv_h2, a, ac, bv);
+    T dv[NPT];
     T *xcur = xa, *xnext = xb;
-    for (int k = 0; k < D; ++k) {
-        const int r = D - 1 - k;
+    for (int st = 0; st < D; ++st) {
+        const int r = D - 1 - st;
         const int ax0 = H - r, ax1 = H + TX + r;
         const int by0 = two_d ? hy - r : 0, by1 = two_d ? hy + TY + r : 1;
-        const T cd = g.cd[k], cr = g.cr[k];
-        FOR_BOX(ax0, ax1, by0, by1, W, {
-            const T xv = xcur[c];
-            const T dn = (k == 0 ? T(0) : cd * dd[c]) + cr * jacobi_res<T, OPK>(At, npl, bt, xcur, c, W);
-            dd[c] = dn;
-            xnext[c] = xv + dn;
-        });
+        const T cd = g.cd[st], cr = g.cr[st];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int c = wi.q(k), ia = c % W, ib = c / W;
+            if (wi.ok(k) && ia >= ax0 && ia < ax1 && ib >= by0 && ib < by1) {
+                const T xv = xcur[c];
+                const T dn = (st == 0 ? T(0) : cd * dv[k]) + cr * own_jres<T, OPK, W>(a[k], bv[k], xcur, c, xv);
+                dv[k] = dn;
+                xnext[c] = xv + dn;
+            }
+        }
         __syncthreads();
         T *t = xcur;
         xcur = xnext;
         xnext = t;
     }
-    FOR_BOX(H, H + TX, hy, hy + (two_d ? TY : 1), W, {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int c = wi.q(k), ia = c % W, ib = c / W;
+        if (!wi.ok(k) || ia < H || ia >= H + TX || ib < hy || ib >= hy + (two_d ? TY : 1)) continue;
         const int gi = i0 + (ia - H), gj = j0 + (ib - hy);
         if (gi < nx && gj < ny) {
             const size_t gidx = (size_t)gj * nx + gi;
             if (out.z) out.z[gidx] = (double)xcur[c] + (out.shift ? out.shift_scale * out.shift[0] : 0.0);
             else g.xout[gidx] = xcur[c];
         }
-    });
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -925,7 +919,7 @@ template <class T, int OPK, int TX, int TY>
 static void down_t(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &in, int deg) {
     const int tiles = ((a.nx + TX - 1) / TX) * (a.ny > 1 ? (a.ny + TY - 1) / TY : 1);
     const int H = deg + 2;
-    const size_t shm = (size_t)window_arrays<T, OPK>() * (TX + 2 * H) *
+    const size_t shm = (size_t)tile_arrays() * (TX + 2 * H) *
                        ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
     switch (deg) {
         case 1: k_mg_down<T, OPK, TX, TY, 1><<<tiles, 256, shm, st>>>(a, in); break;
@@ -939,8 +933,7 @@ template <class T, int OPK, int TX, int TY>
 static void up_t(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int deg) {
     const int tiles = ((a.nx + TX - 1) / TX) * (a.ny > 1 ? (a.ny + TY - 1) / TY : 1);
     const int H = deg;
-    // no A_c array on the way up
-    const size_t shm = (size_t)(window_arrays<T, OPK>() - 1) * (TX + 2 * H) *
+    const size_t shm = (size_t)tile_arrays() * (TX + 2 * H) *
                        ((a.ny > 1 ? TY : 1) + (a.ny > 1 ? 2 * H : 0)) * sizeof(T);
     switch (deg) {
         case 1: k_mg_up<T, OPK, TX, TY, 1><<<tiles, 256, shm, st>>>(a, out); break;
@@ -1050,7 +1043,7 @@ static void level_batch_t(hipStream_t st, MgLevelBatch<T> &b, int deg) {
     }
     for (int e = b.n; e <= IRK_MG_BATCH; ++e) b.prefix[e] = acc;
     const int H = DOWN ? deg + 2 : deg;
-    const int arrays = DOWN ? window_arrays<T, OPK>() : window_arrays<T, OPK>() - 1;
+    const int arrays = tile_arrays();
     const size_t shm = (size_t)arrays * (TX + 2 * H) * ((two_d ? TY : 1) + (two_d ? 2 * H : 0)) * sizeof(T);
     if (DOWN) {
         switch (deg) {
