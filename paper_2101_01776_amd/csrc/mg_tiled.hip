@@ -943,8 +943,10 @@ static void up_t(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &out, int 
     }
 }
 
-// tile shape per level size: wide tiles on big levels, small tiles (more
-// work-groups) on small ones; 1-D levels use 256-point strips
+// tile shape per level size: 32x16 tiles on levels of side >= 1024 (less
+// halo per point where there are work-groups enough to fill the chip),
+// 32x8 down to side 128, 16x8 (more work-groups) below; 1-D levels use
+// 256-point strips
 // The window loads wrap indices once (wrap2), valid when the window of
 // every tile stays within [-n, 2n): tiles * T + halo <= 2 n and halo <= n.
 static bool window_fits(int n, int t, int halo) {
@@ -958,6 +960,8 @@ static void down_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgIn &i
     if (a.ny == 1) {
         if (window_fits(a.nx, 256, H)) down_t<T, OPK, 256, 1>(st, a, in, deg);
         else down_t<T, OPK, 64, 1>(st, a, in, deg);
+    } else if (a.nx >= 1024 && window_fits(a.nx, 32, H) && window_fits(a.ny, 16, H)) {
+        down_t<T, OPK, 32, 16>(st, a, in, deg);
     } else if (a.nx >= 128 && window_fits(a.nx, 32, H) && window_fits(a.ny, 8, H)) {
         down_t<T, OPK, 32, 8>(st, a, in, deg);
     } else {
@@ -971,6 +975,8 @@ static void up_dispatch(hipStream_t st, const MgLevelArgs<T> &a, const MgOut &ou
     if (a.ny == 1) {
         if (window_fits(a.nx, 256, H)) up_t<T, OPK, 256, 1>(st, a, out, deg);
         else up_t<T, OPK, 64, 1>(st, a, out, deg);
+    } else if (a.nx >= 1024 && window_fits(a.nx, 32, H) && window_fits(a.ny, 16, H)) {
+        up_t<T, OPK, 32, 16>(st, a, out, deg);
     } else if (a.nx >= 128 && window_fits(a.nx, 32, H) && window_fits(a.ny, 8, H)) {
         up_t<T, OPK, 32, 8>(st, a, out, deg);
     } else {
@@ -1030,6 +1036,7 @@ void launch_mg_subcycle(hipStream_t st, int opk, const MgSubArgs<T> &s, const Mg
 template <class T>
 static int shape_class(const MgLevelArgs<T> &a, int halo) {
     if (a.ny == 1) return window_fits(a.nx, 256, halo) ? 0 : 1;
+    if (a.nx >= 1024 && window_fits(a.nx, 32, halo) && window_fits(a.ny, 16, halo)) return 2;
     return (a.nx >= 128 && window_fits(a.nx, 32, halo) && window_fits(a.ny, 8, halo)) ? 0 : 1;
 }
 
@@ -1066,14 +1073,16 @@ template <class T, int OPK, bool DOWN>
 static void level_batch_dispatch(hipStream_t st, const MgLevelArgs<T> *g, const MgIn *in, const MgOut *out, int n,
                                  int deg) {
     const int halo = DOWN ? (deg > 4 ? 4 : deg) + 2 : (deg > 4 ? 4 : deg);
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < 3; ++cls) {
         MgLevelBatch<T> b;
         std::memset(&b, 0, sizeof(b));
         b.n = 0;
         auto flush = [&]() {
             if (b.n == 0) return;
             const bool one_d = b.g[0].ny == 1;
-            if (cls == 0) {
+            if (cls == 2) {
+                level_batch_t<T, OPK, 32, 16, DOWN>(st, b, deg);
+            } else if (cls == 0) {
                 if (one_d) level_batch_t<T, OPK, 256, 1, DOWN>(st, b, deg);
                 else level_batch_t<T, OPK, 32, 8, DOWN>(st, b, deg);
             } else {

@@ -216,6 +216,31 @@ def test_adaptive_krylov_tolerance(family, s, n):
     assert out[1][1] <= out[0][1]
 
 
+def test_1024_step_residual_and_precisions():
+    """1024^2 (finest level on 32x16 tiles, the next ones on 32x8, then the
+    16x8 and one-work-group kernels): one Gauss-3 step converges with float32
+    and with float64 V-cycles to the same stages (1e-10), and the oracle's
+    residual of the GPU stage vectors is the one the GPU reports (5 %) and
+    at rounding level."""
+    import torch
+    n, s, dt = 1024, 3, 5e-3
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+    u = inputs.nldiff_u0(n)
+    outs = {}
+    for prec in (1, 0):
+        sol = _solver(op, "gauss", s, prec_fp32=prec)
+        out, st = sol.step(u, 0.0, dt)
+        K = sol.stages().cpu().numpy().reshape(s, -1)
+        outs[prec] = out.cpu().numpy()
+        F = oracle_residual(op, "gauss", s, u, 0.0, dt, K)
+        nF = np.linalg.norm(F)
+        print(f"  1024^2 prec {prec}: |F| {nF:.3e} {st}")
+        assert abs(nF - st["final_res"]) <= 5e-2 * nF
+        assert dt * nF <= 1e-11 * np.linalg.norm(u)
+        sol.close()
+    assert rel(outs[1], outs[0]) < 1e-10
+
+
 def test_gauss_conserves_invariants_on_gpu():
     """nu = 0: enstrophy sum(omega^2) and energy sum(psi omega) are conserved
     by Gauss-2 to solver tolerance; Radau IIA-2 dissipates enstrophy."""
@@ -257,9 +282,10 @@ def test_shared_vcycle_launches_change_nothing():
     as shared launches; with batch_mg = 0 (the default) each V-cycle runs
     alone on its block's stream.  Same kernels, same arithmetic: bitwise-equal steps
     (Gauss-3: one real block and one pair; Gauss-5 at a size with tiled
-    levels: three blocks; float32 and float64 V-cycles)."""
+    levels: three blocks; 1024^2 with its 32x16-tiled finest level; float32
+    and float64 V-cycles)."""
     import torch
-    for n, s, dt in ((96, 3, 5e-3), (128, 5, 1e-2)):
+    for n, s, dt in ((96, 3, 5e-3), (128, 5, 1e-2), (1024, 3, 5e-3)):
         op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
         u0 = torch.tensor(inputs.nldiff_random_u0(n, 3, 0.5), dtype=torch.float64, device="cuda")
         for prec in (1, 0):
