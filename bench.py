@@ -119,8 +119,12 @@ def ablation(torch, irk, inputs, wl, steps):
     problem, n, family, s, dt, _, nu = wl
     op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
     res = []
-    for gm, nl, ka in ((0, 1, 1), (0, 1, 0), (1, 1, 1), (0, 0, 1), (0, 2, 1), (0, 3, 1)):
-        solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl, krylov_adaptive=ka))
+    variants = [(0, 1, 1, 0), (0, 1, 0, 0), (1, 1, 1, 0), (0, 0, 1, 0), (0, 2, 1, 0), (0, 3, 1, 0)]
+    if problem == "vsf":
+        variants.append((0, 1, 1, 1))          # the reordered DAE system, eq (vsf-system-2)
+    for gm, nl, ka, ro in variants:
+        solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl, krylov_adaptive=ka,
+                                                            dae_reorder=ro))
         u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
         b = torch.empty_like(u)
         t = 0.0
@@ -136,7 +140,11 @@ def ablation(torch, irk, inputs, wl, steps):
         wall = time.perf_counter() - t0
         solver.close()
         res.append({"gamma": "gamma*" if gm == 0 else "eta", "newton_like": nl,
-                    "krylov_tol": "adaptive" if ka else "fixed", "ms_per_step": 1e3 * wall / steps,
+                    "krylov_tol": "adaptive" if ka else "fixed",
+                    "dae_system": ("reordered (vsf-system-2)" if ro else "whole (vsf-system-1)") if problem == "vsf"
+                    else None,
+                    "ms_per_step": 1e3 * wall / steps,
+                    "vcycles_per_step": sum(x["vcycles"] for x in stats) / steps,
                     "newton_its_per_step": sum(x["newton_its"] for x in stats) / steps,
                     "krylov_its_per_step": sum(x["krylov_its"] for x in stats) / steps,
                     "krylov_its_per_block": [sum(x["krylov_its_block"][k] for x in stats) / steps

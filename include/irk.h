@@ -135,6 +135,16 @@ typedef struct irk_options {
                                most 0.1, target = the acceptance threshold
                                (never solving further than the outer test
                                can use); 0: krylov_rtol always             */
+    int dae_reorder;        /* IRK_OP_VSF_2D only.  0: Krylov on each block's
+                               whole system (vorticity and streamfunction
+                               rows, eq (vsf-system-1)) preconditioned by
+                               L_P then one Poisson V-cycle per
+                               streamfunction row; 1: the reordered
+                               block-triangular system (eq (vsf-system-2)):
+                               forward substitution, a Krylov solve of the
+                               vorticity rows (preconditioned by L_P), then
+                               one of the streamfunction rows (a Poisson
+                               V-cycle per row as preconditioner)          */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -167,7 +177,8 @@ const char *irk_status_str(irk_status st);
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
  * cheb_degree 3, mg_coarsest 8, coarse_iters 24, batch_mg 0 (shared
  * launches couple the blocks' progress and were measured slower on the
- * bench workloads; see the option), start_extrapolate 1, krylov_adaptive 1.*/
+ * bench workloads; see the option), start_extrapolate 1, krylov_adaptive 1,
+ * dae_reorder 0.                                                           */
 void irk_default_options(irk_options *opt);
 
 /* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,

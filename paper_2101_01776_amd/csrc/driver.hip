@@ -104,7 +104,8 @@ static bool valid_options(const irk_options &o) {
            (o.prec_fp32 == 0 || o.prec_fp32 == 1) && o.cheb_degree >= 1 && o.cheb_degree <= 4 &&
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
-           (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1);
+           (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1) &&
+           (o.dae_reorder == 0 || o.dae_reorder == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -672,6 +673,55 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
 
 static const double *stage_field(irk_ctx *c, int stage) { return c->U + (size_t)stage * c->P.nf; }
 
+// Zero one variable (0: omega, 1: psi) of every component of a VSF block
+// vector ([width][omega, psi][npts]).
+static void zero_var(irk_ctx *c, Lane &ln, double *x, int var) {
+    const Plan &P = c->P;
+    for (int comp = 0; comp < P.eb.width[ln.blk]; ++comp)
+        PROF(c, ln.stream, "k_fill_f64", 8.0 * P.npts, 1,
+             launch_fill(ln.stream, x + comp * P.nf + var * P.npts, 0.0, P.npts));
+}
+
+// Preconditioners of the two solves of the reordered DAE block system (eq
+// (vsf-system-2), the forward substitution): mode 1, the vorticity system
+// alone -- the block-triangular L_P on the omega components, psi parts
+// zero; mode 2, the streamfunction rows alone -- one Poisson V-cycle per
+// component with the vorticity parts zero.  Returns the V-cycles used.
+template <class T>
+static int apply_prec_mode(irk_ctx *c, Lane &ln, const double *v, double *z, int mode) {
+    if (mode == 0) return apply_prec<T>(c, ln, v, z);
+    const Plan &P = c->P;
+    const EigenBlocks &eb = P.eb;
+    const int blk = ln.blk, r = eb.first[blk], width = eb.width[blk];
+    const size_t nf = P.nf, npts = P.npts;
+    int nvc = 0;
+    if (mode == 1) {
+        prec_component<T>(c, ln, z, v, 1.0, nullptr, 0.0, eb.eta[blk], P.row_hier[r]);
+        ++nvc;
+        if (width == 2) {
+            const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eb.eta[blk];
+            if (ln.tmp) {
+                PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">",
+                     8.0 * npts * (2.0 + P.s * P.nvar), 1,
+                     launch_block_matvec_w(ln.stream, c->dp, P.s, 1, 0.0, eb.beta[blk], c->dt, c->U, P.blk_w[blk], z,
+                                           ln.tmp, nullptr, 1));
+                prec_component<T>(c, ln, z + nf, v + nf, 1.0, ln.tmp, 1.0, gam, P.row_hier[r + 1]);
+            } else {
+                prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, eb.beta[blk], gam, P.row_hier[r + 1]);
+            }
+            ++nvc;
+        }
+        zero_var(c, ln, z, 1);
+    } else {
+        zero_var(c, ln, z, 0);
+        for (int comp = 0; comp < width; ++comp) {
+            prec_psi<T>(c, ln, z + comp * nf + npts, v + comp * nf + npts, z + comp * nf);
+            ++nvc;
+        }
+    }
+    return nvc;
+}
+
 static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
     const Plan &P = c->P;
     const EigenBlocks &eb = P.eb;
@@ -749,6 +799,11 @@ struct Fgmres {
     bool first_cycle = true, converged = false, fused = true;
     double beta0 = 0.0;
     enum Phase { WAIT_BETA, WAIT_PREC, WAIT_ITER, DONE } phase = WAIT_BETA;
+    // 0: the whole block system; reordered DAE system (eq (vsf-system-2)):
+    // 1 the vorticity rows, then 2 the streamfunction rows, the second
+    // solve starting from the first's solution (sol keeps accumulating)
+    int mode = 0;
+    bool beta0_set = false;
     double *pend_v = nullptr, *pend_z = nullptr;    // preconditioner input/output waiting in a broker
     irk_status deferred = IRK_OK;                    // error raised while resumed by a broker
 
@@ -772,6 +827,25 @@ struct Fgmres {
         first_cycle = true;
         converged = false;
         beta0 = 0.0;
+        beta0_set = false;
+        mode = (P.op.kind == IRK_OP_VSF_2D && P.opt.dae_reorder) ? 1 : 0;
+    }
+
+    // after the vorticity solve of the reordered system: the streamfunction
+    // rows, from the current sol
+    irk_status to_psi() {
+        mode = 2;
+        first_cycle = false;
+        converged = false;
+        beta0_set = false;
+        j = 0;
+        return start();
+    }
+
+    // the block operator of the current solve
+    void op(const double *x, double *w) {
+        block_matvec(c, *ln, x, w);
+        if (mode == 1) zero_var(c, *ln, w, 1);
     }
 
     double *Vv(int k) { return ln->V + (size_t)k * ln->ldv; }
@@ -779,12 +853,21 @@ struct Fgmres {
 
     // issue ||r0||^2 (r0 = rhs on the first cycle, rhs - D sol on restarts)
     irk_status start() {
-        if (first_cycle) {
+        if (first_cycle && mode == 1) {
+            // the vorticity rows of rhs
+            if (hipMemcpyAsync(Vv(0), rhs, len * sizeof(double), hipMemcpyDeviceToDevice, ln->stream) != hipSuccess)
+                return IRK_E_DEVICE;
+            zero_var(c, *ln, Vv(0), 1);
+            PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
+                 launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, Vv(0), len, 1, ln->part, ln->dv + DV_BETA,
+                                  nullptr));
+        } else if (first_cycle) {
             PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
                  launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, rhs, len, 1, ln->part, ln->dv + DV_BETA, nullptr));
         } else {
             block_matvec(c, *ln, sol, Vv(0));
             PROF(c, ln->stream, "k_axpby", 24.0 * len, 1, launch_axpby(ln->stream, Vv(0), 1.0, rhs, -1.0, Vv(0), len));
+            if (mode) zero_var(c, *ln, Vv(0), mode == 1 ? 1 : 0);
             PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
                  launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, Vv(0), len, 1, ln->part, ln->dv + DV_BETA,
                                   nullptr));
@@ -804,7 +887,7 @@ struct Fgmres {
             static_cast<PrecBroker<T> *>(c->broker)->pending.push_back(this);
             return IRK_OK;
         }
-        vcycles += apply_prec<T>(c, *ln, vj, zj);
+        vcycles += apply_prec_mode<T>(c, *ln, vj, zj, mode);
         return issue_after_prec();
     }
 
@@ -841,7 +924,7 @@ struct Fgmres {
 
     irk_status issue_after_prec() {
         double *zj = Zv(j), *w = Vv(j + 1);
-        block_matvec(c, *ln, zj, w);
+        op(zj, w);
         const int nv = j + 1;
         fused = nv <= 16;
         hipStream_t st = ln->stream;
@@ -882,6 +965,8 @@ struct Fgmres {
         }
         irk_status stt;
         if (first_cycle) {
+            // (the vorticity solve's Z vectors have zero psi parts: sol's psi
+            // parts start at zero too)
             if ((stt = lane_write(*ln, ln->dv + DV_Y, y.data(), j)) != IRK_OK) return stt;
             PROF(c, ln->stream, "k_lincomb", 8.0 * len * (j + 1), 1,
                  launch_lincomb(ln->stream, sol, Zv(0), ln->ldv, j, ln->dv + DV_Y, len));
@@ -905,10 +990,12 @@ struct Fgmres {
         if (phase == WAIT_BETA) {
             const double bnorm = std::sqrt(hb[DV_BETA]);
             if (!std::isfinite(bnorm)) return IRK_E_NONFINITE;
-            if (first_cycle) {
+            if (!beta0_set) {
                 beta0 = bnorm;
+                beta0_set = true;
                 if (bnorm == 0.0) {
-                    PROF(c, ln->stream, "k_fill_f64", 8.0 * len, 1, launch_fill(ln->stream, sol, 0.0, len));
+                    if (first_cycle)
+                        PROF(c, ln->stream, "k_fill_f64", 8.0 * len, 1, launch_fill(ln->stream, sol, 0.0, len));
                     phase = DONE;
                     return IRK_OK;
                 }
@@ -918,7 +1005,8 @@ struct Fgmres {
                 return IRK_OK;
             }
             PROF(c, ln->stream, "k_scale_copy", 16.0 * len, 1,
-                 launch_scale_copy(ln->stream, Vv(0), first_cycle ? rhs : Vv(0), ln->dv + DV_BETA, len));
+                 launch_scale_copy(ln->stream, Vv(0), first_cycle && mode == 0 ? rhs : Vv(0), ln->dv + DV_BETA,
+                                   len));
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = bnorm;
             j = 0;
@@ -1298,8 +1386,13 @@ struct Stepper : StepperBase {
                 if (q == hipErrorNotReady) continue;
                 if (q != hipSuccess) return fail(IRK_E_DEVICE);
                 progressed = true;
-                const irk_status e = fg[b].advance();
+                irk_status e = fg[b].advance();
                 if (e != IRK_OK) return fail(e);
+                if (fg[b].phase == Fgmres<T>::DONE && fg[b].mode == 1) {
+                    // reordered DAE system: the streamfunction rows next
+                    e = fg[b].to_psi();
+                    if (e != IRK_OK) return fail(e);
+                }
                 if (fg[b].phase == Fgmres<T>::DONE) {
                     lane_done[b] = true;
                     --active;
@@ -1464,6 +1557,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->batch_mg = 0;
     o->start_extrapolate = 1;
     o->krylov_adaptive = 1;
+    o->dae_reorder = 0;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("newton_like", ctypes.c_int), ("gamma_mode", ctypes.c_int),
                 ("prec_fp32", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("batch_mg", ctypes.c_int),
-                ("start_extrapolate", ctypes.c_int), ("krylov_adaptive", ctypes.c_int)]
+                ("start_extrapolate", ctypes.c_int), ("krylov_adaptive", ctypes.c_int),
+                ("dae_reorder", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
