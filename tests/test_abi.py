@@ -64,6 +64,20 @@ def test_status_strings_and_defaults():
     o = irk.irk_default_options()
     assert o.newton_rtol == 1e-12 and o.krylov_rtol == 1e-5 and o.restart == 30
     assert o.prec_fp32 == 1 and o.cheb_degree == 3 and o.newton_like == 1 and o.gamma_mode == 0
+    assert o.batch_mg == 0 and o.start_extrapolate == 1 and o.krylov_adaptive == 1 and o.dae_reorder == 0
+
+
+def test_struct_layouts_match_the_header():
+    """The binding's structures have the header's size: irk_default_options
+    writes exactly sizeof(Options) bytes (a guard region after it stays
+    untouched) and its last field lands where the binding expects it."""
+    import ctypes
+    n = ctypes.sizeof(irk.Options)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    irk.lib().irk_default_options(ctypes.cast(buf, ctypes.POINTER(irk.Options)))
+    assert bytes(buf[n:]) == b"\xab" * 64
+    o = irk.Options.from_buffer_copy(bytes(buf[:n]))
+    assert o.krylov_adaptive == 1 and o.dae_reorder == 0 and o.coarse_iters == 24
 
 
 @pytest.mark.parametrize("family,s", [(f, s) for f in ("gauss", "radau", "lobatto") for s in (1, 2, 3, 4, 5)
