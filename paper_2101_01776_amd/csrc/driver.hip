@@ -1130,25 +1130,29 @@ static void fill_stage_coefs(const irk_ctx *c, double t_n, double dt, StageCoefs
 template <class T>
 static void setup_hierarchies(irk_ctx *c) {
     const Plan &P = c->P;
-    for (int hq = 0; hq < P.nhier; ++hq) {
-        // coefficient field of the linearization: U_m (NLDIFF, Burgers) or
-        // Psi_m (VSF) of the hierarchy's stage, or (Newton-like (2), (3)) the
-        // row's weighted combination sum_k d_rr,k U_k
-        const size_t off = P.op.kind == IRK_OP_VSF_2D ? P.npts : 0;
-        if (P.weighted) {
-            PROF(c, c->stream, kn<T>("k_mix_cast"), (double)P.npts * (8.0 * P.s + sizeof(T)), 1,
-                 launch_mix_cast<T>(c->stream, c->coef<T>(hq, 0), c->U, P.nf, off, P.s, P.hier_w[hq], P.npts));
-        } else {
-            const double *src = stage_field(c, P.hier_stage[hq]) + off;
-            PROF(c, c->stream, kn<T>("k_mg_cast_in"), (double)P.npts * (8 + sizeof(T)), 1,
-                 launch_cast_coef<T>(c->stream, c->coef<T>(hq, 0), src, P.npts));
+    // coefficient field of each hierarchy's linearization: U_m (NLDIFF,
+    // Burgers) or Psi_m (VSF) of its stage, or (Newton-like (2), (3)) the
+    // row's weighted combination sum_k d_rr,k U_k -- all hierarchies in one
+    // launch per level
+    const size_t off = P.op.kind == IRK_OP_VSF_2D ? P.npts : 0;
+    const int nh = P.nhier;
+    T *dst[IRK_MAX_STAGES];
+    const T *src[IRK_MAX_STAGES];
+    int nread = 0;                       // stage fields read per point (bytes)
+    for (int hq = 0; hq < nh; ++hq) {
+        dst[hq] = c->coef<T>(hq, 0);
+        for (int k = 0; k < P.s; ++k) nread += P.hier_w[hq][k] != 0.0;
+    }
+    PROF(c, c->stream, kn<T>("k_mix_cast_multi"), (double)P.npts * (8.0 * nread + nh * sizeof(T)), 1,
+         launch_mix_cast_multi<T>(c->stream, dst, c->U, P.nf, off, P.s, P.hier_w, nh, P.npts));
+    for (int l = 0; l + 1 < P.lg.nlev; ++l) {
+        for (int hq = 0; hq < nh; ++hq) {
+            src[hq] = c->coef<T>(hq, l);
+            dst[hq] = c->coef<T>(hq, l + 1);
         }
-        for (int l = 0; l + 1 < P.lg.nlev; ++l) {
-            const double np = (double)P.lg.nx[l] * P.lg.ny[l], npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-            PROF(c, c->stream, kn<T>("k_mg_coef_restrict"), sizeof(T) * (np + npc), 1,
-                 launch_mg_coef_restrict<T>(c->stream, P.lg.nx[l], P.lg.ny[l], c->coef<T>(hq, l),
-                                            c->coef<T>(hq, l + 1)));
-        }
+        const double np = (double)P.lg.nx[l] * P.lg.ny[l], npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
+        PROF(c, c->stream, kn<T>("k_mg_coef_restrict_multi"), sizeof(T) * (np + npc) * nh, 1,
+             launch_mg_coef_restrict_multi<T>(c->stream, P.lg.nx[l], P.lg.ny[l], src, dst, nh));
     }
 }
 

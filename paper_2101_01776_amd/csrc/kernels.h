@@ -30,10 +30,6 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, doub
 void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
                            double dt, const double *U, const BlockWeights &W, const double *x, double *w,
                            const double *xmeans, int coupling);
-// dst = (T) sum_k wts[k] U[k * nf + off + e], e < len (wts: host, s values)
-template <class T>
-void launch_mix_cast(hipStream_t st, T *dst, const double *U, size_t nf, size_t off, int s, const double *wts,
-                     size_t len);
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr);
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);
@@ -49,15 +45,18 @@ void launch_axpby(hipStream_t st, double *dst, double a, const double *x, double
 void launch_zero_u32(hipStream_t st, unsigned *p, int n);
 void launch_fill(hipStream_t st, double *p, double v, size_t len);
 
+// every hierarchy's restriction of one level in one launch (n <= IRK_MAX_STAGES)
 template <class T>
-void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc);
+void launch_mg_coef_restrict_multi(hipStream_t st, int nxf, int nyf, const T *const *src, T *const *dst, int n);
+// dst[h] = (T) sum_k w[h][k] U[k * nf + off + e] for h < n, in one launch
+template <class T>
+void launch_mix_cast_multi(hipStream_t st, T *const *dst, const double *U, size_t nf, size_t off, int s,
+                           const double (*w)[IRK_MAX_STAGES], int n, size_t len);
 template <class T>
 void launch_mg_cast_in(hipStream_t st, T *b0, const double *v1, double a1, const double *v2, double a2,
                        const double *means, size_t len);
 template <class T>
 void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const double *shift, double c,
                         size_t len);
-template <class T>
-void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len);
 
 }  // namespace irk

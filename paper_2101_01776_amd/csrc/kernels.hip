@@ -459,19 +459,6 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
     }
 }
 
-// dst = (T) sum_k wts.b[k] U_k[off + e], e < len (the linearization field of
-// a hierarchy built from stage-weighted stage values)
-template <class T>
-__global__ void __launch_bounds__(IRK_WG) k_mix_cast(T *__restrict__ dst, const double *__restrict__ U, size_t nf,
-                                                     size_t off, int s, StageCoefs wts, size_t len) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
-        double acc = 0.0;
-        for (int k = 0; k < s; ++k) acc += wts.b[k] * U[(size_t)k * nf + off + e];
-        dst[e] = (T)acc;
-    }
-}
-
 // ------------------------------------------------------------------------
 // Arnoldi kernels
 // ------------------------------------------------------------------------
@@ -595,12 +582,22 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 
 // ------------------------------------------------------------------------
 // Multigrid (precision T).  Level operator A = sigma M - dt L(coef) with the
-// operator's linearization rediscretized at the level spacing.
+// operator's linearization rediscretized at the level spacing; a coarse
+// coefficient is the full-weighting restriction of the fine one.
 // ------------------------------------------------------------------------
-// coarse coefficient = full-weighting restriction of the fine coefficient
+// The coefficient hierarchies of one Newton iteration together: blockIdx.y
+// selects the hierarchy (its fields are read from the argument block with a
+// uniform index).
 template <class T>
-__global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict(int nxf, int nyf, const T *__restrict__ cf,
-                                                             T *__restrict__ cc) {
+struct CoefSet {
+    const T *src[IRK_MAX_STAGES];
+    T *dst[IRK_MAX_STAGES];
+};
+
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict_multi(int nxf, int nyf, CoefSet<T> p) {
+    const T *__restrict__ cf = p.src[blockIdx.y];
+    T *__restrict__ cc = p.dst[blockIdx.y];
     const int nxc = nxf / 2, nyc = (nyf > 1) ? nyf / 2 : 1;
     const size_t npc = (size_t)nxc * nyc;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -616,6 +613,30 @@ __global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict(int nxf, int nyf, c
                     acc += wgt[a + 1] * wgt[bb + 1] * cf[(size_t)wrapm(2 * J + bb, nyf) * nxf + wrapm(2 * I + a, nxf)];
         }
         cc[q] = acc;
+    }
+}
+
+// dst_h = (T) sum_k w[h][k] U_k[off + e] for every hierarchy h = blockIdx.y
+// (zero weights skipped: a one-hot row reads one stage field)
+template <class T>
+struct MixSet {
+    T *dst[IRK_MAX_STAGES];
+    double w[IRK_MAX_STAGES][IRK_MAX_STAGES];
+};
+
+template <class T>
+__global__ void __launch_bounds__(IRK_WG) k_mix_cast_multi(const double *__restrict__ U, size_t nf, size_t off,
+                                                           int s, MixSet<T> m, size_t len) {
+    const int h = blockIdx.y;
+    T *__restrict__ dst = m.dst[h];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+        double acc = 0.0;
+        for (int k = 0; k < s; ++k) {
+            const double wk = m.w[h][k];
+            if (wk != 0.0) acc += wk * U[(size_t)k * nf + off + e];
+        }
+        dst[e] = (T)acc;
     }
 }
 
@@ -788,15 +809,6 @@ void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int wi
         block_matvec_w_op<IRK_OP_VSF_2D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
 }
 
-template <class T>
-void launch_mix_cast(hipStream_t st, T *dst, const double *U, size_t nf, size_t off, int s, const double *wts,
-                     size_t len) {
-    StageCoefs C;
-    std::memset(&C, 0, sizeof(C));
-    for (int k = 0; k < s; ++k) C.b[k] = wts[k];
-    k_mix_cast<T><<<grid_for(len), IRK_WG, 0, st>>>(dst, U, nf, off, s, C, len);
-}
-
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr) {
     // chunks of DOT_CHUNK vectors; the norm (if any) rides on the last chunk
@@ -847,9 +859,24 @@ void launch_fill(hipStream_t st, double *p, double v, size_t len) {
 }
 
 template <class T>
-void launch_mg_coef_restrict(hipStream_t st, int nxf, int nyf, const T *cf, T *cc) {
+void launch_mg_coef_restrict_multi(hipStream_t st, int nxf, int nyf, const T *const *src, T *const *dst, int n) {
+    CoefSet<T> p;
+    std::memset(&p, 0, sizeof(p));
+    for (int h = 0; h < n; ++h) { p.src[h] = src[h]; p.dst[h] = dst[h]; }
     const size_t npc = (size_t)(nxf / 2) * (nyf > 1 ? nyf / 2 : 1);
-    k_mg_coef_restrict<T><<<grid_for(npc), IRK_WG, 0, st>>>(nxf, nyf, cf, cc);
+    k_mg_coef_restrict_multi<T><<<dim3(grid_for(npc), n), IRK_WG, 0, st>>>(nxf, nyf, p);
+}
+
+template <class T>
+void launch_mix_cast_multi(hipStream_t st, T *const *dst, const double *U, size_t nf, size_t off, int s,
+                           const double (*w)[IRK_MAX_STAGES], int n, size_t len) {
+    MixSet<T> m;
+    std::memset(&m, 0, sizeof(m));
+    for (int h = 0; h < n; ++h) {
+        m.dst[h] = dst[h];
+        for (int k = 0; k < s; ++k) m.w[h][k] = w[h][k];
+    }
+    k_mix_cast_multi<T><<<dim3(grid_for(len), n), IRK_WG, 0, st>>>(U, nf, off, s, m, len);
 }
 
 template <class T>
@@ -864,18 +891,13 @@ void launch_mg_cast_out(hipStream_t st, double *z, const T *x, double a, const d
     k_mg_cast_out<T><<<grid_for(len), IRK_WG, 0, st>>>(z, x, a, shift, c, len);
 }
 
-template <class T>
-void launch_cast_coef(hipStream_t st, T *dst, const double *src, size_t len) {
-    launch_mg_cast_in<T>(st, dst, src, 1.0, nullptr, 0.0, nullptr, len);
-}
-
 #define INST(T)                                                                                                    \
-    template void launch_mg_coef_restrict<T>(hipStream_t, int, int, const T *, T *);                               \
     template void launch_mg_cast_in<T>(hipStream_t, T *, const double *, double, const double *, double,           \
                                        const double *, size_t);                                                    \
     template void launch_mg_cast_out<T>(hipStream_t, double *, const T *, double, const double *, double, size_t); \
-    template void launch_cast_coef<T>(hipStream_t, T *, const double *, size_t);                                     \
-    template void launch_mix_cast<T>(hipStream_t, T *, const double *, size_t, size_t, int, const double *, size_t);
+    template void launch_mg_coef_restrict_multi<T>(hipStream_t, int, int, const T *const *, T *const *, int);     \
+    template void launch_mix_cast_multi<T>(hipStream_t, T *const *, const double *, size_t, size_t, int,           \
+                                           const double (*)[IRK_MAX_STAGES], int, size_t);
 INST(float)
 INST(double)
 #undef INST
