@@ -247,6 +247,7 @@ using namespace irk;
 enum {
     DV_RES = 0,        // ||F||^2
     DV_ABS = 1,        // squared norm of |terms of F| (rounding scale)
+    DV_CAND = 2,       // Newton level: (||F||^2, |terms|^2) of the starting candidates (6)
     DV_BETA = 4,       // ||r0||^2 of a block solve
     DV_NRM = 5,        // ||w||^2 after orthogonalization (unfused path)
     DV_SUMS = 8,       // field sums (up to 16)
@@ -1178,10 +1179,10 @@ struct Stepper : StepperBase {
     StageCoefs C;
     int it = 0, fold = 0, flat = 0, active = 0;
     double res0 = -1, thresh = 0, prev = 0;
-    // starting stage vectors: K = 0 is evaluated first, then the explicit
-    // k_i = N(u_n, t_n); the one with the smaller residual starts Newton
-    enum Start { START_ZERO, START_EXPLICIT, START_EXTRAP, START_CHOSEN } start = START_CHOSEN;
-    double res_zero = 0, res_expl = 0;
+    // starting stage vectors: the candidates (zero, explicit, extrapolated)
+    // are evaluated back to back with one readback of their residuals
+    enum Start { START_CANDIDATES, START_CHOSEN } start = START_CHOSEN;
+    int ncand = 2;
     Fgmres<T> fg[IRK_MAX_STAGES];
     bool lane_done[IRK_MAX_STAGES];
 
@@ -1194,7 +1195,9 @@ struct Stepper : StepperBase {
         return true;
     }
 
-    irk_status issue_residual() {
+    // stage values and residual of the current K; its norms go to dv[slot],
+    // and (readback) dv[0..2] is copied to the host with an event behind it
+    irk_status issue_residual(int slot = DV_RES, bool readback = true) {
         const Plan &P = c->P;
         const int s = P.s;
         const size_t nf = P.nf;
@@ -1207,10 +1210,45 @@ struct Stepper : StepperBase {
         // reads U and K, writes the transformed residual: 3 s fields
         PROF(c, c->stream, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
              8.0 * nf * 3 * s, 1,
-             launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+             launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + slot,
                              nullptr));
+        if (!readback) return IRK_OK;
         HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipEventRecord(c->ev_res, c->stream));
+        phase = RES_WAIT;
+        return IRK_OK;
+    }
+
+    void set_zero_start() {
+        const Plan &P = c->P;
+        PROF(c, c->stream, "k_fill", 8.0 * P.s * P.nf, 1, launch_fill(c->stream, c->K, 0.0, (size_t)P.s * P.nf));
+    }
+    void set_explicit_start() {
+        const Plan &P = c->P;
+        PROF(c, c->stream, "k_rhs_init<" + std::to_string(P.s) + "," + std::to_string(P.op.kind) + ">",
+             8.0 * P.nf * (1 + P.s), 1,
+             launch_rhs_init(c->stream, P.s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
+    }
+
+    // all candidates evaluated back to back (the last one's stage values and
+    // transformed residual stay current), one readback of their norms
+    irk_status issue_candidates() {
+        const Plan &P = c->P;
+        ncand = c->extrap ? 3 : 2;
+        set_zero_start();
+        irk_status e = issue_residual(DV_CAND, false);
+        if (e != IRK_OK) return e;
+        set_explicit_start();
+        if ((e = issue_residual(DV_CAND + 2, false)) != IRK_OK) return e;
+        if (ncand == 3) {
+            HIP_TRY(hipMemcpyAsync(c->K, c->Y, (size_t)P.s * P.nf * sizeof(double), hipMemcpyDeviceToDevice,
+                                   c->stream));
+            if ((e = issue_residual(DV_CAND + 4, false)) != IRK_OK) return e;
+        }
+        HIP_TRY(hipMemcpyAsync(c->pinned + DV_CAND, c->dv + DV_CAND, 2 * ncand * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipEventRecord(c->ev_res, c->stream));
+        start = START_CANDIDATES;
         phase = RES_WAIT;
         return IRK_OK;
     }
@@ -1252,72 +1290,42 @@ struct Stepper : StepperBase {
             PROF(c, c->stream, "k_stage_extrap<" + std::to_string(s) + ">", 8.0 * nf * 2 * s, 1,
                  launch_stage_extrap(c->stream, s, nf, c->K, c->Y, W));
         }
-        start = START_ZERO;
-        PROF(c, c->stream, "k_fill", 8.0 * s * nf, 1, launch_fill(c->stream, c->K, 0.0, (size_t)s * nf));
-        const irk_status e = issue_residual();
+        const irk_status e = issue_candidates();
         if (e != IRK_OK) fail(e);
     }
 
     // the residual norm has arrived: converge, fail, or start the block solves
     bool on_residual() {
         const Plan &P = c->P;
-        const double res = std::sqrt(c->pinned[DV_RES]);
-        // the residual cannot be resolved below the rounding error of its own
-        // evaluation: 64 eps times the norm of the magnitudes of its terms
-        const double floor_res = 64.0 * 2.220446049250313e-16 * std::sqrt(c->pinned[DV_ABS]);
-        if (start == START_ZERO) {
-            // K = 0 evaluated; now the explicit candidate k_i = N(u_n, t_n)
-            if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
-            res_zero = res;
-            start = START_EXPLICIT;
-            PROF(c, c->stream, "k_rhs_init<" + std::to_string(P.s) + "," + std::to_string(P.op.kind) + ">",
-                 8.0 * P.nf * (1 + P.s), 1,
-                 launch_rhs_init(c->stream, P.s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
-            const irk_status e = issue_residual();
-            return e != IRK_OK ? fail(e) : false;
-        }
-        if (start == START_EXPLICIT || start == START_EXTRAP) {
+        if (start == START_CANDIDATES) {
             // candidates in order zero, explicit, extrapolated: the smallest
             // residual wins, the earlier one on ties (NaN never wins)
-            if (start == START_EXPLICIT) {
-                res_expl = res;
-                if (c->extrap) {
-                    start = START_EXTRAP;
-                    if (hipMemcpyAsync(c->K, c->Y, (size_t)P.s * P.nf * sizeof(double), hipMemcpyDeviceToDevice,
-                                       c->stream) != hipSuccess)
-                        return fail(IRK_E_DEVICE);
-                    const irk_status e = issue_residual();
-                    return e != IRK_OK ? fail(e) : false;
-                }
-            }
-            const bool had_extrap = start == START_EXTRAP;
             start = START_CHOSEN;
+            double rc[3];
+            for (int i = 0; i < ncand; ++i) rc[i] = std::sqrt(c->pinned[DV_CAND + 2 * i]);
+            if (!std::isfinite(rc[0])) return fail(IRK_E_NONFINITE);
+            int best = 0;
+            for (int i = 1; i < ncand; ++i)
+                if (rc[i] < rc[best]) best = i;
+            stats.start = best;
             if (debug_level())
                 fprintf(stderr, "[irk] start candidates: |F(0)| %.6e |F(explicit)| %.6e |F(extrapolated)| %.6e\n",
-                        res_zero, res_expl, had_extrap ? res : -1.0);
-            const bool expl_beats_zero = res_expl < res_zero;
-            const double best = expl_beats_zero ? res_expl : res_zero;
-            if (had_extrap && res < best) {
-                stats.start = 2;
-            } else if (expl_beats_zero) {
-                stats.start = 1;
-                if (had_extrap) {
-                    // back to the explicit candidate
-                    PROF(c, c->stream, "k_rhs_init<" + std::to_string(P.s) + "," + std::to_string(P.op.kind) + ">",
-                         8.0 * P.nf * (1 + P.s), 1,
-                         launch_rhs_init(c->stream, P.s, c->dp, u_n, c->K, std::sin(t_n), std::cos(t_n)));
-                    const irk_status e = issue_residual();
-                    return e != IRK_OK ? fail(e) : false;
-                }
+                        rc[0], rc[1], ncand == 3 ? rc[2] : -1.0);
+            if (best == ncand - 1) {
+                // the last candidate evaluated: its stage values are current
+                c->pinned[DV_RES] = c->pinned[DV_CAND + 2 * best];
+                c->pinned[DV_ABS] = c->pinned[DV_CAND + 2 * best + 1];
             } else {
-                // zero wins: back to K = 0
-                stats.start = 0;
-                PROF(c, c->stream, "k_fill", 8.0 * P.s * P.nf, 1,
-                     launch_fill(c->stream, c->K, 0.0, (size_t)P.s * P.nf));
+                if (best == 0) set_zero_start();
+                else set_explicit_start();
                 const irk_status e = issue_residual();
                 return e != IRK_OK ? fail(e) : false;
             }
         }
+        const double res = std::sqrt(c->pinned[DV_RES]);
+        // the residual cannot be resolved below the rounding error of its own
+        // evaluation: 64 eps times the norm of the magnitudes of its terms
+        const double floor_res = 64.0 * 2.220446049250313e-16 * std::sqrt(c->pinned[DV_ABS]);
         if (!std::isfinite(res)) return fail(IRK_E_NONFINITE);
         if (it == 0) {
             res0 = res;
