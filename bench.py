@@ -323,12 +323,14 @@ def serve_run(torch, irk, reqs, fields, lam, prec_fp32, budget, slots, arena):
                                                       "peak_bytes": st["peak_bytes"]}
 
 
-def serve_bench(torch, irk, inputs, count, budget_gb, slots, load, seed, fp64=True):
+def serve_bench(torch, irk, inputs, count, budget_gb, slots, load, seed, fp64=True, sweep=()):
     """Continuous-batching serving workload: nonlinear-diffusion requests,
     grid side log-uniform in {128..1024}, Gauss or Radau IIA with s in
     {2,3,4}, dt log-uniform in [1e-3, 1e-2], 10 steps each.  First the
     closed-loop saturation throughput mu, then open-loop Poisson arrivals at
-    lambda = load * mu; the same stream with float64 V-cycles beside it."""
+    lambda = load * mu; the same stream with float64 V-cycles beside it.
+    sweep: further loads (fractions of mu) run open-loop with float32
+    V-cycles only."""
     reqs, fields = serve_inputs(torch, inputs, count, seed)
     budget = int(budget_gb * (1 << 30)) & ~255
     arena = torch.empty(budget + 256, dtype=torch.uint8, device="cuda")     # the HBM budget, allocated once
@@ -355,6 +357,16 @@ def serve_bench(torch, irk, inputs, count, budget_gb, slots, load, seed, fp64=Tr
                             "dof_stages_per_s": dofs / wall, "wall_s": wall,
                             "step_p50_ms": pct(step_lat, 50), "step_p99_ms": pct(step_lat, 99),
                             "req_p50_ms": pct(lat, 50), "req_p99_ms": pct(lat, 99), **st}
+        if prec and sweep:
+            res["open_loop_sweep"] = []
+            for ld in sweep:
+                print(f"serve: open loop at {ld:g} x mu", file=sys.stderr, flush=True)
+                wall, lat, step_lat, st = serve_run(torch, irk, reqs, fields, ld * mu, prec, budget, slots, arena)
+                res["open_loop_sweep"].append({
+                    "load": ld, "lambda_req_per_s": ld * mu, "req_per_s": count / wall,
+                    "steps_per_s": st["steps"] / wall, "step_p50_ms": pct(step_lat, 50),
+                    "step_p99_ms": pct(step_lat, 99), "req_p50_ms": pct(lat, 50), "req_p99_ms": pct(lat, 99),
+                    "failed": st["failed"], "peak_running": st["peak_running"]})
         out[key] = res
     return out
 
@@ -394,6 +406,8 @@ def main():
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--load", type=float, default=0.8, help="open-loop lambda as a fraction of mu")
     ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated further open-loop loads (fractions of mu), float32 V-cycles only")
     ap.add_argument("--serve-sample", type=int, default=0,
                     help="also run a serving sample of this many requests in the default bench")
     args = ap.parse_args()
@@ -420,8 +434,9 @@ def main():
         copy_probe(torch)
     if args.serve:
         t0 = time.perf_counter()
+        sweep = tuple(float(x) for x in args.serve_sweep.split(",") if x.strip())
         sv = serve_bench(torch, irk, inputs, args.requests, args.budget_gb, args.slots, args.load,
-                         args.serve_seed, fp64=not args.no_fp64)
+                         args.serve_seed, fp64=not args.no_fp64, sweep=sweep)
         m = sv["mixed"]["open_loop"]
         out = {"metric": METRIC, "value": m["steps_per_s"], "unit": "IRK steps/s", "n_gpus": 1,
                "steps": m["steps"], "warmup": 16, "ms_per_step": 1e3 / m["steps_per_s"],
