@@ -400,12 +400,6 @@ static int debug_level() {
     return lvl;
 }
 
-static irk_status sync_read(irk_ctx *c, const double *dev, int count) {
-    HIP_TRY(hipMemcpyAsync(c->pinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return IRK_OK;
-}
-
 // asynchronous readback of a lane's device scalars; completion via ln.ev
 static irk_status lane_readback(Lane &ln, int count) {
     HIP_TRY(hipMemcpyAsync(ln.pin + PIN_READ, ln.dv, sizeof(double) * count, hipMemcpyDeviceToHost, ln.stream));
