@@ -241,6 +241,38 @@ def test_1024_step_residual_and_precisions():
     assert rel(outs[1], outs[0]) < 1e-10
 
 
+@pytest.mark.parametrize("family,s", [("gauss", 3), ("radau", 3)])
+def test_fourier_symbol_at_full_size(family, s):
+    """1024^2 with a field of amplitude 1e-4 (kappa = 1 + u^2 is 1 to 1e-8,
+    so the operator is the 5-point Laplacian up to that): one step acts on
+    every Fourier mode k as the stability function R(dt lambda_k), lambda_k
+    the stencil symbol -4 n^2 (sin^2(pi k_x/n) + sin^2(pi k_y/n)) -- smooth
+    and stiff modes alike (dt lambda up to -2.1e4)."""
+    n, dt = 1024, 5e-3
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_NONE)
+    x = np.arange(n) / n
+    X, Y = np.meshgrid(x, x)
+    u0 = np.zeros((n, n))
+    for kx, ky, a in ((1, 2, 1.0), (3, 1, 0.7), (5, 7, 0.5), (20, 11, 0.3), (100, 60, 0.2), (300, 500, 0.1)):
+        u0 += a * np.sin(2 * np.pi * (kx * X + ky * Y) + 0.3 * kx)
+    u0 *= 1e-4
+    A, b, _ = tb.tableau(family, s)
+    sol = _solver(op, family, s, prec_fp32=1)
+    out, st = sol.step(u0, 0.0, dt)
+    sol.close()
+    k = np.fft.fftfreq(n, 1.0 / n)
+    s1 = (4.0 * n * n) * np.sin(np.pi * k / n) ** 2
+    lam = -(s1[:, None] + s1[None, :])
+    z = dt * lam
+    # R(z) = 1 + z b^T (I - z A)^{-1} 1 on the distinct symbol values
+    zs, inv = np.unique(z, return_inverse=True)
+    Rz = np.array([tb.stability_function(A, b, zz).real for zz in zs])[inv].reshape(z.shape)
+    want = np.real(np.fft.ifft2(Rz * np.fft.fft2(u0)))
+    err = rel(out.cpu().numpy(), want)
+    print(f"  {family}-{s} 1024^2: rel err vs R(dt lambda_k) {err:.2e}, {st}")
+    assert err < 1e-6
+
+
 def test_gauss_conserves_invariants_on_gpu():
     """nu = 0: enstrophy sum(omega^2) and energy sum(psi omega) are conserved
     by Gauss-2 to solver tolerance; Radau IIA-2 dissipates enstrophy."""
