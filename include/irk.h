@@ -118,7 +118,9 @@ typedef struct irk_options {
     int gamma_mode;         /* 0: gamma_* = eta + beta^2/eta, 1: gamma = eta  */
     int prec_fp32;          /* 1: V-cycles in float32, 0: float64            */
     int cheb_degree;        /* Chebyshev pre- and post-smoothing degree       */
-    int mg_coarsest;        /* coarsest grid side of the V-cycle hierarchy    */
+    int mg_coarsest;        /* coarsening stops before a side below this (the
+                               coarsest level, at most 1024 points, is
+                               solved by Chebyshev iteration)             */
     int coarse_iters;       /* Chebyshev iterations on the coarsest level     */
     int batch_mg;           /* 1: V-cycles of blocks (and, in a server, of
                                requests) waiting at the same time run in
@@ -175,7 +177,7 @@ const char *irk_status_str(irk_status st);
  * Defaults: newton_rtol 1e-12, newton_atol 0 (then 1e-14 ||F(K0)||),
  * krylov_rtol 1e-5 (the paper's GMRES tolerance, Section 7.1), restart 30,
  * max_krylov 200, max_newton 30, newton_like 1, gamma_mode 0, prec_fp32 1,
- * cheb_degree 3, mg_coarsest 8, coarse_iters 24, batch_mg 0 (shared
+ * cheb_degree 3, mg_coarsest 16, coarse_iters 24, batch_mg 0 (shared
  * launches couple the blocks' progress and were measured slower on the
  * bench workloads; see the option), start_extrapolate 1, krylov_adaptive 1,
  * dae_reorder 0.                                                           */

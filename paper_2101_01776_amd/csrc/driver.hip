@@ -1558,7 +1558,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->gamma_mode = 0;
     o->prec_fp32 = 1;
     o->cheb_degree = 3;
-    o->mg_coarsest = 8;
+    o->mg_coarsest = 16;
     o->coarse_iters = 24;
     o->batch_mg = 0;
     o->start_extrapolate = 1;
