@@ -392,9 +392,10 @@ def main():
     ap.add_argument("--sdirk-compare", action="store_true",
                     help="also compare Gauss/Radau IIA with SDIRK of equal order on the workload")
     ap.add_argument("--ablation", action="store_true",
-                    help="also compare gamma* vs eta and Newton-like (1) vs (0) on the workload")
+                    help="also compare gamma* vs eta, the Newton-like truncations (0)-(3), fixed vs "
+                         "adaptive Krylov tolerance and (DAE) the reordered system on the workload")
     ap.add_argument("--cheb-degree", type=int, default=None, help="Chebyshev smoothing degree (default 3)")
-    ap.add_argument("--mg-coarsest", type=int, default=None, help="coarsest multigrid side (default 8)")
+    ap.add_argument("--mg-coarsest", type=int, default=None, help="coarsest multigrid side (default 16)")
     ap.add_argument("--batch-mg", action="store_true",
                     help="run the V-cycles of blocks/requests that wait together as shared launches")
     ap.add_argument("--copy-probe", action="store_true",
