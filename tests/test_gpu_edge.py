@@ -217,14 +217,16 @@ def test_adaptive_krylov_tolerance(family, s, n):
     assert out[1][1] <= out[0][1]
 
 
-def test_1024_step_residual_and_precisions():
+@pytest.mark.parametrize("s,dt", [(3, 5e-3), (5, 1e-2)])
+def test_1024_step_residual_and_precisions(s, dt):
     """1024^2 (finest level on 32x16 tiles, the next ones on 32x8, then the
-    16x8 and one-work-group kernels): one Gauss-3 step converges with float32
+    16x8 and one-work-group kernels): one Gauss-3 step (dt 5e-3) and one
+    step of the Gauss-5 throughput workload (dt 1e-2) converge with float32
     and with float64 V-cycles to the same stages (1e-10), and the oracle's
     residual of the GPU stage vectors is the one the GPU reports (5 %) and
     at rounding level."""
     import torch
-    n, s, dt = 1024, 3, 5e-3
+    n = 1024
     op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
     u = inputs.nldiff_u0(n)
     outs = {}
@@ -235,7 +237,7 @@ def test_1024_step_residual_and_precisions():
         outs[prec] = out.cpu().numpy()
         F = oracle_residual(op, "gauss", s, u, 0.0, dt, K)
         nF = np.linalg.norm(F)
-        print(f"  1024^2 prec {prec}: |F| {nF:.3e} {st}")
+        print(f"  1024^2 gauss-{s} dt {dt} prec {prec}: |F| {nF:.3e} {st}")
         assert abs(nF - st["final_res"]) <= 5e-2 * nF
         assert dt * nF <= 1e-11 * np.linalg.norm(u)
         sol.close()
