@@ -66,21 +66,36 @@ __device__ void finish_partials(const double *myvals, int nv, double *partials, 
         for (int k = 0; k < nv; ++k) partials[(size_t)blockIdx.x * nv + k] = myvals[k];
 }
 
-// out[k] = sum over work-groups b of partials[b * nv + k], fixed order
+#define DOT_CHUNK 16                  // basis vectors per dot-product launch
+#define RED_NV (DOT_CHUNK + 1)        // at most this many values per partial (16 dots and a norm)
+
+// out[k] = sum over work-groups b of partials[b * nv + k] (nv <= RED_NV) in
+// a fixed order: thread t adds b = t, t + 256, ...; each wave reduces by
+// shuffles; then waves 0..3 in order.  Every load of a thread is issued
+// before its first add (the values sit in another XCD's L2 or in HBM).
 __global__ void __launch_bounds__(256) k_reduce_partials(const double *__restrict__ partials, int nb, int nv,
                                                          double *__restrict__ out) {
-    __shared__ double sh[4 * 32];
+    __shared__ double sh[4 * RED_NV];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 0; k < nv; ++k) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partials[(size_t)b * nv + k];
-        a = wave_sum(a);
-        if (lane == 0) sh[wid * 32 + k] = a;
+    double a[RED_NV];
+#pragma unroll
+    for (int k = 0; k < RED_NV; ++k) a[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double *p = partials + (size_t)b * nv;
+#pragma unroll
+        for (int k = 0; k < RED_NV; ++k)
+            if (k < nv) a[k] += p[k];
     }
+#pragma unroll
+    for (int k = 0; k < RED_NV; ++k)
+        if (k < nv) {
+            const double v = wave_sum(a[k]);
+            if (lane == 0) sh[wid * RED_NV + k] = v;
+        }
     __syncthreads();
     if ((int)threadIdx.x < nv) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w * 32 + threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w * RED_NV + threadIdx.x];
         out[threadIdx.x] = t;
     }
 }
@@ -462,7 +477,6 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
 // ------------------------------------------------------------------------
 // Arnoldi kernels
 // ------------------------------------------------------------------------
-#define DOT_CHUNK 16
 // out[k] = <V_k, w> for k < nv (nv <= 16); out[nv] = <w, w> when with_norm
 __global__ void __launch_bounds__(IRK_WG) k_dot_multi(const double *__restrict__ V, size_t ldv, int nv,
                                                       const double *__restrict__ w, size_t len, int with_norm,
