@@ -107,7 +107,9 @@ typedef struct irk_options {
     int newton_like;        /* Section 3.2 in the eigenbasis, d_rq,k =
                                (T^{-1})_rk T_kq:
                                0: simplified Newton (last-stage Jacobian),
-                               1: lump each row to its argmax |d_rr,k| stage,
+                               1: lump each row to its argmax |d_rr,k| stage
+                                  (among weights within a relative 1e-12
+                                  of the largest, the lowest stage index),
                                2: each row its weighted sum_k d_rr,k L(U_k),
                                3: as 2 plus the coupling sum_k d_rq,k L(U_k)
                                   between the two rows of a pair (the
@@ -162,6 +164,17 @@ typedef struct irk_stats {
     double final_res;           /* ||F(K)||_2 at acceptance                   */
     int start;                  /* starting stage vectors Newton began from:
                                    0 zero, 1 explicit, 2 extrapolated       */
+    int acceptance;             /* how the iteration was accepted: 0 the
+                                   threshold (rtol ||F(K0)|| + atol, or the
+                                   rounding level of the residual evaluation),
+                                   1 stagnation within 16x that rounding
+                                   level, 2 stagnation (three iterations each
+                                   reducing ||F|| by less than 10 %) below
+                                   1e-8 ||F(K0)||: the rounding level was
+                                   underestimated -- the step is returned
+                                   with IRK_OK but final_res may exceed the
+                                   threshold.  SDIRK: the largest over the
+                                   stages.                                   */
 } irk_stats;
 
 /* ---------------- host-only entry points (no GPU needed) ---------------- */
@@ -309,6 +322,11 @@ typedef struct irk_request {
     const double *u0;       /* device, initial field; read at admission; the
                                caller keeps it valid until the request ends   */
     double *out;            /* device, final field written at completion      */
+    void *stream;           /* hipStream_t on which u0 is produced (NULL: the
+                               null stream): irk_server_submit records an
+                               event on it, and the admission copy of u0
+                               waits for that event, so u0 may still be in
+                               flight on that stream when it is submitted    */
 } irk_request;
 
 typedef struct irk_request_info {
@@ -324,8 +342,11 @@ typedef struct irk_request_info {
  * bounds the number of requests resident at once.                          */
 irk_status irk_server_create(void *arena, size_t arena_bytes, int max_slots, irk_server **out);
 /* Queue a request (nothing runs until irk_server_progress).  IRK_E_ARG for
- * invalid requests; a request larger than the whole arena is failed with
- * IRK_E_NOMEM when it reaches the head of the queue.                       */
+ * invalid requests, IRK_E_DEVICE if the ordering event on req->stream cannot
+ * be recorded; a request larger than the whole arena is failed with
+ * IRK_E_NOMEM when it reaches the head of the queue.  The result is in
+ * req->out once irk_server_info reports IRK_REQ_DONE (the server has
+ * synchronized the copy by then).                                          */
 irk_status irk_server_submit(irk_server *srv, const irk_request *req, long *id);
 /* One non-blocking scheduling pass: admit what fits, advance every running
  * request; returns the number of requests queued or running (-1 on NULL).  */

@@ -177,6 +177,20 @@ def irk_step(problem, A, b, c, u_n, t_n, dt, max_iter=60, prev=None):
     return u_n + dt * (b @ K), K, info
 
 
+def lumped_stage(dr):
+    """Stage Newton-like (1) lumps a row with diagonal weights ``dr`` to: the
+    largest |d_rr,k|, and among weights within a relative 1e-12 of the
+    largest the lowest index k.  (The real eigenvalue's row of Gauss with odd
+    s and of 3-stage Lobatto IIIC has its two largest weights equal,
+    d_rr,k = d_rr,s-1-k; a plain argmax would decide those by rounding.)"""
+    w = np.abs(np.asarray(dr, dtype=np.float64))
+    big = float(w.max())
+    for k in range(len(w)):
+        if w[k] >= big * (1.0 - 1e-12):
+            return k
+    return int(np.argmax(w))
+
+
 def block_operator(problem, A, c, u_n, t_n, dt, K, T, block, variant):
     """Krylov operator D_b of one eigen-block (equation (diag_blocks)) as a
     sparse matrix on the block's transformed components.  With the stage
@@ -186,8 +200,8 @@ def block_operator(problem, A, c, u_n, t_n, dt, K, T, block, variant):
       Lambda_{ab} M - dt sum_k W_{a b k} L_k
     with the truncations of Section 3.2 written in the eigenbasis:
       0: W_{aak} = [k = s-1] (every row linearized at the last stage),
-      1: W_{aak} = [k = argmax_k |d_{r_a r_a k}|] (lumped to the largest
-         weight),
+      1: W_{aak} = [k = lumped_stage(d_{r_a r_a})] (lumped to the largest
+         weight, the lowest stage index among ties),
       2: W_{aak} = d_{r_a r_a k} (the diagonal weights, not lumped),
       3: W_{abk} = d_{r_a r_b k} for both rows of the block (the truncation to
          the block sparsity of R0; in the eigenbasis R0 is block diagonal).
@@ -209,7 +223,7 @@ def block_operator(problem, A, c, u_n, t_n, dt, K, T, block, variant):
         if variant == 0:
             W[a, a, s - 1] = 1.0
         elif variant == 1:
-            W[a, a, int(np.argmax(np.abs(dr)))] = 1.0
+            W[a, a, lumped_stage(dr)] = 1.0
         elif variant == 2:
             W[a, a, :] = dr
         else:

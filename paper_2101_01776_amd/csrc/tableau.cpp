@@ -429,14 +429,19 @@ bool build_eigen_blocks(int family, int s, EigenBlocks *eb) {
             eb->Tinv[i * s + j] = (double)Ti[i * s + j];
         }
     // d weights d[k][l][i] = Tinv[k][i] T[i][l] (equation (Q0approx)), and the
-    // argmax stage of each diagonal weight vector (Newton-like(1))
+    // stage Newton-like (1) lumps each diagonal weight vector to: the lowest
+    // stage index whose |d_kk,i| is within a relative 1e-12 of the largest.
+    // The real eigenvalue's row of Gauss (odd s) and of 3-stage Lobatto IIIC
+    // has its two largest weights equal (d_kk,i = d_kk,s-1-i), so a plain
+    // argmax would pick the stage by rounding.
     for (int k = 0; k < s; ++k) {
-        int best = 0;
-        ld bv = -1;
+        ld dk[IRK_MAX_STAGES], big = 0;
         for (int i = 0; i < s; ++i) {
-            ld d = fabsl(Ti[k * s + i] * T[i * s + k]);
-            if (d > bv) { bv = d; best = i; }
+            dk[i] = fabsl(Ti[k * s + i] * T[i * s + k]);
+            if (dk[i] > big) big = dk[i];
         }
+        int best = 0;
+        while (best + 1 < s && dk[best] < big * (1.0L - 1e-12L)) ++best;
         eb->argmax_stage[k] = best;
     }
     return true;

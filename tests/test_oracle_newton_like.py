@@ -113,3 +113,26 @@ def test_block_operators_against_exact_newton(kind, family, s):
         ops = [nw.block_operator(lin, A, c, ul, 0.1, dt, Kl, T, blk, v).toarray() for v in range(3)]
         for o in ops[1:]:
             np.testing.assert_allclose(o, ops[0], atol=1e-12 * np.abs(ops[0]).max())
+
+
+@pytest.mark.parametrize("family,s,row", [("gauss", 3, 0), ("gauss", 5, 0), ("lobatto", 3, 0)])
+def test_lumped_stage_tie_break(family, s, row):
+    """Newton-like (1) lumps a row to its largest stage weight.  On the real
+    eigenvalue's row of Gauss-3, Gauss-5 and Lobatto IIIC-3 the two largest
+    weights are the mirror pair d_rr,k = d_rr,s-1-k (equal to rounding), so
+    the convention -- the lowest stage index among weights within a relative
+    1e-12 of the largest -- picks stage 0; rows with a clear maximum keep
+    their argmax."""
+    A, _, _ = tb.tableau(family, s)
+    T, _ = tb.real_eigenbasis(A)
+    d = tb.d_weights(T)
+    w = np.abs(d[row, row, :])
+    k = int(np.argmax(w))
+    assert abs(w[k] - w[s - 1 - k]) <= 1e-14 * w[k] and k != s - 1 - k
+    assert nw.lumped_stage(d[row, row, :]) == min(k, s - 1 - k) == 0
+    for r in range(s):
+        if r == row:
+            continue
+        wr = np.sort(np.abs(d[r, r, :]))
+        assert wr[-1] - wr[-2] > 1e-3
+        assert nw.lumped_stage(d[r, r, :]) == int(np.argmax(np.abs(d[r, r, :])))
