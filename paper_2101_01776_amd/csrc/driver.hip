@@ -1331,13 +1331,22 @@ struct Stepper : StepperBase {
         if (debug_level())
             fprintf(stderr, "[irk] newton it %d res %.6e thresh %.3e floor %.3e\n", it, res, thresh, floor_res);
         bool converged = res <= std::max(thresh, floor_res);
+        stats.acceptance = 0;
         // stagnation within a small factor of the estimated floor: the
         // iteration has reached rounding level
-        if (!converged && it > 0 && res <= 16.0 * floor_res && res > 0.25 * prev) converged = true;
-        // safety net: three non-decreasing iterations far below res0 mean the
-        // rounding floor was underestimated
-        flat = (it > 0 && res > 0.5 * prev) ? flat + 1 : 0;
-        if (!converged && flat >= 3 && res <= 1e-8 * res0) converged = true;
+        if (!converged && it > 0 && res <= 16.0 * floor_res && res > 0.25 * prev) {
+            converged = true;
+            stats.acceptance = 1;
+        }
+        // safety net: three iterations in a row that reduce the residual by
+        // less than 10 % (stagnation, not slow linear convergence, which
+        // goes on to the threshold) far below res0 mean the rounding floor
+        // was underestimated; reported in stats.acceptance
+        flat = (it > 0 && res >= 0.9 * prev) ? flat + 1 : 0;
+        if (!converged && flat >= 3 && res <= 1e-8 * res0) {
+            converged = true;
+            stats.acceptance = 2;
+        }
         if (converged) {
             PROF(c, c->stream, "k_final_update<" + std::to_string(P.s) + ">", 8.0 * P.nf * (P.s + 2), 1,
                  launch_final_update(c->stream, P.s, P.nf, u_n, c->K, u_np1, C, dt));
@@ -1507,6 +1516,7 @@ struct SdirkStepper : StepperBase {
             stats.prec_applications += is.prec_applications;
             stats.res0 = std::max(stats.res0, is.res0);
             stats.final_res = std::max(stats.final_res, is.final_res);
+            stats.acceptance = std::max(stats.acceptance, is.acceptance);
             if (inner.status != IRK_OK) return fail(inner.status);
             if (debug_level())
                 fprintf(stderr, "[irk] sdirk stage %d done: newton %d krylov %d res0 %.3e final %.3e\n", stage,

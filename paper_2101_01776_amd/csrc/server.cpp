@@ -98,6 +98,7 @@ struct Req {
     bool allocated = false;
     irk_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipEvent_t u0_ready = nullptr;            // recorded on the caller's stream at submit
     double *ua = nullptr, *ub = nullptr;      // resident state, ping-pong
     double t = 0.0, step_t0 = 0.0;
 };
@@ -139,6 +140,8 @@ static void finish(irk_server *s, Req *q, irk_status st) {
     }
     if (q->stream) (void)hipStreamDestroy(q->stream);
     q->stream = nullptr;
+    if (q->u0_ready) (void)hipEventDestroy(q->u0_ready);
+    q->u0_ready = nullptr;
     if (q->allocated) s->alloc.release(q->off, q->total);
     q->allocated = false;
     s->finished[q->id] = q;
@@ -166,6 +169,8 @@ static bool try_admit(irk_server *s) {
     unsigned char *ws = base + 2 * ((q->field_bytes + 255) & ~size_t(255));
     irk_status st = IRK_OK;
     if (hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking) != hipSuccess) st = IRK_E_DEVICE;
+    // u0 is read after the work the caller had queued on its stream at submit
+    if (st == IRK_OK && hipStreamWaitEvent(q->stream, q->u0_ready, 0) != hipSuccess) st = IRK_E_DEVICE;
     if (st == IRK_OK &&
         hipMemcpyAsync(q->ua, q->r.u0, q->field_bytes, hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
         st = IRK_E_DEVICE;
@@ -219,6 +224,14 @@ extern "C" irk_status irk_server_submit(irk_server *s, const irk_request *r, lon
     q->ws_bytes = ws;
     q->field_bytes = field_len(r->op) * sizeof(double);
     q->total = 2 * ((q->field_bytes + 255) & ~size_t(255)) + ws;
+    // (a request that can never fit fails at admission without reading u0)
+    if (q->total <= s->alloc.capacity() &&
+        (hipEventCreateWithFlags(&q->u0_ready, hipEventDisableTiming) != hipSuccess ||
+         hipEventRecord(q->u0_ready, (hipStream_t)r->stream) != hipSuccess)) {
+        if (q->u0_ready) (void)hipEventDestroy(q->u0_ready);
+        delete q;
+        return IRK_E_DEVICE;
+    }
     s->queue.push_back(q);
     *id = q->id;
     return IRK_OK;
@@ -301,7 +314,10 @@ extern "C" void irk_server_destroy(irk_server *s) {
     if (!s) return;
     for (Req *q : s->running) finish(s, q, IRK_E_ARG);
     s->running.clear();
-    for (Req *q : s->queue) delete q;
+    for (Req *q : s->queue) {
+        if (q->u0_ready) (void)hipEventDestroy(q->u0_ready);
+        delete q;
+    }
     for (auto &kv : s->finished) delete kv.second;
     if (s->brk32) irk::broker_destroy(s->brk32, 1);
     if (s->brk64) irk::broker_destroy(s->brk64, 0);

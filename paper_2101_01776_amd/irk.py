@@ -54,20 +54,20 @@ class Stats(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("krylov_its", ctypes.c_int),
                 ("krylov_its_block", ctypes.c_int * IRK_MAX_STAGES), ("vcycles", ctypes.c_int),
                 ("prec_applications", ctypes.c_int), ("res0", ctypes.c_double),
-                ("final_res", ctypes.c_double), ("start", ctypes.c_int)]
+                ("final_res", ctypes.c_double), ("start", ctypes.c_int), ("acceptance", ctypes.c_int)]
 
     def as_dict(self):
         return {"newton_its": self.newton_its, "krylov_its": self.krylov_its,
                 "krylov_its_block": list(self.krylov_its_block), "vcycles": self.vcycles,
                 "prec_applications": self.prec_applications, "res0": self.res0,
-                "final_res": self.final_res, "start": self.start}
+                "final_res": self.final_res, "start": self.start, "acceptance": self.acceptance}
 
 
 class Request(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("s", ctypes.c_int), ("op", Operator), ("opt", Options),
                 ("use_options", ctypes.c_int), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("nsteps", ctypes.c_int), ("tol", ctypes.c_double), ("u0", ctypes.c_void_p),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -419,6 +419,7 @@ class Server:
         req.t0, req.dt, req.nsteps, req.tol = t0, dt, nsteps, tol
         req.u0 = u0.data_ptr()
         req.out = out.data_ptr()
+        req.stream = torch.cuda.current_stream(self.device).cuda_stream
         rid = irk_server_submit(self.srv, req)
         self._keep[rid] = (u0, out)
         return rid

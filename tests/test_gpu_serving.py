@@ -98,3 +98,68 @@ def test_request_larger_than_arena_fails_alone():
     ib = srv.info(b)
     assert ib["state"] == "failed" and ib["status"] == "IRK_E_NOMEM"
     srv.close()
+
+
+ORACLE_MIX = [  # (family, s, n, dt, nsteps, seed): small enough for the oracle
+    ("gauss", 2, 32, 4e-3, 3, 11),
+    ("radau", 3, 64, 2e-3, 2, 12),
+    ("gauss", 3, 48, 5e-3, 3, 13),
+    ("radau", 2, 32, 8e-3, 2, 14),
+    ("gauss", 4, 64, 3e-3, 2, 15),
+]
+
+
+@pytest.mark.parametrize("prec_fp32,bar", [(0, 1e-10), (1, 1e-8)], ids=["fp64", "mixed"])
+def test_served_results_match_oracle(prec_fp32, bar):
+    """Every request of a concurrent mix (served together, with overlapping
+    steps) against the oracle's chain of full-Newton steps on the same
+    problem (equations (stages) and (update); continued steps hand the
+    oracle the previous stages, its extrapolated starting candidate)."""
+    from gpu_common import oracle_problem
+    from oracle import newton as nw
+    from oracle import tableau as tb
+    srv = irk.Server(arena_bytes=2 << 30, max_slots=8)
+    ids = []
+    for family, s, n, dt, nsteps, seed in ORACLE_MIX:
+        op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+        ids.append(srv.submit(family, s, op, inputs.nldiff_random_u0(n, seed), dt, nsteps,
+                              opt=irk.make_options(prec_fp32=prec_fp32)))
+    srv.run_until_idle()
+    assert srv.stats()["peak_running"] >= 3
+    for rid, (family, s, n, dt, nsteps, seed) in zip(ids, ORACLE_MIX):
+        info = srv.info(rid)
+        assert info["state"] == "done" and info["steps_done"] == nsteps, info
+        prob = oracle_problem(irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS))
+        A, b, c = tb.tableau(family, s)
+        u, t, prev = inputs.nldiff_random_u0(n, seed).ravel(), 0.0, None
+        for _ in range(nsteps):
+            u, K, _ = nw.irk_step(prob, A, b, c, u, t, dt, prev=prev)
+            prev, t = (K, dt), t + dt
+        got = srv.result(rid).cpu().numpy().ravel()
+        err = float(np.linalg.norm(got - u) / np.linalg.norm(u))
+        print(f"  served {family}{s} {n}^2 x{nsteps}: rel err {err:.3e}", flush=True)
+        assert err < bar, (family, s, n, err)
+    srv.close()
+
+
+def test_u0_produced_on_the_callers_stream():
+    """A request whose initial field is still being written on the caller's
+    stream at submit reads the finished field: the admission copy waits for
+    the event the server records on that stream."""
+    import torch
+    n = 64
+    op = irk.make_operator(irk.OP_NLDIFF_2D, n, forcing=irk.FORCING_MMS)
+    ref = _alone("gauss", 2, n, 4e-3, 2, 21)
+    src = torch.tensor(inputs.nldiff_random_u0(n, 21), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    srv = irk.Server(arena_bytes=1 << 30, max_slots=2)
+    u0 = torch.zeros_like(src)
+    big = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    for _ in range(4):
+        big.mul_(1.0)                 # queue work ahead of the copy on the same stream
+    u0.copy_(src)
+    rid = srv.submit("gauss", 2, op, u0, 4e-3, 2)
+    srv.run_until_idle()
+    assert srv.info(rid)["state"] == "done"
+    assert torch.equal(srv.result(rid), ref)
+    srv.close()
