@@ -1,0 +1,126 @@
+"""Write the oracle's stored step results used by the full-size GPU parity tests.
+
+    python tests/golden/make_oracle_goldens.py [case ...]
+
+Calls only ``oracle/`` (tableaux, operators, full Newton with SuperLU) and the
+seeded input constructors of ``paper_2101_01776_amd.inputs``; nothing here
+touches the HIP library.  Each case writes ``oracle_<case>.npy`` (float64) and
+a line in ``oracle_goldens.txt`` with the Newton iterations of every step
+and the seconds the oracle took.
+
+Cases (the workloads' shapes; the larger grids take minutes, the LU fill of
+the 512^2 Gauss-3 system is a few GB):
+
+* burgers256_gauss2: 1-D viscous Burgers, N = 256, nu = 0.01, Gauss s = 2,
+  dt = 1e-2, the whole 20-step job from t = 0 for seeds 0 and 1 (array of
+  shape (2, 21, 256): the initial field and every step's result);
+* nldiff512_gauss3: 2-D nonlinear diffusion 512^2 with the continuous
+  manufactured forcing, u0 = sin(2 pi x) sin(2 pi y), Gauss s = 3,
+  dt = 5e-3, the first two steps from t = 0 (shape (2, 512, 512));
+* nldiff256_gauss5: the same problem at 256^2 with Gauss s = 5, dt = 1e-2,
+  the first two steps (shape (2, 256, 256));
+* vsf256_radau3: the vorticity-streamfunction DAE at 256^2, nu = 1e-3,
+  32 seeded Gaussian vortices (seed 0), Radau IIA s = 3, dt = 2e-3, the
+  first two steps (shape (2, 2, 256, 256): omega and psi after each step).
+
+Continued steps hand the previous stages to the oracle's start choice, as the
+library's own continued steps do; the converged stages do not depend on it.
+"""
+from __future__ import annotations
+
+import fcntl
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import newton as nw  # noqa: E402
+from oracle import problems as pb  # noqa: E402
+from oracle import tableau as tb  # noqa: E402
+from paper_2101_01776_amd import inputs  # noqa: E402
+
+LOG = os.path.join(HERE, "oracle_goldens.txt")
+
+
+def chain(problem, family, s, u0, dt, steps):
+    """Results of ``steps`` consecutive oracle steps from t = 0."""
+    A, b, c = tb.tableau(family, s)
+    u = np.asarray(u0, dtype=np.float64).ravel()
+    out, its, corr = [], [], []
+    prev = None
+    t = 0.0
+    for _ in range(steps):
+        u, K, info = nw.irk_step(problem, A, b, c, u, t, dt, prev=prev)
+        prev = (K, dt)
+        t += dt
+        out.append(u.copy())
+        its.append(info.newton_its)
+        corr.append(info.corrections[-1])
+    return np.stack(out), its, corr
+
+
+def case_burgers256_gauss2():
+    n, nu, dt, steps = 256, 0.01, 1e-2, 20
+    res, its = [], []
+    for seed in (0, 1):
+        u0 = inputs.burgers_u0(n, seed)
+        traj, it, _ = chain(pb.Burgers1D(n, nu), "gauss", 2, u0, dt, steps)
+        res.append(np.concatenate([u0[None, :], traj]))
+        its += it
+    return np.stack(res), its
+
+
+def case_nldiff512_gauss3():
+    n = 512
+    traj, its, _ = chain(pb.NonlinearDiffusion2D(n), "gauss", 3, inputs.nldiff_u0(n), 5e-3, 2)
+    return traj.reshape(2, n, n), its
+
+
+def case_nldiff256_gauss5():
+    n = 256
+    traj, its, _ = chain(pb.NonlinearDiffusion2D(n), "gauss", 5, inputs.nldiff_u0(n), 1e-2, 2)
+    return traj.reshape(2, n, n), its
+
+
+def case_vsf256_radau3():
+    n = 256
+    u0 = inputs.vsf_state0(n, 0, 32)
+    traj, its, _ = chain(pb.VorticityStreamfunction2D(n, 1e-3), "radau", 3, u0, 2e-3, 2)
+    return traj.reshape(2, 2, n, n), its
+
+
+CASES = {
+    "burgers256_gauss2": case_burgers256_gauss2,
+    "nldiff512_gauss3": case_nldiff512_gauss3,
+    "nldiff256_gauss5": case_nldiff256_gauss5,
+    "vsf256_radau3": case_vsf256_radau3,
+}
+
+
+def main(names):
+    for name in names or list(CASES):
+        t0 = time.perf_counter()
+        arr, its = CASES[name]()
+        dt = time.perf_counter() - t0
+        np.save(os.path.join(HERE, f"oracle_{name}.npy"), arr)
+        line = f"{name} shape={'x'.join(map(str, arr.shape))} newton_its={its} oracle_s={dt:.1f}"
+        print(line, flush=True)
+        with open(LOG, "a+") as f:
+            fcntl.flock(f, fcntl.LOCK_EX)       # cases may run in parallel processes
+            f.seek(0)
+            kept = [ln for ln in f if ln.strip() and not ln.startswith(name + " ") and not ln.startswith("#")]
+            f.seek(0)
+            f.truncate()
+            f.write("# written by make_oracle_goldens.py (oracle/ only); case, array shape, "
+                    "Newton iterations per step, seconds\n")
+            f.writelines(sorted(kept + [line + "\n"]))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
