@@ -195,11 +195,12 @@ def sdirk_compare(torch, irk, inputs, wl, steps):
     return {"dt": dt, "steps": steps, "reference": "gauss-3 at dt/4", "runs": out}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    runs (FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a plain
-    copy of known size), or None when absent or taken on a different kernel
-    source than the one built here."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` in `workload` from the committed
+    rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE averaged over the
+    kernel's dispatches, each scaled by the same counter on a plain device
+    copy of known size), or None when absent or taken on kernel sources other
+    than the ones built here."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
@@ -207,16 +208,18 @@ def measured_traffic(kernel):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, rec.get("source", ""))
-    try:
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
+    run = rec.get("workloads", {}).get(workload)
+    if run is None:
         return None
-    ent = rec.get("kernels", {}).get(kernel)
-    if sha != rec.get("source_sha256") or ent is None:
-        return None
-    return ent["hbm_bytes_per_launch"]
+    for src, want in run.get("sources_sha256", {}).items():
+        try:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+        except OSError:
+            return None
+    ent = run.get("kernels", {}).get(kernel)
+    return None if ent is None else ent["hbm_bytes_per_launch"]
 
 
 def copy_probe(torch, mib=256, reps=3):
@@ -236,9 +239,45 @@ def pct(sorted_vals, q):
     return sorted_vals[k]
 
 
+def host_info():
+    """CPU model, usable cores and the BLAS thread pools of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    blas = None
+    try:
+        import numpy  # noqa: F401  (load the BLAS the oracle uses before listing the pools)
+        import scipy.sparse.linalg  # noqa: F401
+        from threadpoolctl import threadpool_info
+        blas = [{"api": p.get("internal_api"), "threads": p.get("num_threads")} for p in threadpool_info()]
+    except Exception:  # pragma: no cover
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable, "blas_pools": blas,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def sample_problem(wl, n_sample):
+    from paper_2101_01776_amd import inputs
+    problem, _, family, s, dt, _, nu = wl
+    if problem == "vsf":
+        return inputs.vsf_state0(n_sample, 0, 32), 2 * n_sample * n_sample
+    return inputs.nldiff_u0(n_sample), n_sample * n_sample
+
+
 def cpu_baseline(wl, n_sample):
-    """The oracle as it stands (full Newton, SuperLU) on one step of the same
-    workload at a reduced grid, single-threaded."""
+    """The oracle as it stands (full Newton, SuperLU) on the first step of the
+    same workload at a reduced grid, single-threaded (SuperLU factorizes on
+    one thread; the BLAS pools are limited to one as well)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -246,29 +285,53 @@ def cpu_baseline(wl, n_sample):
     from oracle import newton as nw
     from oracle import problems as pb
     from oracle import tableau as tb
-    from paper_2101_01776_amd import inputs
     problem, _, family, s, dt, _, nu = wl
     A, b, c = tb.tableau(family, s)
+    u0, dof = sample_problem(wl, n_sample)
     if problem == "vsf":
         prob = pb.VorticityStreamfunction2D(n_sample, nu=nu)
-        u0 = inputs.vsf_state0(n_sample, 0, 32).ravel()
-        dof = 2 * n_sample * n_sample
     else:
         prob = pb.NonlinearDiffusion2D(n_sample, forcing="continuous")
-        u0 = inputs.nldiff_u0(n_sample).ravel()
-        dof = n_sample * n_sample
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         t0 = time.perf_counter()
-        _, _, info = nw.irk_step(prob, A, b, c, u0, 0.0, dt)
+        _, _, info = nw.irk_step(prob, A, b, c, u0.ravel(), 0.0, dt)
         el = time.perf_counter() - t0
     finally:
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
     return {"value": dof * s / el, "unit": "DOF*stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"one {family} s={s} step (dt={dt:g}) of the same workload on a {n_sample}x{n_sample} "
-                      f"grid: full Newton ({info.newton_its} iterations) with a SuperLU factorization each, "
-                      f"single thread; {el:.2f} s for the step"}
+            "sample": f"the first {family} s={s} step (dt={dt:g}, t=0) of the same workload on a "
+                      f"{n_sample}x{n_sample} grid: full Newton ({info.newton_its} iterations) with a SuperLU "
+                      f"factorization each, one thread; {el:.2f} s for the step",
+            "s_per_step": el, "host": host_info()}
+
+
+def gpu_same_size(torch, irk, wl, n_sample, reps=10):
+    """The library on the oracle's sample: the same first step from t = 0
+    repeated (each from the same input, so none is a continued step), mixed
+    precision, inputs resident on the device."""
+    from paper_2101_01776_amd import inputs  # noqa: F401
+    problem, _, family, s, dt, _, nu = wl
+    u0, dof = sample_problem(wl, n_sample)
+    if problem == "vsf":
+        op = irk.make_operator(irk.OP_VSF_2D, n_sample, nu=nu)
+    else:
+        op = irk.make_operator(irk.OP_NLDIFF_2D, n_sample, forcing=irk.FORCING_MMS)
+    solver = irk.Solver(family, s, op, irk.make_options(prec_fp32=1))
+    a = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        solver.step(a, 0.0, dt, out=b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        solver.step(a, 0.0, dt, out=b)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    solver.close()
+    return {"value": dof * s / el, "unit": "DOF*stages/s", "s_per_step": el,
+            "sample": f"the same first step on {n_sample}x{n_sample}, {reps} repetitions"}
 
 
 def serve_inputs(torch, inputs, count, seed):
@@ -376,10 +439,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's job)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="nldiff512-gauss3", choices=sorted(WORKLOADS),
-                    help="nldiff512-gauss3 (default): 2-D nonlinear diffusion 512^2, Gauss-3, dt 5e-3, "
-                         "50 steps; vsf1024-radau3: vorticity-streamfunction DAE 1024^2, Radau IIA-3, "
-                         "dt 2e-3, 20 steps; nldiff1024-gauss5: nonlinear diffusion 1024^2, Gauss-5, "
+    ap.add_argument("--workload", default="vsf1024-radau3", choices=sorted(WORKLOADS),
+                    help="vsf1024-radau3 (default; the largest single-GPU job by DOF*stages): "
+                         "vorticity-streamfunction DAE 1024^2, Radau IIA-3, dt 2e-3, 20 steps; "
+                         "nldiff512-gauss3: 2-D nonlinear diffusion 512^2, Gauss-3, dt 5e-3, "
+                         "50 steps; nldiff1024-gauss5: nonlinear diffusion 1024^2, Gauss-5, "
                          "dt 1e-2, 20 steps")
     ap.add_argument("--n", type=int, default=None, help="override the grid side")
     ap.add_argument("--stages", type=int, default=None, help="override s")
@@ -459,6 +523,8 @@ def main():
     W = args.warmup
     wl = (problem, n, family, s, dt, K, nu)
     dof = n * n * (2 if problem == "vsf" else 1)
+    dflt = WORKLOADS[args.workload]
+    default_shape = (n, s, dt) == (dflt[1], dflt[3], dflt[4])
 
     wall, lat, stats, _, _ = run_job(torch, irk, inputs, wl, K, W, prec_fp32=1)
     value = dof * s * K / wall
@@ -501,7 +567,7 @@ def main():
         achieved = rep["bytes"] / (rep["ms"] * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": top["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(top["name"]) if args.workload == "nldiff512-gauss3" else None,
+                           "traffic": measured_traffic(args.workload, top["name"]) if default_shape else None,
                            "avg_us": 1e3 * rep["ms"], "avg_bytes": rep["bytes"],
                            "timing": "back-to-back replays of the kernel's most recent launches of the profiled "
                                      "pass (20 rounds) between HIP events on its stream",
@@ -513,7 +579,7 @@ def main():
         out["step_traffic"] = {"algorithmic_MB_per_step": step_bytes / 1e6,
                                "GB_per_s_over_step": step_bytes / (wall / K) / 1e9,
                                "frac_of_peak": step_bytes / (wall / K) / 1e9 / HBM_PEAK_GBS,
-                               "kernel_ms_per_step": tot / kp}
+                               "kernel_ms_per_step_summed_over_concurrent_lanes": tot / kp}
         out["kernel_share"] = [{"kernel": r["name"], "share": r["ms"] / tot, "launches": r["launches"],
                                 "avg_us": 1e3 * r["ms"] / max(1, r["launches"]),
                                 "GB/s": r["bytes"] / max(1e-12, r["ms"] * 1e-3) / 1e9} for r in prof[:8]]
@@ -526,7 +592,11 @@ def main():
                                      args.load, args.serve_seed, fp64=not args.no_fp64)
     if not args.no_cpu_baseline:
         ns = args.cpu_sample_n or {"vsf1024-radau3": 32, "nldiff1024-gauss5": 96}.get(args.workload, 128)
-        out["cpu_baseline"] = cpu_baseline(wl, ns)
+        cb = cpu_baseline(wl, ns)
+        g = gpu_same_size(torch, irk, wl, ns)
+        cb["gpu_same_sample"] = g
+        cb["gpu_over_oracle_same_sample"] = cb["s_per_step"] / g["s_per_step"]
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,15 @@ struct LaneLayout {
     size_t ldv;                         // Krylov vector length (block width * field)
 };
 
+// A side stream of a vorticity-streamfunction pair block: the first
+// streamfunction row's Poisson V-cycle runs there, concurrently with the
+// second row's vorticity V-cycle (which needs only the first vorticity
+// component); its own reduction scratch, device scalars and level arrays.
+struct AuxLayout {
+    bool used = false;
+    LaneLayout lay;
+};
+
 // Everything irk_create decides before touching the device.
 struct Plan {
     irk_operator op;
@@ -77,6 +86,8 @@ struct Plan {
     int m = 30;                         // restart length
     LevelGeom lg;
     int l0 = 0;                         // first level of the one-work-group sub-cycle
+    int fdm_level = 0;                  // VSF: level of the exact Poisson solve (0: none)
+    size_t off_fdm_Q = 0, off_fdm_lam = 0;
     size_t tsz = 4;                     // bytes per V-cycle scalar
     int nhier = 0;                      // distinct linearization stages
     int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
@@ -90,6 +101,7 @@ struct Plan {
     size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
     LaneLayout lane[IRK_MAX_STAGES];
+    AuxLayout aux[IRK_MAX_STAGES];
     // SDIRK: the method's own tableau; the machinery above runs one stage at
     // a time as a 1-stage method (s = 1, A = [gamma], c = [c_i])
     int sd_s = 0;
@@ -165,6 +177,16 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
             }
         }
     }
+    // VSF streamfunction rows: the Poisson V-cycles stop at the first level
+    // below the finest one of side <= IRK_FDM_MAX (at or above the
+    // sub-cycle's) and solve it exactly
+    P->fdm_level = 0;
+    if (o.kind == IRK_OP_VSF_2D)
+        for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
+            if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] == P->lg.ny[l]) {
+                P->fdm_level = l;
+                break;
+            }
 
     // linearization of every transformed row (Section 3.2, written in the
     // eigenbasis with d_rq,k = (T^{-1})_rk T_kq): Newton-like (0) the last
@@ -214,6 +236,11 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->off_part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
     P->off_dv = take(512 * f64);
     P->off_tab = take((size_t)2 * (o.nx + o.ny) * f64);
+    if (P->fdm_level > 0) {
+        const size_t n = P->lg.nx[P->fdm_level];
+        P->off_fdm_Q = take(n * n * P->tsz);
+        P->off_fdm_lam = take(n * P->tsz);
+    }
     for (int hq = 0; hq < P->nhier; ++hq)
         for (int l = 0; l < P->lg.nlev; ++l)
             P->off_coef[hq][l] = take((size_t)P->lg.nx[l] * P->lg.ny[l] * P->tsz);
@@ -228,6 +255,17 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         for (int l = 0; l < P->lg.nlev; ++l) {
             const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
             for (int q = 0; q < 4; ++q) ln.lev[l][q] = take(n * P->tsz);
+        }
+        AuxLayout &ax = P->aux[b];
+        ax.used = o.kind == IRK_OP_VSF_2D && P->eb.width[b] == 2 && family != IRK_SDIRK;
+        if (ax.used) {
+            ax.lay.ldv = ln.ldv;
+            ax.lay.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
+            ax.lay.dv = take(512 * f64);
+            for (int l = 0; l < P->lg.nlev; ++l) {
+                const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
+                for (int q = 0; q < 4; ++q) ax.lay.lev[l][q] = take(n * P->tsz);
+            }
         }
     }
     if (family == IRK_SDIRK) {
@@ -256,6 +294,7 @@ enum {
     DV_H1 = 64,        // first Gram-Schmidt coefficients (<= 64)
     DV_H2 = 160,       // second pass (<= 64) and the norm
     DV_Y = 256,        // least-squares solution (<= 64)
+    DV_GMAX = 480,     // Newton level, VSF: largest one-cell streamfunction difference per stage (s)
 };
 #define PIN_READ 0          // per-lane pinned staging: readbacks
 #define PIN_WRITE 512       // per-lane pinned staging: uploads
@@ -271,6 +310,11 @@ struct Lane {
     double *pin = nullptr;
     size_t ldv = 0;
     const LaneLayout *lay = nullptr;
+    // vorticity-streamfunction pairs: the side lane of the first
+    // streamfunction row (fork after the first vorticity V-cycle, join before
+    // the block operator reads z)
+    Lane *aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct StepperBase;
@@ -290,6 +334,7 @@ struct irk_ctx {
     void *broker = nullptr;
     bool broker_owned = false;
     Lane lanes[IRK_MAX_STAGES];
+    Lane aux_lanes[IRK_MAX_STAGES];
     int nlanes = 0;
     bool have_stages = false;
     bool have_U = false;                 // U holds the stage values of some K
@@ -304,6 +349,11 @@ struct irk_ctx {
     double lmax = 2.0, lmin = 0.5;
     irk_stats *st = nullptr;
     double dt = 0;
+    // VSF: per hierarchy, a bound on the one-cell differences of the
+    // streamfunction it linearizes at (valid for the current Newton
+    // iteration's hierarchies); decides where vorticity V-cycles stop
+    bool hier_g_valid = false;
+    double hier_g[IRK_MAX_STAGES];
     // optional per-kernel timing with HIP events (irk_profile_enable)
     bool prof = false;
     std::vector<std::string> prof_names;
@@ -427,6 +477,13 @@ static irk_status lane_write(Lane &ln, double *dev, const double *host, int coun
 template <class T>
 struct VcJob {
     int opk = 0, l0 = 0, deg = 3;
+    // how the cycle's coarsest level l0 is solved: the one-work-group
+    // sub-cycle (levels l0 and below), D Jacobi sweeps (a diagonally dominant
+    // level operator), or exactly (periodic Poisson, fast diagonalization)
+    enum Coarse { SUBCYCLE, JACOBI, FDM } coarse = SUBCYCLE;
+    const T *fdm_Q = nullptr, *fdm_lam = nullptr, *fdm_b = nullptr;
+    T *fdm_x = nullptr;
+    double fdm_dt = 0;
     hipStream_t st = nullptr;
     MgLevelArgs<T> lev[IRK_MAX_LEVELS];
     MgSubArgs<T> sub;
@@ -435,13 +492,40 @@ struct VcJob {
     double by_down[IRK_MAX_LEVELS], by_up[IRK_MAX_LEVELS], by_sub = 0;   // algorithmic bytes
 };
 
+// Where a vorticity V-cycle may stop: the first level l >= 1 (above the
+// sub-cycle's) whose operator A = sigma - dt (J_A(psi, .) + nu Lap) is
+// diagonally dominant with Gershgorin ratio rho_l = sum_q |a_q| / a_c <= 1/4,
+// so that D Jacobi sweeps there reduce its error by rho_l^D in the max norm.
+// Bound: the advective coefficients of Arakawa's Jacobian are 12 differences
+// of psi between points two cells apart (Manhattan) over 12 h^2, and a
+// one-cell difference on level l is at most 2^l times the finest level's
+// largest one, g (restriction averages with non-negative weights of sum 1):
+// sum_q |a_q| <= dt (2 g / (h_0^2 2^l) + 4 nu / h_l^2),
+// a_c = sigma + 4 dt nu / h_l^2.  Returns 0 (the full cycle) otherwise.
+static int vorticity_coarsest(const irk_ctx *c, int opk, double sigma, double dt, int hier) {
+    const Plan &P = c->P;
+    if (opk != MG_VSF_OMEGA || hier < 0 || !c->hier_g_valid || c->broker || !(sigma > 0)) return 0;
+    const double h0 = P.op.length / P.op.nx, g = c->hier_g[hier];
+    for (int l = 1; l < P.l0; ++l) {
+        const double hl = h0 * (double)(1 << l);
+        const double visc = 4.0 * dt * P.op.nu / (hl * hl);
+        const double adv = dt * 2.0 * g / (h0 * h0 * (double)(1 << l));
+        if (visc + adv <= 0.25 * (sigma + visc)) return l;
+    }
+    return 0;
+}
+
 template <class T>
 static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int hier, const MgIn &in,
                        const MgOut &out, VcJob<T> *J) {
     const Plan &P = c->P;
-    const int L = P.lg.nlev, l0 = P.l0, deg = P.opt.cheb_degree;
+    const int L = P.lg.nlev, deg = P.opt.cheb_degree;
     const double nu = P.op.nu;
     const double ts = sizeof(T);
+    const int lc = vorticity_coarsest(c, opk, sigma, dtop, hier);
+    const bool fdm = opk == MG_POISSON && P.fdm_level > 0;
+    const int l0 = lc > 0 ? lc : (fdm ? P.fdm_level : P.l0);
+    J->coarse = lc > 0 ? VcJob<T>::JACOBI : (fdm ? VcJob<T>::FDM : VcJob<T>::SUBCYCLE);
     J->opk = opk;
     J->l0 = l0;
     J->deg = deg;
@@ -449,8 +533,6 @@ static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop,
     J->in = in;
     J->out = out;
     auto hl = [&](int l) { return P.op.length / P.op.nx * (double)(1 << l); };
-    const double hc = hier >= 0 ? 1.0 : 0.0;
-    const double nin = in.v1 ? (in.v2 ? 16.0 : 8.0) : ts;      // bytes per point of the finest b
     for (int l = 0; l < l0; ++l) {
         MgLevelArgs<T> &a = J->lev[l];
         a.nx = P.lg.nx[l];
@@ -471,11 +553,50 @@ static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop,
             a.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
             a.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
         }
-        const double np = (double)a.nx * a.ny, npc = (double)P.lg.nx[l + 1] * P.lg.ny[l + 1];
-        // down: reads coef, b; writes x and the coarse right-hand side
-        J->by_down[l] = np * (hc * ts + (l == 0 ? nin : ts) + ts) + npc * ts;
-        // up: reads coef, b, x, coarse correction; writes x (float64 z on level 0)
-        J->by_up[l] = np * (hc * ts + (l == 0 ? nin : ts) + ts + (l == 0 && out.z ? 8.0 : ts)) + npc * ts;
+        const double np = (double)a.nx * a.ny;
+        // algorithmic bytes: the unfused per-level traffic of a 2-D V-cycle
+        // (every field read or written once per sweep): a Chebyshev sweep
+        // moves 6 fields, residual + full-weighting restriction 3.25,
+        // prolongation + correction 2.25, so 12 deg + 5.5 fields per level
+        // (41.5 at degree 3); the down launch carries the pre-smoothing and
+        // the restriction, the up launch the rest.  The fused kernels move
+        // far less (temporal blocking keeps iterates in registers and LDS).
+        J->by_down[l] = np * ts * (6.0 * deg + 3.25);
+        J->by_up[l] = np * ts * (6.0 * deg + 2.25);
+    }
+    if (J->coarse == VcJob<T>::FDM) {
+        J->fdm_Q = reinterpret_cast<const T *>(c->ws + P.off_fdm_Q);
+        J->fdm_lam = reinterpret_cast<const T *>(c->ws + P.off_fdm_lam);
+        J->fdm_b = c->lev<T>(ln, l0, 3);
+        J->fdm_x = c->lev<T>(ln, l0, 0);
+        J->fdm_dt = dtop;
+        const double n = P.lg.nx[l0];
+        J->by_sub = (3.0 * n * n + n) * ts;            // reads b, Q, lam; writes x
+        return;
+    }
+    if (J->coarse == VcJob<T>::JACOBI) {
+        // the coarsest level: D Jacobi sweeps from zero (the down kernel
+        // without its residual and restriction), result in buffer 0
+        MgLevelArgs<T> &a = J->lev[l0];
+        a.nx = P.lg.nx[l0];
+        a.ny = P.lg.ny[l0];
+        a.h = (T)hl(l0);
+        a.nu = (T)nu;
+        a.sigma = (T)sigma;
+        a.dt = (T)dtop;
+        a.coef = c->coef<T>(hier, l0);
+        a.b = c->lev<T>(ln, l0, 3);
+        a.x = c->lev<T>(ln, l0, 0);
+        a.xout = nullptr;
+        a.bc = nullptr;
+        a.xc = nullptr;
+        for (int k = 0; k < IRK_MAX_CHEB; ++k) {
+            a.cd[k] = T(0);
+            a.cr[k] = (T)(k < deg ? 1.0 : 0.0);
+        }
+        J->by_down[l0] = (double)a.nx * a.ny * ts * 6.0 * deg;
+        J->by_sub = 0;
+        return;
     }
     MgSubArgs<T> &sa = J->sub;
     sa.nlev = L - l0;
@@ -499,8 +620,7 @@ static void make_vcjob(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop,
         sa.cd[k] = (T)(k < deg ? c->cheb_cd[k] : 0.0);
         sa.cr[k] = (T)(k < deg ? c->cheb_cr[k] : 0.0);
     }
-    const double np0 = (double)sa.nx[0] * sa.ny[0];
-    J->by_sub = np_all * hc * ts + np0 * ((l0 == 0 ? nin : ts) + (l0 == 0 && out.z ? 8.0 : ts));
+    J->by_sub = np_all * ts * (12.0 * deg + 5.5);
 }
 
 // one job, launched on its lane's stream
@@ -513,7 +633,14 @@ static void run_vcjob(irk_ctx *c, const VcJob<T> &J) {
         const MgIn in = l == 0 ? J.in : MgIn{};
         PROF(c, st, kn<T>("k_mg_down", opk), J.by_down[l], 1, launch_mg_down<T>(st, opk, a, in, deg));
     }
-    {
+    if (J.coarse == VcJob<T>::JACOBI) {
+        const MgLevelArgs<T> a = J.lev[l0];
+        PROF(c, st, kn<T>("k_mg_down", opk), J.by_down[l0], 1, launch_mg_down<T>(st, opk, a, MgIn{}, deg));
+    } else if (J.coarse == VcJob<T>::FDM) {
+        const int n = c->P.lg.nx[l0];
+        PROF(c, st, kn<T>("k_poisson_fdm"), J.by_sub, 1,
+             launch_poisson_fdm<T>(st, n, (T)J.fdm_dt, J.fdm_Q, J.fdm_lam, J.fdm_b, J.fdm_x));
+    } else {
         const MgSubArgs<T> sa = J.sub;
         const MgIn in = l0 == 0 ? J.in : MgIn{};
         const MgOut out = l0 == 0 ? J.out : MgOut{};
@@ -644,7 +771,18 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
     int nvc = 0;
     prec_component<T>(c, ln, z, v, 1.0, nullptr, 0.0, eta, ha);
     ++nvc;
-    if (vsf) { prec_psi<T>(c, ln, z + npts, v + npts, z); ++nvc; }
+    // the first streamfunction row needs z1 only; with a side lane it runs
+    // there while the second row's vorticity V-cycle runs here
+    const bool fork = vsf && ln.aux && eb.width[blk] == 2;
+    if (fork) {
+        (void)hipEventRecord(ln.ev_fork, ln.stream);
+        (void)hipStreamWaitEvent(ln.aux->stream, ln.ev_fork, 0);
+        prec_psi<T>(c, *ln.aux, z + npts, v + npts, z);
+        ++nvc;
+    } else if (vsf) {
+        prec_psi<T>(c, ln, z + npts, v + npts, z);
+        ++nvc;
+    }
     if (eb.width[blk] == 2) {
         const double beta = eb.beta[blk];
         const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eta;
@@ -662,6 +800,10 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
         }
         ++nvc;
         if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf); ++nvc; }
+    }
+    if (fork) {
+        (void)hipEventRecord(ln.ev_join, ln.aux->stream);
+        (void)hipStreamWaitEvent(ln.stream, ln.ev_join, 0);
     }
     return nvc;
 }
@@ -1189,6 +1331,14 @@ struct Stepper : StepperBase {
         return true;
     }
 
+    // VSF: the stages' largest one-cell streamfunction differences of the
+    // latest residual evaluation, read back with its norms
+    hipError_t read_gmax() {
+        if (c->P.op.kind != IRK_OP_VSF_2D) return hipSuccess;
+        return hipMemcpyAsync(c->pinned + DV_GMAX, c->dv + DV_GMAX, c->P.s * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream);
+    }
+
     // stage values and residual of the current K; its norms go to dv[slot],
     // and (readback) dv[0..2] is copied to the host with an event behind it
     irk_status issue_residual(int slot = DV_RES, bool readback = true) {
@@ -1205,9 +1355,10 @@ struct Stepper : StepperBase {
         PROF(c, c->stream, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
              8.0 * nf * 3 * s, 1,
              launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + slot,
-                             nullptr));
+                             c->dv + DV_GMAX));
         if (!readback) return IRK_OK;
         HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(read_gmax());
         HIP_TRY(hipEventRecord(c->ev_res, c->stream));
         phase = RES_WAIT;
         return IRK_OK;
@@ -1241,6 +1392,7 @@ struct Stepper : StepperBase {
         }
         HIP_TRY(hipMemcpyAsync(c->pinned + DV_CAND, c->dv + DV_CAND, 2 * ncand * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(read_gmax());        // of the last candidate evaluated
         HIP_TRY(hipEventRecord(c->ev_res, c->stream));
         start = START_CANDIDATES;
         phase = RES_WAIT;
@@ -1356,6 +1508,17 @@ struct Stepper : StepperBase {
         }
         prev = res;
         if (res > 1e8 * std::max(res0, 1e-300) || it >= P.opt.max_newton) return fail(IRK_E_NOCONV);
+        // VSF: per hierarchy a bound on its streamfunction's one-cell
+        // differences (the stage's, or the weighted sum's), which lets the
+        // vorticity V-cycles stop at a diagonally dominant level
+        c->hier_g_valid = P.op.kind == IRK_OP_VSF_2D;
+        if (c->hier_g_valid)
+            for (int h = 0; h < P.nhier; ++h) {
+                double g = 0.0;
+                for (int k = 0; k < P.s; ++k) g += std::fabs(P.hier_w[h][k]) * c->pinned[DV_GMAX + k];
+                c->hier_g[h] = g;
+                if (!std::isfinite(g)) c->hier_g_valid = false;
+            }
         setup_hierarchies<T>(c);
         if (hipEventRecord(c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
         active = c->nlanes;
@@ -1625,7 +1788,14 @@ static void release(irk_ctx *c) {
         if (ln.ev) (void)hipEventDestroy(ln.ev);
         if (ln.done) (void)hipEventDestroy(ln.done);
         if (ln.ev_prec) (void)hipEventDestroy(ln.ev_prec);
+        if (ln.ev_fork) (void)hipEventDestroy(ln.ev_fork);
+        if (ln.ev_join) (void)hipEventDestroy(ln.ev_join);
         if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        Lane &ax = c->aux_lanes[b];
+        if (ax.stream) {
+            (void)hipStreamSynchronize(ax.stream);
+            (void)hipStreamDestroy(ax.stream);
+        }
     }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
@@ -1634,6 +1804,50 @@ static void release(irk_ctx *c) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
+}
+
+// Real orthonormal Fourier basis of the periodic n-point second difference
+// on the exact-solve level (columns: the constant, cos and sin pairs of
+// modes 1 .. (n-1)/2, and for even n the alternating mode) and its
+// eigenvalues 4 sin^2(pi m / n) / h^2, in the V-cycle precision.
+static irk_status upload_fdm_basis(irk_ctx *c) {
+    const Plan &P = c->P;
+    const int n = P.lg.nx[P.fdm_level];
+    const double h = P.op.length / P.op.nx * (double)(1 << P.fdm_level);
+    const double pi = 3.14159265358979323846;
+    std::vector<double> Q((size_t)n * n), lam(n);
+    int col = 0;
+    auto put = [&](int m, int kind) {          // kind 0: cos (or constant), 1: sin
+        const bool single = (m == 0) || (2 * m == n);
+        const double sc = single ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+        for (int j = 0; j < n; ++j) {
+            const double a = 2.0 * pi * m * j / n;
+            Q[(size_t)j * n + col] = sc * (kind == 0 ? std::cos(a) : std::sin(a));
+        }
+        const double sv = std::sin(pi * m / n);
+        lam[col] = 4.0 * sv * sv / (h * h);
+        ++col;
+    };
+    put(0, 0);
+    for (int m = 1; 2 * m < n; ++m) {
+        put(m, 0);
+        put(m, 1);
+    }
+    if (n % 2 == 0) put(n / 2, 0);
+    if (col != n) return IRK_E_ARG;
+    lam[0] = 0.0;
+    void *dQ = c->ws + P.off_fdm_Q, *dl = c->ws + P.off_fdm_lam;
+    if (P.tsz == sizeof(float)) {
+        std::vector<float> qf(Q.begin(), Q.end()), lf(lam.begin(), lam.end());
+        HIP_TRY(hipMemcpyAsync(dQ, qf.data(), qf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(dl, lf.data(), lf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(dQ, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(dl, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return IRK_OK;
 }
 
 extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,
@@ -1697,6 +1911,21 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
             release(c);
             return IRK_E_DEVICE;
         }
+        if (P.aux[b].used) {
+            Lane &ax = c->aux_lanes[b];
+            ax.blk = b;
+            ax.lay = &c->P.aux[b].lay;
+            ax.ldv = ln.ldv;
+            ax.part = (double *)(c->ws + ax.lay->part);
+            ax.dv = (double *)(c->ws + ax.lay->dv);
+            if (hipStreamCreateWithFlags(&ax.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ln.ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ln.ev_join, hipEventDisableTiming) != hipSuccess) {
+                release(c);
+                return IRK_E_DEVICE;
+            }
+            ln.aux = &ax;
+        }
     }
     // a private broker batches the V-cycles of this context's blocks
     // (Newton-like (3) pairs apply an operator between their two V-cycles:
@@ -1745,6 +1974,10 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     if (hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
+        release(c);
+        return IRK_E_DEVICE;
+    }
+    if (P.fdm_level > 0 && upload_fdm_basis(c) != IRK_OK) {
         release(c);
         return IRK_E_DEVICE;
     }
@@ -1918,7 +2151,8 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
         launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS, nullptr);
     // identity transform: Tinv = I gives F itself
     for (int i = 0; i < s * s; ++i) C.Tinv[i] = (i / s == i % s) ? 1.0 : 0.0;
-    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES, nullptr);
+    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+                    c->dv + DV_GMAX);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_stages = false;

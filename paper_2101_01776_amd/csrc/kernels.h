@@ -12,8 +12,10 @@ enum MgOp { MG_NLDIFF = 0, MG_BURGERS = 1, MG_VSF_OMEGA = 2, MG_POISSON = 3 };
 
 void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, double *K, const double *Y, double *U,
                        const StageCoefs &C, double dt, int fold);
+// out[0] = ||F||^2, out[1] = squared norm of the magnitudes of F's terms;
+// VSF also gmax[0..s): each stage's largest one-cell streamfunction difference
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                     const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr);
+                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax);
 void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
                      double cos_tn);
 // Kx_i = sum_j W.A[i][j] K_j (s stage fields of length nf; Kx must not alias K)

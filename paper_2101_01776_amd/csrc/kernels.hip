@@ -54,6 +54,21 @@ __device__ __forceinline__ double block_sum(double v, double *sh /* >= 4 */) {
     return r;
 }
 
+// max over the 256 threads of a work-group; result valid in thread 0
+__device__ __forceinline__ double block_max(double v, double *sh /* >= 4 */) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
 // Each work-group stores its `nv` partial sums; k_reduce_partials (launched
 // right after on the same stream) adds them in a fixed order.  The kernel
 // boundary makes the partials visible: no device-scope fences, which on a
@@ -69,14 +84,24 @@ __device__ void finish_partials(const double *myvals, int nv, double *partials, 
 #define DOT_CHUNK 16                  // basis vectors per dot-product launch
 #define RED_NV (DOT_CHUNK + 1)        // at most this many values per partial (16 dots and a norm)
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 // out[k] = sum over work-groups b of partials[b * nv + k] (nv <= RED_NV) in
 // a fixed order: thread t adds b = t, t + 256, ...; each wave reduces by
 // shuffles; then waves 0..3 in order.  Every load of a thread is issued
-// before its first add (the values sit in another XCD's L2 or in HBM).
+// before its first add (the values sit in another XCD's L2 or in HBM).  The
+// last nmax values of a partial are maxima of non-negative values instead:
+// they are reduced by max and written to out2[0..nmax).
 __global__ void __launch_bounds__(256) k_reduce_partials(const double *__restrict__ partials, int nb, int nv,
-                                                         double *__restrict__ out) {
+                                                         int nmax, double *__restrict__ out,
+                                                         double *__restrict__ out2) {
     __shared__ double sh[4 * RED_NV];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nsum = nv - nmax;
     double a[RED_NV];
 #pragma unroll
     for (int k = 0; k < RED_NV; ++k) a[k] = 0.0;
@@ -84,19 +109,22 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double *__restric
         const double *p = partials + (size_t)b * nv;
 #pragma unroll
         for (int k = 0; k < RED_NV; ++k)
-            if (k < nv) a[k] += p[k];
+            if (k < nv) a[k] = k < nsum ? a[k] + p[k] : fmax(a[k], p[k]);
     }
 #pragma unroll
     for (int k = 0; k < RED_NV; ++k)
         if (k < nv) {
-            const double v = wave_sum(a[k]);
+            const double v = k < nsum ? wave_sum(a[k]) : wave_max(a[k]);
             if (lane == 0) sh[wid * RED_NV + k] = v;
         }
     __syncthreads();
-    if ((int)threadIdx.x < nv) {
+    const int k = (int)threadIdx.x;
+    if (k < nv) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w * RED_NV + threadIdx.x];
-        out[threadIdx.x] = t;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            t = k < nsum ? t + sh[w * RED_NV + k] : fmax(t, sh[w * RED_NV + k]);
+        if (k < nsum) out[k] = t;
+        else out2[k - nsum] = t;
     }
 }
 
@@ -196,17 +224,24 @@ __device__ __forceinline__ double mms_forcing(const DeviceProblem &P, int i, int
 // Residual F_i = M k_i - N(U_i), transformed residual and ||F||^2.
 // Layout: U, K, Fh are [S][nvar][npts]; means (VSF) = [S][2] (omega, psi).
 // ------------------------------------------------------------------------
+// VSF: also the largest one-cell difference of every stage's streamfunction,
+// max(|Psi(i+1,j) - Psi(i,j)|, |Psi(i,j+1) - Psi(i,j)|) (it bounds the
+// advective coefficients of the vorticity operator on every multigrid level),
+// as S more per-work-group values reduced by max.
 template <int S, int OP>
 __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const double *__restrict__ U,
                                                      const double *__restrict__ K, double *__restrict__ Fh,
                                                      StageCoefs C, const double *__restrict__ means,
-                                                     double *partials, double *out, unsigned *counter) {
+                                                     double *partials) {
     const int nx = P.g.nx, ny = P.g.ny;
     const size_t npts = (size_t)nx * ny;
     constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
     const size_t nf = NV * npts;
     const double h = P.g.h, inv_h2 = 1.0 / (h * h);
     double sumsq = 0.0, abssq = 0.0;
+    double gmax[S];
+#pragma unroll
+    for (int st = 0; st < S; ++st) gmax[st] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
         const int i = (int)(p % nx), j = (int)(p / nx);
@@ -252,6 +287,7 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
                 const double a1 = (fabs(ps[1][2]) + fabs(ps[1][0]) + fabs(ps[2][1]) + fabs(ps[0][1]) + 4.0 * fabs(ps[1][1])) * inv_h2 +
                                   fabs(w[1][1]) + fabs(means[2 * st]) + fabs(means[2 * st + 1]);
                 abssq += a0 * a0 + a1 * a1;
+                gmax[st] = fmax(gmax[st], fmax(fabs(ps[1][2] - ps[1][1]), fabs(ps[2][1] - ps[1][1])));
             }
         }
 #pragma unroll
@@ -268,10 +304,15 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
         }
     }
     __shared__ double sh[8];
-    double tot[2];
+    double tot[2 + S];
     tot[0] = block_sum(sumsq, sh);
     tot[1] = block_sum(abssq, sh);
-    finish_partials(tot, 2, partials, out, counter);
+    constexpr int NVAL = (OP == IRK_OP_VSF_2D) ? 2 + S : 2;
+    if constexpr (OP == IRK_OP_VSF_2D) {
+#pragma unroll
+        for (int st = 0; st < S; ++st) tot[2 + st] = block_max(gmax[st], sh);
+    }
+    finish_partials(tot, NVAL, partials, nullptr, nullptr);
 }
 
 // k_i <- N(u_n, t_n) on differential rows, 0 on algebraic rows (explicit candidate for the
@@ -707,32 +748,36 @@ void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, doubl
     }
 }
 
-static void reduce_partials(hipStream_t st, const double *partials, unsigned nb, int nv, double *out) {
-    k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, out);
+static void reduce_partials(hipStream_t st, const double *partials, unsigned nb, int nv, double *out,
+                            int nmax = 0, double *out2 = nullptr) {
+    k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, nmax, out, out2);
 }
 
 template <int S>
 static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                       const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr) {
+                       const StageCoefs &C, const double *means, double *partials, double *out, double *gmax) {
     const size_t npts = (size_t)P.g.nx * P.g.ny;
     const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
-    if (P.kind == IRK_OP_NLDIFF_2D)
-        k_residual<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
-    else if (P.kind == IRK_OP_BURGERS_1D)
-        k_residual<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
-    else
-        k_residual<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials, out, ctr);
-    reduce_partials(st, partials, g, 2, out);
+    if (P.kind == IRK_OP_NLDIFF_2D) {
+        k_residual<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
+        reduce_partials(st, partials, g, 2, out);
+    } else if (P.kind == IRK_OP_BURGERS_1D) {
+        k_residual<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
+        reduce_partials(st, partials, g, 2, out);
+    } else {
+        k_residual<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
+        reduce_partials(st, partials, g, 2 + S, out, S, gmax);
+    }
 }
 
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                     const StageCoefs &C, const double *means, double *partials, double *out, unsigned *ctr) {
+                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax) {
     switch (s) {
-        case 1: residual_s<1>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
-        case 2: residual_s<2>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
-        case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
-        case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
-        case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, ctr); break;
+        case 1: residual_s<1>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
+        case 2: residual_s<2>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
+        case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
+        case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
+        case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
     }
 }
 

@@ -99,6 +99,13 @@ void launch_mg_up_batch(hipStream_t st, int opk, const MgLevelArgs<T> *g, const 
 template <class T>
 void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, const MgIn *in, const MgOut *out,
                               int n);
+// Exact solve of the periodic Poisson problem -dt Lap_h x = b (mean-free
+// part) on an n x n level (n <= IRK_FDM_MAX) by fast diagonalization: Q is
+// the n x n real orthonormal Fourier basis (row = grid index, column = mode),
+// lam[k] = 4 sin^2(pi m_k / n) / h^2 its eigenvalues of -D2; one work-group.
+#define IRK_FDM_MAX 32
+template <class T>
+void launch_poisson_fdm(hipStream_t st, int n, T dt, const T *Q, const T *lam, const T *b, T *x);
 // LDS bytes of the one-work-group sub-cycle over levels nx[0..nlev-1]
 size_t mg_subcycle_lds_bytes(int opk, int nlev, const int *nx, const int *ny, size_t tsz);
 

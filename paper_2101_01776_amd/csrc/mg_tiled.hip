@@ -323,6 +323,9 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
         xnext = t;
     }
     // write the smoothed iterate on the tile; residual b - A x on R(1)
+    // (not on the coarsest level of a cycle that stops here: bc == nullptr,
+    // the same for the whole work-group)
+    const bool restrict_down = g.bc != nullptr;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int c = wi.q(k), ia = c % W, ib = c / W;
@@ -332,9 +335,10 @@ __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn
             const int gi = i0 + (ia - H), gj = j0 + (ib - hy);
             if (gi < nx && gj < ny) g.x[(size_t)gj * nx + gi] = xv;
         }
-        if (ia >= H - 1 && ia < H + TX + 1 && (!two_d || (ib >= hy - 1 && ib < hy + TY + 1)))
+        if (restrict_down && ia >= H - 1 && ia < H + TX + 1 && (!two_d || (ib >= hy - 1 && ib < hy + TY + 1)))
             xnext[c] = ac[k] * own_jres<T, OPK, W>(a[k], bv[k], xcur, c, xv);
     }
+    if (!restrict_down) return;
     __syncthreads();
     const T *rr = xnext;
     // full-weighting restriction to coarse points whose fine node lies in the tile
@@ -1154,6 +1158,78 @@ void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, co
         }
     }
 }
+
+// ---------------------------------------------------------------------------
+// Exact coarsest-level solve of the periodic 5-point Poisson problem
+// -dt Lap_h x = b (its constant mode dropped: b's mean is ignored and x is
+// mean-free) on an n x n level, n <= IRK_FDM_MAX, by fast diagonalization:
+// -Lap_h = S (x) I + I (x) S with S = Q diag(lam) Q^T the 1-D periodic second
+// difference (Q a real orthonormal Fourier basis), so
+//   x = Q [ (Q^T B Q)_ab / (dt (lam_a + lam_b)) ] Q^T,   (a, b) != (0, 0).
+// One work-group; Q (row stride n + 1 in LDS: both its rows and columns are
+// read conflict-free), the field and one temporary live in LDS; four dense
+// n x n x n products, each output a dot product of length n.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_poisson_fdm(int n, T dt, const T *__restrict__ Q, const T *__restrict__ lam,
+                                                     const T *__restrict__ b, T *__restrict__ x) {
+    extern __shared__ unsigned char smem_raw[];
+    T *Qs = reinterpret_cast<T *>(smem_raw);      // n x (n + 1)
+    T *Fa = Qs + n * (n + 1);                      // n x n
+    T *Fb = Fa + n * n;                            // n x n
+    __shared__ T ls[IRK_FDM_MAX];
+    const int nn = n * n, q1 = n + 1;
+    for (int q = threadIdx.x; q < nn; q += blockDim.x) {
+        const int r = q / n, c = q - r * n;
+        Qs[r * q1 + c] = Q[q];
+        Fa[q] = b[q];
+    }
+    if ((int)threadIdx.x < n) ls[threadIdx.x] = lam[threadIdx.x];
+    __syncthreads();
+    // Fb = B Q
+    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
+        const int r = o / n, c = o - r * n;
+        T acc = 0;
+        for (int k = 0; k < n; ++k) acc += Fa[r * n + k] * Qs[k * q1 + c];
+        Fb[o] = acc;
+    }
+    __syncthreads();
+    // Fa = (Q^T Fb) ./ (dt (lam_a + lam_b)), the constant mode dropped
+    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
+        const int r = o / n, c = o - r * n;
+        T acc = 0;
+        for (int k = 0; k < n; ++k) acc += Qs[k * q1 + r] * Fb[k * n + c];
+        const T den = dt * (ls[r] + ls[c]);
+        Fa[o] = (r == 0 && c == 0) ? T(0) : acc / den;
+    }
+    __syncthreads();
+    // Fb = Fa Q^T
+    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
+        const int r = o / n, c = o - r * n;
+        T acc = 0;
+        for (int k = 0; k < n; ++k) acc += Fa[r * n + k] * Qs[c * q1 + k];
+        Fb[o] = acc;
+    }
+    __syncthreads();
+    // x = Q Fb
+    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
+        const int r = o / n, c = o - r * n;
+        T acc = 0;
+        for (int k = 0; k < n; ++k) acc += Qs[r * q1 + k] * Fb[k * n + c];
+        x[o] = acc;
+    }
+}
+
+template <class T>
+void launch_poisson_fdm(hipStream_t st, int n, T dt, const T *Q, const T *lam, const T *b, T *x) {
+    const size_t shm = (size_t)(n * (n + 1) + 2 * n * n) * sizeof(T);
+    k_poisson_fdm<T><<<1, 256, shm, st>>>(n, dt, Q, lam, b, x);
+}
+
+template void launch_poisson_fdm<float>(hipStream_t, int, float, const float *, const float *, const float *,
+                                        float *);
+template void launch_poisson_fdm<double>(hipStream_t, int, double, const double *, const double *,
+                                         const double *, double *);
 
 template void launch_mg_down_batch<float>(hipStream_t, int, const MgLevelArgs<float> *, const MgIn *, int, int);
 template void launch_mg_down_batch<double>(hipStream_t, int, const MgLevelArgs<double> *, const MgIn *, int, int);

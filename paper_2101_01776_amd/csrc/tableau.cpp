@@ -32,32 +32,41 @@ static ld binom(int n, int k) {
     return r;
 }
 
+// A polynomial of degree < IRK_MAX_STAGES + 2 (ascending coefficients) or a
+// short list of nodes, in a fixed-size array: the tableau construction works
+// without heap memory.
+struct Poly {
+    ld c[IRK_MAX_STAGES + 2];
+    int n = 0;                          // number of coefficients (entries)
+    void push(ld v) { c[n++] = v; }
+};
+
 // ascending coefficients of P_n(2x - 1) = sum_k (-1)^(n+k) C(n,k) C(n+k,k) x^k
-static std::vector<ld> shifted_legendre(int n) {
-    std::vector<ld> c(n + 1);
+static Poly shifted_legendre(int n) {
+    Poly c;
     for (int k = 0; k <= n; ++k)
-        c[k] = (((n + k) % 2) ? -1.0L : 1.0L) * binom(n, k) * binom(n + k, k);
+        c.push((((n + k) % 2) ? -1.0L : 1.0L) * binom(n, k) * binom(n + k, k));
     return c;
 }
 
-static ld horner(const std::vector<ld> &c, ld x, ld *deriv) {
+static ld horner(const Poly &c, ld x, ld *deriv) {
     ld p = 0, dp = 0;
-    for (int k = (int)c.size() - 1; k >= 0; --k) {
+    for (int k = c.n - 1; k >= 0; --k) {
         dp = dp * x + p;
-        p = p * x + c[k];
+        p = p * x + c.c[k];
     }
     if (deriv) *deriv = dp;
     return p;
 }
 
 // real roots of c in [0, 1] (all simple), ascending
-static std::vector<ld> roots_unit_interval(const std::vector<ld> &c, int expect) {
-    std::vector<ld> r;
+static Poly roots_unit_interval(const Poly &c, int expect) {
+    Poly r;
     const int G = 20000;
     ld xa = 0, fa = horner(c, 0, nullptr);
-    for (int g = 1; g <= G && (int)r.size() < expect; ++g) {
+    for (int g = 1; g <= G && r.n < expect; ++g) {
         ld xb = (ld)g / G, fb = horner(c, xb, nullptr);
-        if (fb == 0) { r.push_back(xb); xa = xb; fa = fb; continue; }
+        if (fb == 0) { r.push(xb); xa = xb; fa = fb; continue; }
         if ((fa < 0) != (fb < 0) && fa != 0) {
             ld lo = xa, hi = xb, flo = fa;
             for (int it = 0; it < 200; ++it) {          // bisection
@@ -69,30 +78,34 @@ static std::vector<ld> roots_unit_interval(const std::vector<ld> &c, int expect)
                 ld d, f = horner(c, x, &d);
                 if (d != 0) x -= f / d;
             }
-            r.push_back(x);
+            r.push(x);
         }
         xa = xb; fa = fb;
     }
     return r;
 }
 
-static std::vector<ld> lagrange(const std::vector<ld> &c, int j) {
-    std::vector<ld> p(1, 1.0L);
+// Lagrange basis polynomial l_j on the nodes c
+static Poly lagrange(const Poly &c, int j) {
+    Poly p;
+    p.push(1.0L);
     ld den = 1;
-    for (size_t m = 0; m < c.size(); ++m) {
-        if ((int)m == j) continue;
-        std::vector<ld> q(p.size() + 1, 0.0L);
-        for (size_t k = 0; k < p.size(); ++k) { q[k] -= p[k] * c[m]; q[k + 1] += p[k]; }
-        p.swap(q);
-        den *= (c[j] - c[m]);
+    for (int m = 0; m < c.n; ++m) {
+        if (m == j) continue;
+        Poly q;
+        q.n = p.n + 1;
+        for (int k = 0; k < q.n; ++k) q.c[k] = 0.0L;
+        for (int k = 0; k < p.n; ++k) { q.c[k] -= p.c[k] * c.c[m]; q.c[k + 1] += p.c[k]; }
+        p = q;
+        den *= (c.c[j] - c.c[m]);
     }
-    for (auto &v : p) v /= den;
+    for (int k = 0; k < p.n; ++k) p.c[k] /= den;
     return p;
 }
 
-static ld integrate0(const std::vector<ld> &p, ld x) {
+static ld integrate0(const Poly &p, ld x) {
     ld s = 0, xp = x;
-    for (size_t k = 0; k < p.size(); ++k) { s += p[k] * xp / (ld)(k + 1); xp *= x; }
+    for (int k = 0; k < p.n; ++k) { s += p.c[k] * xp / (ld)(k + 1); xp *= x; }
     return s;
 }
 
@@ -139,42 +152,44 @@ static bool sdirk_tableau(int s, ld *A, ld *b, ld *c) {
 bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
     if (s < 1 || s > IRK_MAX_STAGES) return false;
     if (family == IRK_SDIRK) return sdirk_tableau(s, A, b, c);
-    std::vector<ld> nodes;
+    Poly nodes;
     if (family == IRK_GAUSS) {
         nodes = roots_unit_interval(shifted_legendre(s), s);
     } else if (family == IRK_RADAU_IIA) {
         if (s == 1) {
-            nodes.push_back(1.0L);
+            nodes.push(1.0L);
         } else {
-            std::vector<ld> p = shifted_legendre(s), q = shifted_legendre(s - 1);
-            for (size_t k = 0; k < q.size(); ++k) p[k] -= q[k];
+            Poly p = shifted_legendre(s), q = shifted_legendre(s - 1);
+            for (int k = 0; k < q.n; ++k) p.c[k] -= q.c[k];
             // deflate the root at x = 1: divide by (x - 1) (synthetic division)
-            int deg = s;
-            std::vector<ld> d(deg);
-            ld carry = p[deg];
-            for (int k = deg - 1; k >= 0; --k) { d[k] = carry; carry = p[k] + carry; }
+            const int deg = s;
+            Poly d;
+            d.n = deg;
+            ld carry = p.c[deg];
+            for (int k = deg - 1; k >= 0; --k) { d.c[k] = carry; carry = p.c[k] + carry; }
             nodes = roots_unit_interval(d, s - 1);
-            nodes.push_back(1.0L);
+            nodes.push(1.0L);
         }
     } else if (family == IRK_LOBATTO_IIIC) {
         // nodes 0, the roots of d/dx P_{s-1}(2x-1), 1
         if (s < 2) return false;
-        nodes.push_back(0.0L);
+        nodes.push(0.0L);
         if (s > 2) {
-            std::vector<ld> q = shifted_legendre(s - 1), dq(s - 1);
-            for (int k = 1; k < s; ++k) dq[k - 1] = k * q[k];
-            std::vector<ld> r = roots_unit_interval(dq, s - 2);
-            nodes.insert(nodes.end(), r.begin(), r.end());
+            Poly q = shifted_legendre(s - 1), dq;
+            dq.n = s - 1;
+            for (int k = 1; k < s; ++k) dq.c[k - 1] = k * q.c[k];
+            const Poly r = roots_unit_interval(dq, s - 2);
+            for (int k = 0; k < r.n; ++k) nodes.push(r.c[k]);
         }
-        nodes.push_back(1.0L);
+        nodes.push(1.0L);
     } else {
         return false;
     }
-    if ((int)nodes.size() != s) return false;
-    std::sort(nodes.begin(), nodes.end());
+    if (nodes.n != s) return false;
+    std::sort(nodes.c, nodes.c + nodes.n);
     for (int j = 0; j < s; ++j) {
-        std::vector<ld> l = lagrange(nodes, j);
-        for (int i = 0; i < s; ++i) A[i * s + j] = integrate0(l, nodes[i]);
+        const Poly l = lagrange(nodes, j);
+        for (int i = 0; i < s; ++i) A[i * s + j] = integrate0(l, nodes.c[i]);
         b[j] = integrate0(l, 1.0L);
     }
     if (family == IRK_LOBATTO_IIIC) {
@@ -184,8 +199,8 @@ bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
         for (int i = 0; i < s; ++i) {
             ld M[IRK_MAX_STAGES][IRK_MAX_STAGES + 1];
             for (int k = 1; k <= m; ++k) {
-                for (int j = 1; j < s; ++j) M[k - 1][j - 1] = powl(nodes[j], (ld)(k - 1));
-                M[k - 1][m] = powl(nodes[i], (ld)k) / k - (k == 1 ? b[0] : 0.0L);
+                for (int j = 1; j < s; ++j) M[k - 1][j - 1] = powl(nodes.c[j], (ld)(k - 1));
+                M[k - 1][m] = powl(nodes.c[i], (ld)k) / k - (k == 1 ? b[0] : 0.0L);
             }
             for (int col = 0; col < m; ++col) {             // Gaussian elimination, partial pivoting
                 int piv = col;
@@ -203,7 +218,7 @@ bool build_tableau_ld(int family, int s, ld *A, ld *b, ld *c) {
             for (int j = 1; j < s; ++j) A[i * s + j] = M[j - 1][m] / M[j - 1][j - 1];
         }
     }
-    for (int i = 0; i < s; ++i) c[i] = nodes[i];
+    for (int i = 0; i < s; ++i) c[i] = nodes.c[i];
     return true;
 }
 

@@ -19,9 +19,11 @@ the 512^2 Gauss-3 system is a few GB):
   dt = 5e-3, the first two steps from t = 0 (shape (2, 512, 512));
 * nldiff256_gauss5: the same problem at 256^2 with Gauss s = 5, dt = 1e-2,
   the first two steps (shape (2, 256, 256));
-* vsf256_radau3: the vorticity-streamfunction DAE at 256^2, nu = 1e-3,
+* vsf128_radau3: the vorticity-streamfunction DAE at 128^2, nu = 1e-3,
   32 seeded Gaussian vortices (seed 0), Radau IIA s = 3, dt = 2e-3, the
-  first two steps (shape (2, 2, 256, 256): omega and psi after each step).
+  first two steps (shape (2, 2, 128, 128): omega and psi after each step);
+* vsf256_radau3: the same at 256^2 (shape (2, 2, 256, 256)); the LU of the
+  coupled omega-psi Newton matrix needs about 34 GB and half an hour a step.
 
 Continued steps hand the previous stages to the oracle's start choice, as the
 library's own continued steps do; the converged stages do not depend on it.
@@ -95,10 +97,18 @@ def case_vsf256_radau3():
     return traj.reshape(2, 2, n, n), its
 
 
+def case_vsf128_radau3():
+    n = 128
+    u0 = inputs.vsf_state0(n, 0, 32)
+    traj, its, _ = chain(pb.VorticityStreamfunction2D(n, 1e-3), "radau", 3, u0, 2e-3, 2)
+    return traj.reshape(2, 2, n, n), its
+
+
 CASES = {
     "burgers256_gauss2": case_burgers256_gauss2,
     "nldiff512_gauss3": case_nldiff512_gauss3,
     "nldiff256_gauss5": case_nldiff256_gauss5,
+    "vsf128_radau3": case_vsf128_radau3,
     "vsf256_radau3": case_vsf256_radau3,
 }
 
