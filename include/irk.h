@@ -253,6 +253,27 @@ irk_status irk_step(irk_ctx *ctx, const double *u_n, double t_n, double dt,
 irk_status irk_eval_residual(irk_ctx *ctx, const double *u_n, double t_n,
                              double dt, const double *K, double *F);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * irk_eval_residual without a context or a caller workspace.  F_i =
+ * M k_i - N(u_n + dt sum_j a_ij k_j, t_n + c_i dt) for the s-stage method of
+ * `family` on operator *op, with the same kernels and the same arithmetic
+ * as irk_eval_residual.  u_n (field layout above), K and F ([s][field]) are
+ * device pointers on the current device; the work is enqueued on hip_stream
+ * (NULL = the null stream) and F is complete when that stream's work is: the
+ * call itself neither waits nor allocates (no hipMalloc, hipFree, memset or
+ * host-staged copy; its host-side tableau arithmetic uses stack memory only),
+ * so it can be captured into a HIP graph.  Its scratch (the stage values,
+ * reduction partials, forcing tables) is one fixed device array of
+ * IRK_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends and shared
+ * by every call on that GPU: calls that overlap on one GPU race.  Errors:
+ * IRK_E_NOMEM when s * field * 8 bytes plus about 140 KiB exceed that size
+ * (e.g. a 1024^2 vorticity-streamfunction field with s = 4), IRK_E_ARG,
+ * IRK_E_UNSUPPORTED for IRK_SDIRK, IRK_E_DEVICE (a launch failed).        */
+#define IRK_NOALLOC_SCRATCH_BYTES (64u << 20)
+irk_status irk_eval_residual_noalloc(irk_family family, int s, const irk_operator *op, const double *u_n,
+                                     double t_n, double dt, const double *K, double *F, void *hip_stream);
+
 /* y = D_b x: the Krylov operator of eigen-block `block` (0 <= block <
  * nblocks of irk_eigen_blocks; equation (diag_blocks) under the context's
  * Newton-like truncation, Section 3.2) at the stage values of the last

@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.irk_step.argtypes = [P, P, D, D, D, P, ctypes.POINTER(Stats)]
     L.irk_eval_residual.restype = I
     L.irk_eval_residual.argtypes = [P, P, D, D, P, P]
+    L.irk_eval_residual_noalloc.restype = I
+    L.irk_eval_residual_noalloc.argtypes = [I, I, ctypes.POINTER(Operator), P, D, D, P, P, P]
     L.irk_get_stages.restype = I
     L.irk_get_stages.argtypes = [P, P]
     L.irk_apply_block.restype = I
@@ -224,6 +226,15 @@ def irk_step(ctx, u_ptr: int, t_n: float, dt: float, tol: float, out_ptr: int) -
 def irk_eval_residual(ctx, u_ptr: int, t_n: float, dt: float, K_ptr: int, F_ptr: int):
     _check(lib().irk_eval_residual(ctx, ctypes.c_void_p(u_ptr), t_n, dt, ctypes.c_void_p(K_ptr),
                                    ctypes.c_void_p(F_ptr)), "irk_eval_residual")
+
+
+def irk_eval_residual_noalloc(family: str, s: int, op: Operator, u_ptr: int, t_n: float, dt: float, K_ptr: int,
+                              F_ptr: int, stream: int = 0):
+    """The stage residual without a context or workspace (enqueued on
+    ``stream``; nothing is allocated and nothing waits)."""
+    _check(lib().irk_eval_residual_noalloc(FAMILY[family], s, ctypes.byref(op), ctypes.c_void_p(u_ptr), t_n, dt,
+                                           ctypes.c_void_p(K_ptr), ctypes.c_void_p(F_ptr), ctypes.c_void_p(stream)),
+           "irk_eval_residual_noalloc")
 
 
 def irk_get_stages(ctx, K_ptr: int):
