@@ -226,26 +226,31 @@ class VorticityStreamfunction2D:
 
     def _lin_matrix(self, fn):
         """Sparse matrix of the linear map x -> fn(x) on n x n arrays, built
-        column by column from unit vectors placed on a 3 x 3 colouring (the
-        stencils reach one cell), so 9 applications recover every column."""
+        column by column from unit vectors placed on an m x m colouring with
+        m the smallest divisor of n that is at least 3 (the stencils reach
+        one cell, so probed points of one colour are at least three cells
+        apart also across the periodic wrap): m^2 applications recover every
+        column.  Without such a divisor below n, column by column."""
         n, nn = self.n, self.nn
-        if n % 3:
+        m = next((d for d in range(3, n) if n % d == 0), n)
+        if m == n:
             return self._lin_matrix_dense(fn)
         rows, cols, vals = [], [], []
         jj, ii = np.divmod(np.arange(nn), n)
-        for cj in range(3):
-            for ci in range(3):
-                mask = ((jj % 3) == cj) & ((ii % 3) == ci)
+        for cj in range(m):
+            for ci in range(m):
+                mask = ((jj % m) == cj) & ((ii % m) == ci)
                 e = mask.astype(float).reshape(n, n)
                 col = fn(e).ravel()
                 nz = np.nonzero(col)[0]
                 # each nonzero row r comes from the unique probed point within
-                # one cell of it: offset d in {-1, 0, 1} with (r + d) = colour mod 3
+                # one cell of it: offset d in {-1, 0, 1} with r + d = colour (mod m)
                 rj, ri = np.divmod(nz, n)
-                dj = (cj - rj) % 3
-                di = (ci - ri) % 3
-                dj[dj == 2] = -1
-                di[di == 2] = -1
+                dj = (cj - rj) % m
+                di = (ci - ri) % m
+                dj[dj == m - 1] = -1
+                di[di == m - 1] = -1
+                assert np.all(np.abs(dj) <= 1) and np.all(np.abs(di) <= 1)
                 src = ((rj + dj) % n) * n + (ri + di) % n
                 rows.append(nz)
                 cols.append(src)

@@ -38,6 +38,30 @@ def test_vsf_jacobian_fd():
     assert _fd_check(p, st) < 1e-8
 
 
+@pytest.mark.parametrize("n", [8, 10, 14, 16])
+def test_vsf_jacobian_fd_coloured(n):
+    """Grids whose side is not a multiple of 3 (colourings of period 4, 5,
+    7 and 4) against finite differences too."""
+    p = pb.VorticityStreamfunction2D(n, 1e-3)
+    st = inputs.vsf_state0(n, 2, 4).ravel()
+    st[n * n:] += 0.01 * np.random.default_rng(1).standard_normal(n * n)
+    assert _fd_check(p, st) < 1e-8
+
+
+@pytest.mark.parametrize("n", [8, 9, 10, 7])
+def test_vsf_coloured_assembly_equals_column_by_column(n):
+    """The coloured assembly of each linear block equals the matrix built
+    one unit vector at a time (n = 7 has no divisor in [3, n): column by
+    column itself)."""
+    p = pb.VorticityStreamfunction2D(n, 1e-3)
+    om, psi = p.split(inputs.vsf_state0(n, 3, 4).ravel())
+    for fn in (lambda x: pb.arakawa(psi, x, p.h) + p.nu * pb.laplacian(x, p.h),
+               lambda x: pb.arakawa(x, om, p.h), lambda x: pb.laplacian(x, p.h)):
+        a = p._lin_matrix(fn).toarray()
+        b = p._lin_matrix_dense(fn).toarray()
+        assert np.array_equal(a, b)
+
+
 def test_burgers_truncation_second_order():
     """N_h(u) vs -(u^2/2)_x + nu u_xx for u = sin(2 pi x) + 0.5 cos(4 pi x)."""
     errs = []
