@@ -98,7 +98,7 @@ struct Plan {
     bool weighted = false;
     double hier_w[IRK_MAX_STAGES][IRK_MAX_STAGES];
     BlockWeights blk_w[IRK_MAX_STAGES];
-    size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab;
+    size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab, off_K2 = 0;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
     LaneLayout lane[IRK_MAX_STAGES];
     AuxLayout aux[IRK_MAX_STAGES];
@@ -233,8 +233,13 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->off_Y = take(s * P->nf * f64);
     P->off_Fh = take(s * P->nf * f64);
     P->off_U = take(s * P->nf * f64);
-    P->off_part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
+    // reduction partials: 512 work-groups x up to 32 values, or the fused
+    // stage residual's 2 per tile
+    P->off_part = take(std::max((size_t)IRK_RED_BLOCKS * 32, 2 * stage_residual_blocks(o.kind, o.nx, o.ny)) * f64);
     P->off_dv = take(512 * f64);
+    // the fused stage residual writes the folded stages to a second buffer
+    // (neighbouring tiles still read the first); the two swap roles
+    P->off_K2 = (o.kind != IRK_OP_VSF_2D) ? take(s * P->nf * f64) : 0;
     P->off_tab = take((size_t)2 * (o.nx + o.ny) * f64);
     if (P->fdm_level > 0) {
         const size_t n = P->lg.nx[P->fdm_level];
@@ -324,6 +329,7 @@ struct irk_ctx {
     hipStream_t stream = nullptr;        // the caller's stream (Newton level)
     unsigned char *ws = nullptr;
     double *K, *Y, *Fh, *U, *part, *dv, *tab;
+    double *K2 = nullptr;                // second stage buffer of the fused stage residual
     DeviceProblem dp;
     double *pinned = nullptr;            // host staging: Newton level + lanes
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
@@ -741,9 +747,8 @@ template <class T>
 static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, const double *zomega) {
     const size_t npts = c->P.npts;
     double *means = ln.dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
-    PROF(c, ln.stream, "k_field_sums", 16.0 * npts, 2,
-         launch_field_sums(ln.stream, rpsi, 0, 1, npts, 1.0 / npts, ln.part, means, nullptr);
-         launch_field_sums(ln.stream, zomega, 0, 1, npts, 1.0 / npts, ln.part, means + 1, nullptr));
+    PROF(c, ln.stream, "k_field_sums2", 16.0 * npts, 1,
+         launch_field_sums2(ln.stream, rpsi, zomega, npts, 1.0 / npts, ln.part, means));
     MgIn in;
     in.v1 = rpsi; in.a1 = 1.0; in.v2 = zomega; in.a2 = c->dt; in.mean = means;
     MgOut out;
@@ -1345,6 +1350,31 @@ struct Stepper : StepperBase {
         const Plan &P = c->P;
         const int s = P.s;
         const size_t nf = P.nf;
+        if (c->K2 && stage_residual_fused(c->dp)) {
+            // one sweep: fold, stage values, residual, transform, norms;
+            // the folded stages land in K2, which becomes K
+            PROF(c, c->stream, "k_stage_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
+                 8.0 * nf * (fold ? 5 * s + 1 : 3 * s + 1), 1,
+                 launch_stage_residual(c->stream, s, c->dp, u_n, c->K, c->K2, c->Y, c->U, c->Fh, C, dt, fold,
+                                       c->part, c->dv + slot));
+            if (fold) std::swap(c->K, c->K2);
+        } else {
+            issue_residual_unfused(slot);
+        }
+        if (!readback) return IRK_OK;
+        HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(read_gmax());
+        HIP_TRY(hipEventRecord(c->ev_res, c->stream));
+        phase = RES_WAIT;
+        return IRK_OK;
+    }
+
+    // stage preparation and residual as two sweeps (the vorticity-
+    // streamfunction DAE: its constraint rows need the stages' means first)
+    void issue_residual_unfused(int slot) {
+        const Plan &P = c->P;
+        const int s = P.s;
+        const size_t nf = P.nf;
         PROF(c, c->stream, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
              launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
         if (P.op.kind == IRK_OP_VSF_2D)
@@ -1356,12 +1386,6 @@ struct Stepper : StepperBase {
              8.0 * nf * 3 * s, 1,
              launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + slot,
                              c->dv + DV_GMAX));
-        if (!readback) return IRK_OK;
-        HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(read_gmax());
-        HIP_TRY(hipEventRecord(c->ev_res, c->stream));
-        phase = RES_WAIT;
-        return IRK_OK;
     }
 
     void set_zero_start() {
@@ -1865,6 +1889,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->ws = (unsigned char *)device_workspace;
     const Plan &P = c->P;
     c->K = (double *)(c->ws + P.off_K);
+    c->K2 = P.off_K2 ? (double *)(c->ws + P.off_K2) : nullptr;
     c->Y = (double *)(c->ws + P.off_Y);
     c->Fh = (double *)(c->ws + P.off_Fh);
     c->U = (double *)(c->ws + P.off_U);
@@ -2146,13 +2171,19 @@ extern "C" irk_status irk_eval_residual(irk_ctx *c, const double *u_n, double t_
     c->have_U = false;
     (void)hipGetLastError();
     HIP_TRY(hipMemcpyAsync(c->K, K, bytes, hipMemcpyDeviceToDevice, c->stream));
-    launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
-    if (P.op.kind == IRK_OP_VSF_2D)
-        launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS, nullptr);
     // identity transform: Tinv = I gives F itself
     for (int i = 0; i < s * s; ++i) C.Tinv[i] = (i / s == i % s) ? 1.0 : 0.0;
-    launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
-                    c->dv + DV_GMAX);
+    if (c->K2 && stage_residual_fused(c->dp)) {
+        launch_stage_residual(c->stream, s, c->dp, u_n, c->K, nullptr, c->Y, c->U, F, C, dt, 0, c->part,
+                              c->dv + DV_RES);
+    } else {
+        launch_stage_prep(c->stream, s, P.nf, u_n, c->K, c->Y, c->U, C, dt, 0);
+        if (P.op.kind == IRK_OP_VSF_2D)
+            launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
+                              nullptr);
+        launch_residual(c->stream, s, c->dp, c->U, c->K, F, C, c->dv + DV_MEANS, c->part, c->dv + DV_RES,
+                        c->dv + DV_GMAX);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_stages = false;

@@ -16,6 +16,16 @@ void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, doubl
 // VSF also gmax[0..s): each stage's largest one-cell streamfunction difference
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
                      const StageCoefs &C, const double *means, double *partials, double *out, double *gmax);
+// Stage values and residual in one sweep (nonlinear diffusion and Burgers
+// only: stage_residual_fused): with fold, k = K + (T Lambda (x) I) Y is
+// written to Kout (not K); U, the transformed residual Fh and out[0..1] as
+// launch_residual.  The partials hold stage_residual_blocks(kind, nx, ny) x 2
+// values.
+bool stage_residual_fused(const DeviceProblem &P);
+size_t stage_residual_blocks(int kind, int nx, int ny);
+void launch_stage_residual(hipStream_t st, int s, const DeviceProblem &P, const double *un, const double *K,
+                           double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
+                           int fold, double *partials, double *out);
 void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
                      double cos_tn);
 // Kx_i = sum_j W.A[i][j] K_j (s stage fields of length nf; Kx must not alias K)
@@ -24,6 +34,9 @@ void launch_final_update(hipStream_t st, int s, size_t nf, const double *un, con
                          const StageCoefs &C, double dt);
 void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, size_t len, double scale,
                        double *partials, double *out, unsigned *ctr);
+// out[0] = scale * sum X0, out[1] = scale * sum X1 (len each)
+void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size_t len, double scale,
+                        double *partials, double *out);
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
 // Eigen-block operator with stage-weighted linearizations (U: the s stage

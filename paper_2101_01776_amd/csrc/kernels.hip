@@ -315,6 +315,128 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
     finish_partials(tot, NVAL, partials, nullptr, nullptr);
 }
 
+// ------------------------------------------------------------------------
+// Stage values and residual in one sweep (nonlinear diffusion, Burgers):
+// for every point of a TX x TY tile and its one-cell halo
+//   k_j <- K_j + sum_l (T Lambda)_jl Y_l   (the fold of the previous block
+//                                           solves, when fold != 0)
+//   U_i  = u_n + dt sum_j a_ij k_j          (in LDS)
+// then, on the tile, F_i = k_i - N(U_i, t_n + c_i dt), fhat = (T^{-1} (x) I) F,
+// ||F||^2 and the rounding scale of F as per-work-group partials.  U and the
+// folded stages go to HBM (Kout: a different buffer than K, which
+// neighbouring tiles still read in their halos); fields are read once from
+// HBM (the halo from L2): (2s+1) reads and 3s writes per point with the
+// fold, (s+1) and 2s without.
+// ------------------------------------------------------------------------
+template <int S, int OP, int TX, int TY>
+__global__ void __launch_bounds__(IRK_WG) k_stage_residual(DeviceProblem P, const double *__restrict__ un,
+                                                           const double *__restrict__ K, double *__restrict__ Kout,
+                                                           const double *__restrict__ Y, double *__restrict__ U,
+                                                           double *__restrict__ Fh, StageCoefs C, double dt,
+                                                           int fold, double *partials) {
+    constexpr bool TWO_D = (OP == IRK_OP_NLDIFF_2D);
+    constexpr int W = TX + 2, HH = TWO_D ? TY + 2 : 1, NW = W * HH;
+    static_assert(TX * TY == IRK_WG, "one interior point per thread");
+    __shared__ double Us[S][NW];
+    __shared__ double Ks[S][TX * TY];
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t nf = (size_t)nx * ny;
+    const int tiles_x = (nx + TX - 1) / TX;
+    const int tile = xcd_block();
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int i0 = txi * TX, j0 = TWO_D ? tyi * TY : 0;
+    // window: every point of the tile and its halo (periodic wrap)
+    for (int q = threadIdx.x; q < NW; q += blockDim.x) {
+        const int ia = q % W, ib = q / W;
+        const int ri = i0 + ia - 1, rj = TWO_D ? j0 + ib - 1 : 0;
+        const int gi = ((ri % nx) + nx) % nx, gj = TWO_D ? ((rj % ny) + ny) % ny : 0;
+        const size_t g = (size_t)gj * nx + gi;
+        double k[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) k[j] = K[j * nf + g];
+        const double u = un[g];
+        if (fold) {
+            double y[S];
+#pragma unroll
+            for (int l = 0; l < S; ++l) y[l] = Y[l * nf + g];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                double acc = k[j];
+#pragma unroll
+                for (int l = 0; l < S; ++l) acc += C.TLam[j * S + l] * y[l];
+                k[j] = acc;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double acc = 0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc += C.A[i * S + j] * k[j];
+            Us[i][q] = u + dt * acc;
+        }
+        const bool inner = ia >= 1 && ia <= TX && (!TWO_D || (ib >= 1 && ib <= TY));
+        if (inner) {
+            const int pl = (TWO_D ? (ib - 1) * TX : 0) + ia - 1;
+#pragma unroll
+            for (int j = 0; j < S; ++j) Ks[j][pl] = k[j];
+            if (fold && ri < nx && rj < ny) {
+#pragma unroll
+                for (int j = 0; j < S; ++j) Kout[j * nf + g] = k[j];
+            }
+        }
+    }
+    __syncthreads();
+    const int pl = threadIdx.x;
+    const int li = pl % TX, lj = TWO_D ? pl / TX : 0;
+    const int gi = i0 + li, gj = j0 + lj;
+    double sumsq = 0.0, abssq = 0.0;
+    if (gi < nx && gj < ny) {
+        const size_t g = (size_t)gj * nx + gi;
+        const int c = (TWO_D ? (lj + 1) * W : 0) + li + 1;
+        const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+        double F[S];
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const double uc = Us[st][c], ue = Us[st][c + 1], uw = Us[st][c - 1];
+            const double k = Ks[st][pl];
+            if constexpr (TWO_D) {
+                const double unn = Us[st][c + W], us = Us[st][c - W];
+                double N = nldiff_flux5(uc, ue, uw, unn, us, inv_h2);
+                double a = nldiff_flux5_abs(uc, ue, uw, unn, us, inv_h2);
+                if (P.forcing != IRK_FORCING_NONE) {
+                    const double f = mms_forcing(P, gi, gj, C.sin_t[st], C.cos_t[st]);
+                    N += f;
+                    a += fabs(f);
+                }
+                F[st] = k - N;
+                a += fabs(k);
+                abssq += a * a;
+            } else {
+                const double N = -(ue * ue - uw * uw) / (4.0 * h) + P.g.nu * (ue - 2.0 * uc + uw) * inv_h2;
+                F[st] = k - N;
+                const double a = fabs(k) + (ue * ue + uw * uw) / (4.0 * h) +
+                                 P.g.nu * (fabs(ue) + 2.0 * fabs(uc) + fabs(uw)) * inv_h2;
+                abssq += a * a;
+            }
+            U[st * nf + g] = uc;
+        }
+#pragma unroll
+        for (int st = 0; st < S; ++st) sumsq += F[st] * F[st];
+#pragma unroll
+        for (int m = 0; m < S; ++m) {
+            double acc = 0;
+#pragma unroll
+            for (int st = 0; st < S; ++st) acc += C.Tinv[m * S + st] * F[st];
+            Fh[m * nf + g] = acc;
+        }
+    }
+    __shared__ double sh[8];
+    double tot[2];
+    tot[0] = block_sum(sumsq, sh);
+    tot[1] = block_sum(abssq, sh);
+    finish_partials(tot, 2, partials, nullptr, nullptr);
+}
+
 // k_i <- N(u_n, t_n) on differential rows, 0 on algebraic rows (explicit candidate for the
 // starting stage vectors)
 template <int S, int OP>
@@ -396,6 +518,22 @@ __global__ void __launch_bounds__(IRK_WG) k_field_sums(const double *__restrict_
     double tot[2 * IRK_MAX_STAGES];
     for (int f = 0; f < nfields; ++f) tot[f] = scale * block_sum(acc[f], sh);
     finish_partials(tot, nfields, partials, out, counter);
+}
+
+// sums of two fields of length len at unrelated addresses
+__global__ void __launch_bounds__(IRK_WG) k_field_sums2(const double *__restrict__ X0, const double *__restrict__ X1,
+                                                        size_t len, double scale, double *partials) {
+    double a0 = 0.0, a1 = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride) {
+        a0 += X0[e];
+        a1 += X1[e];
+    }
+    __shared__ double sh[8];
+    double tot[2];
+    tot[0] = scale * block_sum(a0, sh);
+    tot[1] = scale * block_sum(a1, sh);
+    finish_partials(tot, 2, partials, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------------
@@ -782,6 +920,51 @@ void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double
 }
 
 template <int S>
+static void stage_residual_s(hipStream_t st, const DeviceProblem &P, const double *un, const double *K,
+                             double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
+                             int fold, double *partials, double *out) {
+    unsigned g;
+    if (P.kind == IRK_OP_NLDIFF_2D) {
+        if (P.g.nx >= 64) {
+            g = (unsigned)(((P.g.nx + 63) / 64) * ((P.g.ny + 3) / 4));
+            k_stage_residual<S, IRK_OP_NLDIFF_2D, 64, 4><<<g, IRK_WG, 0, st>>>(P, un, K, Kout, Y, U, Fh, C, dt, fold,
+                                                                            partials);
+        } else {
+            g = (unsigned)(((P.g.nx + 15) / 16) * ((P.g.ny + 15) / 16));
+            k_stage_residual<S, IRK_OP_NLDIFF_2D, 16, 16><<<g, IRK_WG, 0, st>>>(P, un, K, Kout, Y, U, Fh, C, dt,
+                                                                             fold, partials);
+        }
+    } else {
+        g = (unsigned)((P.g.nx + 255) / 256);
+        k_stage_residual<S, IRK_OP_BURGERS_1D, 256, 1><<<g, IRK_WG, 0, st>>>(P, un, K, Kout, Y, U, Fh, C, dt, fold,
+                                                                          partials);
+    }
+    reduce_partials(st, partials, g, 2, out);
+}
+
+bool stage_residual_fused(const DeviceProblem &P) {
+    return P.kind == IRK_OP_NLDIFF_2D || P.kind == IRK_OP_BURGERS_1D;
+}
+
+size_t stage_residual_blocks(int kind, int nx, int ny) {
+    if (kind == IRK_OP_NLDIFF_2D)
+        return nx >= 64 ? (size_t)((nx + 63) / 64) * ((ny + 3) / 4) : (size_t)((nx + 15) / 16) * ((ny + 15) / 16);
+    return (size_t)(nx + 255) / 256;
+}
+
+void launch_stage_residual(hipStream_t st, int s, const DeviceProblem &P, const double *un, const double *K,
+                           double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
+                           int fold, double *partials, double *out) {
+    switch (s) {
+        case 1: stage_residual_s<1>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+        case 2: stage_residual_s<2>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+        case 3: stage_residual_s<3>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+        case 4: stage_residual_s<4>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+        case 5: stage_residual_s<5>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+    }
+}
+
+template <int S>
 static void rhs_init_s(hipStream_t st, const DeviceProblem &P, const double *un, double *K, double s_n, double c_n) {
     const size_t npts = (size_t)P.g.nx * P.g.ny;
     const unsigned g = grid_for(npts);
@@ -829,6 +1012,13 @@ void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, 
     const unsigned g = grid_for(len, IRK_RED_BLOCKS);
     k_field_sums<<<g, IRK_WG, 0, st>>>(X, ld, nfields, len, scale, partials, out, ctr);
     reduce_partials(st, partials, g, nfields, out);
+}
+
+void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size_t len, double scale,
+                        double *partials, double *out) {
+    const unsigned g = grid_for(len, IRK_RED_BLOCKS);
+    k_field_sums2<<<g, IRK_WG, 0, st>>>(X0, X1, len, scale, partials);
+    reduce_partials(st, partials, g, 2, out);
 }
 
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
