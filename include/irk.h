@@ -30,6 +30,15 @@
  * Field layout: a scalar field is row-major [ny][nx] float64, x fastest
  * (1-D problems have ny = 1).  The vorticity-streamfunction state is
  * [2][ny][nx]: omega then psi.
+ *
+ * Mapping onto the proposed boundary (irk_create / irk_step / irk_destroy
+ * plus a serving interface): the stages are always transformed into the
+ * real eigenbasis of A0^{-1} (its blocks are independent, so they run
+ * concurrently), so irk_options has no basis selector (the paper's real
+ * Schur basis needs back-substitution between blocks); serving polls with
+ * irk_server_progress (one pass for all requests) and reads a request's
+ * state with irk_server_info, its result landing in the request's own
+ * output buffer, instead of a per-request poll and result call.
  */
 #ifndef IRK_H
 #define IRK_H
@@ -122,7 +131,13 @@ typedef struct irk_options {
     int cheb_degree;        /* Chebyshev pre- and post-smoothing degree       */
     int mg_coarsest;        /* coarsening stops before a side below this (the
                                coarsest level, at most 1024 points, is
-                               solved by Chebyshev iteration)             */
+                               solved by Chebyshev iteration); vorticity
+                               V-cycles stop earlier, at the first level
+                               whose operator is diagonally dominant
+                               (Gershgorin ratio <= 1/4: D Jacobi sweeps
+                               there), and streamfunction (Poisson) cycles at
+                               the first level of side <= 32 (solved
+                               exactly, by fast diagonalization)          */
     int coarse_iters;       /* Chebyshev iterations on the coarsest level     */
     int batch_mg;           /* 1: V-cycles of blocks (and, in a server, of
                                requests) waiting at the same time run in
@@ -360,17 +375,22 @@ typedef struct irk_request_info {
 
 /* arena: caller-owned device memory (256-byte aligned) the server carves
  * request state from; arena_bytes is the HBM admission budget; max_slots
- * bounds the number of requests resident at once.                          */
+ * bounds the number of requests resident at once.  Every slot's HIP
+ * streams, events and pinned host staging are made here (grids of side up
+ * to 16384), so that admitting a request allocates nothing and waits for
+ * nothing.  IRK_E_DEVICE if they cannot be made (no GPU).                  */
 irk_status irk_server_create(void *arena, size_t arena_bytes, int max_slots, irk_server **out);
 /* Queue a request (nothing runs until irk_server_progress).  IRK_E_ARG for
- * invalid requests, IRK_E_DEVICE if the ordering event on req->stream cannot
- * be recorded; a request larger than the whole arena is failed with
- * IRK_E_NOMEM when it reaches the head of the queue.  The result is in
- * req->out once irk_server_info reports IRK_REQ_DONE (the server has
- * synchronized the copy by then).                                          */
+ * invalid requests (also grids of side above 16384), IRK_E_DEVICE if the
+ * ordering event on req->stream cannot be recorded; a request larger than
+ * the whole arena is failed with IRK_E_NOMEM when it reaches the head of
+ * the queue.  The result is in req->out once irk_server_info reports
+ * IRK_REQ_DONE (an event behind the copy has completed by then).          */
 irk_status irk_server_submit(irk_server *srv, const irk_request *req, long *id);
-/* One non-blocking scheduling pass: admit what fits, advance every running
- * request; returns the number of requests queued or running (-1 on NULL).  */
+/* One non-blocking scheduling pass: retire finished requests whose last
+ * work has completed, admit what fits (enqueueing only), advance every
+ * running request; returns the number of requests queued, running or
+ * finishing (-1 on NULL).                                                  */
 int irk_server_progress(irk_server *srv);
 irk_status irk_server_info(irk_server *srv, long id, irk_request_info *info);
 /* Latencies (milliseconds, host clock) of every completed step so far (up to

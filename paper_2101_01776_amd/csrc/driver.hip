@@ -324,6 +324,19 @@ struct Lane {
 
 struct StepperBase;
 
+// Streams, events and pinned host staging a context runs on.  irk_create
+// makes a private set; a server makes one per slot when it is created, so
+// that admitting a request allocates nothing and waits for nothing.
+struct CtxRes {
+    int nlanes = 0;                                  // lanes with streams and events
+    hipStream_t lane_st[IRK_MAX_STAGES] = {}, aux_st[IRK_MAX_STAGES] = {};
+    hipEvent_t ev[IRK_MAX_STAGES] = {}, done[IRK_MAX_STAGES] = {}, prec[IRK_MAX_STAGES] = {};
+    hipEvent_t fork[IRK_MAX_STAGES] = {}, join[IRK_MAX_STAGES] = {};
+    hipEvent_t ev_main = nullptr, ev_res = nullptr;
+    double *pinned = nullptr;                        // readback/upload staging, then the upload area
+    size_t upload = 0;                               // doubles of the upload area
+};
+
 struct irk_ctx {
     Plan P;
     hipStream_t stream = nullptr;        // the caller's stream (Newton level)
@@ -331,7 +344,9 @@ struct irk_ctx {
     double *K, *Y, *Fh, *U, *part, *dv, *tab;
     double *K2 = nullptr;                // second stage buffer of the fused stage residual
     DeviceProblem dp;
-    double *pinned = nullptr;            // host staging: Newton level + lanes
+    double *pinned = nullptr;            // host staging: Newton level + lanes (res->pinned)
+    CtxRes *res = nullptr;               // streams, events, pinned staging
+    bool res_owned = false;              // made by irk_create (else a server slot's)
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
     hipEvent_t ev_res = nullptr;        // Newton-level readbacks
     StepperBase *stepper = nullptr;
@@ -1794,6 +1809,57 @@ static void set_chebyshev(irk_ctx *c) {
     chebyshev_coefs(c->lmin, c->lmax, c->P.opt.cheb_degree, c->cheb_cd, c->cheb_cr);
 }
 
+// doubles of the upload area a problem needs: forcing tables, the Fourier
+// basis and eigenvalues of the exactly solved Poisson level
+static size_t upload_doubles(const Plan &P) {
+    size_t n = (size_t)2 * (P.op.nx + P.op.ny);
+    if (P.fdm_level > 0) {
+        const size_t m = P.lg.nx[P.fdm_level];
+        n += m * m + m;
+    }
+    return n;
+}
+
+// Create every stream, event and the pinned staging of a resource set
+// (default-priority, non-blocking streams: ordering with the caller's
+// stream is explicit, through events).
+static irk_status res_create(CtxRes *r, int nlanes, size_t upload) {
+    r->nlanes = nlanes;
+    r->upload = upload;
+    const size_t pin = (size_t)(1 + IRK_MAX_STAGES) * PIN_LANE + upload;
+    if (hipHostMalloc((void **)&r->pinned, pin * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        r->pinned = nullptr;
+        return IRK_E_DEVICE;
+    }
+    auto ev = [](hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess; };
+    if (!ev(&r->ev_main) || !ev(&r->ev_res)) return IRK_E_DEVICE;
+    for (int b = 0; b < nlanes; ++b) {
+        if (hipStreamCreateWithFlags(&r->lane_st[b], hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&r->aux_st[b], hipStreamNonBlocking) != hipSuccess || !ev(&r->ev[b]) ||
+            !ev(&r->done[b]) || !ev(&r->prec[b]) || !ev(&r->fork[b]) || !ev(&r->join[b]))
+            return IRK_E_DEVICE;
+    }
+    return IRK_OK;
+}
+
+// Wait for and release everything res_create made (also a partial set).
+static void res_destroy(CtxRes *r) {
+    if (!r) return;
+    for (int b = 0; b < IRK_MAX_STAGES; ++b) {
+        for (hipStream_t st : {r->lane_st[b], r->aux_st[b]})
+            if (st) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+            }
+        for (hipEvent_t e : {r->ev[b], r->done[b], r->prec[b], r->fork[b], r->join[b]})
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (r->ev_main) (void)hipEventDestroy(r->ev_main);
+    if (r->ev_res) (void)hipEventDestroy(r->ev_res);
+    if (r->pinned) (void)hipHostFree(r->pinned);
+    *r = CtxRes();
+}
+
 static void release(irk_ctx *c) {
     if (!c) return;
     if (c->broker) {
@@ -1806,26 +1872,12 @@ static void release(irk_ctx *c) {
         }
         c->broker = nullptr;
     }
-    for (int b = 0; b < c->nlanes; ++b) {
-        Lane &ln = c->lanes[b];
-        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
-        if (ln.ev) (void)hipEventDestroy(ln.ev);
-        if (ln.done) (void)hipEventDestroy(ln.done);
-        if (ln.ev_prec) (void)hipEventDestroy(ln.ev_prec);
-        if (ln.ev_fork) (void)hipEventDestroy(ln.ev_fork);
-        if (ln.ev_join) (void)hipEventDestroy(ln.ev_join);
-        if (ln.stream) (void)hipStreamDestroy(ln.stream);
-        Lane &ax = c->aux_lanes[b];
-        if (ax.stream) {
-            (void)hipStreamSynchronize(ax.stream);
-            (void)hipStreamDestroy(ax.stream);
-        }
+    if (c->res_owned) {
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        res_destroy(c->res);
+        delete c->res;
     }
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
-    if (c->ev_res) (void)hipEventDestroy(c->ev_res);
     delete c->stepper;
-    if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -1833,20 +1885,26 @@ static void release(irk_ctx *c) {
 // Real orthonormal Fourier basis of the periodic n-point second difference
 // on the exact-solve level (columns: the constant, cos and sin pairs of
 // modes 1 .. (n-1)/2, and for even n the alternating mode) and its
-// eigenvalues 4 sin^2(pi m / n) / h^2, in the V-cycle precision.
-static irk_status upload_fdm_basis(irk_ctx *c) {
+// eigenvalues 4 sin^2(pi m / n) / h^2, in the V-cycle precision, written to
+// `stage` (pinned) and copied to the workspace on the context's stream.
+static irk_status upload_fdm_basis(irk_ctx *c, double *stage) {
     const Plan &P = c->P;
     const int n = P.lg.nx[P.fdm_level];
     const double h = P.op.length / P.op.nx * (double)(1 << P.fdm_level);
     const double pi = 3.14159265358979323846;
-    std::vector<double> Q((size_t)n * n), lam(n);
+    const bool f32 = P.tsz == sizeof(float);
+    float *qf = reinterpret_cast<float *>(stage);
+    double *qd = stage;
+    double lam[IRK_FDM_MAX];
     int col = 0;
     auto put = [&](int m, int kind) {          // kind 0: cos (or constant), 1: sin
         const bool single = (m == 0) || (2 * m == n);
         const double sc = single ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
         for (int j = 0; j < n; ++j) {
             const double a = 2.0 * pi * m * j / n;
-            Q[(size_t)j * n + col] = sc * (kind == 0 ? std::cos(a) : std::sin(a));
+            const double v = sc * (kind == 0 ? std::cos(a) : std::sin(a));
+            if (f32) qf[(size_t)j * n + col] = (float)v;
+            else qd[(size_t)j * n + col] = v;
         }
         const double sv = std::sin(pi * m / n);
         lam[col] = 4.0 * sv * sv / (h * h);
@@ -1860,23 +1918,20 @@ static irk_status upload_fdm_basis(irk_ctx *c) {
     if (n % 2 == 0) put(n / 2, 0);
     if (col != n) return IRK_E_ARG;
     lam[0] = 0.0;
-    void *dQ = c->ws + P.off_fdm_Q, *dl = c->ws + P.off_fdm_lam;
-    if (P.tsz == sizeof(float)) {
-        std::vector<float> qf(Q.begin(), Q.end()), lf(lam.begin(), lam.end());
-        HIP_TRY(hipMemcpyAsync(dQ, qf.data(), qf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(dl, lf.data(), lf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-    } else {
-        HIP_TRY(hipMemcpyAsync(dQ, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(dl, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t qbytes = (size_t)n * n * P.tsz;
+    unsigned char *lstage = reinterpret_cast<unsigned char *>(stage) + qbytes;
+    for (int k = 0; k < n; ++k) {
+        if (f32) reinterpret_cast<float *>(lstage)[k] = (float)lam[k];
+        else reinterpret_cast<double *>(lstage)[k] = lam[k];
     }
+    HIP_TRY(hipMemcpyAsync(c->ws + P.off_fdm_Q, stage, qbytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + P.off_fdm_lam, lstage, (size_t)n * P.tsz, hipMemcpyHostToDevice, c->stream));
     return IRK_OK;
 }
 
-extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,
-                                 void *device_workspace, size_t workspace_bytes, void *hip_stream, irk_ctx **out) {
-    if (!out) return IRK_E_ARG;
+// A new context for a checked plan on a workspace (host only).
+static irk_status ctx_new(irk_family family, int s, const irk_operator *op, const irk_options *opt,
+                          void *device_workspace, size_t workspace_bytes, irk_ctx **out) {
     *out = nullptr;
     irk_ctx *c = new (std::nothrow) irk_ctx();
     if (!c) return IRK_E_NOMEM;
@@ -1884,8 +1939,6 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     if (stt != IRK_OK) { delete c; return stt; }
     if (!device_workspace || ((uintptr_t)device_workspace & 255) != 0) { delete c; return IRK_E_ARG; }
     if (workspace_bytes < c->P.total) { delete c; return IRK_E_NOMEM; }
-    (void)hipGetLastError();   // clear an error left by earlier, unrelated HIP calls
-    c->stream = (hipStream_t)hip_stream;
     c->ws = (unsigned char *)device_workspace;
     const Plan &P = c->P;
     c->K = (double *)(c->ws + P.off_K);
@@ -1897,24 +1950,31 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->dv = (double *)(c->ws + P.off_dv);
     c->tab = (double *)(c->ws + P.off_tab);
     c->nlanes = P.eb.nblocks;
-    if (hipHostMalloc((void **)&c->pinned, (size_t)(1 + c->nlanes) * PIN_LANE * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_res, hipEventDisableTiming) != hipSuccess) {
-        release(c);
-        return IRK_E_DEVICE;
-    }
-    if (c->P.sd_s > 0) {
-        if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) SdirkStepper<float>(c);
+    *out = c;
+    return IRK_OK;
+}
+
+// Bind a context to its stream and resource set and enqueue its device
+// set-up (forcing tables, Fourier basis, Y = 0) on that stream from the
+// pinned upload area; with `wait` the call returns after the set-up has
+// completed, else it only enqueues.  private_broker: irk_create's contexts
+// batch their own blocks' V-cycles when the option asks for it.
+static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait, bool private_broker) {
+    const Plan &P = c->P;
+    if (r->nlanes < c->nlanes || r->upload < upload_doubles(P)) return IRK_E_ARG;
+    c->stream = stream;
+    c->res = r;
+    c->pinned = r->pinned;
+    c->ev_main = r->ev_main;
+    c->ev_res = r->ev_res;
+    if (P.sd_s > 0) {
+        if (P.opt.prec_fp32) c->stepper = new (std::nothrow) SdirkStepper<float>(c);
         else c->stepper = new (std::nothrow) SdirkStepper<double>(c);
     } else {
-        if (c->P.opt.prec_fp32) c->stepper = new (std::nothrow) Stepper<float>(c);
+        if (P.opt.prec_fp32) c->stepper = new (std::nothrow) Stepper<float>(c);
         else c->stepper = new (std::nothrow) Stepper<double>(c);
     }
-    if (!c->stepper) {
-        release(c);
-        return IRK_E_NOMEM;
-    }
+    if (!c->stepper) return IRK_E_NOMEM;
     for (int b = 0; b < c->nlanes; ++b) {
         Lane &ln = c->lanes[b];
         const LaneLayout &lay = P.lane[b];
@@ -1927,15 +1987,10 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         ln.dv = (double *)(c->ws + lay.dv);
         ln.tmp = lay.tmp ? (double *)(c->ws + lay.tmp) : nullptr;
         ln.pin = c->pinned + (size_t)(1 + b) * PIN_LANE;
-        // default-priority, non-blocking streams (ordering with the caller's
-        // stream is explicit, through events)
-        if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ln.ev_prec, hipEventDisableTiming) != hipSuccess) {
-            release(c);
-            return IRK_E_DEVICE;
-        }
+        ln.stream = r->lane_st[b];
+        ln.ev = r->ev[b];
+        ln.done = r->done[b];
+        ln.ev_prec = r->prec[b];
         if (P.aux[b].used) {
             Lane &ax = c->aux_lanes[b];
             ax.blk = b;
@@ -1943,21 +1998,18 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
             ax.ldv = ln.ldv;
             ax.part = (double *)(c->ws + ax.lay->part);
             ax.dv = (double *)(c->ws + ax.lay->dv);
-            if (hipStreamCreateWithFlags(&ax.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&ln.ev_fork, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ln.ev_join, hipEventDisableTiming) != hipSuccess) {
-                release(c);
-                return IRK_E_DEVICE;
-            }
+            ax.stream = r->aux_st[b];
+            ln.ev_fork = r->fork[b];
+            ln.ev_join = r->join[b];
             ln.aux = &ax;
         }
     }
     // a private broker batches the V-cycles of this context's blocks
     // (Newton-like (3) pairs apply an operator between their two V-cycles:
     // they are not batched)
-    if (c->P.opt.batch_mg && c->nlanes > 1 && c->P.op.kind != IRK_OP_VSF_2D && c->P.opt.newton_like != 3) {
+    if (private_broker && P.opt.batch_mg && c->nlanes > 1 && P.op.kind != IRK_OP_VSF_2D && P.opt.newton_like != 3) {
         bool ok;
-        if (c->P.opt.prec_fp32) {
+        if (P.opt.prec_fp32) {
             auto *b = new (std::nothrow) PrecBroker<float>();
             ok = b && b->init();
             c->broker = b;
@@ -1967,10 +2019,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
             c->broker = b;
         }
         c->broker_owned = c->broker != nullptr;
-        if (!ok) {
-            release(c);
-            return IRK_E_DEVICE;
-        }
+        if (!ok) return IRK_E_DEVICE;
     }
     set_chebyshev(c);
     // device problem descriptor and forcing tables sin/cos(2 pi x_i)
@@ -1982,7 +2031,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->dp.g.h = P.op.length / P.op.nx;
     c->dp.g.nu = P.op.nu;
     const int nx = P.op.nx, ny = P.op.ny;
-    std::vector<double> tab(2 * (nx + ny));
+    double *tab = c->pinned + (size_t)(1 + IRK_MAX_STAGES) * PIN_LANE;   // the upload area
     const double two_pi = 2.0 * 3.14159265358979323846;
     for (int i = 0; i < nx; ++i) {
         tab[i] = std::sin(two_pi * (i * c->dp.g.h));
@@ -1996,20 +2045,35 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
     c->dp.cosx = c->tab + nx;
     c->dp.siny = c->tab + 2 * nx;
     c->dp.cosy = c->tab + 2 * nx + ny;
-    if (hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        release(c);
-        return IRK_E_DEVICE;
-    }
-    if (P.fdm_level > 0 && upload_fdm_basis(c) != IRK_OK) {
-        release(c);
-        return IRK_E_DEVICE;
+    HIP_TRY(hipMemcpyAsync(c->tab, tab, (size_t)2 * (nx + ny) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (P.fdm_level > 0) {
+        const irk_status e = upload_fdm_basis(c, tab + 2 * (nx + ny));
+        if (e != IRK_OK) return e;
     }
     launch_fill(c->stream, c->Y, 0.0, (size_t)P.s * P.nf);   // the plan's s (1 for SDIRK)
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    HIP_TRY(hipGetLastError());
+    if (wait) HIP_TRY(hipStreamSynchronize(c->stream));
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *op, const irk_options *opt,
+                                 void *device_workspace, size_t workspace_bytes, void *hip_stream, irk_ctx **out) {
+    if (!out) return IRK_E_ARG;
+    irk_ctx *c = nullptr;
+    irk_status stt = ctx_new(family, s, op, opt, device_workspace, workspace_bytes, &c);
+    if (stt != IRK_OK) return stt;
+    (void)hipGetLastError();   // clear an error left by earlier, unrelated HIP calls
+    c->res = new (std::nothrow) CtxRes();
+    if (!c->res) {
+        delete c;
+        return IRK_E_NOMEM;
+    }
+    c->res_owned = true;
+    c->stream = (hipStream_t)hip_stream;
+    if ((stt = res_create(c->res, c->nlanes, upload_doubles(c->P))) != IRK_OK ||
+        (stt = ctx_init(c, (hipStream_t)hip_stream, c->res, true, true)) != IRK_OK) {
         release(c);
-        return IRK_E_DEVICE;
+        return stt == IRK_E_NOMEM ? IRK_E_NOMEM : IRK_E_DEVICE;
     }
     *out = c;
     return IRK_OK;
@@ -2047,10 +2111,63 @@ int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats) {
     return 1;
 }
 
-void drain_all(irk_ctx *c) {
-    for (int b = 0; b < c->nlanes; ++b) (void)hipStreamSynchronize(c->lanes[b].stream);
-    (void)hipStreamSynchronize(c->stream);
+// Serving: resource sets made once per slot, contexts bound to them without
+// allocating or waiting, and released without waiting (the server releases
+// a context only after an event behind all of its work has completed).
+void *res_new(int nlanes, size_t upload) {
+    CtxRes *r = new (std::nothrow) CtxRes();
+    if (!r) return nullptr;
+    if (res_create(r, nlanes, upload) != IRK_OK) {
+        res_destroy(r);
+        delete r;
+        return nullptr;
+    }
+    return r;
 }
+
+void res_free(void *r) {
+    res_destroy(static_cast<CtxRes *>(r));
+    delete static_cast<CtxRes *>(r);
+}
+
+// upload doubles a problem needs (0 if the plan is invalid)
+size_t res_upload_need(int family, int s, const irk_operator *op, const irk_options *opt) {
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return 0;
+    const size_t n = make_plan(family, s, op, opt, P) == IRK_OK ? upload_doubles(*P) : 0;
+    delete P;
+    return n;
+}
+
+irk_status create_in_res(int family, int s, const irk_operator *op, const irk_options *opt, void *ws,
+                         size_t ws_bytes, hipStream_t stream, void *res, irk_ctx **out) {
+    irk_ctx *c = nullptr;
+    irk_status stt = ctx_new((irk_family)family, s, op, opt, ws, ws_bytes, &c);
+    if (stt != IRK_OK) return stt;
+    stt = ctx_init(c, stream, static_cast<CtxRes *>(res), false, false);
+    if (stt != IRK_OK) {
+        release(c);
+        return stt;
+    }
+    *out = c;
+    return IRK_OK;
+}
+
+// every stream of a context's resource set, then `ev` recorded on its
+// Newton-level stream: behind all of the context's work
+irk_status record_all_done(irk_ctx *c, hipEvent_t ev) {
+    CtxRes *r = c->res;
+    for (int b = 0; b < r->nlanes; ++b) {
+        HIP_TRY(hipEventRecord(r->done[b], r->lane_st[b]));
+        HIP_TRY(hipStreamWaitEvent(c->stream, r->done[b], 0));
+        HIP_TRY(hipEventRecord(r->join[b], r->aux_st[b]));
+        HIP_TRY(hipStreamWaitEvent(c->stream, r->join[b], 0));
+    }
+    HIP_TRY(hipEventRecord(ev, c->stream));
+    return IRK_OK;
+}
+
+void ctx_free(irk_ctx *c) { release(c); }
 
 // Shared V-cycle brokers for a server: one per precision (fp32 = 1: float).
 void *broker_create(int fp32) {
@@ -2095,7 +2212,13 @@ extern "C" irk_status irk_step(irk_ctx *c, const double *u_n, double t_n, double
     irk_stats local;
     while (!step_poll(c, &stt, &local)) {
     }
-    drain_all(c);
+    // the step is complete on the device (also work a failed step left on
+    // the block streams)
+    for (int b = 0; b < c->nlanes; ++b) {
+        (void)hipStreamSynchronize(c->lanes[b].stream);
+        if (c->lanes[b].aux) (void)hipStreamSynchronize(c->lanes[b].aux->stream);
+    }
+    (void)hipStreamSynchronize(c->stream);
     if (c->prof) prof_harvest(c);
     if (stats) *stats = local;
     return stt;

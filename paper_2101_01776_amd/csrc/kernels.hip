@@ -349,7 +349,11 @@ __global__ void __launch_bounds__(IRK_WG) k_stage_residual(DeviceProblem P, cons
     for (int q = threadIdx.x; q < NW; q += blockDim.x) {
         const int ia = q % W, ib = q / W;
         const int ri = i0 + ia - 1, rj = TWO_D ? j0 + ib - 1 : 0;
-        const int gi = ((ri % nx) + nx) % nx, gj = TWO_D ? ((rj % ny) + ny) % ny : 0;
+        // periodic wrap without integer division (ri >= -1: one step up,
+        // and usually at most one step down)
+        int gi = ri < 0 ? ri + nx : ri, gj = TWO_D ? (rj < 0 ? rj + ny : rj) : 0;
+        while (gi >= nx) gi -= nx;
+        while (gj >= ny) gj -= ny;
         const size_t g = (size_t)gj * nx + gi;
         double k[S];
 #pragma unroll
@@ -509,14 +513,34 @@ __global__ void __launch_bounds__(IRK_WG) k_stage_extrap(size_t nf, const double
 __global__ void __launch_bounds__(IRK_WG) k_field_sums(const double *__restrict__ X, size_t ld, int nfields,
                                                        size_t len, double scale, double *partials, double *out,
                                                        unsigned *counter) {
-    double acc[2 * IRK_MAX_STAGES];
-    for (int f = 0; f < nfields; ++f) acc[f] = 0.0;
+    constexpr int NF = 2 * IRK_MAX_STAGES, UN = 4;
+    double acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride)
-        for (int f = 0; f < nfields; ++f) acc[f] += X[f * ld + e];
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // UN elements per field loaded before the first add (same order as one
+    // at a time)
+    for (; e + (UN - 1) * stride < len; e += UN * stride) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < nfields) {
+                double x[UN];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) x[u] = X[f * ld + e + u * stride];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) acc[f] += x[u];
+            }
+    }
+    for (; e < len; e += stride)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < nfields) acc[f] += X[f * ld + e];
     __shared__ double sh[8];
-    double tot[2 * IRK_MAX_STAGES];
-    for (int f = 0; f < nfields; ++f) tot[f] = scale * block_sum(acc[f], sh);
+    double tot[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+        if (f < nfields) tot[f] = scale * block_sum(acc[f], sh);
     finish_partials(tot, nfields, partials, out, counter);
 }
 
@@ -524,8 +548,23 @@ __global__ void __launch_bounds__(IRK_WG) k_field_sums(const double *__restrict_
 __global__ void __launch_bounds__(IRK_WG) k_field_sums2(const double *__restrict__ X0, const double *__restrict__ X1,
                                                         size_t len, double scale, double *partials) {
     double a0 = 0.0, a1 = 0.0;
+    constexpr int UN = 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += stride) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + (UN - 1) * stride < len; e += UN * stride) {
+        double x0[UN], x1[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            x0[u] = X0[e + u * stride];
+            x1[u] = X1[e + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            a0 += x0[u];
+            a1 += x1[u];
+        }
+    }
+    for (; e < len; e += stride) {
         a0 += X0[e];
         a1 += X1[e];
     }
@@ -657,60 +696,105 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
 // Arnoldi kernels
 // ------------------------------------------------------------------------
 // out[k] = <V_k, w> for k < nv (nv <= 16); out[nv] = <w, w> when with_norm
+// (The reduction kernels run on at most 512 work-groups, so each thread
+// covers many elements: UN of them are loaded before the first is used, in
+// the same order e, e + stride, e + 2 stride, ... as one at a time, so the
+// sums are the same; NVMAX x UN values in flight per thread.)
+template <int NVMAX, int UN>
 __global__ void __launch_bounds__(IRK_WG) k_dot_multi(const double *__restrict__ V, size_t ldv, int nv,
                                                       const double *__restrict__ w, size_t len, int with_norm,
-                                                      double *partials, double *out, unsigned *counter) {
-    double acc[DOT_CHUNK + 1];
+                                                      double *partials) {
+    double acc[NVMAX + 1];
 #pragma unroll
-    for (int k = 0; k <= DOT_CHUNK; ++k) acc[k] = 0.0;
+    for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
+    size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+    for (; e + (UN - 1) * stride < len; e += UN * stride) {
+        double we[UN], v[UN][NVMAX];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            we[u] = w[e + u * stride];
+#pragma unroll
+            for (int k = 0; k < NVMAX; ++k)
+                if (k < nv) v[u][k] = V[k * ldv + e + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+#pragma unroll
+            for (int k = 0; k < NVMAX; ++k)
+                if (k < nv) acc[k] += v[u][k] * we[u];
+            if (with_norm) acc[NVMAX] += we[u] * we[u];
+        }
+    }
+    for (; e < len; e += stride) {
         const double we = w[e];
 #pragma unroll
-        for (int k = 0; k < DOT_CHUNK; ++k)
+        for (int k = 0; k < NVMAX; ++k)
             if (k < nv) acc[k] += V[k * ldv + e] * we;
-        if (with_norm) acc[DOT_CHUNK] += we * we;
+        if (with_norm) acc[NVMAX] += we * we;
     }
-    __shared__ double sh[4 * (DOT_CHUNK + 1)];
+    __shared__ double sh[4 * (NVMAX + 1)];
     const int nout = nv + (with_norm ? 1 : 0);
     double mine;
-    block_reduce_multi<DOT_CHUNK + 1>(acc, nv, with_norm != 0, sh, mine);
-    finish_multi<DOT_CHUNK + 1>(mine, nout, partials);
+    block_reduce_multi<NVMAX + 1>(acc, nv, with_norm != 0, sh, mine);
+    finish_multi<NVMAX + 1>(mine, nout, partials);
 }
 
 // Second Gram-Schmidt pass fused with the first update (one sweep over V):
 //   w <- w - sum_k h1[k] V_k ;  h2[k] = <V_k, w> ;  out[nv] = <w, w>
 // (out = h2 followed by the norm).
+template <int NVMAX, int UN>
 __global__ void __launch_bounds__(IRK_WG) k_axpy_dot(double *__restrict__ w, const double *__restrict__ V,
                                                      size_t ldv, int nv, const double *__restrict__ h1,
-                                                     size_t len, double *partials, double *out,
-                                                     unsigned *counter) {
-    double acc[DOT_CHUNK + 1];
-    double hk[DOT_CHUNK];
+                                                     size_t len, double *partials) {
+    double acc[NVMAX + 1];
+    double hk[NVMAX];
 #pragma unroll
-    for (int k = 0; k <= DOT_CHUNK; ++k) acc[k] = 0.0;
+    for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
 #pragma unroll
-    for (int k = 0; k < DOT_CHUNK; ++k) hk[k] = k < nv ? h1[k] : 0.0;
+    for (int k = 0; k < NVMAX; ++k) hk[k] = k < nv ? h1[k] : 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < len; e += stride) {
-        double v[DOT_CHUNK];
+    size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+    for (; e + (UN - 1) * stride < len; e += UN * stride) {
+        double we[UN], v[UN][NVMAX];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            we[u] = w[e + u * stride];
+#pragma unroll
+            for (int k = 0; k < NVMAX; ++k)
+                if (k < nv) v[u][k] = V[k * ldv + e + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+#pragma unroll
+            for (int k = 0; k < NVMAX; ++k)
+                if (k < nv) we[u] -= hk[k] * v[u][k];
+            w[e + u * stride] = we[u];
+#pragma unroll
+            for (int k = 0; k < NVMAX; ++k)
+                if (k < nv) acc[k] += v[u][k] * we[u];
+            acc[NVMAX] += we[u] * we[u];
+        }
+    }
+    for (; e < len; e += stride) {
+        double v[NVMAX];
         double we = w[e];
 #pragma unroll
-        for (int k = 0; k < DOT_CHUNK; ++k)
+        for (int k = 0; k < NVMAX; ++k)
             if (k < nv) {
                 v[k] = V[k * ldv + e];
                 we -= hk[k] * v[k];
             }
         w[e] = we;
 #pragma unroll
-        for (int k = 0; k < DOT_CHUNK; ++k)
+        for (int k = 0; k < NVMAX; ++k)
             if (k < nv) acc[k] += v[k] * we;
-        acc[DOT_CHUNK] += we * we;
+        acc[NVMAX] += we * we;
     }
-    __shared__ double sh[4 * (DOT_CHUNK + 1)];
+    __shared__ double sh[4 * (NVMAX + 1)];
     double mine;
-    block_reduce_multi<DOT_CHUNK + 1>(acc, nv, true, sh, mine);
-    finish_multi<DOT_CHUNK + 1>(mine, nv + 1, partials);
+    block_reduce_multi<NVMAX + 1>(acc, nv, true, sh, mine);
+    finish_multi<NVMAX + 1>(mine, nv + 1, partials);
 }
 
 // Final update and normalization of the new Arnoldi vector:
@@ -1067,7 +1151,9 @@ void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const
         const int last = (done + c == nv);
         const unsigned g = grid_for(len, IRK_RED_BLOCKS);
         const int wn = last ? with_norm : 0;
-        k_dot_multi<<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials, out + done, ctr);
+        if (c <= 4) k_dot_multi<4, 4><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
+        else if (c <= 8) k_dot_multi<8, 2><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
+        else k_dot_multi<DOT_CHUNK, 1><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
         reduce_partials(st, partials, g, c + wn, out + done);
         done += c;
     } while (done < nv);
@@ -1076,7 +1162,9 @@ void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const
 void launch_axpy_dot(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h1, size_t len,
                      double *partials, double *out, unsigned *ctr) {
     const unsigned g = grid_for(len, IRK_RED_BLOCKS);
-    k_axpy_dot<<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials, out, ctr);
+    if (nv <= 4) k_axpy_dot<4, 4><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
+    else if (nv <= 8) k_axpy_dot<8, 2><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
+    else k_axpy_dot<DOT_CHUNK, 1><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
     reduce_partials(st, partials, g, nv + 1, out);
 }
 

@@ -5,10 +5,14 @@
 // state -- the solver workspace (stage vectors, Krylov bases, multigrid
 // hierarchies) plus two state fields -- fits in the caller's device arena.
 // Admitted requests stay resident until their last step; every running
-// request is a non-blocking step state machine with its own HIP streams, and
-// one progress pass advances all of them, so requests that arrive while
+// request is a non-blocking step state machine on its slot's HIP streams,
+// and one progress pass advances all of them, so requests that arrive while
 // others run start as soon as memory and a slot free up and their kernels
-// overlap on the device.  Arithmetic is exactly that of irk_step on the same
+// overlap on the device.  Slots (streams, events, pinned staging) are made
+// when the server is created: admitting a request only enqueues work (the
+// u0 copy, the context's table uploads) and a finished request is retired
+// when an event behind all of its work has completed, so no progress pass
+// waits for the device.  Arithmetic is exactly that of irk_step on the same
 // problem (same kernels, deterministic reductions), so a request's result
 // does not depend on what else is running.
 #include <hip/hip_runtime.h>
@@ -22,11 +26,18 @@
 #include <vector>
 
 #include "irk_internal.h"
+#include "mg_tiled.h"
 
 namespace irk {
 irk_status step_begin(irk_ctx *c, const double *u_n, double t_n, double dt, double tol, double *u_np1);
 int step_poll(irk_ctx *c, irk_status *st, irk_stats *stats);
-void drain_all(irk_ctx *c);
+void *res_new(int nlanes, size_t upload);
+void res_free(void *r);
+size_t res_upload_need(int family, int s, const irk_operator *op, const irk_options *opt);
+irk_status create_in_res(int family, int s, const irk_operator *op, const irk_options *opt, void *ws,
+                         size_t ws_bytes, hipStream_t stream, void *res, irk_ctx **out);
+irk_status record_all_done(irk_ctx *c, hipEvent_t ev);
+void ctx_free(irk_ctx *c);
 void *broker_create(int fp32);
 void broker_destroy(void *b, int fp32);
 int broker_flush(void *b, int fp32);
@@ -90,6 +101,24 @@ class Arena {
     size_t cap_ = 0, used_ = 0;
 };
 
+// A slot: the Newton-level stream and the resource set (block streams,
+// events, pinned staging) one admitted request runs on, made when the server
+// is created so that admitting a request allocates nothing and waits for
+// nothing.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t fin = nullptr;                 // behind all of a finishing request's work
+    void *res = nullptr;
+    bool busy = false;
+};
+
+// largest grid side and eigen-blocks a slot's staging and streams cover
+constexpr int kSlotMaxSide = 16384;
+constexpr int kSlotLanes = 3;                 // eigen-blocks of s <= 5
+// pinned upload area: forcing tables 2 (nx + ny) and the exactly solved
+// Poisson level's basis and eigenvalues
+constexpr size_t kSlotUpload = (size_t)4 * kSlotMaxSide + (size_t)IRK_FDM_MAX * IRK_FDM_MAX + IRK_FDM_MAX;
+
 struct Req {
     long id = 0;
     irk_request r;
@@ -97,10 +126,12 @@ struct Req {
     size_t ws_bytes = 0, field_bytes = 0, off = 0, total = 0;
     bool allocated = false;
     irk_ctx *ctx = nullptr;
-    hipStream_t stream = nullptr;
+    int slot = -1;
+    hipStream_t stream = nullptr;             // the slot's stream
     hipEvent_t u0_ready = nullptr;            // recorded on the caller's stream at submit
     double *ua = nullptr, *ub = nullptr;      // resident state, ping-pong
     double t = 0.0, step_t0 = 0.0;
+    irk_status final_status = IRK_OK;         // while finishing
 };
 
 }  // namespace
@@ -115,7 +146,9 @@ struct irk_server {
     long next_id = 1;
     std::deque<Req *> queue;
     std::vector<Req *> running;
+    std::vector<Req *> finishing;             // done stepping, waiting for their last copy
     std::map<long, Req *> finished;
+    std::vector<Slot> slots;
     std::vector<double> step_ms;              // latency of every completed step
     int peak_running = 0;
     size_t peak_bytes = 0;
@@ -126,19 +159,17 @@ static size_t field_len(const irk_operator &op) {
     return op.kind == IRK_OP_VSF_2D ? 2 * n : n;
 }
 
-static void finish(irk_server *s, Req *q, irk_status st) {
+// the request's slot, arena range and event are free again; its result is
+// final
+static void complete(irk_server *s, Req *q) {
+    const irk_status st = q->final_status;
     q->info.status = st;
     q->info.state = st == IRK_OK ? IRK_REQ_DONE : IRK_REQ_FAILED;
     q->info.t_done = now_s();
-    if (q->ctx) {
-        irk::drain_all(q->ctx);
-        if (st == IRK_OK && q->r.out)
-            (void)hipMemcpyAsync(q->r.out, q->ua, q->field_bytes, hipMemcpyDeviceToDevice, q->stream);
-        if (q->stream) (void)hipStreamSynchronize(q->stream);
-        irk_destroy(q->ctx);
-        q->ctx = nullptr;
-    }
-    if (q->stream) (void)hipStreamDestroy(q->stream);
+    if (q->ctx) irk::ctx_free(q->ctx);
+    q->ctx = nullptr;
+    if (q->slot >= 0) s->slots[q->slot].busy = false;
+    q->slot = -1;
     q->stream = nullptr;
     if (q->u0_ready) (void)hipEventDestroy(q->u0_ready);
     q->u0_ready = nullptr;
@@ -147,9 +178,50 @@ static void finish(irk_server *s, Req *q, irk_status st) {
     s->finished[q->id] = q;
 }
 
+// A request is done stepping (or failed): its result copy and an event
+// behind all of its work are enqueued, and it completes when that event has
+// (progress polls it); nothing here waits for the device.
+static void finish(irk_server *s, Req *q, irk_status st) {
+    q->final_status = st;
+    if (!q->ctx) {
+        complete(s, q);
+        return;
+    }
+    Slot &sl = s->slots[q->slot];
+    if (st == IRK_OK && q->r.out &&
+        hipMemcpyAsync(q->r.out, q->ua, q->field_bytes, hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
+        q->final_status = IRK_E_DEVICE;
+    if (irk::record_all_done(q->ctx, sl.fin) != IRK_OK) {
+        // the event could not be recorded: wait here instead
+        (void)hipDeviceSynchronize();
+        q->final_status = IRK_E_DEVICE;
+        complete(s, q);
+        return;
+    }
+    s->finishing.push_back(q);
+}
+
+static void poll_finishing(irk_server *s) {
+    for (size_t k = 0; k < s->finishing.size();) {
+        Req *q = s->finishing[k];
+        const hipError_t e = hipEventQuery(s->slots[q->slot].fin);
+        if (e == hipErrorNotReady) {
+            ++k;
+            continue;
+        }
+        if (e != hipSuccess) q->final_status = IRK_E_DEVICE;
+        s->finishing.erase(s->finishing.begin() + k);
+        complete(s, q);
+    }
+}
+
 // admit the queue head if a slot and memory are available
 static bool try_admit(irk_server *s) {
     if (s->queue.empty() || (int)s->running.size() >= s->max_slots) return false;
+    int slot = -1;
+    for (int k = 0; k < (int)s->slots.size() && slot < 0; ++k)
+        if (!s->slots[k].busy) slot = k;
+    if (slot < 0) return false;                   // every slot still finishing
     Req *q = s->queue.front();
     if (q->total > s->alloc.capacity()) {          // can never fit
         s->queue.pop_front();
@@ -163,26 +235,24 @@ static bool try_admit(irk_server *s) {
     q->allocated = true;
     q->info.t_admit = now_s();
     q->info.state = IRK_REQ_RUNNING;
+    Slot &sl = s->slots[slot];
+    sl.busy = true;
+    q->slot = slot;
+    q->stream = sl.stream;
     unsigned char *base = s->arena + off;
     q->ua = (double *)base;
     q->ub = (double *)(base + ((q->field_bytes + 255) & ~size_t(255)));
     unsigned char *ws = base + 2 * ((q->field_bytes + 255) & ~size_t(255));
     irk_status st = IRK_OK;
-    if (hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking) != hipSuccess) st = IRK_E_DEVICE;
-    // u0 is read after the work the caller had queued on its stream at submit
-    if (st == IRK_OK && hipStreamWaitEvent(q->stream, q->u0_ready, 0) != hipSuccess) st = IRK_E_DEVICE;
+    // u0 is read after the work the caller had queued on its stream at
+    // submit; everything below only enqueues on the slot's streams
+    if (hipStreamWaitEvent(q->stream, q->u0_ready, 0) != hipSuccess) st = IRK_E_DEVICE;
     if (st == IRK_OK &&
         hipMemcpyAsync(q->ua, q->r.u0, q->field_bytes, hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
         st = IRK_E_DEVICE;
-    if (st == IRK_OK && hipStreamSynchronize(q->stream) != hipSuccess) st = IRK_E_DEVICE;
-    // the shared brokers are created with the first admitted request (they
-    // own a stream and an event each)
-    if (st == IRK_OK && !s->brk32) s->brk32 = irk::broker_create(1);
-    if (st == IRK_OK && !s->brk64) s->brk64 = irk::broker_create(0);
-    if (st == IRK_OK && (!s->brk32 || !s->brk64)) st = IRK_E_DEVICE;
     if (st == IRK_OK)
-        st = irk_create((irk_family)q->r.family, q->r.s, &q->r.op, q->r.use_options ? &q->r.opt : nullptr, ws,
-                        q->ws_bytes, q->stream, &q->ctx);
+        st = irk::create_in_res(q->r.family, q->r.s, &q->r.op, q->r.use_options ? &q->r.opt : nullptr, ws,
+                                q->ws_bytes, q->stream, sl.res, &q->ctx);
     if (st == IRK_OK) (void)irk::attach_broker(q->ctx, s->brk32, s->brk64);
     q->t = q->r.t0;
     if (st == IRK_OK) {
@@ -206,6 +276,23 @@ extern "C" irk_status irk_server_create(void *arena, size_t arena_bytes, int max
     s->arena = (unsigned char *)arena;
     s->alloc.init(arena_bytes & ~size_t(255));
     s->max_slots = max_slots;
+    // every slot's streams, events and pinned staging, and the shared V-cycle
+    // brokers, now: admission then allocates nothing
+    const size_t upload = kSlotUpload;
+    s->slots.resize(max_slots);
+    bool ok = true;
+    for (Slot &sl : s->slots) {
+        ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&sl.fin, hipEventDisableTiming) == hipSuccess &&
+             (sl.res = irk::res_new(kSlotLanes, upload)) != nullptr;
+        if (!ok) break;
+    }
+    s->brk32 = ok ? irk::broker_create(1) : nullptr;
+    s->brk64 = ok ? irk::broker_create(0) : nullptr;
+    if (!ok || !s->brk32 || !s->brk64) {
+        irk_server_destroy(s);
+        return IRK_E_DEVICE;
+    }
     *out = s;
     return IRK_OK;
 }
@@ -214,6 +301,10 @@ extern "C" irk_status irk_server_submit(irk_server *s, const irk_request *r, lon
     if (!s || !r || !id || !r->u0 || !r->out || r->nsteps < 1 || !(r->dt > 0)) return IRK_E_ARG;
     const size_t ws = irk_workspace_bytes((irk_family)r->family, r->s, &r->op, r->use_options ? &r->opt : nullptr);
     if (ws == 0) return IRK_E_ARG;
+    // a slot's staging covers grids of side <= kSlotMaxSide
+    if (r->op.nx > kSlotMaxSide || r->op.ny > kSlotMaxSide ||
+        irk::res_upload_need(r->family, r->s, &r->op, r->use_options ? &r->opt : nullptr) > kSlotUpload)
+        return IRK_E_ARG;
     Req *q = new (std::nothrow) Req();
     if (!q) return IRK_E_NOMEM;
     q->id = s->next_id++;
@@ -241,6 +332,7 @@ static void poll_running(irk_server *s);
 
 extern "C" int irk_server_progress(irk_server *s) {
     if (!s) return -1;
+    poll_finishing(s);
     while (try_admit(s)) {
     }
     poll_running(s);
@@ -248,7 +340,7 @@ extern "C" int irk_server_progress(irk_server *s) {
     // launches; the resumed lanes continue at the next poll
     irk::broker_flush(s->brk32, 1);
     irk::broker_flush(s->brk64, 0);
-    return (int)s->running.size() + (int)s->queue.size();
+    return (int)s->running.size() + (int)s->queue.size() + (int)s->finishing.size();
 }
 
 static void poll_running(irk_server *s) {
@@ -293,6 +385,8 @@ extern "C" irk_status irk_server_info(irk_server *s, long id, irk_request_info *
     }
     for (Req *q : s->running)
         if (q->id == id) { *info = q->info; return IRK_OK; }
+    for (Req *q : s->finishing)
+        if (q->id == id) { *info = q->info; return IRK_OK; }
     for (Req *q : s->queue)
         if (q->id == id) { *info = q->info; return IRK_OK; }
     return IRK_E_ARG;
@@ -314,6 +408,9 @@ extern "C" void irk_server_destroy(irk_server *s) {
     if (!s) return;
     for (Req *q : s->running) finish(s, q, IRK_E_ARG);
     s->running.clear();
+    for (const Slot &sl : s->slots)
+        if (sl.busy && sl.fin) (void)hipEventSynchronize(sl.fin);
+    poll_finishing(s);
     for (Req *q : s->queue) {
         if (q->u0_ready) (void)hipEventDestroy(q->u0_ready);
         delete q;
@@ -321,5 +418,13 @@ extern "C" void irk_server_destroy(irk_server *s) {
     for (auto &kv : s->finished) delete kv.second;
     if (s->brk32) irk::broker_destroy(s->brk32, 1);
     if (s->brk64) irk::broker_destroy(s->brk64, 0);
+    for (Slot &sl : s->slots) {
+        if (sl.res) irk::res_free(sl.res);
+        if (sl.stream) {
+            (void)hipStreamSynchronize(sl.stream);
+            (void)hipStreamDestroy(sl.stream);
+        }
+        if (sl.fin) (void)hipEventDestroy(sl.fin);
+    }
     delete s;
 }

@@ -163,3 +163,79 @@ def test_u0_produced_on_the_callers_stream():
     assert srv.info(rid)["state"] == "done"
     assert torch.equal(srv.result(rid), ref)
     srv.close()
+
+
+def test_admission_waits_for_nothing():
+    """Admitting a request only enqueues work: while the caller's stream is
+    still busy with the work that produces a new request's initial field,
+    progress passes return at once (the request is admitted, its copy waits
+    on the device) and the request already running keeps being served; both
+    results are the same as alone."""
+    import time
+    import torch
+    na, nb = 128, 64
+    opa = irk.make_operator(irk.OP_NLDIFF_2D, na, forcing=irk.FORCING_MMS)
+    opb = irk.make_operator(irk.OP_NLDIFF_2D, nb, forcing=irk.FORCING_MMS)
+    ref_a = _alone("gauss", 3, na, 2e-3, 8, 31)
+    ref_b = _alone("radau", 2, nb, 4e-3, 2, 32)
+    src_b = torch.tensor(inputs.nldiff_random_u0(nb, 32), dtype=torch.float64, device="cuda")
+    big = torch.ones(1 << 27, dtype=torch.float64, device="cuda")       # 1 GiB
+    torch.cuda.synchronize()
+    srv = irk.Server(arena_bytes=1 << 30, max_slots=4)
+    a = srv.submit("gauss", 3, opa, inputs.nldiff_random_u0(na, 31), 2e-3, 8)
+    while srv.info(a)["steps_done"] < 1:
+        srv.progress()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        big.mul_(1.0)                 # tens of milliseconds queued on the caller's stream
+    u0_b = src_b.clone()              # b's initial field, produced after that work
+    b = srv.submit("radau", 2, opb, u0_b, 4e-3, 2)
+    longest, passes = 0.0, 0
+    stream = torch.cuda.current_stream()
+    while not stream.query():
+        t = time.perf_counter()
+        srv.progress()
+        longest = max(longest, time.perf_counter() - t)
+        passes += 1
+    busy = time.perf_counter() - t0
+    state_b = srv.info(b)["state"]
+    print(f"  caller's stream busy {1e3 * busy:.1f} ms: {passes} progress passes, longest "
+          f"{1e3 * longest:.2f} ms, b {state_b}", flush=True)
+    assert busy > 0.02
+    assert state_b in ("running", "done")      # admitted while its u0 was still pending
+    assert longest < 0.25 * busy and longest < 0.02
+    srv.run_until_idle()
+    assert srv.info(a)["state"] == "done" and srv.info(b)["state"] == "done"
+    assert torch.equal(srv.result(a), ref_a)
+    assert torch.equal(srv.result(b), ref_b)
+    srv.close()
+
+
+def test_server_admission_checks():
+    """Request validation, and a request larger than the whole arena fails
+    with IRK_E_NOMEM at admission without touching the arena (whose address
+    is never dereferenced here)."""
+    srv = irk.irk_server_create(256, 1 << 20, 2)
+    req = irk.Request()
+    req.family, req.s = irk.GAUSS, 3
+    req.op = irk.make_operator(irk.OP_NLDIFF_2D, 512, forcing=irk.FORCING_MMS)
+    req.t0, req.dt, req.nsteps, req.tol = 0.0, 5e-3, 2, 0.0
+    req.u0, req.out = 4096, 8192
+    rid = irk.irk_server_submit(srv, req)
+    assert irk.irk_server_progress(srv) == 0
+    info = irk.irk_server_info(srv, rid)
+    assert info["state"] == "failed" and info["status"] == "IRK_E_NOMEM"
+    bad = irk.Request()
+    bad.family, bad.s, bad.op = irk.GAUSS, 3, req.op
+    bad.dt, bad.nsteps, bad.u0, bad.out = 5e-3, 0, 4096, 8192
+    with pytest.raises(irk.IrkError):
+        irk.irk_server_submit(srv, bad)
+    huge = irk.Request()
+    huge.family, huge.s = irk.GAUSS, 2
+    huge.op = irk.make_operator(irk.OP_NLDIFF_2D, 32768, forcing=irk.FORCING_MMS)
+    huge.dt, huge.nsteps, huge.u0, huge.out = 5e-3, 1, 4096, 8192
+    with pytest.raises(irk.IrkError):             # beyond a slot's staging
+        irk.irk_server_submit(srv, huge)
+    st = irk.irk_server_stats(srv)
+    assert st["peak_running"] == 0 and st["peak_bytes"] == 0
+    irk.irk_server_destroy(srv)
