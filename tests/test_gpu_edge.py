@@ -318,7 +318,10 @@ def test_fourier_symbol_at_full_size(family, s):
     want = np.real(np.fft.ifft2(Rz * np.fft.fft2(u0)))
     err = rel(out.cpu().numpy(), want)
     print(f"  {family}-{s} 1024^2: rel err vs R(dt lambda_k) {err:.2e}, {st}")
-    assert err < 1e-6
+    # the nonlinearity u^2 <= (3.8e-4)^2 = 1.4e-7 at its largest, about 1e-8
+    # on average, is what separates the step from the linear symbol (observed
+    # 2.5e-9)
+    assert err < 1e-8
 
 
 def test_gauss_conserves_invariants_on_gpu():
