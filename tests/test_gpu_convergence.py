@@ -48,7 +48,10 @@ def test_gauss5_convergence_at_config_steps():
         print(f"  dt {dt}: err fp64 {e64:.3e} mixed {e32:.3e} |mixed - fp64| {rel(u32, u64):.3e} "
               f"newton/step {n64:.2f} {n32:.2f}")
         assert rel(u32, u64) < 1e-10
-        assert abs(e32 - e64) <= 1e-3 * e64
+        # the same error in both precisions; at dt = 0.01 the error sits at
+        # the float64 rounding floor (about 1e-15), where the two differ by
+        # rounding alone
+        assert abs(e32 - e64) <= max(1e-3 * e64, 1e-14)
     orders = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
     print("  observed orders", orders)
     assert errs[0] > errs[1] > errs[2]
