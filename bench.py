@@ -113,18 +113,23 @@ def ablation(torch, irk, inputs, wl, steps):
     gamma* = eta + beta^2/eta vs gamma = eta in the 2x2 Schur approximation
     (Table 4's comparison), and the Newton-like truncations (0) last stage,
     (1) lumped to the largest stage weight, (2) the row's stage weights,
-    (3) plus the coupling of the rows of a pair; and the adaptive Krylov
-    tolerance against the paper's fixed one.  Preconditioner applications
-    are the paper's cost unit."""
+    (3) plus the coupling of the rows of a pair; (1) and (3) in the real Schur
+    basis (blocks by back-substitution, (3) with the stage-weighted coupling
+    of the blocks); and the adaptive Krylov tolerance against the paper's
+    fixed one.  Preconditioner applications are the paper's cost unit."""
     problem, n, family, s, dt, _, nu = wl
     op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
     res = []
-    variants = [(0, 1, 1, 0), (0, 1, 0, 0), (1, 1, 1, 0), (0, 0, 1, 0), (0, 2, 1, 0), (0, 3, 1, 0)]
+    # (gamma_mode, newton_like, krylov_adaptive, dae_reorder, transform)
+    variants = [(0, 1, 1, 0, 0), (0, 1, 0, 0, 0), (1, 1, 1, 0, 0), (0, 0, 1, 0, 0), (0, 2, 1, 0, 0),
+                (0, 3, 1, 0, 0)]
     if problem == "vsf":
-        variants.append((0, 1, 1, 1))          # the reordered DAE system, eq (vsf-system-2)
-    for gm, nl, ka, ro in variants:
+        variants.append((0, 1, 1, 1, 0))       # the reordered DAE system, eq (vsf-system-2)
+    else:
+        variants += [(0, 1, 1, 0, 1), (0, 3, 1, 0, 1)]   # real Schur basis, back-substitution
+    for gm, nl, ka, ro, tr in variants:
         solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl, krylov_adaptive=ka,
-                                                            dae_reorder=ro))
+                                                            dae_reorder=ro, transform=tr))
         u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
         b = torch.empty_like(u)
         t = 0.0
@@ -140,6 +145,7 @@ def ablation(torch, irk, inputs, wl, steps):
         wall = time.perf_counter() - t0
         solver.close()
         res.append({"gamma": "gamma*" if gm == 0 else "eta", "newton_like": nl,
+                    "basis": "real Schur (back-substitution)" if tr else "eigenbasis (independent blocks)",
                     "krylov_tol": "adaptive" if ka else "fixed",
                     "dae_system": ("reordered (vsf-system-2)" if ro else "whole (vsf-system-1)") if problem == "vsf"
                     else None,

@@ -164,6 +164,18 @@ typedef struct irk_options {
                                vorticity rows (preconditioned by L_P), then
                                one of the streamfunction rows (a Poisson
                                V-cycle per row as preconditioner)          */
+    int transform;          /* 0: the real eigenbasis of A0^{-1} (blocks
+                               independent, solved concurrently); 1: the
+                               real Schur basis (Section 3.1, irk_schur_
+                               blocks): the blocks are solved last to first
+                               by back-substitution (Section 5, equation
+                               (D+U)), each block's right-hand side losing
+                               R0_ij M y_j for every solved block j (and,
+                               under Newton-like (3), the stage-weighted
+                               Jacobian terms -dt sum_k d_rq,k L(U_k) y_j
+                               of the truncation to R0's block-upper
+                               pattern).  Burgers and nonlinear diffusion
+                               only (IRK_E_UNSUPPORTED otherwise)          */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -208,7 +220,7 @@ const char *irk_status_str(irk_status st);
  * cheb_degree 3, mg_coarsest 16, coarse_iters 24, batch_mg 0 (shared
  * launches couple the blocks' progress and were measured slower on the
  * bench workloads; see the option), start_extrapolate 1, krylov_adaptive 1,
- * dae_reorder 0.                                                           */
+ * dae_reorder 0, transform 0.                                              */
 void irk_default_options(irk_options *opt);
 
 /* Butcher tableau of the s-stage method (Section 1.1): A row-major s x s,
@@ -229,6 +241,16 @@ irk_status irk_tableau(irk_family family, int s, double *A, double *b, double *c
 irk_status irk_eigen_blocks(irk_family family, int s, double *T, double *Tinv,
                             int *nblocks, int *width, double *eta, double *beta,
                             double *gamma_star, int *first_row);
+
+/* Real Schur basis of A0^{-1} (Section 3.1): A0^{-1} = Q0 R0 Q0^T with Q0
+ * orthogonal and R0 block upper triangular, its diagonal blocks those of
+ * irk_eigen_blocks in the same order (eta, or [[eta, phi], [-beta^2/phi,
+ * eta]] with |phi| <= beta: the standardized form), the blocks above the
+ * diagonal coupling them.  Built from the real eigenbasis by Gram-Schmidt
+ * (long double); each column's largest entry positive.  Host outputs Q0, R0
+ * (s x s row-major).  IRK_E_ARG for IRK_SDIRK or bad s.  The option
+ * `transform` = 1 runs the Newton-like iteration in this basis.          */
+irk_status irk_schur_blocks(irk_family family, int s, double *Q0, double *R0);
 
 /* Bytes of device workspace irk_create needs for this problem (0 on bad
  * arguments).                                                               */

@@ -98,6 +98,9 @@ struct Plan {
     bool weighted = false;
     double hier_w[IRK_MAX_STAGES][IRK_MAX_STAGES];
     BlockWeights blk_w[IRK_MAX_STAGES];
+    // real Schur basis: the blocks of R0 above the diagonal, cpl[i][j] for
+    // i < j, applied in the back-substitution
+    BlockCouple cpl[IRK_MAX_STAGES][IRK_MAX_STAGES];
     size_t off_K, off_Y, off_Fh, off_U, off_part, off_dv, off_tab, off_K2 = 0;
     size_t off_coef[IRK_MAX_STAGES][IRK_MAX_LEVELS];
     LaneLayout lane[IRK_MAX_STAGES];
@@ -117,7 +120,7 @@ static bool valid_options(const irk_options &o) {
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
            (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1) &&
-           (o.dae_reorder == 0 || o.dae_reorder == 1);
+           (o.dae_reorder == 0 || o.dae_reorder == 1) && (o.transform == 0 || o.transform == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -147,9 +150,15 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         for (int i = 0; i < s; ++i) { P->sd_b[i] = (double)b[i]; P->sd_c[i] = (double)c[i]; }
         build_sdirk_stage_block(P->sd_A[0], P->sd_c[0], &P->eb);
         s = 1;
+    } else if (P->opt.transform == 1) {
+        // the real Schur basis: blocks solved by back-substitution (ODE
+        // operators; the DAE's constraint rows are not coupled this way)
+        if (o.kind == IRK_OP_VSF_2D) return IRK_E_UNSUPPORTED;
+        if (!build_schur_blocks(family, s, &P->eb)) return IRK_E_ARG;
     } else if (!build_eigen_blocks(family, s, &P->eb)) {
         return IRK_E_ARG;
     }
+    if (family == IRK_SDIRK && P->opt.transform == 1) return IRK_E_UNSUPPORTED;
     for (int k = 0; k < P->eb.nblocks; ++k)
         if (!(P->eb.eta[k] > 0)) return IRK_E_UNSUPPORTED;     // Assumption 1
     P->family = family;
@@ -178,12 +187,12 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         }
     }
     // VSF streamfunction rows: the Poisson V-cycles stop at the first level
-    // below the finest one of side <= IRK_FDM_MAX (at or above the
-    // sub-cycle's) and solve it exactly
+    // below the finest one of side <= IRK_FDM_MAX and a multiple of 4 (at or
+    // above the sub-cycle's) and solve it exactly
     P->fdm_level = 0;
     if (o.kind == IRK_OP_VSF_2D)
         for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
-            if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] == P->lg.ny[l]) {
+            if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] % 4 == 0 && P->lg.nx[l] == P->lg.ny[l]) {
                 P->fdm_level = l;
                 break;
             }
@@ -223,6 +232,27 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
             P->row_hier[r] = hidx;
         }
         for (int q = 0; q < P->nhier; ++q) P->hier_w[q][P->hier_stage[q]] = 1.0;
+    }
+    // back-substitution couplings of the real Schur basis: R0_ij M, and under
+    // Newton-like (3) also -dt sum_k d_rq,k L(U_k) for rows r of block i and
+    // columns q of block j (d_rq,k = (Q0^T)_rk (Q0)_kq; equation (Q0approx))
+    std::memset(P->cpl, 0, sizeof(P->cpl));
+    if (P->eb.schur) {
+        const double *T = P->eb.T, *Ti = P->eb.Tinv;
+        for (int i = 0; i < P->eb.nblocks; ++i)
+            for (int j = i + 1; j < P->eb.nblocks; ++j) {
+                BlockCouple &C = P->cpl[i][j];
+                const int fi = P->eb.first[i], fj = P->eb.first[j];
+                C.wi = P->eb.width[i];
+                C.wj = P->eb.width[j];
+                C.jac = P->opt.newton_like == 3 && s > 1;
+                for (int a = 0; a < C.wi; ++a)
+                    for (int q = 0; q < C.wj; ++q) {
+                        C.R[a][q] = P->eb.R[(fi + a) * s + fj + q];
+                        if (C.jac)
+                            for (int k = 0; k < s; ++k) C.W.w[a][q][k] = Ti[(fi + a) * s + k] * T[k * s + fj + q];
+                    }
+            }
     }
 
     // workspace layout
@@ -739,6 +769,14 @@ static void vcycle(irk_ctx *c, Lane &ln, int opk, double sigma, double dtop, int
     run_vcjob<T>(c, J);
 }
 
+static BlockLam block_lam(const EigenBlocks &eb, int blk) {
+    BlockLam l;
+    l.eta = eb.eta[blk];
+    l.c12 = eb.c12[blk];
+    l.c21 = eb.c21[blk];
+    return l;
+}
+
 static int mg_op_of(int kind) {
     return kind == IRK_OP_NLDIFF_2D ? MG_NLDIFF : (kind == IRK_OP_BURGERS_1D ? MG_BURGERS : MG_VSF_OMEGA);
 }
@@ -804,19 +842,19 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
         ++nvc;
     }
     if (eb.width[blk] == 2) {
-        const double beta = eb.beta[blk];
         const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eta;
         const int hb = P.row_hier[r + 1];
         if (ln.tmp) {
-            // Newton-like (3): the (2,1) block of D is -beta M - dt sum_k
+            // Newton-like (3): the (2,1) block of D is c21 M - dt sum_k
             // d_21,k L_k; its negation applied to z1 joins the right-hand side
             PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">",
                  8.0 * P.npts * (2.0 + P.s * P.nvar), 1,
-                 launch_block_matvec_w(ln.stream, c->dp, P.s, 1, 0.0, beta, c->dt, c->U, P.blk_w[blk], z, ln.tmp,
-                                       nullptr, 1));
+                 launch_block_matvec_w(ln.stream, c->dp, P.s, 1, block_lam(eb, blk), c->dt, c->U, P.blk_w[blk], z,
+                                       ln.tmp, nullptr, 1));
             prec_component<T>(c, ln, z + nf, v + nf, 1.0, ln.tmp, 1.0, gam, hb);
         } else {
-            prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, beta, gam, hb);
+            // the (2,1) block c21 M (eigenbasis: -beta M) moved to the right
+            prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, -eb.c21[blk], gam, hb);
         }
         ++nvc;
         if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf); ++nvc; }
@@ -860,11 +898,11 @@ static int apply_prec_mode(irk_ctx *c, Lane &ln, const double *v, double *z, int
             if (ln.tmp) {
                 PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">",
                      8.0 * npts * (2.0 + P.s * P.nvar), 1,
-                     launch_block_matvec_w(ln.stream, c->dp, P.s, 1, 0.0, eb.beta[blk], c->dt, c->U, P.blk_w[blk], z,
-                                           ln.tmp, nullptr, 1));
+                     launch_block_matvec_w(ln.stream, c->dp, P.s, 1, block_lam(eb, blk), c->dt, c->U, P.blk_w[blk],
+                                           z, ln.tmp, nullptr, 1));
                 prec_component<T>(c, ln, z + nf, v + nf, 1.0, ln.tmp, 1.0, gam, P.row_hier[r + 1]);
             } else {
-                prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, eb.beta[blk], gam, P.row_hier[r + 1]);
+                prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, -eb.c21[blk], gam, P.row_hier[r + 1]);
             }
             ++nvc;
         }
@@ -898,14 +936,14 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
         // reads x, w (width * nvar fields each) and the s stage fields
         const double byw = 8.0 * P.npts * (2.0 * width * P.nvar + P.s * P.nvar);
         PROF(c, ln.stream, "k_block_matvec_w<" + std::to_string(P.op.kind) + ">", byw, 1,
-             launch_block_matvec_w(ln.stream, c->dp, P.s, width, eb.eta[blk], eb.beta[blk], c->dt, c->U,
-                                   P.blk_w[blk], x, w, xm, 0));
+             launch_block_matvec_w(ln.stream, c->dp, P.s, width, block_lam(eb, blk), c->dt, c->U, P.blk_w[blk], x,
+                                   w, xm, 0));
         return;
     }
     // reads x and writes w (width * nvar fields each), reads one linearization field per component
     const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0);
     PROF(c, ln.stream, "k_block_matvec<" + std::to_string(P.op.kind) + ">", by, 1,
-         launch_block_matvec(ln.stream, c->dp, width, eb.eta[blk], eb.beta[blk], c->dt, Ua, Ub, x, w, xm));
+         launch_block_matvec(ln.stream, c->dp, width, block_lam(eb, blk), c->dt, Ua, Ub, x, w, xm));
 }
 
 // ---------------------------------------------------------------------------
@@ -1065,8 +1103,8 @@ struct Fgmres {
             make_vcjob<T>(c, *ln, opk, eb.eta[blk], c->dt, P.row_hier[r], in, out, &jobs.back());
         } else if (eb.width[blk] == 2) {
             const double gam = P.opt.gamma_mode == 0 ? eb.gamma_star[blk] : eb.eta[blk];
-            in.v1 = pend_v + nf; in.a1 = 1.0; in.v2 = pend_z; in.a2 = eb.beta[blk];
-            out.z = pend_z + nf; out.v1 = pend_v + nf; out.a1 = 1.0; out.v2 = pend_z; out.a2 = eb.beta[blk];
+            in.v1 = pend_v + nf; in.a1 = 1.0; in.v2 = pend_z; in.a2 = -eb.c21[blk];
+            out.z = pend_z + nf; out.v1 = pend_v + nf; out.a1 = 1.0; out.v2 = pend_z; out.a2 = -eb.c21[blk];
             jobs.emplace_back();
             make_vcjob<T>(c, *ln, opk, gam, c->dt, P.row_hier[r + 1], in, out, &jobs.back());
         }
@@ -1341,6 +1379,8 @@ struct Stepper : StepperBase {
     int ncand = 2;
     Fgmres<T> fg[IRK_MAX_STAGES];
     bool lane_done[IRK_MAX_STAGES];
+    bool lane_started[IRK_MAX_STAGES];
+    double block_ktol = 1e-5;
 
     explicit Stepper(irk_ctx *cc) : c(cc) {}
 
@@ -1567,15 +1607,43 @@ struct Stepper : StepperBase {
         // forcing term: solving further cannot change the accepted stages)
         double ktol = P.opt.krylov_rtol;
         if (P.opt.krylov_adaptive) ktol = std::min(0.1, std::max(ktol, 0.1 * std::max(thresh, floor_res) / res));
+        block_ktol = ktol;
         for (int b = 0; b < c->nlanes; ++b) {
             lane_done[b] = false;
+            lane_started[b] = false;
             if (hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0) != hipSuccess) return fail(IRK_E_DEVICE);
-            fg[b].init(c, &c->lanes[b], ktol, P.opt.max_krylov);
-            const irk_status e = fg[b].start();
+            // real Schur basis: back-substitution, the last block first
+            if (P.eb.schur && b != c->nlanes - 1) continue;
+            const irk_status e = start_block(b);
             if (e != IRK_OK) return fail(e);
         }
         phase = BLOCKS;
         return false;
+    }
+
+    irk_status start_block(int b) {
+        lane_started[b] = true;
+        fg[b].init(c, &c->lanes[b], block_ktol, c->P.opt.max_krylov);
+        return fg[b].start();
+    }
+
+    // real Schur basis, block b solved: every earlier block's right-hand side
+    // loses its coupling to y_b (on b's stream), then block b - 1 starts
+    // after it
+    irk_status back_substitute(int b) {
+        const Plan &P = c->P;
+        const size_t nf = P.nf;
+        Lane &ln = c->lanes[b];
+        const double *yb = c->Y + (size_t)P.eb.first[b] * nf;
+        for (int i = 0; i < b; ++i) {
+            const BlockCouple &C = P.cpl[i][b];
+            PROF(c, ln.stream, "k_block_couple<" + std::to_string(P.op.kind) + ">",
+                 8.0 * nf * (C.wj + 2 * C.wi + (C.jac ? P.s : 0)), 1,
+                 launch_block_couple(ln.stream, c->dp, P.s, C, c->dt, c->U, yb, c->Fh + (size_t)P.eb.first[i] * nf));
+        }
+        HIP_TRY(hipEventRecord(ln.done, ln.stream));
+        HIP_TRY(hipStreamWaitEvent(c->lanes[b - 1].stream, ln.done, 0));
+        return start_block(b - 1);
     }
 
     bool poll() override {
@@ -1596,7 +1664,7 @@ struct Stepper : StepperBase {
             // BLOCKS: advance every lane whose readback has landed
             bool progressed = false;
             for (int b = 0; b < c->nlanes; ++b) {
-                if (lane_done[b]) continue;
+                if (lane_done[b] || !lane_started[b]) continue;
                 if (fg[b].deferred != IRK_OK) return fail(fg[b].deferred);
                 if (fg[b].phase == Fgmres<T>::WAIT_PREC) continue;      // in a broker batch
                 const hipError_t q = hipEventQuery(c->lanes[b].ev);
@@ -1613,6 +1681,10 @@ struct Stepper : StepperBase {
                 if (fg[b].phase == Fgmres<T>::DONE) {
                     lane_done[b] = true;
                     --active;
+                    if (P.eb.schur && b > 0) {
+                        e = back_substitute(b);
+                        if (e != IRK_OK) return fail(e);
+                    }
                     if (hipEventRecord(c->lanes[b].done, c->lanes[b].stream) != hipSuccess ||
                         hipStreamWaitEvent(c->stream, c->lanes[b].done, 0) != hipSuccess)
                         return fail(IRK_E_DEVICE);
@@ -1776,6 +1848,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->start_extrapolate = 1;
     o->krylov_adaptive = 1;
     o->dae_reorder = 0;
+    o->transform = 0;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
@@ -2007,7 +2080,8 @@ static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait,
     // a private broker batches the V-cycles of this context's blocks
     // (Newton-like (3) pairs apply an operator between their two V-cycles:
     // they are not batched)
-    if (private_broker && P.opt.batch_mg && c->nlanes > 1 && P.op.kind != IRK_OP_VSF_2D && P.opt.newton_like != 3) {
+    if (private_broker && P.opt.batch_mg && c->nlanes > 1 && P.op.kind != IRK_OP_VSF_2D && P.opt.newton_like != 3 &&
+        !P.eb.schur) {
         bool ok;
         if (P.opt.prec_fp32) {
             auto *b = new (std::nothrow) PrecBroker<float>();
@@ -2194,7 +2268,8 @@ int broker_flush(void *b, int fp32) {
 // Let a context's blocks join a shared broker (replacing its private one);
 // false when the context does not batch (option off, or the DAE operator).
 bool attach_broker(irk_ctx *c, void *fp32_broker, void *fp64_broker) {
-    if (!c->P.opt.batch_mg || c->P.op.kind == IRK_OP_VSF_2D || c->P.opt.newton_like == 3) return false;
+    if (!c->P.opt.batch_mg || c->P.op.kind == IRK_OP_VSF_2D || c->P.opt.newton_like == 3 || c->P.eb.schur)
+        return false;
     if (c->broker_owned) {
         if (c->P.opt.prec_fp32) delete static_cast<PrecBroker<float> *>(c->broker);
         else delete static_cast<PrecBroker<double> *>(c->broker);

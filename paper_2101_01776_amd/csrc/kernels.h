@@ -37,14 +37,18 @@ void launch_field_sums(hipStream_t st, const double *X, size_t ld, int nfields, 
 // out[0] = scale * sum X0, out[1] = scale * sum X1 (len each)
 void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size_t len, double scale,
                         double *partials, double *out);
-void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
+void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
 // Eigen-block operator with stage-weighted linearizations (U: the s stage
-// fields); coupling = 1 gives beta M x_0 + dt sum_k W[1][0][k] L(U_k) x_0 on
+// fields); coupling = 1 gives -c21 M x_0 + dt sum_k W[1][0][k] L(U_k) x_0 on
 // the differential variable instead
-void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, const BlockLam &lam,
                            double dt, const double *U, const BlockWeights &W, const double *x, double *w,
                            const double *xmeans, int coupling);
+// f (block i's wi components) -= (R_ij M - dt sum_k W L(U_k)) y (block j's wj
+// components): the back-substitution of the real Schur basis (ODE operators)
+void launch_block_couple(hipStream_t st, const DeviceProblem &P, int s, const BlockCouple &C, double dt,
+                         const double *U, const double *y, double *f);
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
                       int with_norm, double *partials, double *out, unsigned *ctr);
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);

@@ -578,14 +578,16 @@ __global__ void __launch_bounds__(IRK_WG) k_field_sums2(const double *__restrict
 // ------------------------------------------------------------------------
 // Eigen-block matvec w = D_b x (float64).
 //   width 1: w = eta M x - dt L_a x
-//   width 2: w_a = eta M x_a + beta M x_b - dt L_a x_a
-//            w_b = -beta M x_a + eta M x_b - dt L_b x_b
+//   width 2: w_a = eta M x_a + c12 M x_b - dt L_a x_a
+//            w_b = c21 M x_a + eta M x_b - dt L_b x_b
+// (eigenbasis: c12 = beta, c21 = -beta; real Schur basis: the standardized
+// block's phi and -beta^2/phi)
 // For VSF each component is (omega, psi); omega rows use the Picard
 // linearization K(Psi_m) = J_A(Psi_m, .) + nu Lap, psi rows
 // -dt [(x_omega - mean x_omega) + Lap x_psi - mean x_psi] (mass 0).
 // ------------------------------------------------------------------------
 template <int OP>
-__global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int width, double eta, double beta,
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int width, BlockLam lam,
                                                          double dt, const double *__restrict__ Ua,
                                                          const double *__restrict__ Ub,
                                                          const double *__restrict__ x, double *__restrict__ w,
@@ -610,10 +612,10 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int wi
             xc[comp] = xx[p];
         }
         if (width == 1) {
-            w[p] = eta * xc[0] - dt * Lx[0];
+            w[p] = lam.eta * xc[0] - dt * Lx[0];
         } else {
-            w[p] = eta * xc[0] + beta * xc[1] - dt * Lx[0];
-            w[nf + p] = -beta * xc[0] + eta * xc[1] - dt * Lx[1];
+            w[p] = lam.eta * xc[0] + lam.c12 * xc[1] - dt * Lx[0];
+            w[nf + p] = lam.c21 * xc[0] + lam.eta * xc[1] - dt * Lx[1];
         }
         if constexpr (NV == 2) {
             for (int comp = 0; comp < width; ++comp) {
@@ -629,15 +631,15 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int wi
 
 // Eigen-block operator with stage-weighted linearizations (Newton-like (2),
 // (3)): L_kb = L(U_k) x_b at the point for every stage k and component b,
-//   coupling = 0:  w_a = eta M x_a (+ beta M x_1 | - beta M x_0)
+//   coupling = 0:  w_a = eta M x_a (+ c12 M x_1 | + c21 M x_0)
 //                        - dt sum_b sum_k W[a][b][k] L_kb
 //                  (the algebraic rows of the DAE as in k_block_matvec);
-//   coupling = 1:  w = beta M x_0 + dt sum_k W[1][0][k] L_k0 on the
+//   coupling = 1:  w = -c21 M x_0 + dt sum_k W[1][0][k] L_k0 on the
 //                  differential variable only (the negated (2,1) block of the
 //                  pair applied to x_0: the second row's right-hand side of
 //                  the block-triangular preconditioner).
 template <int OP, int S>
-__global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int width, double eta, double beta,
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int width, BlockLam lam,
                                                            double dt, const double *__restrict__ U,
                                                            BlockWeights W, const double *__restrict__ x,
                                                            double *__restrict__ w,
@@ -671,14 +673,14 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
             }
         }
         if (coupling) {
-            w[p] = beta * xc[0] + dt * acc[0];
+            w[p] = -lam.c21 * xc[0] + dt * acc[0];
             continue;
         }
         if (width == 1) {
-            w[p] = eta * xc[0] - dt * acc[0];
+            w[p] = lam.eta * xc[0] - dt * acc[0];
         } else {
-            w[p] = eta * xc[0] + beta * xc[1] - dt * acc[0];
-            w[nf + p] = -beta * xc[0] + eta * xc[1] - dt * acc[1];
+            w[p] = lam.eta * xc[0] + lam.c12 * xc[1] - dt * acc[0];
+            w[nf + p] = lam.c21 * xc[0] + lam.eta * xc[1] - dt * acc[1];
         }
         if constexpr (NV == 2) {
             for (int comp = 0; comp < width; ++comp) {
@@ -689,6 +691,42 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
                 w[comp * nf + npts + p] = -dt * ((xc[comp] - mw) + lp - mp);
             }
         }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Block back-substitution in the real Schur basis (ODE operators): the
+// right-hand side of block i loses the coupling to the solved block j,
+//   f_a <- f_a - sum_b (R_ab y_b - dt sum_k W[a][b][k] L(U_k) y_b),
+// a < wi, b < wj (the Jacobian terms only when C.jac).
+// ------------------------------------------------------------------------
+template <int OP, int S>
+__global__ void __launch_bounds__(IRK_WG) k_block_couple(DeviceProblem P, BlockCouple C, double dt,
+                                                         const double *__restrict__ U, const double *__restrict__ y,
+                                                         double *__restrict__ f) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t nf = (size_t)nx * ny;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < nf; p += stride) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double acc[2] = {0.0, 0.0};
+        for (int b = 0; b < C.wj; ++b) {
+            const double *yb = y + b * nf;
+            const double yc = yb[p];
+            for (int a = 0; a < C.wi; ++a) acc[a] += C.R[a][b] * yc;
+            if (C.jac) {
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const double *Uk = U + (size_t)k * nf;
+                    double lx, ld;
+                    if constexpr (OP == IRK_OP_NLDIFF_2D) nldiff_lin<double, true>(Uk, yb, i, j, nx, ny, inv_h2, lx, ld);
+                    else burgers_lin<double, true>(Uk, yb, i, nx, h, P.g.nu, lx, ld);
+                    for (int a = 0; a < C.wi; ++a) acc[a] -= dt * C.W.w[a][b][k] * lx;
+                }
+            }
+        }
+        for (int a = 0; a < C.wi; ++a) f[a * nf + p] -= acc[a];
     }
 }
 
@@ -1105,41 +1143,60 @@ void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size
     reduce_partials(st, partials, g, 2, out);
 }
 
-void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, double eta, double beta, double dt,
+void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans) {
     const size_t npts = (size_t)P.g.nx * P.g.ny;
     const unsigned g = grid_for(npts);
     if (P.kind == IRK_OP_NLDIFF_2D)
-        k_block_matvec<IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+        k_block_matvec<IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
     else if (P.kind == IRK_OP_BURGERS_1D)
-        k_block_matvec<IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+        k_block_matvec<IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
     else
-        k_block_matvec<IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, Ua, Ub, x, w, xmeans);
+        k_block_matvec<IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
 }
 
 template <int OP>
-static void block_matvec_w_op(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+static void block_matvec_w_op(hipStream_t st, const DeviceProblem &P, int s, int width, const BlockLam &lam,
                               double dt, const double *U, const BlockWeights &W, const double *x, double *w,
                               const double *xmeans, int coupling) {
     const unsigned g = grid_for((size_t)P.g.nx * P.g.ny);
     switch (s) {
-        case 1: k_block_matvec_w<OP, 1><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
-        case 2: k_block_matvec_w<OP, 2><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
-        case 3: k_block_matvec_w<OP, 3><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
-        case 4: k_block_matvec_w<OP, 4><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
-        case 5: k_block_matvec_w<OP, 5><<<g, IRK_WG, 0, st>>>(P, width, eta, beta, dt, U, W, x, w, xmeans, coupling); break;
+        case 1: k_block_matvec_w<OP, 1><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, U, W, x, w, xmeans, coupling); break;
+        case 2: k_block_matvec_w<OP, 2><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, U, W, x, w, xmeans, coupling); break;
+        case 3: k_block_matvec_w<OP, 3><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, U, W, x, w, xmeans, coupling); break;
+        case 4: k_block_matvec_w<OP, 4><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, U, W, x, w, xmeans, coupling); break;
+        case 5: k_block_matvec_w<OP, 5><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, U, W, x, w, xmeans, coupling); break;
     }
 }
 
-void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, double eta, double beta,
+void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int width, const BlockLam &lam,
                            double dt, const double *U, const BlockWeights &W, const double *x, double *w,
                            const double *xmeans, int coupling) {
     if (P.kind == IRK_OP_NLDIFF_2D)
-        block_matvec_w_op<IRK_OP_NLDIFF_2D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+        block_matvec_w_op<IRK_OP_NLDIFF_2D>(st, P, s, width, lam, dt, U, W, x, w, xmeans, coupling);
     else if (P.kind == IRK_OP_BURGERS_1D)
-        block_matvec_w_op<IRK_OP_BURGERS_1D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+        block_matvec_w_op<IRK_OP_BURGERS_1D>(st, P, s, width, lam, dt, U, W, x, w, xmeans, coupling);
     else
-        block_matvec_w_op<IRK_OP_VSF_2D>(st, P, s, width, eta, beta, dt, U, W, x, w, xmeans, coupling);
+        block_matvec_w_op<IRK_OP_VSF_2D>(st, P, s, width, lam, dt, U, W, x, w, xmeans, coupling);
+}
+
+template <int OP>
+static void block_couple_op(hipStream_t st, const DeviceProblem &P, int s, const BlockCouple &C, double dt,
+                            const double *U, const double *y, double *f) {
+    const unsigned g = grid_for((size_t)P.g.nx * P.g.ny);
+    switch (s) {
+        case 1: k_block_couple<OP, 1><<<g, IRK_WG, 0, st>>>(P, C, dt, U, y, f); break;
+        case 2: k_block_couple<OP, 2><<<g, IRK_WG, 0, st>>>(P, C, dt, U, y, f); break;
+        case 3: k_block_couple<OP, 3><<<g, IRK_WG, 0, st>>>(P, C, dt, U, y, f); break;
+        case 4: k_block_couple<OP, 4><<<g, IRK_WG, 0, st>>>(P, C, dt, U, y, f); break;
+        case 5: k_block_couple<OP, 5><<<g, IRK_WG, 0, st>>>(P, C, dt, U, y, f); break;
+    }
+}
+
+void launch_block_couple(hipStream_t st, const DeviceProblem &P, int s, const BlockCouple &C, double dt,
+                         const double *U, const double *y, double *f) {
+    if (P.kind == IRK_OP_NLDIFF_2D) block_couple_op<IRK_OP_NLDIFF_2D>(st, P, s, C, dt, U, y, f);
+    else if (P.kind == IRK_OP_BURGERS_1D) block_couple_op<IRK_OP_BURGERS_1D>(st, P, s, C, dt, U, y, f);
 }
 
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,

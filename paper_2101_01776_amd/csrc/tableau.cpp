@@ -346,6 +346,128 @@ static std::vector<cld> null_vector(int n, const ld *M, cld lam) {
     return v;
 }
 
+// Real Schur basis of A0^{-1} (Section 3.1): A0^{-1} = Q0 R0 Q0^T with Q0
+// orthogonal and R0 block upper triangular.  Built from the real eigenbasis
+// T (blocks in its order: real eigenvalues, then pairs by decreasing beta):
+// T = Q R (Gram-Schmidt), so Q^T A0^{-1} Q = R Lambda R^{-1} is block upper
+// triangular; each 2x2 diagonal block is then rotated to equal diagonal
+// entries [[eta, phi], [-beta^2/phi, eta]], with a quarter turn if needed so
+// that |phi| <= beta (the standardized form), and every column's sign is
+// fixed so that its largest entry is positive.
+bool build_schur_blocks(int family, int s, EigenBlocks *eb) {
+    EigenBlocks e;
+    if (!build_eigen_blocks(family, s, &e)) return false;
+    ld Q[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    for (int i = 0; i < s * s; ++i) Q[i] = e.T[i];
+    // modified Gram-Schmidt on the columns, twice (long double)
+    for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < s; ++j) {
+            for (int q = 0; q < j; ++q) {
+                ld dot = 0;
+                for (int i = 0; i < s; ++i) dot += Q[i * s + q] * Q[i * s + j];
+                for (int i = 0; i < s; ++i) Q[i * s + j] -= dot * Q[i * s + q];
+            }
+            ld nrm = 0;
+            for (int i = 0; i < s; ++i) nrm += Q[i * s + j] * Q[i * s + j];
+            nrm = sqrtl(nrm);
+            if (!(nrm > 0)) return false;
+            for (int i = 0; i < s; ++i) Q[i * s + j] /= nrm;
+        }
+    ld Ai[IRK_MAX_STAGES * IRK_MAX_STAGES], R[IRK_MAX_STAGES * IRK_MAX_STAGES];
+    for (int i = 0; i < s * s; ++i) Ai[i] = e.Ainv[i];
+    {   // a long double A0^{-1} (the float64 copy costs digits)
+        ld A[IRK_MAX_STAGES * IRK_MAX_STAGES], b[IRK_MAX_STAGES], c[IRK_MAX_STAGES];
+        if (!build_tableau_ld(family, s, A, b, c) || !invert_ld(s, A, Ai)) return false;
+    }
+    auto rform = [&]() {                   // R = Q^T A0^{-1} Q
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) {
+                ld acc = 0;
+                for (int k = 0; k < s; ++k) {
+                    ld t = 0;
+                    for (int l = 0; l < s; ++l) t += Ai[k * s + l] * Q[l * s + j];
+                    acc += Q[k * s + i] * t;
+                }
+                R[i * s + j] = acc;
+            }
+    };
+    auto rotate = [&](int r, ld cs, ld sn) {    // Q <- Q G on columns r, r+1
+        for (int i = 0; i < s; ++i) {
+            const ld a = Q[i * s + r], b = Q[i * s + r + 1];
+            Q[i * s + r] = cs * a + sn * b;
+            Q[i * s + r + 1] = -sn * a + cs * b;
+        }
+    };
+    rform();
+    for (int k = 0; k < e.nblocks; ++k) {
+        if (e.width[k] != 2) continue;
+        const int r = e.first[k];
+        const ld p = R[r * s + r], q = R[r * s + r + 1], u = R[(r + 1) * s + r], t = R[(r + 1) * s + r + 1];
+        // G = [[cos, -sin], [sin, cos]]: a' - d' = (p - t) cos 2th + (q + u) sin 2th = 0
+        const ld th = 0.5L * atan2l(-(p - t), q + u);
+        rotate(r, cosl(th), sinl(th));
+        rform();
+        if (fabsl(R[r * s + r + 1]) > fabsl(R[(r + 1) * s + r])) {     // quarter turn
+            rotate(r, 0.0L, 1.0L);
+            rform();
+        }
+    }
+    for (int j = 0; j < s; ++j) {          // sign: largest entry of each column positive
+        int ib = 0;
+        ld big = 0;
+        for (int i = 0; i < s; ++i)
+            if (fabsl(Q[i * s + j]) > big) { big = fabsl(Q[i * s + j]); ib = i; }
+        if (Q[ib * s + j] < 0)
+            for (int i = 0; i < s; ++i) Q[i * s + j] = -Q[i * s + j];
+    }
+    rform();
+    *eb = e;
+    eb->schur = true;
+    for (int k = 0; k < e.nblocks; ++k) {
+        const int r = e.first[k];
+        if (e.width[k] == 2) {
+            eb->eta[k] = (double)(0.5L * (R[r * s + r] + R[(r + 1) * s + r + 1]));
+            eb->c12[k] = (double)R[r * s + r + 1];
+            eb->c21[k] = (double)R[(r + 1) * s + r];
+            eb->beta[k] = (double)sqrtl(fmaxl(-R[r * s + r + 1] * R[(r + 1) * s + r], 0.0L));
+        } else {
+            eb->eta[k] = (double)R[r * s + r];
+            eb->c12[k] = eb->c21[k] = 0.0;
+            eb->beta[k] = 0.0;
+        }
+        eb->gamma_star[k] = eb->eta[k] + eb->beta[k] * eb->beta[k] / eb->eta[k];
+    }
+    // R0 with its entries below the block diagonal (rounding level) dropped
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+            int bi = 0, bj = 0;
+            for (int k = 0; k < e.nblocks; ++k) {
+                if (i >= e.first[k] && i < e.first[k] + e.width[k]) bi = k;
+                if (j >= e.first[k] && j < e.first[k] + e.width[k]) bj = k;
+            }
+            eb->R[i * s + j] = bj < bi ? 0.0 : (double)R[i * s + j];
+        }
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+            ld tl = 0;
+            for (int q = 0; q < s; ++q) tl += Q[i * s + q] * (ld)eb->R[q * s + j];
+            eb->TLam[i * s + j] = (double)tl;
+            eb->T[i * s + j] = (double)Q[i * s + j];
+            eb->Tinv[i * s + j] = (double)Q[j * s + i];
+        }
+    for (int k = 0; k < s; ++k) {              // Newton-like (1) stage of each row
+        ld dk[IRK_MAX_STAGES], big = 0;
+        for (int i = 0; i < s; ++i) {
+            dk[i] = Q[i * s + k] * Q[i * s + k];
+            if (dk[i] > big) big = dk[i];
+        }
+        int best = 0;
+        while (best + 1 < s && dk[best] < big * (1.0L - 1e-12L)) ++best;
+        eb->argmax_stage[k] = best;
+    }
+    return true;
+}
+
 // One SDIRK stage as a 1-stage method: A = [gamma], b = [1], c = [c_i];
 // one real block, eta = 1/gamma.
 void build_sdirk_stage_block(double gamma, double ci, EigenBlocks *eb) {
@@ -363,6 +485,8 @@ void build_sdirk_stage_block(double gamma, double ci, EigenBlocks *eb) {
     eb->eta[0] = 1.0 / gamma;
     eb->beta[0] = 0.0;
     eb->gamma_star[0] = 1.0 / gamma;
+    eb->c12[0] = eb->c21[0] = 0.0;
+    eb->R[0] = 1.0 / gamma;
     eb->argmax_stage[0] = 0;
 }
 
@@ -433,8 +557,11 @@ bool build_eigen_blocks(int family, int s, EigenBlocks *eb) {
         if (eb->width[k] == 2) {
             Lam[r * s + r + 1] = bt; Lam[(r + 1) * s + r] = -bt; Lam[(r + 1) * s + r + 1] = e;
         }
+        eb->c12[k] = (double)bt;
+        eb->c21[k] = (double)-bt;
         eb->gamma_star[k] = (double)(e + bt * bt / e);
     }
+    for (int i = 0; i < s * s; ++i) eb->R[i] = (double)Lam[i];
     for (int i = 0; i < s; ++i)
         for (int j = 0; j < s; ++j) {
             ld tl = 0;
@@ -486,5 +613,14 @@ extern "C" irk_status irk_eigen_blocks(irk_family family, int s, double *T, doub
         width[k] = eb.width[k]; eta[k] = eb.eta[k]; beta[k] = eb.beta[k];
         gamma_star[k] = eb.gamma_star[k]; first_row[k] = eb.first[k];
     }
+    return IRK_OK;
+}
+
+extern "C" irk_status irk_schur_blocks(irk_family family, int s, double *Q0, double *R0) {
+    if (!Q0 || !R0 || s < 1 || s > IRK_MAX_STAGES) return IRK_E_ARG;
+    irk::EigenBlocks eb;
+    if (!irk::build_schur_blocks(family, s, &eb)) return IRK_E_ARG;
+    std::memcpy(Q0, eb.T, sizeof(double) * s * s);
+    std::memcpy(R0, eb.R, sizeof(double) * s * s);
     return IRK_OK;
 }

@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
                 ("prec_fp32", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("batch_mg", ctypes.c_int),
                 ("start_extrapolate", ctypes.c_int), ("krylov_adaptive", ctypes.c_int),
-                ("dae_reorder", ctypes.c_int)]
+                ("dae_reorder", ctypes.c_int), ("transform", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.irk_tableau.argtypes = [I, I, P, P, P]
     L.irk_eigen_blocks.restype = I
     L.irk_eigen_blocks.argtypes = [I, I, P, P, P, P, P, P, P, P]
+    L.irk_schur_blocks.restype = I
+    L.irk_schur_blocks.argtypes = [I, I, P, P]
     L.irk_workspace_bytes.restype = Z
     L.irk_workspace_bytes.argtypes = [I, I, ctypes.POINTER(Operator), ctypes.POINTER(Options)]
     L.irk_create.restype = I
@@ -196,6 +198,14 @@ def make_options(**kw) -> Options:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def irk_schur_blocks(family: str, s: int):
+    """(Q0, R0) of the real Schur basis of A0^{-1}."""
+    Q = np.zeros((s, s))
+    R = np.zeros((s, s))
+    _check(lib().irk_schur_blocks(FAMILY[family], s, Q.ctypes.data, R.ctypes.data), "irk_schur_blocks")
+    return Q, R
 
 
 def irk_workspace_bytes(family: str, s: int, op: Operator, opt: Options = None) -> int:

@@ -164,3 +164,59 @@ def test_server_create_without_a_device_fails_cleanly():
     with pytest.raises(irk.IrkError) as e:
         irk.irk_server_create(256, 1 << 20, 2)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("family,s", [(f, s) for f in ("gauss", "radau", "lobatto") for s in (2, 3, 4, 5)])
+def test_host_schur_basis(family, s):
+    """Real Schur basis of A0^{-1} (Section 3.1): Q0 orthogonal, Q0^T A0^{-1} Q0
+    = R0 block upper triangular with the eigenvalues of the eigen-blocks on
+    its diagonal blocks, each 2x2 block standardized (equal diagonal entries,
+    |phi| <= beta)."""
+    Q, R = irk.irk_schur_blocks(family, s)
+    A, _, _ = tb.tableau(family, s)
+    Ainv = np.linalg.inv(A)
+    assert np.abs(Q.T @ Q - np.eye(s)).max() < 1e-14
+    assert np.abs(Q.T @ Ainv @ Q - R).max() < 1e-12 * np.abs(Ainv).max()
+    e = irk.irk_eigen_blocks(family, s)
+    for k in range(e["nblocks"]):
+        r, w = e["first_row"][k], e["width"][k]
+        assert np.all(R[r:r + w, :r] == 0.0)                 # nothing left of the block
+        if w == 1:
+            assert abs(R[r, r] - e["eta"][k]) < 1e-12 * e["eta"][k]
+        else:
+            blk = R[r:r + 2, r:r + 2]
+            assert abs(blk[0, 0] - blk[1, 1]) < 1e-12 * abs(blk[0, 0])
+            assert abs(blk[0, 0] - e["eta"][k]) < 1e-12 * e["eta"][k]
+            assert abs(-blk[0, 1] * blk[1, 0] - e["beta"][k] ** 2) < 1e-11 * e["beta"][k] ** 2
+            assert abs(blk[0, 1]) <= e["beta"][k] * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("family", ["gauss", "radau"])
+def test_host_schur_basis_reproduces_worked_example(family):
+    """The d weights d_kl,i = (Q0^T)_ki (Q0)_il of equation (Q0approx) in the
+    host's Schur basis against the worked example printed for the two-stage
+    methods (equation (Gauss4Radau3_example)): diagonal entries, and the
+    magnitudes of the off-diagonal ones (their sign follows the sign chosen for
+    each Schur vector)."""
+    from conftest import read_golden
+    Q, _ = irk.irk_schur_blocks(family, 2)
+    rows = [r for r in read_golden("worked_example_d.txt") if r[0] == family]
+    assert len(rows) == 4
+    for _, _, k, l, d1, d2 in rows:
+        k, l = int(k) - 1, int(l) - 1
+        d = [Q[i, k] * Q[i, l] for i in range(2)]
+        want = [float(d1), float(d2)]
+        if k == l:
+            assert np.allclose(d, want, atol=6e-4)
+        else:
+            assert np.allclose(np.abs(d), np.abs(want), atol=6e-4)
+
+
+def test_schur_basis_option_scope():
+    """transform = 1 runs on the ODE operators; the DAE and SDIRK refuse it."""
+    opt = irk.make_options(transform=1)
+    nl = irk.make_operator(irk.OP_NLDIFF_2D, 64, forcing=irk.FORCING_MMS)
+    assert irk.irk_workspace_bytes("gauss", 3, nl, opt) > 0
+    assert irk.irk_workspace_bytes("gauss", 3, irk.make_operator(irk.OP_VSF_2D, 64, nu=1e-3), opt) == 0
+    assert irk.irk_workspace_bytes("sdirk", 2, nl, opt) == 0
+    assert irk.irk_workspace_bytes("gauss", 3, nl, irk.make_options(transform=2)) == 0

@@ -147,3 +147,43 @@ def test_slowly_contracting_iteration_reaches_threshold(name, mk, family, s, dt)
     assert st["acceptance"] in (0, 1), st
     assert err < 1e-10, err
     sol.close()
+
+
+SCHUR = [
+    ("nldiff64-gauss3", lambda: irk.make_operator(irk.OP_NLDIFF_2D, 64, forcing=irk.FORCING_MMS), "gauss", 3, 5e-3),
+    ("nldiff32-gauss5", lambda: irk.make_operator(irk.OP_NLDIFF_2D, 32, forcing=irk.FORCING_MMS), "gauss", 5, 1e-2),
+    ("nldiff48-radau3", lambda: irk.make_operator(irk.OP_NLDIFF_2D, 48, forcing=irk.FORCING_MMS), "radau", 3, 5e-3),
+    ("nldiff40-gauss4", lambda: irk.make_operator(irk.OP_NLDIFF_2D, 40, forcing=irk.FORCING_MMS), "gauss", 4, 5e-3),
+    ("burgers128-radau5", lambda: irk.make_operator(irk.OP_BURGERS_1D, 128, nu=0.01), "radau", 5, 1e-2),
+]
+
+
+@pytest.mark.parametrize("prec_fp32,bar", [(0, 1e-10), (1, 1e-8)], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name,mk,family,s,dt", SCHUR, ids=[c[0] for c in SCHUR])
+def test_step_schur_basis_matches_oracle(name, mk, family, s, dt, prec_fp32, bar):
+    """The real Schur basis (option transform = 1): blocks solved last to
+    first by back-substitution (Section 5, equation (D+U)), under Newton-like
+    (1) (the couplings R0_ij M) and (3) (also the stage-weighted Jacobian
+    terms of the truncation to R0's block-upper pattern), reach the oracle's
+    full-Newton step at the parity bars; two steps, the second continued."""
+    op = mk()
+    u0 = inputs.burgers_u0(op.nx, 3) if op.kind == irk.OP_BURGERS_1D else inputs.nldiff_random_u0(op.nx, 6)
+    w1, K1, _ = oracle_step(op, family, s, u0, 0.0, dt)
+    w2, _, _ = oracle_step(op, family, s, w1, dt, dt)
+    for v in (1, 3):
+        sol = irk.Solver(family, s, op, irk.make_options(newton_like=v, transform=1, prec_fp32=prec_fp32))
+        a = sol._dev(u0)
+        b = torch_empty_like(a)
+        _, st1 = sol.step(a, 0.0, dt, out=b)
+        e1 = rel(b.cpu().numpy(), w1)
+        _, st2 = sol.step(b, dt, dt, out=a)
+        e2 = rel(a.cpu().numpy(), w2)
+        print(f"  {name} Schur NL({v}): rel err {e1:.3e} {e2:.3e}; Newton/Krylov "
+              f"{st1['newton_its']}/{st1['krylov_its']}, {st2['newton_its']}/{st2['krylov_its']}", flush=True)
+        assert e1 < bar and e2 < bar, (v, e1, e2)
+        sol.close()
+
+
+def torch_empty_like(t):
+    import torch
+    return torch.empty_like(t)
