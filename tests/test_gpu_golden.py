@@ -13,7 +13,7 @@ Cases: the 20-step Burgers job (N = 256, Gauss-2, dt 1e-2, seeds 0 and 1);
 two steps of the 512^2 Gauss-3 nonlinear-diffusion workload (dt 5e-3, the
 bench's grid and launch configuration); two steps of Gauss-5 (dt 1e-2) at
 256^2 and of the Radau IIA-3 vorticity-streamfunction DAE (dt 2e-3, 32
-vortices) at 128^2, where the finest levels run in the tiled kernels (the
+vortices) at 128^2 and 256^2, where the finest levels run in the tiled kernels (the
 vorticity cycles stop at a diagonally dominant level, the streamfunction
 cycles at the exactly solved 32^2 level).
 Each under gamma_* and gamma = eta (equation (gamma*) against the plain
@@ -102,7 +102,7 @@ def test_burgers_job_matches_oracle(prec_fp32, bar, gamma_mode):
 
 @pytest.mark.parametrize("gamma_mode", GAMMA, ids=["gamma_star", "gamma_eta"])
 @pytest.mark.parametrize("prec_fp32,bar", PREC, ids=["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["nldiff512_gauss3", "nldiff256_gauss5", "vsf128_radau3"])
+@pytest.mark.parametrize("name", ["nldiff512_gauss3", "nldiff256_gauss5", "vsf128_radau3", "vsf256_radau3"])
 def test_workload_steps_match_oracle(name, prec_fp32, bar, gamma_mode):
     import torch
     want = _load(name)
