@@ -246,7 +246,8 @@ def pct(sorted_vals, q):
 
 
 def host_info():
-    """CPU model, usable cores and the BLAS thread pools of this host."""
+    """CPU model, usable cores and the BLAS thread pools of this process
+    (their current limits)."""
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -303,6 +304,7 @@ def cpu_baseline(wl, n_sample):
         t0 = time.perf_counter()
         _, _, info = nw.irk_step(prob, A, b, c, u0.ravel(), 0.0, dt)
         el = time.perf_counter() - t0
+        host = host_info()                 # the thread pools as limited for the oracle's run
     finally:
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
@@ -310,7 +312,7 @@ def cpu_baseline(wl, n_sample):
             "sample": f"the first {family} s={s} step (dt={dt:g}, t=0) of the same workload on a "
                       f"{n_sample}x{n_sample} grid: full Newton ({info.newton_its} iterations) with a SuperLU "
                       f"factorization each, one thread; {el:.2f} s for the step",
-            "s_per_step": el, "host": host_info()}
+            "s_per_step": el, "threads_used": 1, "host": host}
 
 
 def gpu_same_size(torch, irk, wl, n_sample, reps=10):

@@ -100,7 +100,8 @@ template <class T>
 void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, const MgIn *in, const MgOut *out,
                               int n);
 // Exact solve of the periodic Poisson problem -dt Lap_h x = b (mean-free
-// part) on an n x n level (n <= IRK_FDM_MAX) by fast diagonalization: Q is
+// part) on an n x n level (n <= IRK_FDM_MAX, a multiple of 4) by fast
+// diagonalization: Q is
 // the n x n real orthonormal Fourier basis (row = grid index, column = mode),
 // lam[k] = 4 sin^2(pi m_k / n) / h^2 its eigenvalues of -D2; one work-group.
 #define IRK_FDM_MAX 32

@@ -1168,62 +1168,100 @@ void launch_mg_subcycle_batch(hipStream_t st, int opk, const MgSubArgs<T> *s, co
 //   x = Q [ (Q^T B Q)_ab / (dt (lam_a + lam_b)) ] Q^T,   (a, b) != (0, 0).
 // One work-group; Q (row stride n + 1 in LDS: both its rows and columns are
 // read conflict-free), the field and one temporary live in LDS; four dense
-// n x n x n products, each output a dot product of length n.
+// n x n x n products, each output a dot product of length n.  The side is a
+// template parameter, so every loop below is unrolled and no load waits on a
+// branch.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256) k_poisson_fdm(int n, T dt, const T *__restrict__ Q, const T *__restrict__ lam,
-                                                     const T *__restrict__ b, T *__restrict__ x) {
-    extern __shared__ unsigned char smem_raw[];
-    T *Qs = reinterpret_cast<T *>(smem_raw);      // n x (n + 1)
-    T *Fa = Qs + n * (n + 1);                      // n x n
-    T *Fb = Fa + n * n;                            // n x n
-    __shared__ T ls[IRK_FDM_MAX];
-    const int nn = n * n, q1 = n + 1;
-    for (int q = threadIdx.x; q < nn; q += blockDim.x) {
-        const int r = q / n, c = q - r * n;
-        Qs[r * q1 + c] = Q[q];
-        Fa[q] = b[q];
+// One dense n x n x n product phase of the fast diagonalization: thread t
+// computes row r = t / (N / 4) and the four columns c0 .. c0 + 3 of
+// out[r][c] = sum_k a(r, k) b(k, c), where a(r, k) is read as A[r * LD + k]
+// (ATR: A[k * LD + r]) and b(k, c) as B[k * LD + c] (BTR: B[c * LD + k]).
+template <class T, int N, bool ATR, bool BTR>
+__device__ __forceinline__ void fdm_product(const T *A, const T *B, int r, int c0, T (&acc)[4]) {
+    constexpr int LD = N + 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const T a = ATR ? A[k * LD + r] : A[r * LD + k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += a * (BTR ? B[(c0 + q) * LD + k] : B[k * LD + c0 + q]);
     }
-    if ((int)threadIdx.x < n) ls[threadIdx.x] = lam[threadIdx.x];
+}
+
+template <class T, int N>
+__global__ void __launch_bounds__(256) k_poisson_fdm(T dt, const T *__restrict__ Q, const T *__restrict__ lam,
+                                                     const T *__restrict__ b, T *__restrict__ x) {
+    static_assert(N % 4 == 0 && N <= IRK_FDM_MAX, "side a multiple of 4, at most IRK_FDM_MAX");
+    constexpr int LD = N + 1, NN = N * N, PER = (NN + 255) / 256, GROUPS = N / 4;
+    __shared__ T Qs[N * LD], Fa[N * LD], Fb[N * LD], ls[N];
+    const int t = threadIdx.x;
+    // every global load of the kernel is issued before the first is used
+    T qv[PER], bv[PER], lv = T(0);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int q = t + 256 * p;
+        qv[p] = q < NN ? Q[q] : T(0);
+        bv[p] = q < NN ? b[q] : T(0);
+    }
+    if (t < N) lv = lam[t];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int q = t + 256 * p;
+        if (q < NN) {
+            const int r = q / N, c = q % N;
+            Qs[r * LD + c] = qv[p];
+            Fa[r * LD + c] = bv[p];
+        }
+    }
+    if (t < N) ls[t] = lv;
     __syncthreads();
+    // N / 4 column groups per row: the threads cover N * N / 4 <= 256 groups
+    const bool on = t < N * GROUPS;
+    const int r = on ? t / GROUPS : 0, c0 = on ? 4 * (t % GROUPS) : 0;
+    T acc[4];
     // Fb = B Q
-    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
-        T acc = 0;
-        for (int k = 0; k < n; ++k) acc += Fa[r * n + k] * Qs[k * q1 + c];
-        Fb[o] = acc;
+    if (on) {
+        fdm_product<T, N, false, false>(Fa, Qs, r, c0, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Fb[r * LD + c0 + q] = acc[q];
     }
     __syncthreads();
     // Fa = (Q^T Fb) ./ (dt (lam_a + lam_b)), the constant mode dropped
-    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
-        T acc = 0;
-        for (int k = 0; k < n; ++k) acc += Qs[k * q1 + r] * Fb[k * n + c];
-        const T den = dt * (ls[r] + ls[c]);
-        Fa[o] = (r == 0 && c == 0) ? T(0) : acc / den;
+    if (on) {
+        fdm_product<T, N, true, false>(Qs, Fb, r, c0, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + q;
+            Fa[r * LD + c] = (r == 0 && c == 0) ? T(0) : acc[q] / (dt * (ls[r] + ls[c]));
+        }
     }
     __syncthreads();
     // Fb = Fa Q^T
-    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
-        T acc = 0;
-        for (int k = 0; k < n; ++k) acc += Fa[r * n + k] * Qs[c * q1 + k];
-        Fb[o] = acc;
+    if (on) {
+        fdm_product<T, N, false, true>(Fa, Qs, r, c0, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Fb[r * LD + c0 + q] = acc[q];
     }
     __syncthreads();
     // x = Q Fb
-    for (int o = threadIdx.x; o < nn; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
-        T acc = 0;
-        for (int k = 0; k < n; ++k) acc += Qs[r * q1 + k] * Fb[k * n + c];
-        x[o] = acc;
+    if (on) {
+        fdm_product<T, N, false, false>(Qs, Fb, r, c0, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[r * N + c0 + q] = acc[q];
     }
 }
 
 template <class T>
 void launch_poisson_fdm(hipStream_t st, int n, T dt, const T *Q, const T *lam, const T *b, T *x) {
-    const size_t shm = (size_t)(n * (n + 1) + 2 * n * n) * sizeof(T);
-    k_poisson_fdm<T><<<1, 256, shm, st>>>(n, dt, Q, lam, b, x);
+    switch (n) {
+#define IRK_FDM_CASE(N) \
+    case N: k_poisson_fdm<T, N><<<1, 256, 0, st>>>(dt, Q, lam, b, x); break;
+        IRK_FDM_CASE(4) IRK_FDM_CASE(8) IRK_FDM_CASE(12) IRK_FDM_CASE(16)
+        IRK_FDM_CASE(20) IRK_FDM_CASE(24) IRK_FDM_CASE(28) IRK_FDM_CASE(32)
+#undef IRK_FDM_CASE
+    default: break;                     // the level choice admits no other side
+    }
 }
 
 template void launch_poisson_fdm<float>(hipStream_t, int, float, const float *, const float *, const float *,
