@@ -176,6 +176,15 @@ typedef struct irk_options {
                                of the truncation to R0's block-upper
                                pattern).  Burgers and nonlinear diffusion
                                only (IRK_E_UNSUPPORTED otherwise)          */
+    int psi_solve;          /* IRK_OP_VSF_2D only: how the streamfunction rows'
+                               Poisson block -dt Lap_h is applied in the
+                               preconditioner.  0: exactly, by a spectral
+                               solve on the finest grid (its discrete
+                               Fourier modes diagonalize the periodic
+                               5-point Laplacian) when the side is a power of
+                               two from 16 up to 2048 (float32 V-cycle
+                               precision) or 1024 (float64), else as 1;
+                               1: one Poisson V-cycle                      */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's
@@ -185,7 +194,9 @@ typedef struct irk_stats {
     int newton_its;
     int krylov_its;             /* all blocks, all Newton iterations          */
     int krylov_its_block[IRK_MAX_STAGES];
-    int vcycles;
+    int vcycles;                /* diagonal-block solves of the preconditioner:
+                                   V-cycles, and the spectral Poisson solves
+                                   of psi_solve = 0                         */
     int prec_applications;
     double res0;                /* ||F(K0)||_2                                */
     double final_res;           /* ||F(K)||_2 at acceptance                   */
@@ -202,6 +213,11 @@ typedef struct irk_stats {
                                    with IRK_OK but final_res may exceed the
                                    threshold.  SDIRK: the largest over the
                                    stages.                                   */
+    int krylov_its_psi;         /* reordered DAE system (dae_reorder = 1):
+                                   the iterations of the streamfunction
+                                   solves, included in krylov_its (one per
+                                   block and Newton iteration when the
+                                   Poisson block is solved exactly)          */
 } irk_stats;
 
 /* ---------------- host-only entry points (no GPU needed) ---------------- */

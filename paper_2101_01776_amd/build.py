@@ -19,7 +19,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libirk.so")
-SOURCES = ["tableau.cpp", "kernels.hip", "mg_tiled.hip", "driver.hip", "server.cpp", "noalloc.hip"]
+SOURCES = ["tableau.cpp", "kernels.hip", "mg_tiled.hip", "fft_poisson.hip", "driver.hip", "server.cpp",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

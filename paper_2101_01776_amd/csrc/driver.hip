@@ -25,6 +25,7 @@
 #include <string>
 #include <vector>
 
+#include "fft_poisson.h"
 #include "irk_internal.h"
 #include "kernels.h"
 #include "mg_tiled.h"
@@ -65,6 +66,7 @@ struct LaneLayout {
     size_t tmp;                         // one float64 field (Newton-like (3) pairs), else 0
     size_t lev[IRK_MAX_LEVELS][4];
     size_t ldv;                         // Krylov vector length (block width * field)
+    size_t spec;                        // half spectrum of the spectral Poisson solve, else 0
 };
 
 // A side stream of a vorticity-streamfunction pair block: the first
@@ -88,6 +90,8 @@ struct Plan {
     int l0 = 0;                         // first level of the one-work-group sub-cycle
     int fdm_level = 0;                  // VSF: level of the exact Poisson solve (0: none)
     size_t off_fdm_Q = 0, off_fdm_lam = 0;
+    bool fft_psi = false;               // VSF: streamfunction rows solved spectrally on the finest grid
+    size_t off_fft_tw = 0, off_fft_lam = 0;
     size_t tsz = 4;                     // bytes per V-cycle scalar
     int nhier = 0;                      // distinct linearization stages
     int hier_stage[IRK_MAX_STAGES];     // hierarchy -> stage index
@@ -120,7 +124,8 @@ static bool valid_options(const irk_options &o) {
            o.mg_coarsest >= 2 && o.coarse_iters >= 1 && o.coarse_iters <= 64 && o.krylov_rtol > 0 &&
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
            (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1) &&
-           (o.dae_reorder == 0 || o.dae_reorder == 1) && (o.transform == 0 || o.transform == 1);
+           (o.dae_reorder == 0 || o.dae_reorder == 1) && (o.transform == 0 || o.transform == 1) &&
+           (o.psi_solve == 0 || o.psi_solve == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -190,7 +195,10 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     // below the finest one of side <= IRK_FDM_MAX and a multiple of 4 (at or
     // above the sub-cycle's) and solve it exactly
     P->fdm_level = 0;
-    if (o.kind == IRK_OP_VSF_2D)
+    // ... unless the finest grid is solved spectrally (a power-of-two side
+    // the transforms take, option psi_solve = 0)
+    P->fft_psi = o.kind == IRK_OP_VSF_2D && P->opt.psi_solve == 0 && fft_poisson_supported(o.nx, P->tsz);
+    if (o.kind == IRK_OP_VSF_2D && !P->fft_psi)
         for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
             if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] % 4 == 0 && P->lg.nx[l] == P->lg.ny[l]) {
                 P->fdm_level = l;
@@ -276,6 +284,11 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         P->off_fdm_Q = take(n * n * P->tsz);
         P->off_fdm_lam = take(n * P->tsz);
     }
+    const size_t spec_bytes = P->fft_psi ? fft_poisson_spectrum_values(o.nx) * P->tsz : 0;
+    if (P->fft_psi) {
+        P->off_fft_tw = take((size_t)2 * o.nx * P->tsz);      // n complex twiddles
+        P->off_fft_lam = take((size_t)o.nx * P->tsz);
+    }
     for (int hq = 0; hq < P->nhier; ++hq)
         for (int l = 0; l < P->lg.nlev; ++l)
             P->off_coef[hq][l] = take((size_t)P->lg.nx[l] * P->lg.ny[l] * P->tsz);
@@ -287,6 +300,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         ln.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
         ln.dv = take(512 * f64);
         ln.tmp = (P->weighted && P->opt.newton_like == 3 && P->eb.width[b] == 2) ? take(P->nf * f64) : 0;
+        ln.spec = spec_bytes ? take(spec_bytes) : 0;
         for (int l = 0; l < P->lg.nlev; ++l) {
             const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
             for (int q = 0; q < 4; ++q) ln.lev[l][q] = take(n * P->tsz);
@@ -297,6 +311,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
             ax.lay.ldv = ln.ldv;
             ax.lay.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
             ax.lay.dv = take(512 * f64);
+            ax.lay.spec = spec_bytes ? take(spec_bytes) : 0;
             for (int l = 0; l < P->lg.nlev; ++l) {
                 const size_t n = (size_t)P->lg.nx[l] * P->lg.ny[l];
                 for (int q = 0; q < 4; ++q) ax.lay.lev[l][q] = take(n * P->tsz);
@@ -807,6 +822,18 @@ static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, con
     MgOut out;
     out.z = zpsi; out.shift = means; out.shift_scale = 1.0 / c->dt;
     out.v1 = rpsi; out.a1 = 1.0; out.v2 = zomega; out.a2 = c->dt; out.mean_in = means;
+    if (c->P.fft_psi) {
+        // exact: the spectral solve on the finest grid.  Bytes: q's two
+        // float64 inputs and z (24 per point), the half spectrum written,
+        // read, written and read again (4 n (n/2 + 1) complex values)
+        const int n = c->P.op.nx;
+        const double by = 24.0 * npts + 4.0 * fft_poisson_spectrum_values(n) * c->P.tsz;
+        PROF(c, ln.stream, std::string("k_fft_poisson<") + (sizeof(T) == 4 ? "float" : "double") + ">", by, 1,
+             launch_fft_poisson<T>(ln.stream, n, (T)c->dt, reinterpret_cast<const T *>(c->ws + c->P.off_fft_tw),
+                                   reinterpret_cast<const T *>(c->ws + c->P.off_fft_lam), in, out,
+                                   reinterpret_cast<T *>(c->ws + ln.lay->spec)));
+        return;
+    }
     vcycle<T>(c, ln, MG_POISSON, 0.0, c->dt, -1, in, out);
 }
 
@@ -991,6 +1018,7 @@ struct Fgmres {
     size_t len = 0;
     std::vector<double> H, cs, sn, g, y;
     int j = 0, total = 0, vcycles = 0;
+    int omega_total = 0;                // reordered DAE system: iterations of the vorticity solve
     bool first_cycle = true, converged = false, fused = true;
     double beta0 = 0.0;
     enum Phase { WAIT_BETA, WAIT_PREC, WAIT_ITER, DONE } phase = WAIT_BETA;
@@ -1030,6 +1058,7 @@ struct Fgmres {
     // rows, from the current sol
     irk_status to_psi() {
         mode = 2;
+        omega_total = total;
         first_cycle = false;
         converged = false;
         beta0_set = false;
@@ -1690,6 +1719,7 @@ struct Stepper : StepperBase {
                         return fail(IRK_E_DEVICE);
                     stats.krylov_its += fg[b].total;
                     stats.krylov_its_block[b] += fg[b].total;
+                    if (fg[b].mode == 2) stats.krylov_its_psi += fg[b].total - fg[b].omega_total;
                     stats.vcycles += fg[b].vcycles;
                     stats.prec_applications += fg[b].total * P.eb.width[b];
                     if (debug_level() > 1)
@@ -1786,6 +1816,7 @@ struct SdirkStepper : StepperBase {
             stats.newton_its += is.newton_its;
             stats.krylov_its += is.krylov_its;
             stats.krylov_its_block[stage] += is.krylov_its;
+            stats.krylov_its_psi += is.krylov_its_psi;
             stats.vcycles += is.vcycles;
             stats.prec_applications += is.prec_applications;
             stats.res0 = std::max(stats.res0, is.res0);
@@ -1849,6 +1880,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->krylov_adaptive = 1;
     o->dae_reorder = 0;
     o->transform = 0;
+    o->psi_solve = 0;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
@@ -1890,6 +1922,7 @@ static size_t upload_doubles(const Plan &P) {
         const size_t m = P.lg.nx[P.fdm_level];
         n += m * m + m;
     }
+    if (P.fft_psi) n += (size_t)3 * P.op.nx;
     return n;
 }
 
@@ -1999,6 +2032,36 @@ static irk_status upload_fdm_basis(irk_ctx *c, double *stage) {
     }
     HIP_TRY(hipMemcpyAsync(c->ws + P.off_fdm_Q, stage, qbytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->ws + P.off_fdm_lam, lstage, (size_t)n * P.tsz, hipMemcpyHostToDevice, c->stream));
+    return IRK_OK;
+}
+
+// Twiddles exp(-2 pi i j / n), j < n, as (re, im) pairs and the
+// eigenvalues 4 sin^2(pi m / n) / h^2 of the 1-D periodic second difference
+// on the finest grid, in the V-cycle precision, written to `stage` (pinned)
+// and copied to the workspace on the context's stream.
+static irk_status upload_fft_tables(irk_ctx *c, double *stage) {
+    const Plan &P = c->P;
+    const int n = P.op.nx;
+    const double h = P.op.length / n;
+    const double pi = 3.14159265358979323846;
+    const bool f32 = P.tsz == sizeof(float);
+    auto put = [&](size_t i, double v) {
+        if (f32) reinterpret_cast<float *>(stage)[i] = (float)v;
+        else stage[i] = v;
+    };
+    for (int j = 0; j < n; ++j) {
+        const double a = 2.0 * pi * j / n;
+        put(2 * (size_t)j, std::cos(a));
+        put(2 * (size_t)j + 1, -std::sin(a));
+    }
+    for (int m = 0; m < n; ++m) {
+        const double sv = std::sin(pi * m / n);
+        put((size_t)2 * n + m, 4.0 * sv * sv / (h * h));
+    }
+    const size_t bytes = (size_t)n * P.tsz;
+    HIP_TRY(hipMemcpyAsync(c->ws + P.off_fft_tw, stage, 2 * bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + P.off_fft_lam, reinterpret_cast<unsigned char *>(stage) + 2 * bytes, bytes,
+                           hipMemcpyHostToDevice, c->stream));
     return IRK_OK;
 }
 
@@ -2122,6 +2185,10 @@ static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait,
     HIP_TRY(hipMemcpyAsync(c->tab, tab, (size_t)2 * (nx + ny) * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (P.fdm_level > 0) {
         const irk_status e = upload_fdm_basis(c, tab + 2 * (nx + ny));
+        if (e != IRK_OK) return e;
+    }
+    if (P.fft_psi) {
+        const irk_status e = upload_fft_tables(c, tab + 2 * (nx + ny));
         if (e != IRK_OK) return e;
     }
     launch_fill(c->stream, c->Y, 0.0, (size_t)P.s * P.nf);   // the plan's s (1 for SDIRK)

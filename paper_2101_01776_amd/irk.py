@@ -47,20 +47,23 @@ class Options(ctypes.Structure):
                 ("prec_fp32", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("batch_mg", ctypes.c_int),
                 ("start_extrapolate", ctypes.c_int), ("krylov_adaptive", ctypes.c_int),
-                ("dae_reorder", ctypes.c_int), ("transform", ctypes.c_int)]
+                ("dae_reorder", ctypes.c_int), ("transform", ctypes.c_int),
+                ("psi_solve", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("krylov_its", ctypes.c_int),
                 ("krylov_its_block", ctypes.c_int * IRK_MAX_STAGES), ("vcycles", ctypes.c_int),
                 ("prec_applications", ctypes.c_int), ("res0", ctypes.c_double),
-                ("final_res", ctypes.c_double), ("start", ctypes.c_int), ("acceptance", ctypes.c_int)]
+                ("final_res", ctypes.c_double), ("start", ctypes.c_int), ("acceptance", ctypes.c_int),
+                ("krylov_its_psi", ctypes.c_int)]
 
     def as_dict(self):
         return {"newton_its": self.newton_its, "krylov_its": self.krylov_its,
                 "krylov_its_block": list(self.krylov_its_block), "vcycles": self.vcycles,
                 "prec_applications": self.prec_applications, "res0": self.res0,
-                "final_res": self.final_res, "start": self.start, "acceptance": self.acceptance}
+                "final_res": self.final_res, "start": self.start, "acceptance": self.acceptance,
+                "krylov_its_psi": self.krylov_its_psi}
 
 
 class Request(ctypes.Structure):

@@ -220,3 +220,24 @@ def test_schur_basis_option_scope():
     assert irk.irk_workspace_bytes("gauss", 3, irk.make_operator(irk.OP_VSF_2D, 64, nu=1e-3), opt) == 0
     assert irk.irk_workspace_bytes("sdirk", 2, nl, opt) == 0
     assert irk.irk_workspace_bytes("gauss", 3, nl, irk.make_options(transform=2)) == 0
+
+
+def test_streamfunction_solve_option():
+    """psi_solve: 0 (default) the spectral solve on power-of-two grids, 1 the
+    Poisson V-cycle; other values are refused.  The spectral solve keeps a
+    half spectrum per lane in the workspace, so the sizes differ exactly
+    where it applies."""
+    assert irk.irk_default_options().psi_solve == 0
+    sizes = {}
+    for n in (64, 48):
+        vsf = irk.make_operator(irk.OP_VSF_2D, n, nu=1e-3)
+        assert irk.irk_workspace_bytes("radau", 3, vsf, irk.make_options(psi_solve=2)) == 0
+        sizes[n] = [irk.irk_workspace_bytes("radau", 3, vsf, irk.make_options(psi_solve=p)) for p in (0, 1)]
+    assert sizes[64][0] != sizes[64][1] and sizes[48][0] == sizes[48][1]
+    # float64 V-cycles: sides up to 1024 (2048 needs more than 64 KiB of LDS per row work-group)
+    big = irk.make_operator(irk.OP_VSF_2D, 2048, nu=1e-3)
+    f32 = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=0))
+    f32_mg = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=1))
+    f64 = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=0, prec_fp32=0))
+    f64_mg = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=1, prec_fp32=0))
+    assert f32 != f32_mg and f64 == f64_mg
