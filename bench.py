@@ -116,20 +116,23 @@ def ablation(torch, irk, inputs, wl, steps):
     (3) plus the coupling of the rows of a pair; (1) and (3) in the real Schur
     basis (blocks by back-substitution, (3) with the stage-weighted coupling
     of the blocks); and the adaptive Krylov tolerance against the paper's
-    fixed one.  Preconditioner applications are the paper's cost unit."""
+    fixed one; for the DAE also the reordered system and the streamfunction
+    rows' Poisson block applied by a V-cycle instead of the spectral solve.
+    Preconditioner applications are the paper's cost unit."""
     problem, n, family, s, dt, _, nu = wl
     op, u_init, dof = make_problem(irk, inputs, problem, n, nu)
     res = []
-    # (gamma_mode, newton_like, krylov_adaptive, dae_reorder, transform)
-    variants = [(0, 1, 1, 0, 0), (0, 1, 0, 0, 0), (1, 1, 1, 0, 0), (0, 0, 1, 0, 0), (0, 2, 1, 0, 0),
-                (0, 3, 1, 0, 0)]
+    # (gamma_mode, newton_like, krylov_adaptive, dae_reorder, transform, psi_solve)
+    variants = [(0, 1, 1, 0, 0, 0), (0, 1, 0, 0, 0, 0), (1, 1, 1, 0, 0, 0), (0, 0, 1, 0, 0, 0),
+                (0, 2, 1, 0, 0, 0), (0, 3, 1, 0, 0, 0)]
     if problem == "vsf":
-        variants.append((0, 1, 1, 1, 0))       # the reordered DAE system, eq (vsf-system-2)
+        variants.append((0, 1, 1, 1, 0, 0))       # the reordered DAE system, eq (vsf-system-2)
+        variants.append((0, 1, 1, 0, 0, 1))       # Poisson V-cycle for the streamfunction rows
     else:
-        variants += [(0, 1, 1, 0, 1), (0, 3, 1, 0, 1)]   # real Schur basis, back-substitution
-    for gm, nl, ka, ro, tr in variants:
+        variants += [(0, 1, 1, 0, 1, 0), (0, 3, 1, 0, 1, 0)]   # real Schur basis, back-substitution
+    for gm, nl, ka, ro, tr, ps in variants:
         solver = irk.Solver(family, s, op, irk.make_options(gamma_mode=gm, newton_like=nl, krylov_adaptive=ka,
-                                                            dae_reorder=ro, transform=tr))
+                                                            dae_reorder=ro, transform=tr, psi_solve=ps))
         u = torch.tensor(u_init, dtype=torch.float64, device="cuda")
         b = torch.empty_like(u)
         t = 0.0
@@ -149,6 +152,7 @@ def ablation(torch, irk, inputs, wl, steps):
                     "krylov_tol": "adaptive" if ka else "fixed",
                     "dae_system": ("reordered (vsf-system-2)" if ro else "whole (vsf-system-1)") if problem == "vsf"
                     else None,
+                    "psi_solve": ("V-cycle" if ps else "spectral") if problem == "vsf" else None,
                     "ms_per_step": 1e3 * wall / steps,
                     "vcycles_per_step": sum(x["vcycles"] for x in stats) / steps,
                     "newton_its_per_step": sum(x["newton_its"] for x in stats) / steps,
