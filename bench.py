@@ -242,6 +242,27 @@ def copy_probe(torch, mib=256, reps=3):
     torch.cuda.synchronize()
 
 
+def copy_bandwidth(torch, mib=512, reps=5):
+    """Rate of a plain device-to-device copy (read + write of `mib` MiB),
+    best of `reps`, between events on the current stream: the HBM rate a
+    streaming kernel can reach on this GPU, as context for `frac`."""
+    x = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
 def pct(sorted_vals, q):
     if not sorted_vals:
         return None
@@ -586,6 +607,9 @@ def main():
                            "in_run": {"launches": top["launches"],
                                       "avg_us_event_bracketed": 1e3 * top["ms"] / max(1, top["launches"]),
                                       "avg_bytes": top["bytes"] / max(1, top["launches"])}}
+        cb = copy_bandwidth(torch)
+        out["roofline"]["copy_reference"] = {"GB_per_s": cb, "frac_of_peak": cb / HBM_PEAK_GBS,
+                                             "what": "512 MiB device-to-device copy (read + write), best of 5"}
         tot = sum(r["ms"] for r in prof)
         step_bytes = sum(r["bytes"] for r in prof) / kp
         out["step_traffic"] = {"algorithmic_MB_per_step": step_bytes / 1e6,

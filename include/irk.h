@@ -181,10 +181,13 @@ typedef struct irk_options {
                                preconditioner.  0: exactly, by a spectral
                                solve on the finest grid (its discrete
                                Fourier modes diagonalize the periodic
-                               5-point Laplacian) when the side is a power of
-                               two from 16 up to 2048 (float32 V-cycle
-                               precision) or 1024 (float64), else as 1;
-                               1: one Poisson V-cycle                      */
+                               5-point Laplacian), in the V-cycle precision,
+                               when the side is a power of two from 16 up
+                               to 2048 (float32) or 1024 (float64), else
+                               as 1; 1: one Poisson V-cycle.  In float32
+                               the solve is exact only to about the
+                               Laplacian's condition number times float32
+                               rounding (1e-2 at 1024^2)                  */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's

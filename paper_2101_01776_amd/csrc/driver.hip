@@ -91,6 +91,7 @@ struct Plan {
     int fdm_level = 0;                  // VSF: level of the exact Poisson solve (0: none)
     size_t off_fdm_Q = 0, off_fdm_lam = 0;
     bool fft_psi = false;               // VSF: streamfunction rows solved spectrally on the finest grid
+    size_t fft_tsz = 0;                 // bytes per value of that solve's arithmetic
     size_t off_fft_tw = 0, off_fft_lam = 0;
     size_t tsz = 4;                     // bytes per V-cycle scalar
     int nhier = 0;                      // distinct linearization stages
@@ -196,8 +197,10 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     // above the sub-cycle's) and solve it exactly
     P->fdm_level = 0;
     // ... unless the finest grid is solved spectrally (a power-of-two side
-    // the transforms take, option psi_solve = 0)
-    P->fft_psi = o.kind == IRK_OP_VSF_2D && P->opt.psi_solve == 0 && fft_poisson_supported(o.nx, P->tsz);
+    // the transforms take, option psi_solve = 0), in the V-cycle precision
+    P->fft_tsz = (o.kind == IRK_OP_VSF_2D && P->opt.psi_solve == 0 && fft_poisson_supported(o.nx, P->tsz))
+                     ? P->tsz : 0;
+    P->fft_psi = P->fft_tsz > 0;
     if (o.kind == IRK_OP_VSF_2D && !P->fft_psi)
         for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
             if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] % 4 == 0 && P->lg.nx[l] == P->lg.ny[l]) {
@@ -284,10 +287,10 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         P->off_fdm_Q = take(n * n * P->tsz);
         P->off_fdm_lam = take(n * P->tsz);
     }
-    const size_t spec_bytes = P->fft_psi ? fft_poisson_spectrum_values(o.nx) * P->tsz : 0;
+    const size_t spec_bytes = P->fft_psi ? fft_poisson_spectrum_values(o.nx) * P->fft_tsz : 0;
     if (P->fft_psi) {
-        P->off_fft_tw = take((size_t)2 * o.nx * P->tsz);      // n complex twiddles
-        P->off_fft_lam = take((size_t)o.nx * P->tsz);
+        P->off_fft_tw = take((size_t)2 * o.nx * P->fft_tsz);  // n complex twiddles
+        P->off_fft_lam = take((size_t)o.nx * P->fft_tsz);
     }
     for (int hq = 0; hq < P->nhier; ++hq)
         for (int l = 0; l < P->lg.nlev; ++l)
@@ -827,11 +830,21 @@ static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, con
         // float64 inputs and z (24 per point), the half spectrum written,
         // read, written and read again (4 n (n/2 + 1) complex values)
         const int n = c->P.op.nx;
-        const double by = 24.0 * npts + 4.0 * fft_poisson_spectrum_values(n) * c->P.tsz;
-        PROF(c, ln.stream, std::string("k_fft_poisson<") + (sizeof(T) == 4 ? "float" : "double") + ">", by, 1,
-             launch_fft_poisson<T>(ln.stream, n, (T)c->dt, reinterpret_cast<const T *>(c->ws + c->P.off_fft_tw),
-                                   reinterpret_cast<const T *>(c->ws + c->P.off_fft_lam), in, out,
-                                   reinterpret_cast<T *>(c->ws + ln.lay->spec)));
+        const size_t fs = c->P.fft_tsz;
+        const double by = 24.0 * npts + 4.0 * fft_poisson_spectrum_values(n) * fs;
+        unsigned char *ws = c->ws;
+        if (fs == sizeof(double)) {
+            PROF(c, ln.stream, "k_fft_poisson<double>", by, 1,
+                 launch_fft_poisson<double>(ln.stream, n, c->dt, reinterpret_cast<const double *>(ws + c->P.off_fft_tw),
+                                            reinterpret_cast<const double *>(ws + c->P.off_fft_lam), in, out,
+                                            reinterpret_cast<double *>(ws + ln.lay->spec)));
+        } else {
+            PROF(c, ln.stream, "k_fft_poisson<float>", by, 1,
+                 launch_fft_poisson<float>(ln.stream, n, (float)c->dt,
+                                           reinterpret_cast<const float *>(ws + c->P.off_fft_tw),
+                                           reinterpret_cast<const float *>(ws + c->P.off_fft_lam), in, out,
+                                           reinterpret_cast<float *>(ws + ln.lay->spec)));
+        }
         return;
     }
     vcycle<T>(c, ln, MG_POISSON, 0.0, c->dt, -1, in, out);
@@ -2037,14 +2050,14 @@ static irk_status upload_fdm_basis(irk_ctx *c, double *stage) {
 
 // Twiddles exp(-2 pi i j / n), j < n, as (re, im) pairs and the
 // eigenvalues 4 sin^2(pi m / n) / h^2 of the 1-D periodic second difference
-// on the finest grid, in the V-cycle precision, written to `stage` (pinned)
-// and copied to the workspace on the context's stream.
+// on the finest grid, in the spectral solve's precision, written to `stage`
+// (pinned) and copied to the workspace on the context's stream.
 static irk_status upload_fft_tables(irk_ctx *c, double *stage) {
     const Plan &P = c->P;
     const int n = P.op.nx;
     const double h = P.op.length / n;
     const double pi = 3.14159265358979323846;
-    const bool f32 = P.tsz == sizeof(float);
+    const bool f32 = P.fft_tsz == sizeof(float);
     auto put = [&](size_t i, double v) {
         if (f32) reinterpret_cast<float *>(stage)[i] = (float)v;
         else stage[i] = v;
@@ -2058,7 +2071,7 @@ static irk_status upload_fft_tables(irk_ctx *c, double *stage) {
         const double sv = std::sin(pi * m / n);
         put((size_t)2 * n + m, 4.0 * sv * sv / (h * h));
     }
-    const size_t bytes = (size_t)n * P.tsz;
+    const size_t bytes = (size_t)n * P.fft_tsz;
     HIP_TRY(hipMemcpyAsync(c->ws + P.off_fft_tw, stage, 2 * bytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->ws + P.off_fft_lam, reinterpret_cast<unsigned char *>(stage) + 2 * bytes, bytes,
                            hipMemcpyHostToDevice, c->stream));

@@ -20,8 +20,9 @@ size_t fft_poisson_spectrum_values(int n);
 
 // Solves -dt Lap_h x = q on the periodic n x n grid (5-point Laplacian,
 // spacing h; the constant mode of q is dropped and x is mean-free), with
-// q = in.a1 in.v1 + in.a2 in.v2 (in.v2 optional, in.mean ignored: the
-// constant mode is dropped anyway), and writes
+// q = in.a1 in.v1 + in.a2 in.v2 - (in.a1 in.mean[0] + in.a2 in.mean[1])
+// (in.v2 and in.mean optional; the mean is subtracted in float64 before the
+// transforms, which run in T), and writes
 // out.z = x + out.shift_scale * out.shift[0] (out.shift optional) in float64.
 // tw: the n twiddles exp(-2 pi i j / n) as (re, im) pairs; lam: the n
 // eigenvalues 4 sin^2(pi m / n) / h^2 of the 1-D second difference; spec:

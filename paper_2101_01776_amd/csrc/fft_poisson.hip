@@ -156,9 +156,13 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ t
     cx<T> *Y = X + N;
     cx<T> *tw = Y + N;
     const size_t r0 = 2 * (size_t)xcd_order();
-    // rows r0, r0 + 1 of q = a1 v1 + a2 v2, packed q_r0 + i q_r0+1; every
-    // global load is in flight before the first is used
+    // rows r0, r0 + 1 of q = a1 v1 + a2 v2 less its mean (when given), packed
+    // q_r0 + i q_r0+1; every global load is in flight before the first is
+    // used.  The mean is subtracted in float64: the constant mode is dropped
+    // anyway, but a large mean rounded to the transform precision would
+    // swamp the other modes.
     const double *p1 = in.v1 + r0 * N;
+    const double qm = in.mean ? in.a1 * in.mean[0] + (in.v2 ? in.a2 * in.mean[1] : 0.0) : 0.0;
     double qa[PT], qb[PT];
     if (in.v2) {
         const double *p2 = in.v2 + r0 * N;
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ t
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
         const int j = u * FFT_NT + (int)threadIdx.x;
-        if (N % FFT_NT == 0 || j < N) X[j] = {(T)qa[u], (T)qb[u]};
+        if (N % FFT_NT == 0 || j < N) X[j] = {(T)(qa[u] - qm), (T)(qb[u] - qm)};
     }
     __syncthreads();
     const cx<T> *R = fft_lds<T, false, LG>(X, Y, tw);

@@ -574,12 +574,97 @@ __device__ __forceinline__ double crew_max(double v, double *red) {
     }
 }
 
+// The work-group form of the Chebyshev steps below with each thread's points
+// (p = tid + u blockDim, at most MAXP of them) fixed across the steps: their
+// scaled stencil rows, b~, Chebyshev directions and neighbour indices stay in
+// registers, so a step reads only the iterate from LDS (the point and its
+// neighbours) and does no index arithmetic.  The same operations in the same
+// order as the generic form.  With R non-null, the scaled residual
+// R = Ac (b~ - x - sum_q a~_q x_q) of the result is written after the last
+// step (R may be the ping-pong buffer xn).
+template <class T, int OPK, int MAXP>
+__device__ void wg_cheb_reg(const T *At, const T *bt, T *x, T *xn, int nx, int ny, const T *cd, const T *cr,
+                            int nsteps, bool from_zero, T *R, const T *Ac) {
+    constexpr int NS = StencilShape<OPK>::NS;
+    const int np = nx * ny, nt = (int)blockDim.x, tid = (int)threadIdx.x;
+    T a[MAXP][NS], b[MAXP], d[MAXP];
+    int nb[MAXP][NS];
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+        const int p = tid + u * nt;
+        const int pp = p < np ? p : 0;
+        const int j = pp / nx, i = pp - j * nx;       // once per level
+        nb_index<OPK>(i, j, nx, ny, nb[u]);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) a[u][q] = At[q * np + pp];
+        b[u] = bt[pp];
+        d[u] = T(0);
+    }
+    T *xc = x, *xo = xn;
+    for (int k = 0; k < nsteps; ++k) {
+        const T cdk = cd[k], crk = cr[k];
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u) {
+            const int p = tid + u * nt;
+            if (p < np) {
+                T xv, dn;
+                if (from_zero && k == 0) {
+                    xv = T(0);
+                    dn = crk * b[u];
+                } else {
+                    xv = xc[p];
+                    T r = b[u] - xv;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) r -= a[u][q] * xc[nb[u][q]];
+                    dn = (k == 0 ? T(0) : cdk * d[u]) + crk * r;
+                }
+                d[u] = dn;
+                xo[p] = xv + dn;
+            }
+        }
+        __syncthreads();
+        T *t = xc;
+        xc = xo;
+        xo = t;
+    }
+    if (xc != x) {
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u) {
+            const int p = tid + u * nt;
+            if (p < np) x[p] = xc[p];
+        }
+        __syncthreads();
+    }
+    if (R) {
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u) {
+            const int p = tid + u * nt;
+            if (p < np) {
+                T r = b[u] - x[p];
+#pragma unroll
+                for (int q = 0; q < NS; ++q) r -= a[u][q] * x[nb[u][q]];
+                R[p] = Ac[p] * r;
+            }
+        }
+    }
+}
+
+// points per thread of a work-group crew on an np-point level (the
+// register form takes up to 2 points of a 5- or 3-point stencil: more, or
+// the 9-point vorticity stencil, would spill; those keep the generic form)
+__device__ __forceinline__ int group_points(int np) { return (np + (int)blockDim.x - 1) / (int)blockDim.x; }
+
 // nsteps Chebyshev steps on a level; x and xn alternate (one crew sync per
 // step), the result is left in x.
 template <class T, int OPK, class C>
 __device__ void wg_cheb(const T *At, const T *bt, T *x, T *xn, T *d, int nx, int ny, const T *cd, const T *cr,
                         int nsteps, bool from_zero) {
     const int np = nx * ny;
+    if constexpr (!C::size_is_wave && StencilShape<OPK>::NS <= 4) {
+        const int per = group_points(np);
+        if (per <= 1) return wg_cheb_reg<T, OPK, 1>(At, bt, x, xn, nx, ny, cd, cr, nsteps, from_zero, nullptr, nullptr);
+        if (per == 2) return wg_cheb_reg<T, OPK, 2>(At, bt, x, xn, nx, ny, cd, cr, nsteps, from_zero, nullptr, nullptr);
+    }
     T *xc = x, *xo = xn;
     for (int k = 0; k < nsteps; ++k) {
         if (from_zero && k == 0) {
@@ -613,8 +698,18 @@ template <class T, int OPK, class C>
 __device__ void sub_down(const MgSubArgs<T> &s, int l, const T *At, const T *Ac, const T *bt, T *x, T *R, T *Dv,
                          const T *acc_c, T *bc) {
     const int nx = s.nx[l], ny = s.ny[l], np = nx * ny;
-    wg_cheb<T, OPK, C>(At, bt, x, R, Dv, nx, ny, s.cd, s.cr, s.deg, true);
-    FOR_PTS_C(C, np, nx, R[p] = Ac[p] * level_jres<T, OPK>(At, np, bt, x, p, i, j, nx, ny));
+    bool done = false;
+    if constexpr (!C::size_is_wave && StencilShape<OPK>::NS <= 4) {
+        // smoothing and the residual with the points' stencils in registers
+        const int per = group_points(np);
+        done = per <= 2;
+        if (per <= 1) wg_cheb_reg<T, OPK, 1>(At, bt, x, R, nx, ny, s.cd, s.cr, s.deg, true, R, Ac);
+        else if (per == 2) wg_cheb_reg<T, OPK, 2>(At, bt, x, R, nx, ny, s.cd, s.cr, s.deg, true, R, Ac);
+    }
+    if (!done) {
+        wg_cheb<T, OPK, C>(At, bt, x, R, Dv, nx, ny, s.cd, s.cr, s.deg, true);
+        FOR_PTS_C(C, np, nx, R[p] = Ac[p] * level_jres<T, OPK>(At, np, bt, x, p, i, j, nx, ny));
+    }
     C::sync();
     const int nxc = s.nx[l + 1], nyc = s.ny[l + 1];
     FOR_PTS_C(C, nxc * nyc, nxc, {

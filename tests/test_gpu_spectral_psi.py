@@ -58,3 +58,31 @@ def test_step_matches_oracle_with_either_streamfunction_solve(n, prec_fp32, bar)
     print(f"  n={n}: Krylov its spectral {its[0]}, V-cycle {its[1]}", flush=True)
     if n & (n - 1):
         assert its[0] == its[1]        # not a power of two: both settings use the V-cycle
+
+
+def test_full_size_spectral_solve_matches_vcycle():
+    """The bench's 1024^2 DAE step (Radau IIA-3, dt 2e-3, 32 vortices; mixed
+    precision) with the spectral streamfunction solve and with the Poisson
+    V-cycle: the converged steps agree (the preconditioner changes, the fixed
+    point does not).  In the reordered system with float64 transforms
+    (float64 V-cycle precision) every streamfunction solve is a one-iteration
+    Krylov solve at full size; float32 transforms are exact only to about
+    the Laplacian's condition number (1e5 here) times float32 rounding."""
+    import torch
+    n = 1024
+    op = irk.make_operator(irk.OP_VSF_2D, n, nu=1e-3)
+    u = torch.tensor(inputs.vsf_state0(n, 0, 32), dtype=torch.float64, device="cuda")
+    outs = {}
+    for psi in (0, 1):
+        sol = irk.Solver("radau", 3, op, irk.make_options(psi_solve=psi))
+        out, st = sol.step(u, 0.0, 2e-3)
+        outs[psi] = out.cpu().numpy()
+        sol.close()
+        print(f"  psi_solve={psi}: Newton {st['newton_its']} Krylov {st['krylov_its']}", flush=True)
+    assert rel(outs[0], outs[1]) < 1e-8, rel(outs[0], outs[1])
+    sol = irk.Solver("radau", 3, op, irk.make_options(psi_solve=0, dae_reorder=1, prec_fp32=0))
+    out, st = sol.step(u, 0.0, 2e-3)
+    sol.close()
+    print(f"  reordered, float64: Newton {st['newton_its']} streamfunction Krylov {st['krylov_its_psi']}", flush=True)
+    assert st["krylov_its_psi"] == st["newton_its"] * 2          # one real block and one pair
+    assert rel(out.cpu().numpy(), outs[0]) < 1e-8
