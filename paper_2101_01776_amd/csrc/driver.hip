@@ -986,6 +986,37 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
          launch_block_matvec(ln.stream, c->dp, width, block_lam(eb, blk), c->dt, Ua, Ub, x, w, xm));
 }
 
+// The plain block matvec fused with the first Gram-Schmidt pass,
+// out[k] = (V_k, w) for the nv basis vectors at V (stride ldv); false
+// (nothing issued) where it does not apply: the stage-weighted operators of
+// Newton-like (2), (3), or more than 16 basis vectors.
+static bool block_matvec_dot(irk_ctx *c, Lane &ln, const double *x, double *w, const double *V, size_t ldv, int nv,
+                             double *out) {
+    const Plan &P = c->P;
+    if (P.weighted || nv < 1 || nv > 16) return false;
+    const EigenBlocks &eb = P.eb;
+    const int blk = ln.blk;
+    const int r = eb.first[blk];
+    const int width = eb.width[blk];
+    const double *Ua = stage_field(c, P.hier_stage[P.row_hier[r]]);
+    const double *Ub = width == 2 ? stage_field(c, P.hier_stage[P.row_hier[r + 1]]) : Ua;
+    const double *xm = nullptr;
+    if (P.op.kind == IRK_OP_VSF_2D) {
+        PROF(c, ln.stream, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
+             launch_field_sums(ln.stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, ln.part, ln.dv + DV_XMEANS,
+                               nullptr));
+        xm = ln.dv + DV_XMEANS;
+    }
+    // reads x and writes w (width * nvar fields each), one linearization
+    // field per component, and the nv basis vectors
+    const double len = (double)width * P.nf;
+    const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0) + 8.0 * len * nv;
+    PROF(c, ln.stream, "k_block_matvec_dot<" + std::to_string(P.op.kind) + ">", by, 1,
+         (void)launch_block_matvec_dot(ln.stream, c->dp, width, block_lam(eb, blk), c->dt, Ua, Ub, x, w, xm, V,
+                                       ldv, nv, ln.part, out));
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Right-preconditioned FGMRES(m) on D_b y = fhat_b (y in the block's rows of
 // Y), classical Gram-Schmidt with reorthogonalization, Givens QR of the
@@ -1161,17 +1192,22 @@ struct Fgmres {
 
     irk_status issue_after_prec() {
         double *zj = Zv(j), *w = Vv(j + 1);
-        op(zj, w);
         const int nv = j + 1;
         fused = nv <= 16;
         hipStream_t st = ln->stream;
         double *dv = ln->dv;
+        // the matvec, with h1 = V^T w in the same sweep where it applies (the
+        // vorticity solve of the reordered system zeroes part of w after the
+        // matvec, so there the projection stays a pass of its own)
+        const bool with_h1 = fused && mode != 1 && block_matvec_dot(c, *ln, zj, w, Vv(0), ln->ldv, nv, dv + DV_H1);
+        if (!with_h1) op(zj, w);
         if (fused) {
             // classical Gram-Schmidt twice in three sweeps: h1 = V^T w;
             // w -= V h1 with h2 = V^T w and ||w||^2 in the same sweep;
             // w = (w - V h2) / ||.||
-            PROF(c, st, "k_dot_multi", 8.0 * len * (nv + 1), 1,
-                 launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, nullptr));
+            if (!with_h1)
+                PROF(c, st, "k_dot_multi", 8.0 * len * (nv + 1), 1,
+                     launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, nullptr));
             PROF(c, st, "k_axpy_dot", 8.0 * len * (nv + 2), 1,
                  launch_axpy_dot(st, w, Vv(0), ln->ldv, nv, dv + DV_H1, len, ln->part, dv + DV_H2, nullptr));
             PROF(c, st, "k_axpy_scale", 8.0 * len * (nv + 2), 1,

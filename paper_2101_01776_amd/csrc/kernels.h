@@ -39,6 +39,12 @@ void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size
                         double *partials, double *out);
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
+// The same matvec fused with the first Gram-Schmidt pass: out[k] = (V_k, w)
+// for k < nv (basis vectors at stride ldv), through per-work-group partials
+// and their reduction; false (nothing launched) when nv > 16
+bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
+                             const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans,
+                             const double *V, size_t ldv, int nv, double *partials, double *out);
 // Eigen-block operator with stage-weighted linearizations (U: the s stage
 // fields); coupling = 1 gives -c21 M x_0 + dt sum_k W[1][0][k] L(U_k) x_0 on
 // the differential variable instead

@@ -586,47 +586,102 @@ __global__ void __launch_bounds__(IRK_WG) k_field_sums2(const double *__restrict
 // linearization K(Psi_m) = J_A(Psi_m, .) + nu Lap, psi rows
 // -dt [(x_omega - mean x_omega) + Lap x_psi - mean x_psi] (mass 0).
 // ------------------------------------------------------------------------
+// One point p of the eigen-block matvec: writes w at p (width * NV fields)
+// and returns the written values in wv (component-major: comp * NV + var).
+template <int OP>
+__device__ __forceinline__ void block_matvec_point(const DeviceProblem &P, int width, const BlockLam &lam, double dt,
+                                                   const double *__restrict__ Ua, const double *__restrict__ Ub,
+                                                   const double *__restrict__ x, double *__restrict__ w,
+                                                   const double *__restrict__ xmeans, size_t p, double (&wv)[4]) {
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t nf = NV * npts;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    double Lx[2], xc[2];
+    for (int comp = 0; comp < width; ++comp) {
+        const double *Uc = comp == 0 ? Ua : Ub;
+        const double *xx = x + comp * nf;
+        double lx, ld;
+        if constexpr (OP == IRK_OP_NLDIFF_2D) nldiff_lin<double, true>(Uc, xx, i, j, nx, ny, inv_h2, lx, ld);
+        else if constexpr (OP == IRK_OP_BURGERS_1D) burgers_lin<double, true>(Uc, xx, i, nx, h, P.g.nu, lx, ld);
+        else vsf_omega_lin<double, true>(Uc + npts, xx, i, j, nx, ny, h, P.g.nu, lx, ld);
+        Lx[comp] = lx;
+        xc[comp] = xx[p];
+    }
+    if (width == 1) {
+        wv[0] = lam.eta * xc[0] - dt * Lx[0];
+        w[p] = wv[0];
+    } else {
+        wv[0] = lam.eta * xc[0] + lam.c12 * xc[1] - dt * Lx[0];
+        wv[NV] = lam.c21 * xc[0] + lam.eta * xc[1] - dt * Lx[1];
+        w[p] = wv[0];
+        w[nf + p] = wv[NV];
+    }
+    if constexpr (NV == 2) {
+        for (int comp = 0; comp < width; ++comp) {
+            const double *xx = x + comp * nf;
+            double lp, ld;
+            poisson_lin<double, true>(xx + npts, i, j, nx, ny, h, lp, ld);
+            const double mw = xmeans[2 * comp], mp = xmeans[2 * comp + 1];
+            const double v = -dt * ((xc[comp] - mw) + lp - mp);
+            wv[comp * NV + 1] = v;
+            w[comp * nf + npts + p] = v;
+        }
+    }
+}
+
 template <int OP>
 __global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int width, BlockLam lam,
                                                          double dt, const double *__restrict__ Ua,
                                                          const double *__restrict__ Ub,
                                                          const double *__restrict__ x, double *__restrict__ w,
                                                          const double *__restrict__ xmeans) {
-    const int nx = P.g.nx, ny = P.g.ny;
-    const size_t npts = (size_t)nx * ny;
-    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
-    const size_t nf = NV * npts;
-    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        double Lx[2], xc[2];
-        for (int comp = 0; comp < width; ++comp) {
-            const double *Uc = comp == 0 ? Ua : Ub;
-            const double *xx = x + comp * nf;
-            double lx, ld;
-            if constexpr (OP == IRK_OP_NLDIFF_2D) nldiff_lin<double, true>(Uc, xx, i, j, nx, ny, inv_h2, lx, ld);
-            else if constexpr (OP == IRK_OP_BURGERS_1D) burgers_lin<double, true>(Uc, xx, i, nx, h, P.g.nu, lx, ld);
-            else vsf_omega_lin<double, true>(Uc + npts, xx, i, j, nx, ny, h, P.g.nu, lx, ld);
-            Lx[comp] = lx;
-            xc[comp] = xx[p];
-        }
-        if (width == 1) {
-            w[p] = lam.eta * xc[0] - dt * Lx[0];
-        } else {
-            w[p] = lam.eta * xc[0] + lam.c12 * xc[1] - dt * Lx[0];
-            w[nf + p] = lam.c21 * xc[0] + lam.eta * xc[1] - dt * Lx[1];
-        }
-        if constexpr (NV == 2) {
-            for (int comp = 0; comp < width; ++comp) {
-                const double *xx = x + comp * nf;
-                double lp, ld;
-                poisson_lin<double, true>(xx + npts, i, j, nx, ny, h, lp, ld);
-                const double mw = xmeans[2 * comp], mp = xmeans[2 * comp + 1];
-                w[comp * nf + npts + p] = -dt * ((xc[comp] - mw) + lp - mp);
+        double wv[4];
+        block_matvec_point<OP>(P, width, lam, dt, Ua, Ub, x, w, xmeans, p, wv);
+    }
+}
+
+// The matvec fused with the first Gram-Schmidt pass: w = D_b x and, per
+// work-group, the partial sums of (V_k, w) for k < nv (the basis vectors
+// V_k at stride ldv, each of width * NV fields), so w is not read back for
+// the first projection.  A separate reduction of the partials follows.
+template <int OP, int NVMAX>
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec_dot(DeviceProblem P, int width, BlockLam lam,
+                                                             double dt, const double *__restrict__ Ua,
+                                                             const double *__restrict__ Ub,
+                                                             const double *__restrict__ x, double *__restrict__ w,
+                                                             const double *__restrict__ xmeans,
+                                                             const double *__restrict__ V, size_t ldv, int nv,
+                                                             double *partials) {
+    constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const int nfld = width * NV;
+    double acc[NVMAX + 1];
+#pragma unroll
+    for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+        double wv[4];
+        block_matvec_point<OP>(P, width, lam, dt, Ua, Ub, x, w, xmeans, p, wv);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (f < nfld) {
+                const size_t e = (size_t)f * npts + p;
+#pragma unroll
+                for (int k = 0; k < NVMAX; ++k)
+                    if (k < nv) acc[k] += V[k * ldv + e] * wv[f];
             }
         }
     }
+    __shared__ double sh[4 * (NVMAX + 1)];
+    double mine;
+    block_reduce_multi<NVMAX + 1>(acc, nv, false, sh, mine);
+    finish_multi<NVMAX + 1>(mine, nv, partials);
 }
 
 // Eigen-block operator with stage-weighted linearizations (Newton-like (2),
@@ -1141,6 +1196,38 @@ void launch_field_sums2(hipStream_t st, const double *X0, const double *X1, size
     const unsigned g = grid_for(len, IRK_RED_BLOCKS);
     k_field_sums2<<<g, IRK_WG, 0, st>>>(X0, X1, len, scale, partials);
     reduce_partials(st, partials, g, 2, out);
+}
+
+template <int OP, int NVMAX>
+static void block_matvec_dot_op(hipStream_t st, unsigned g, const DeviceProblem &P, int width, const BlockLam &lam,
+                                double dt, const double *Ua, const double *Ub, const double *x, double *w,
+                                const double *xmeans, const double *V, size_t ldv, int nv, double *partials) {
+    k_block_matvec_dot<OP, NVMAX><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+}
+
+template <int OP>
+static void block_matvec_dot_nv(hipStream_t st, unsigned g, const DeviceProblem &P, int width, const BlockLam &lam,
+                                double dt, const double *Ua, const double *Ub, const double *x, double *w,
+                                const double *xmeans, const double *V, size_t ldv, int nv, double *partials) {
+    if (nv <= 4) block_matvec_dot_op<OP, 4>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+    else if (nv <= 8) block_matvec_dot_op<OP, 8>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+    else block_matvec_dot_op<OP, DOT_CHUNK>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+}
+
+bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
+                             const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans,
+                             const double *V, size_t ldv, int nv, double *partials, double *out) {
+    if (nv < 1 || nv > DOT_CHUNK) return false;
+    const size_t npts = (size_t)P.g.nx * P.g.ny;
+    const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
+    if (P.kind == IRK_OP_NLDIFF_2D)
+        block_matvec_dot_nv<IRK_OP_NLDIFF_2D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+    else if (P.kind == IRK_OP_BURGERS_1D)
+        block_matvec_dot_nv<IRK_OP_BURGERS_1D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+    else
+        block_matvec_dot_nv<IRK_OP_VSF_2D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
+    reduce_partials(st, partials, g, nv, out);
+    return true;
 }
 
 void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
