@@ -989,11 +989,13 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
 // The plain block matvec fused with the first Gram-Schmidt pass,
 // out[k] = (V_k, w) for the nv basis vectors at V (stride ldv); false
 // (nothing issued) where it does not apply: the stage-weighted operators of
-// Newton-like (2), (3), or more than 16 basis vectors.
+// Newton-like (2), (3), more than 16 basis vectors, or the DAE (its 9-point
+// matvec ran slower fused: the reduction grid of 512 work-groups leaves too
+// few waves to hide the stencil's latency).
 static bool block_matvec_dot(irk_ctx *c, Lane &ln, const double *x, double *w, const double *V, size_t ldv, int nv,
                              double *out) {
     const Plan &P = c->P;
-    if (P.weighted || nv < 1 || nv > 16) return false;
+    if (P.weighted || nv < 1 || nv > 16 || P.op.kind == IRK_OP_VSF_2D) return false;
     const EigenBlocks &eb = P.eb;
     const int blk = ln.blk;
     const int r = eb.first[blk];
