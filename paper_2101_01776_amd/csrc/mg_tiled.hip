@@ -40,6 +40,16 @@ namespace irk {
 // index wrap for i in [-n, 2n)
 __device__ __forceinline__ int wrap2(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// 1 / x for the Jacobi scaling of a level stencil: float32 uses the
+// hardware reciprocal (within 1 ulp; the diagonal is at least sigma > 0, far
+// from denormals) instead of the correctly rounded division sequence,
+// float64 divides
+template <class T>
+__device__ __forceinline__ T stencil_rcp(T x) {
+    if constexpr (sizeof(T) == sizeof(float)) return __builtin_amdgcn_rcpf(x);
+    else return T(1) / x;
+}
+
 __device__ __forceinline__ int xcd_tile() {
     const int nb = gridDim.x, b = blockIdx.x;
     if ((nb & 7) != 0) return b;
@@ -229,7 +239,7 @@ __device__ __forceinline__ void own_stencils(const T *cf, const WindowIndex<NPT>
         const bool inner = wi.ok(k) && ia >= 1 && ia < W - 1 && (!two_d || (ib >= 1 && ib < Hh - 1));
         if (inner) {
             build_stencil<T, OPK>(cf, q, W, inv_h2, g.h, g.nu, g.sigma, g.dt, a[k], ac[k]);
-            const T inv = T(1) / ac[k];
+            const T inv = stencil_rcp(ac[k]);
 #pragma unroll
             for (int m = 0; m < NS; ++m) a[k][m] *= inv;
             bv[k] *= inv;
@@ -488,7 +498,7 @@ __device__ __forceinline__ void store_level_stencil(const T *pad, int c, int pw,
     constexpr int NS = StencilShape<OPK>::NS;
     T a[NS], ac;
     build_stencil<T, OPK>(pad, c, pw, inv_h2, h, nu, sigma, dt, a, ac);
-    const T inv = T(1) / ac;
+    const T inv = stencil_rcp(ac);
 #pragma unroll
     for (int q = 0; q < NS; ++q) at[q * np + p] = a[q] * inv;
     acl[p] = ac;
