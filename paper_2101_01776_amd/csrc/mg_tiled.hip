@@ -268,7 +268,7 @@ template <class T, int OPK, int TX, int TY, int D>
 __device__ __forceinline__ void mg_down_body(const MgLevelArgs<T> &g, const MgIn &in, const int tile) {
     constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D + 2;                                   // halo of the window
-    const bool two_d = g.ny > 1;
+    constexpr bool two_d = OPK != MG_BURGERS;                 // (1-D Burgers: ny == 1)
     const int hy = two_d ? H : 0;
     constexpr int W = TX + 2 * H;
     const int Hh = (two_d ? TY : 1) + 2 * hy;
@@ -379,7 +379,7 @@ template <class T, int OPK, int TX, int TY, int D>
 __device__ __forceinline__ void mg_up_body(const MgLevelArgs<T> &g, const MgOut &out, const int tile) {
     constexpr int NS = StencilShape<OPK>::NS;
     constexpr int H = D;                                       // halo of the window
-    const bool two_d = g.ny > 1;
+    constexpr bool two_d = OPK != MG_BURGERS;                 // (1-D Burgers: ny == 1)
     const int hy = two_d ? H : 0;
     constexpr int W = TX + 2 * H;
     const int Hh = (two_d ? TY : 1) + 2 * hy;
