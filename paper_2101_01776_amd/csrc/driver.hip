@@ -1510,12 +1510,16 @@ struct Stepper : StepperBase {
         const Plan &P = c->P;
         const int s = P.s;
         const size_t nf = P.nf;
-        PROF(c, c->stream, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
-             launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
-        if (P.op.kind == IRK_OP_VSF_2D)
-            PROF(c, c->stream, "k_field_sums", 8.0 * s * nf, 1,
-                 launch_field_sums(c->stream, c->U, P.npts, 2 * s, P.npts, 1.0 / P.npts, c->part, c->dv + DV_MEANS,
-                                   nullptr));
+        if (P.op.kind == IRK_OP_VSF_2D) {
+            // the stage values with the stage means the constraint rows need
+            PROF(c, c->stream, "k_stage_prep_sums<" + std::to_string(s) + ">",
+                 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1), 1,
+                 launch_stage_prep_sums(c->stream, s, P.npts, u_n, c->K, c->Y, c->U, C, dt, fold, 1.0 / P.npts,
+                                        c->part, c->dv + DV_MEANS));
+        } else {
+            PROF(c, c->stream, "k_stage_prep<" + std::to_string(s) + ">", 8.0 * nf * (fold ? 4 * s + 1 : 2 * s + 1),
+                 1, launch_stage_prep(c->stream, s, nf, u_n, c->K, c->Y, c->U, C, dt, fold));
+        }
         // reads U and K, writes the transformed residual: 3 s fields
         PROF(c, c->stream, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
              8.0 * nf * 3 * s, 1,

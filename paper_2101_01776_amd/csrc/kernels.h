@@ -12,6 +12,12 @@ enum MgOp { MG_NLDIFF = 0, MG_BURGERS = 1, MG_VSF_OMEGA = 2, MG_POISSON = 3 };
 
 void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, double *K, const double *Y, double *U,
                        const StageCoefs &C, double dt, int fold);
+// The same for a two-variable field of npts points per variable (the DAE),
+// with out[2 i + var] = scale * sum of stage i's variable var (omega 0, psi 1)
+// through per-work-group partials and their reduction, in the same sweep
+void launch_stage_prep_sums(hipStream_t st, int s, size_t npts, const double *un, double *K, const double *Y,
+                            double *U, const StageCoefs &C, double dt, int fold, double scale, double *partials,
+                            double *out);
 // out[0] = ||F||^2, out[1] = squared norm of the magnitudes of F's terms;
 // VSF also gmax[0..s): each stage's largest one-cell streamfunction difference
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,

@@ -1068,6 +1068,72 @@ static void reduce_partials(hipStream_t st, const double *partials, unsigned nb,
     k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, nmax, out, out2);
 }
 
+// The stage preparation of a two-variable field (the DAE: omega, psi) with
+// the per-work-group partial sums of every stage's omega and psi, times
+// scale (the stage means the residual needs), in the same sweep.  The same
+// stage arithmetic as k_stage_prep; point p carries elements p and npts + p.
+template <int S>
+__global__ void __launch_bounds__(IRK_WG) k_stage_prep_sums(size_t npts, const double *__restrict__ un,
+                                                            double *__restrict__ K, const double *__restrict__ Y,
+                                                            double *__restrict__ U, StageCoefs C, double dt,
+                                                            int fold, double scale, double *partials) {
+    const size_t nf = 2 * npts;
+    double acc[2 * S + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * S; ++k) acc[k] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
+#pragma unroll
+        for (int var = 0; var < 2; ++var) {
+            const size_t e = var * npts + p;
+            double k[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j) k[j] = K[j * nf + e];
+            if (fold) {
+                double y[S];
+#pragma unroll
+                for (int l = 0; l < S; ++l) y[l] = Y[l * nf + e];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    double a = k[j];
+#pragma unroll
+                    for (int l = 0; l < S; ++l) a += C.TLam[j * S + l] * y[l];
+                    k[j] = a;
+                    K[j * nf + e] = a;
+                }
+            }
+            const double u = un[e];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                double a = 0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) a += C.A[i * S + j] * k[j];
+                const double v = u + dt * a;
+                U[i * nf + e] = v;
+                acc[2 * i + var] += v;
+            }
+        }
+    }
+    __shared__ double sh[4 * (2 * S + 1)];
+    double mine;
+    block_reduce_multi<2 * S + 1>(acc, 2 * S, false, sh, mine);
+    finish_multi<2 * S + 1>(mine * scale, 2 * S, partials);
+}
+
+void launch_stage_prep_sums(hipStream_t st, int s, size_t npts, const double *un, double *K, const double *Y,
+                            double *U, const StageCoefs &C, double dt, int fold, double scale, double *partials,
+                            double *out) {
+    const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
+    switch (s) {
+        case 1: k_stage_prep_sums<1><<<g, IRK_WG, 0, st>>>(npts, un, K, Y, U, C, dt, fold, scale, partials); break;
+        case 2: k_stage_prep_sums<2><<<g, IRK_WG, 0, st>>>(npts, un, K, Y, U, C, dt, fold, scale, partials); break;
+        case 3: k_stage_prep_sums<3><<<g, IRK_WG, 0, st>>>(npts, un, K, Y, U, C, dt, fold, scale, partials); break;
+        case 4: k_stage_prep_sums<4><<<g, IRK_WG, 0, st>>>(npts, un, K, Y, U, C, dt, fold, scale, partials); break;
+        case 5: k_stage_prep_sums<5><<<g, IRK_WG, 0, st>>>(npts, un, K, Y, U, C, dt, fold, scale, partials); break;
+    }
+    reduce_partials(st, partials, g, 2 * s, out);
+}
+
 template <int S>
 static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, const double *K, double *Fh,
                        const StageCoefs &C, const double *means, double *partials, double *out, double *gmax) {
