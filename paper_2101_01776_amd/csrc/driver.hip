@@ -201,6 +201,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
     P->fft_tsz = (o.kind == IRK_OP_VSF_2D && P->opt.psi_solve == 0 && fft_poisson_supported(o.nx, P->tsz))
                      ? P->tsz : 0;
     P->fft_psi = P->fft_tsz > 0;
+    static_assert(2 * 2048 <= IRK_RED_BLOCKS * 32, "the spectral solve's row sums use a lane's partials");
     if (o.kind == IRK_OP_VSF_2D && !P->fft_psi)
         for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
             if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] % 4 == 0 && P->lg.nx[l] == P->lg.ny[l]) {
@@ -812,19 +813,16 @@ static void prec_component(irk_ctx *c, Lane &ln, double *z, const double *v1, do
 }
 
 // VSF streamfunction row of a block: solve B psi = q, B = -dt (Lap - mean),
-// q = r_psi + dt (z_omega - mean z_omega).  The mean-free part comes from one
-// Poisson V-cycle on -dt Lap, the mean exactly: mean(psi) = mean(r_psi)/dt.
+// q = r_psi + dt (z_omega - mean z_omega).  The mean-free part comes from
+// the spectral solve or one Poisson V-cycle on -dt Lap, the mean exactly:
+// mean(psi) = mean(r_psi)/dt.  The spectral solve reduces the means itself
+// and, with xm, also hands the block matvec the means of its input
+// (xm[0] = mean z_omega, xm[1] = mean psi).
 template <class T>
-static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, const double *zomega) {
+static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, const double *zomega,
+                     double *xm = nullptr) {
     const size_t npts = c->P.npts;
     double *means = ln.dv + DV_SUMS;            // [0] mean r_psi, [1] mean z_omega
-    PROF(c, ln.stream, "k_field_sums2", 16.0 * npts, 1,
-         launch_field_sums2(ln.stream, rpsi, zomega, npts, 1.0 / npts, ln.part, means));
-    MgIn in;
-    in.v1 = rpsi; in.a1 = 1.0; in.v2 = zomega; in.a2 = c->dt; in.mean = means;
-    MgOut out;
-    out.z = zpsi; out.shift = means; out.shift_scale = 1.0 / c->dt;
-    out.v1 = rpsi; out.a1 = 1.0; out.v2 = zomega; out.a2 = c->dt; out.mean_in = means;
     if (c->P.fft_psi) {
         // exact: the spectral solve on the finest grid.  Bytes: q's two
         // float64 inputs and z (24 per point), the half spectrum written,
@@ -832,21 +830,32 @@ static void prec_psi(irk_ctx *c, Lane &ln, double *zpsi, const double *rpsi, con
         const int n = c->P.op.nx;
         const size_t fs = c->P.fft_tsz;
         const double by = 24.0 * npts + 4.0 * fft_poisson_spectrum_values(n) * fs;
+        FftPoissonArgs a;
+        a.v1 = rpsi; a.a1 = 1.0; a.v2 = zomega; a.a2 = c->dt;
+        a.z = zpsi; a.shift_scale = 1.0 / c->dt;
+        a.sums = ln.part; a.means = means; a.zmeans = xm;
         unsigned char *ws = c->ws;
         if (fs == sizeof(double)) {
             PROF(c, ln.stream, "k_fft_poisson<double>", by, 1,
                  launch_fft_poisson<double>(ln.stream, n, c->dt, reinterpret_cast<const double *>(ws + c->P.off_fft_tw),
-                                            reinterpret_cast<const double *>(ws + c->P.off_fft_lam), in, out,
+                                            reinterpret_cast<const double *>(ws + c->P.off_fft_lam), a,
                                             reinterpret_cast<double *>(ws + ln.lay->spec)));
         } else {
             PROF(c, ln.stream, "k_fft_poisson<float>", by, 1,
                  launch_fft_poisson<float>(ln.stream, n, (float)c->dt,
                                            reinterpret_cast<const float *>(ws + c->P.off_fft_tw),
-                                           reinterpret_cast<const float *>(ws + c->P.off_fft_lam), in, out,
+                                           reinterpret_cast<const float *>(ws + c->P.off_fft_lam), a,
                                            reinterpret_cast<float *>(ws + ln.lay->spec)));
         }
         return;
     }
+    PROF(c, ln.stream, "k_field_sums2", 16.0 * npts, 1,
+         launch_field_sums2(ln.stream, rpsi, zomega, npts, 1.0 / npts, ln.part, means));
+    MgIn in;
+    in.v1 = rpsi; in.a1 = 1.0; in.v2 = zomega; in.a2 = c->dt; in.mean = means;
+    MgOut out;
+    out.z = zpsi; out.shift = means; out.shift_scale = 1.0 / c->dt;
+    out.v1 = rpsi; out.a1 = 1.0; out.v2 = zomega; out.a2 = c->dt; out.mean_in = means;
     vcycle<T>(c, ln, MG_POISSON, 0.0, c->dt, -1, in, out);
 }
 
@@ -875,10 +884,10 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
     if (fork) {
         (void)hipEventRecord(ln.ev_fork, ln.stream);
         (void)hipStreamWaitEvent(ln.aux->stream, ln.ev_fork, 0);
-        prec_psi<T>(c, *ln.aux, z + npts, v + npts, z);
+        prec_psi<T>(c, *ln.aux, z + npts, v + npts, z, ln.dv + DV_XMEANS);
         ++nvc;
     } else if (vsf) {
-        prec_psi<T>(c, ln, z + npts, v + npts, z);
+        prec_psi<T>(c, ln, z + npts, v + npts, z, ln.dv + DV_XMEANS);
         ++nvc;
     }
     if (eb.width[blk] == 2) {
@@ -897,7 +906,7 @@ static int apply_prec(irk_ctx *c, Lane &ln, const double *v, double *z) {
             prec_component<T>(c, ln, z + nf, v + nf, 1.0, z, -eb.c21[blk], gam, hb);
         }
         ++nvc;
-        if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf); ++nvc; }
+        if (vsf) { prec_psi<T>(c, ln, z + nf + npts, v + nf + npts, z + nf, ln.dv + DV_XMEANS + 2); ++nvc; }
     }
     if (fork) {
         (void)hipEventRecord(ln.ev_join, ln.aux->stream);
@@ -950,14 +959,18 @@ static int apply_prec_mode(irk_ctx *c, Lane &ln, const double *v, double *z, int
     } else {
         zero_var(c, ln, z, 0);
         for (int comp = 0; comp < width; ++comp) {
-            prec_psi<T>(c, ln, z + comp * nf + npts, v + comp * nf + npts, z + comp * nf);
+            prec_psi<T>(c, ln, z + comp * nf + npts, v + comp * nf + npts, z + comp * nf,
+                        ln.dv + DV_XMEANS + 2 * comp);
             ++nvc;
         }
     }
     return nvc;
 }
 
-static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
+// w = D_b x for the lane's block.  The DAE's constraint rows need the means
+// of x: xm_ready says the spectral streamfunction solves that produced x
+// (the preconditioner's output, both its variables) already left them.
+static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w, bool xm_ready = false) {
     const Plan &P = c->P;
     const EigenBlocks &eb = P.eb;
     const int blk = ln.blk;
@@ -967,9 +980,10 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w) {
     const double *Ub = width == 2 ? stage_field(c, P.hier_stage[P.row_hier[r + 1]]) : Ua;
     const double *xm = nullptr;
     if (P.op.kind == IRK_OP_VSF_2D) {
-        PROF(c, ln.stream, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
-             launch_field_sums(ln.stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, ln.part, ln.dv + DV_XMEANS,
-                               nullptr));
+        if (!(xm_ready && P.fft_psi))
+            PROF(c, ln.stream, "k_field_sums", 8.0 * 2 * width * P.npts, 1,
+                 launch_field_sums(ln.stream, x, P.npts, 2 * width, P.npts, 1.0 / P.npts, ln.part,
+                                   ln.dv + DV_XMEANS, nullptr));
         xm = ln.dv + DV_XMEANS;
     }
     if (P.weighted) {
@@ -1114,7 +1128,7 @@ struct Fgmres {
 
     // the block operator of the current solve
     void op(const double *x, double *w) {
-        block_matvec(c, *ln, x, w);
+        block_matvec(c, *ln, x, w, mode != 1);
         if (mode == 1) zero_var(c, *ln, w, 1);
     }
 

@@ -4,8 +4,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include "mg_tiled.h"
-
 namespace irk {
 
 // Sides the spectral solve takes: powers of two from IRK_FFT_MIN up to
@@ -18,20 +16,36 @@ bool fft_poisson_supported(int n, size_t tsz);
 // complex entries.
 size_t fft_poisson_spectrum_values(int n);
 
+// Arguments of the spectral solve: q = a1 v1 + a2 v2 (v2 optional), the
+// float64 result z = x + shift_scale mean(v1), with x the mean-free solution.
+// The means come from the solve itself: the work-group of a row pair adds
+// its rows in float64 and subtracts each row's mean of q before the
+// transforms (a large mean rounded to the transform precision would swamp
+// the other modes), and the column pass of mode 0 rebuilds that column from
+// the row sums, also in float64.
+struct FftPoissonArgs {
+    const double *v1 = nullptr;
+    double a1 = 1.0;
+    const double *v2 = nullptr;
+    double a2 = 0.0;
+    double *z = nullptr;
+    double shift_scale = 0.0;
+    double *sums = nullptr;     // scratch, 2 n values: per row, the sums of v1 and v2
+    double *means = nullptr;    // written: mean v1, mean v2
+    double *zmeans = nullptr;   // optional, written: mean v2, mean z (= shift_scale mean v1)
+};
+
 // Solves -dt Lap_h x = q on the periodic n x n grid (5-point Laplacian,
-// spacing h; the constant mode of q is dropped and x is mean-free), with
-// q = in.a1 in.v1 + in.a2 in.v2 - (in.a1 in.mean[0] + in.a2 in.mean[1])
-// (in.v2 and in.mean optional; the mean is subtracted in float64 before the
-// transforms, which run in T), and writes
-// out.z = x + out.shift_scale * out.shift[0] (out.shift optional) in float64.
+// spacing h; the constant mode of q is dropped and x is mean-free) and writes
+// a.z as above (the transforms run in T).
 // tw: the n twiddles exp(-2 pi i j / n) as (re, im) pairs; lam: the n
 // eigenvalues 4 sin^2(pi m / n) / h^2 of the 1-D second difference; spec:
 // fft_poisson_spectrum_values(n) values of scratch.  Three launches on st:
-// row transforms of row pairs packed as one complex row, column transforms
-// with the division by dt (lam_a + lam_b) and the inverse column
-// transforms, and the inverse row transforms.
+// row transforms of row pairs packed as one complex row (with the row
+// sums), column transforms with the division by dt (lam_a + lam_b) and the
+// inverse column transforms (mode 0 also reduces the row sums to the means),
+// and the inverse row transforms.
 template <class T>
-void launch_fft_poisson(hipStream_t st, int n, T dt, const T *tw, const T *lam, const MgIn &in, const MgOut &out,
-                        T *spec);
+void launch_fft_poisson(hipStream_t st, int n, T dt, const T *tw, const T *lam, const FftPoissonArgs &a, T *spec);
 
 }  // namespace irk

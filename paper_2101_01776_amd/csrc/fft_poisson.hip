@@ -6,12 +6,16 @@
 // 5-point Laplacian: -Lap_h has eigenvalue lam_a + lam_b with
 // lam_m = 4 sin^2(pi m / n) / h^2, so x^_ab = q^_ab / (dt (lam_a + lam_b)),
 // the constant mode (a, b) = (0, 0) dropped.  Three launches:
-//   k_fft_rows_fwd  rows 2r and 2r+1 of q packed as one complex row
-//                   (q_2r + i q_2r+1), transformed in LDS, then separated by
-//                   Hermitian symmetry into the half spectra (modes 0..n/2)
-//                   of both rows;
+//   k_fft_rows_fwd  rows 2r and 2r+1 of q, each less its own mean, packed
+//                   as one complex row (q_2r + i q_2r+1), transformed in LDS,
+//                   then separated by Hermitian symmetry into the half
+//                   spectra (modes 0..n/2) of both rows; the row sums of
+//                   the inputs go to a small buffer;
 //   k_fft_cols      one column (mode k) of the half spectrum: transform,
 //                   divide by dt (lam_a + lam_k) n^2, inverse transform;
+//                   column 0 is rebuilt from the row sums (the row sums of q
+//                   less n times its mean), which it also reduces to the
+//                   means;
 //   k_fft_rows_inv  rows 2r and 2r+1 again: their full spectra rebuilt from
 //                   the halves (X_{n-k} = conj X_k), packed as X + i Y, one
 //                   inverse transform whose real and imaginary parts are the
@@ -68,6 +72,28 @@ __device__ __forceinline__ int xcd_order() {
     const int nb = gridDim.x, b = blockIdx.x;
     if ((nb & 7) != 0) return b;
     return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Sums of NV values over the work-group in a fixed order (each wave by
+// shuffles, then the waves in order), returned to every thread.  sh: NV
+// values per wave.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double *sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (lane == 0) sh[wid * NV + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < FFT_NT / 64; ++w) t += sh[w * NV + k];
+        v[k] = t;
+    }
 }
 
 }  // namespace
@@ -148,51 +174,62 @@ __device__ __forceinline__ void load_twiddles(const T *__restrict__ twg, cx<T> *
 // Half spectrum layout: column-major, spec[k n + r] for mode k <= n/2 of
 // row r (the column pass reads and writes whole contiguous columns).
 template <class T, int LG>
-__global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ twg, MgIn in,
+__global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ twg, FftPoissonArgs in,
                                                          cx<T> *__restrict__ spec) {
     constexpr int N = 1 << LG, HALF = N / 2, PT = (N + FFT_NT - 1) / FFT_NT;
     extern __shared__ unsigned char smem_raw[];
+    __shared__ double red[4 * (FFT_NT / 64)];
     cx<T> *X = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *Y = X + N;
     cx<T> *tw = Y + N;
     const size_t r0 = 2 * (size_t)xcd_order();
-    // rows r0, r0 + 1 of q = a1 v1 + a2 v2 less its mean (when given), packed
-    // q_r0 + i q_r0+1; every global load is in flight before the first is
-    // used.  The mean is subtracted in float64: the constant mode is dropped
-    // anyway, but a large mean rounded to the transform precision would
-    // swamp the other modes.
+    // rows r0, r0 + 1 of v1 and v2 (every global load in flight before the
+    // first is used), their sums in float64, and q = a1 v1 + a2 v2 less the
+    // row's mean, packed q_r0 + i q_r0+1
     const double *p1 = in.v1 + r0 * N;
-    const double qm = in.mean ? in.a1 * in.mean[0] + (in.v2 ? in.a2 * in.mean[1] : 0.0) : 0.0;
-    double qa[PT], qb[PT];
+    double qa[PT], qb[PT], va[PT], vb[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int j = (u * FFT_NT + (int)threadIdx.x) & (N - 1);
+        qa[u] = p1[j];
+        qb[u] = p1[N + j];
+    }
     if (in.v2) {
         const double *p2 = in.v2 + r0 * N;
-        double va[PT], vb[PT];
 #pragma unroll
         for (int u = 0; u < PT; ++u) {
             const int j = (u * FFT_NT + (int)threadIdx.x) & (N - 1);
-            qa[u] = p1[j];
-            qb[u] = p1[N + j];
             va[u] = p2[j];
             vb[u] = p2[N + j];
         }
-#pragma unroll
-        for (int u = 0; u < PT; ++u) {
-            qa[u] = in.a1 * qa[u] + in.a2 * va[u];
-            qb[u] = in.a1 * qb[u] + in.a2 * vb[u];
-        }
     } else {
 #pragma unroll
-        for (int u = 0; u < PT; ++u) {
-            const int j = (u * FFT_NT + (int)threadIdx.x) & (N - 1);
-            qa[u] = in.a1 * p1[j];
-            qb[u] = in.a1 * p1[N + j];
-        }
+        for (int u = 0; u < PT; ++u) va[u] = vb[u] = 0.0;
     }
     load_twiddles<T, N>(twg, tw);
+    double sm[4] = {0.0, 0.0, 0.0, 0.0};       // sums of v1 row a, row b, v2 row a, row b
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        if (N % FFT_NT == 0 || u * FFT_NT + (int)threadIdx.x < N) {
+            sm[0] += qa[u];
+            sm[1] += qb[u];
+            sm[2] += va[u];
+            sm[3] += vb[u];
+        }
+    }
+    block_sums<4>(sm, red);
+    if (threadIdx.x == 0) {
+        in.sums[2 * r0] = sm[0];
+        in.sums[2 * r0 + 1] = sm[2];
+        in.sums[2 * r0 + 2] = sm[1];
+        in.sums[2 * r0 + 3] = sm[3];
+    }
+    const double ma = (in.a1 * sm[0] + in.a2 * sm[2]) / N, mb = (in.a1 * sm[1] + in.a2 * sm[3]) / N;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
         const int j = u * FFT_NT + (int)threadIdx.x;
-        if (N % FFT_NT == 0 || j < N) X[j] = {(T)(qa[u] - qm), (T)(qb[u] - qm)};
+        if (N % FFT_NT == 0 || j < N)
+            X[j] = {(T)(in.a1 * qa[u] + in.a2 * va[u] - ma), (T)(in.a1 * qb[u] + in.a2 * vb[u] - mb)};
     }
     __syncthreads();
     const cx<T> *R = fft_lds<T, false, LG>(X, Y, tw);
@@ -208,7 +245,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ t
 
 template <class T, int LG>
 __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, const T *__restrict__ lamg, T dt,
-                                                     cx<T> *__restrict__ spec) {
+                                                     FftPoissonArgs in, cx<T> *__restrict__ spec) {
     constexpr int N = 1 << LG, PT = (N + FFT_NT - 1) / FFT_NT;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *X = reinterpret_cast<cx<T> *>(smem_raw);
@@ -224,6 +261,39 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
         const int r = (u * FFT_NT + (int)threadIdx.x) & (N - 1);
         v[u] = col[r];
         lv[u] = lamg[r];
+    }
+    if (k == 0) {
+        // column 0 holds the row sums of q less n times its mean (the rows'
+        // own means were subtracted before their transforms): rebuilt here
+        // in float64 from the row sums, which also give the means
+        __shared__ double red[2 * (FFT_NT / 64)];
+        double sr[PT][2];
+        double sm[2] = {0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int r = (u * FFT_NT + (int)threadIdx.x) & (N - 1);
+            sr[u][0] = in.sums[2 * r];
+            sr[u][1] = in.sums[2 * r + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < PT; ++u)
+            if (N % FFT_NT == 0 || u * FFT_NT + (int)threadIdx.x < N) {
+                sm[0] += sr[u][0];
+                sm[1] += sr[u][1];
+            }
+        block_sums<2>(sm, red);
+        const double nm = (in.a1 * sm[0] + in.a2 * sm[1]) / N;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) v[u] = {(T)(in.a1 * sr[u][0] + in.a2 * sr[u][1] - nm), T(0)};
+        if (threadIdx.x == 0) {
+            const double inv = 1.0 / ((double)N * N);
+            in.means[0] = sm[0] * inv;
+            in.means[1] = sm[1] * inv;
+            if (in.zmeans) {
+                in.zmeans[0] = sm[1] * inv;
+                in.zmeans[1] = in.shift_scale * sm[0] * inv;
+            }
+        }
     }
     load_twiddles<T, N>(twg, tw);
 #pragma unroll
@@ -260,7 +330,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
 
 template <class T, int LG>
 __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ twg, const cx<T> *__restrict__ spec,
-                                                         MgOut out) {
+                                                         FftPoissonArgs out) {
     constexpr int N = 1 << LG, HALF = N / 2, PT = (N + FFT_NT - 1) / FFT_NT;
     constexpr int PH = (HALF + 1 + FFT_NT - 1) / FFT_NT;
     extern __shared__ unsigned char smem_raw[];
@@ -290,7 +360,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ t
     }
     __syncthreads();
     const cx<T> *R = fft_lds<T, true, LG>(X, Y, tw);
-    const double shift = out.shift ? out.shift_scale * out.shift[0] : 0.0;
+    const double shift = out.shift_scale * out.means[0];
     double *z = out.z + r0 * N;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
@@ -303,36 +373,34 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ t
 }
 
 template <class T, int LG>
-static void launch_fft_sized(hipStream_t st, T dt, const T *tw, const T *lam, const MgIn &in, const MgOut &out,
-                             cx<T> *sp) {
+static void launch_fft_sized(hipStream_t st, T dt, const T *tw, const T *lam, const FftPoissonArgs &a, cx<T> *sp) {
     constexpr int N = 1 << LG;
-    k_fft_rows_fwd<T, LG><<<N / 2, FFT_NT, row_lds(N, sizeof(T)), st>>>(tw, in, sp);
-    k_fft_cols<T, LG><<<N / 2 + 1, FFT_NT, col_lds(N, sizeof(T)), st>>>(tw, lam, dt, sp);
-    k_fft_rows_inv<T, LG><<<N / 2, FFT_NT, row_lds(N, sizeof(T)), st>>>(tw, sp, out);
+    k_fft_rows_fwd<T, LG><<<N / 2, FFT_NT, row_lds(N, sizeof(T)), st>>>(tw, a, sp);
+    k_fft_cols<T, LG><<<N / 2 + 1, FFT_NT, col_lds(N, sizeof(T)), st>>>(tw, lam, dt, a, sp);
+    k_fft_rows_inv<T, LG><<<N / 2, FFT_NT, row_lds(N, sizeof(T)), st>>>(tw, sp, a);
 }
 
 template <class T>
-void launch_fft_poisson(hipStream_t st, int n, T dt, const T *tw, const T *lam, const MgIn &in, const MgOut &out,
-                        T *spec) {
+void launch_fft_poisson(hipStream_t st, int n, T dt, const T *tw, const T *lam, const FftPoissonArgs &a, T *spec) {
     cx<T> *sp = reinterpret_cast<cx<T> *>(spec);
     switch (log2_exact(n)) {
-        case 4: launch_fft_sized<T, 4>(st, dt, tw, lam, in, out, sp); break;
-        case 5: launch_fft_sized<T, 5>(st, dt, tw, lam, in, out, sp); break;
-        case 6: launch_fft_sized<T, 6>(st, dt, tw, lam, in, out, sp); break;
-        case 7: launch_fft_sized<T, 7>(st, dt, tw, lam, in, out, sp); break;
-        case 8: launch_fft_sized<T, 8>(st, dt, tw, lam, in, out, sp); break;
-        case 9: launch_fft_sized<T, 9>(st, dt, tw, lam, in, out, sp); break;
-        case 10: launch_fft_sized<T, 10>(st, dt, tw, lam, in, out, sp); break;
+        case 4: launch_fft_sized<T, 4>(st, dt, tw, lam, a, sp); break;
+        case 5: launch_fft_sized<T, 5>(st, dt, tw, lam, a, sp); break;
+        case 6: launch_fft_sized<T, 6>(st, dt, tw, lam, a, sp); break;
+        case 7: launch_fft_sized<T, 7>(st, dt, tw, lam, a, sp); break;
+        case 8: launch_fft_sized<T, 8>(st, dt, tw, lam, a, sp); break;
+        case 9: launch_fft_sized<T, 9>(st, dt, tw, lam, a, sp); break;
+        case 10: launch_fft_sized<T, 10>(st, dt, tw, lam, a, sp); break;
         case 11:
-            if (sizeof(T) == sizeof(float)) launch_fft_sized<T, 11>(st, dt, tw, lam, in, out, sp);
+            if (sizeof(T) == sizeof(float)) launch_fft_sized<T, 11>(st, dt, tw, lam, a, sp);
             break;
         default: break;                       // fft_poisson_supported admits no other side
     }
 }
 
-template void launch_fft_poisson<float>(hipStream_t, int, float, const float *, const float *, const MgIn &,
-                                        const MgOut &, float *);
-template void launch_fft_poisson<double>(hipStream_t, int, double, const double *, const double *, const MgIn &,
-                                         const MgOut &, double *);
+template void launch_fft_poisson<float>(hipStream_t, int, float, const float *, const float *, const FftPoissonArgs &,
+                                        float *);
+template void launch_fft_poisson<double>(hipStream_t, int, double, const double *, const double *,
+                                         const FftPoissonArgs &, double *);
 
 }  // namespace irk
