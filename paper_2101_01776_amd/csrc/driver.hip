@@ -350,7 +350,7 @@ enum {
     DV_Y = 256,        // least-squares solution (<= 64)
     DV_GMAX = 480,     // Newton level, VSF: largest one-cell streamfunction difference per stage (s)
 };
-#define PIN_READ 0          // per-lane pinned staging: readbacks
+#define PIN_READ 0          // per-lane pinned staging: readbacks (the reductions write there too)
 #define PIN_WRITE 512       // per-lane pinned staging: uploads
 #define PIN_LANE 1024       // doubles of pinned staging per lane
 
@@ -362,6 +362,7 @@ struct Lane {
     double *V = nullptr, *Z = nullptr, *part = nullptr, *dv = nullptr;
     double *tmp = nullptr;              // the (2,1) coupling of Newton-like (3) pairs
     double *pin = nullptr;
+    double *pin_dev = nullptr;          // pin as a device address
     size_t ldv = 0;
     const LaneLayout *lay = nullptr;
     // vorticity-streamfunction pairs: the side lane of the first
@@ -383,6 +384,7 @@ struct CtxRes {
     hipEvent_t fork[IRK_MAX_STAGES] = {}, join[IRK_MAX_STAGES] = {};
     hipEvent_t ev_main = nullptr, ev_res = nullptr;
     double *pinned = nullptr;                        // readback/upload staging, then the upload area
+    double *pinned_dev = nullptr;                    // pinned as a device address
     size_t upload = 0;                               // doubles of the upload area
 };
 
@@ -394,6 +396,7 @@ struct irk_ctx {
     double *K2 = nullptr;                // second stage buffer of the fused stage residual
     DeviceProblem dp;
     double *pinned = nullptr;            // host staging: Newton level + lanes (res->pinned)
+    double *pinned_dev = nullptr;        // the same as a device address
     CtxRes *res = nullptr;               // streams, events, pinned staging
     bool res_owned = false;              // made by irk_create (else a server slot's)
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
@@ -523,6 +526,13 @@ static int debug_level() {
 // asynchronous readback of a lane's device scalars; completion via ln.ev
 static irk_status lane_readback(Lane &ln, int count) {
     HIP_TRY(hipMemcpyAsync(ln.pin + PIN_READ, ln.dv, sizeof(double) * count, hipMemcpyDeviceToHost, ln.stream));
+    HIP_TRY(hipEventRecord(ln.ev, ln.stream));
+    return IRK_OK;
+}
+
+// the same for scalars the reductions already wrote to the lane's pinned
+// staging as well (their hout): only the event
+static irk_status lane_mark(Lane &ln) {
     HIP_TRY(hipEventRecord(ln.ev, ln.stream));
     return IRK_OK;
 }
@@ -1007,7 +1017,7 @@ static void block_matvec(irk_ctx *c, Lane &ln, const double *x, double *w, bool 
 // matvec ran slower fused: the reduction grid of 512 work-groups leaves too
 // few waves to hide the stencil's latency).
 static bool block_matvec_dot(irk_ctx *c, Lane &ln, const double *x, double *w, const double *V, size_t ldv, int nv,
-                             double *out) {
+                             double *out, double *hout) {
     const Plan &P = c->P;
     if (P.weighted || nv < 1 || nv > 16 || P.op.kind == IRK_OP_VSF_2D) return false;
     const EigenBlocks &eb = P.eb;
@@ -1029,7 +1039,7 @@ static bool block_matvec_dot(irk_ctx *c, Lane &ln, const double *x, double *w, c
     const double by = 8.0 * P.npts * width * (2.0 * P.nvar + 1.0) + 8.0 * len * nv;
     PROF(c, ln.stream, "k_block_matvec_dot<" + std::to_string(P.op.kind) + ">", by, 1,
          (void)launch_block_matvec_dot(ln.stream, c->dp, width, block_lam(eb, blk), c->dt, Ua, Ub, x, w, xm, V,
-                                       ldv, nv, ln.part, out));
+                                       ldv, nv, ln.part, out, hout));
     return true;
 }
 
@@ -1135,6 +1145,10 @@ struct Fgmres {
     double *Vv(int k) { return ln->V + (size_t)k * ln->ldv; }
     double *Zv(int k) { return ln->Z + (size_t)k * ln->ldv; }
 
+    // device address of the lane's readback value k (the reductions write
+    // there as well as to dv + k)
+    double *hb_dev(int k) { return ln->pin_dev + PIN_READ + k; }
+
     // issue ||r0||^2 (r0 = rhs on the first cycle, rhs - D sol on restarts)
     irk_status start() {
         if (first_cycle && mode == 1) {
@@ -1144,20 +1158,20 @@ struct Fgmres {
             zero_var(c, *ln, Vv(0), 1);
             PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
                  launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, Vv(0), len, 1, ln->part, ln->dv + DV_BETA,
-                                  nullptr));
+                                  hb_dev(DV_BETA)));
         } else if (first_cycle) {
             PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
-                 launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, rhs, len, 1, ln->part, ln->dv + DV_BETA, nullptr));
+                 launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, rhs, len, 1, ln->part, ln->dv + DV_BETA, hb_dev(DV_BETA)));
         } else {
             block_matvec(c, *ln, sol, Vv(0));
             PROF(c, ln->stream, "k_axpby", 24.0 * len, 1, launch_axpby(ln->stream, Vv(0), 1.0, rhs, -1.0, Vv(0), len));
             if (mode) zero_var(c, *ln, Vv(0), mode == 1 ? 1 : 0);
             PROF(c, ln->stream, "k_dot_multi", 8.0 * len, 1,
                  launch_dot_multi(ln->stream, Vv(0), ln->ldv, 0, Vv(0), len, 1, ln->part, ln->dv + DV_BETA,
-                                  nullptr));
+                                  hb_dev(DV_BETA)));
         }
         phase = WAIT_BETA;
-        return lane_readback(*ln, DV_BETA + 1);
+        return lane_mark(*ln);
     }
 
     // one Arnoldi iteration: preconditioner, matvec, CGS2; readback of h.
@@ -1215,19 +1229,26 @@ struct Fgmres {
         // the matvec, with h1 = V^T w in the same sweep where it applies (the
         // vorticity solve of the reordered system zeroes part of w after the
         // matvec, so there the projection stays a pass of its own)
-        const bool with_h1 = fused && mode != 1 && block_matvec_dot(c, *ln, zj, w, Vv(0), ln->ldv, nv, dv + DV_H1);
+        const bool with_h1 =
+            fused && mode != 1 && block_matvec_dot(c, *ln, zj, w, Vv(0), ln->ldv, nv, dv + DV_H1, hb_dev(DV_H1));
         if (!with_h1) op(zj, w);
         if (fused) {
             // classical Gram-Schmidt twice in three sweeps: h1 = V^T w;
             // w -= V h1 with h2 = V^T w and ||w||^2 in the same sweep;
-            // w = (w - V h2) / ||.||
+            // w = (w - V h2) / ||.||.  The coefficients reach the host
+            // through the pinned staging as they are reduced, so the event
+            // goes in before the last sweep: the host works out the next
+            // step while it runs.
             if (!with_h1)
                 PROF(c, st, "k_dot_multi", 8.0 * len * (nv + 1), 1,
-                     launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, nullptr));
+                     launch_dot_multi(st, Vv(0), ln->ldv, nv, w, len, 0, ln->part, dv + DV_H1, hb_dev(DV_H1)));
             PROF(c, st, "k_axpy_dot", 8.0 * len * (nv + 2), 1,
-                 launch_axpy_dot(st, w, Vv(0), ln->ldv, nv, dv + DV_H1, len, ln->part, dv + DV_H2, nullptr));
+                 launch_axpy_dot(st, w, Vv(0), ln->ldv, nv, dv + DV_H1, len, ln->part, dv + DV_H2, hb_dev(DV_H2)));
+            phase = WAIT_ITER;
+            if (lane_mark(*ln) != IRK_OK) return IRK_E_DEVICE;
             PROF(c, st, "k_axpy_scale", 8.0 * len * (nv + 2), 1,
                  launch_axpy_scale(st, w, Vv(0), ln->ldv, nv, dv + DV_H2, dv + DV_H2 + nv, len));
+            return IRK_OK;
         } else {
             const int nch = (nv + 15) / 16;   // dot launches (16 basis vectors each)
             PROF(c, st, "k_dot_multi", 8.0 * len * (nv + nch), nch,
@@ -1485,16 +1506,10 @@ struct Stepper : StepperBase {
         return true;
     }
 
-    // VSF: the stages' largest one-cell streamfunction differences of the
-    // latest residual evaluation, read back with its norms
-    hipError_t read_gmax() {
-        if (c->P.op.kind != IRK_OP_VSF_2D) return hipSuccess;
-        return hipMemcpyAsync(c->pinned + DV_GMAX, c->dv + DV_GMAX, c->P.s * sizeof(double), hipMemcpyDeviceToHost,
-                              c->stream);
-    }
-
-    // stage values and residual of the current K; its norms go to dv[slot],
-    // and (readback) dv[0..2] is copied to the host with an event behind it
+    // stage values and residual of the current K; its norms go to dv[slot]
+    // and the host's pinned[slot] (VSF: the stages' largest one-cell
+    // streamfunction differences to dv and pinned[DV_GMAX..]), with
+    // (readback) an event behind them
     irk_status issue_residual(int slot = DV_RES, bool readback = true) {
         const Plan &P = c->P;
         const int s = P.s;
@@ -1505,14 +1520,12 @@ struct Stepper : StepperBase {
             PROF(c, c->stream, "k_stage_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
                  8.0 * nf * (fold ? 5 * s + 1 : 3 * s + 1), 1,
                  launch_stage_residual(c->stream, s, c->dp, u_n, c->K, c->K2, c->Y, c->U, c->Fh, C, dt, fold,
-                                       c->part, c->dv + slot));
+                                       c->part, c->dv + slot, c->pinned_dev + slot));
             if (fold) std::swap(c->K, c->K2);
         } else {
             issue_residual_unfused(slot);
         }
         if (!readback) return IRK_OK;
-        HIP_TRY(hipMemcpyAsync(c->pinned, c->dv, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(read_gmax());
         HIP_TRY(hipEventRecord(c->ev_res, c->stream));
         phase = RES_WAIT;
         return IRK_OK;
@@ -1538,7 +1551,7 @@ struct Stepper : StepperBase {
         PROF(c, c->stream, "k_residual<" + std::to_string(s) + "," + std::to_string(P.op.kind) + ">",
              8.0 * nf * 3 * s, 1,
              launch_residual(c->stream, s, c->dp, c->U, c->K, c->Fh, C, c->dv + DV_MEANS, c->part, c->dv + slot,
-                             c->dv + DV_GMAX));
+                             c->dv + DV_GMAX, c->pinned_dev + slot, c->pinned_dev + DV_GMAX));
     }
 
     void set_zero_start() {
@@ -1567,9 +1580,8 @@ struct Stepper : StepperBase {
                                    c->stream));
             if ((e = issue_residual(DV_CAND + 4, false)) != IRK_OK) return e;
         }
-        HIP_TRY(hipMemcpyAsync(c->pinned + DV_CAND, c->dv + DV_CAND, 2 * ncand * sizeof(double),
-                               hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(read_gmax());        // of the last candidate evaluated
+        // (each candidate's norms went to pinned[DV_CAND + 2 i]; the last
+        // one's streamfunction differences stay in pinned[DV_GMAX..])
         HIP_TRY(hipEventRecord(c->ev_res, c->stream));
         start = START_CANDIDATES;
         phase = RES_WAIT;
@@ -2002,10 +2014,14 @@ static irk_status res_create(CtxRes *r, int nlanes, size_t upload) {
     r->nlanes = nlanes;
     r->upload = upload;
     const size_t pin = (size_t)(1 + IRK_MAX_STAGES) * PIN_LANE + upload;
-    if (hipHostMalloc((void **)&r->pinned, pin * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    // fine-grained (coherent) and mapped: the reductions write their results
+    // here directly, visible to the host once an event behind them completes
+    if (hipHostMalloc((void **)&r->pinned, pin * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
         r->pinned = nullptr;
         return IRK_E_DEVICE;
     }
+    if (hipHostGetDevicePointer((void **)&r->pinned_dev, r->pinned, 0) != hipSuccess) return IRK_E_DEVICE;
     auto ev = [](hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess; };
     if (!ev(&r->ev_main) || !ev(&r->ev_res)) return IRK_E_DEVICE;
     for (int b = 0; b < nlanes; ++b) {
@@ -2170,6 +2186,7 @@ static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait,
     c->stream = stream;
     c->res = r;
     c->pinned = r->pinned;
+    c->pinned_dev = r->pinned_dev;
     c->ev_main = r->ev_main;
     c->ev_res = r->ev_res;
     if (P.sd_s > 0) {
@@ -2192,6 +2209,7 @@ static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait,
         ln.dv = (double *)(c->ws + lay.dv);
         ln.tmp = lay.tmp ? (double *)(c->ws + lay.tmp) : nullptr;
         ln.pin = c->pinned + (size_t)(1 + b) * PIN_LANE;
+        ln.pin_dev = c->pinned_dev + (size_t)(1 + b) * PIN_LANE;
         ln.stream = r->lane_st[b];
         ln.ev = r->ev[b];
         ln.done = r->done[b];

@@ -19,9 +19,14 @@ void launch_stage_prep_sums(hipStream_t st, int s, size_t npts, const double *un
                             double *U, const StageCoefs &C, double dt, int fold, double scale, double *partials,
                             double *out);
 // out[0] = ||F||^2, out[1] = squared norm of the magnitudes of F's terms;
-// VSF also gmax[0..s): each stage's largest one-cell streamfunction difference
+// VSF also gmax[0..s): each stage's largest one-cell streamfunction
+// difference.  hout, hgmax (optional): the same values in pinned
+// fine-grained host memory as well (the reductions write both), which the
+// host reads once an event behind the launch has completed.  Every launcher
+// below with an hout argument does the same for its out.
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax);
+                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax,
+                     double *hout = nullptr, double *hgmax = nullptr);
 // Stage values and residual in one sweep (nonlinear diffusion and Burgers
 // only: stage_residual_fused): with fold, k = K + (T Lambda (x) I) Y is
 // written to Kout (not K); U, the transformed residual Fh and out[0..1] as
@@ -31,7 +36,7 @@ bool stage_residual_fused(const DeviceProblem &P);
 size_t stage_residual_blocks(int kind, int nx, int ny);
 void launch_stage_residual(hipStream_t st, int s, const DeviceProblem &P, const double *un, const double *K,
                            double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
-                           int fold, double *partials, double *out);
+                           int fold, double *partials, double *out, double *hout = nullptr);
 void launch_rhs_init(hipStream_t st, int s, const DeviceProblem &P, const double *un, double *K, double sin_tn,
                      double cos_tn);
 // Kx_i = sum_j W.A[i][j] K_j (s stage fields of length nf; Kx must not alias K)
@@ -50,7 +55,8 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, cons
 // and their reduction; false (nothing launched) when nv > 16
 bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                              const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans,
-                             const double *V, size_t ldv, int nv, double *partials, double *out);
+                             const double *V, size_t ldv, int nv, double *partials, double *out,
+                             double *hout = nullptr);
 // Eigen-block operator with stage-weighted linearizations (U: the s stage
 // fields); coupling = 1 gives -c21 M x_0 + dt sum_k W[1][0][k] L(U_k) x_0 on
 // the differential variable instead
@@ -62,11 +68,11 @@ void launch_block_matvec_w(hipStream_t st, const DeviceProblem &P, int s, int wi
 void launch_block_couple(hipStream_t st, const DeviceProblem &P, int s, const BlockCouple &C, double dt,
                          const double *U, const double *y, double *f);
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
-                      int with_norm, double *partials, double *out, unsigned *ctr);
+                      int with_norm, double *partials, double *out, double *hout = nullptr);
 void launch_axpy_multi(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h, size_t len);
 // w <- w - V h1, then h2 = V^T w and ||w||^2 into out[0..nv] (nv <= 16)
 void launch_axpy_dot(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h1, size_t len,
-                     double *partials, double *out, unsigned *ctr);
+                     double *partials, double *out, double *hout = nullptr);
 // w <- (w - V h2) / sqrt(nrm2 - |h2|^2)
 void launch_axpy_scale(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h2,
                        const double *nrm2, size_t len);

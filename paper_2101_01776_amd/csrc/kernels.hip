@@ -95,10 +95,13 @@ __device__ __forceinline__ double wave_max(double v) {
 // shuffles; then waves 0..3 in order.  Every load of a thread is issued
 // before its first add (the values sit in another XCD's L2 or in HBM).  The
 // last nmax values of a partial are maxima of non-negative values instead:
-// they are reduced by max and written to out2[0..nmax).
+// they are reduced by max and written to out2[0..nmax).  hout, hout2
+// (optional): the same values again in host memory (pinned, fine-grained),
+// which the host reads once an event behind this kernel has completed, with
+// no copy.
 __global__ void __launch_bounds__(256) k_reduce_partials(const double *__restrict__ partials, int nb, int nv,
                                                          int nmax, double *__restrict__ out,
-                                                         double *__restrict__ out2) {
+                                                         double *__restrict__ out2, double *hout, double *hout2) {
     __shared__ double sh[4 * RED_NV];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nsum = nv - nmax;
@@ -123,8 +126,13 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double *__restric
         double t = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
             t = k < nsum ? t + sh[w * RED_NV + k] : fmax(t, sh[w * RED_NV + k]);
-        if (k < nsum) out[k] = t;
-        else out2[k - nsum] = t;
+        if (k < nsum) {
+            out[k] = t;
+            if (hout) hout[k] = t;
+        } else {
+            out2[k - nsum] = t;
+            if (hout2) hout2[k - nsum] = t;
+        }
     }
 }
 
@@ -1064,8 +1072,8 @@ void launch_stage_prep(hipStream_t st, int s, size_t nf, const double *un, doubl
 }
 
 static void reduce_partials(hipStream_t st, const double *partials, unsigned nb, int nv, double *out,
-                            int nmax = 0, double *out2 = nullptr) {
-    k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, nmax, out, out2);
+                            int nmax = 0, double *out2 = nullptr, double *hout = nullptr, double *hout2 = nullptr) {
+    k_reduce_partials<<<1, 256, 0, st>>>(partials, (int)nb, nv, nmax, out, out2, hout, hout2);
 }
 
 // The stage preparation of a two-variable field (the DAE: omega, psi) with
@@ -1136,36 +1144,38 @@ void launch_stage_prep_sums(hipStream_t st, int s, size_t npts, const double *un
 
 template <int S>
 static void residual_s(hipStream_t st, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                       const StageCoefs &C, const double *means, double *partials, double *out, double *gmax) {
+                       const StageCoefs &C, const double *means, double *partials, double *out, double *gmax,
+                       double *hout, double *hgmax) {
     const size_t npts = (size_t)P.g.nx * P.g.ny;
     const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
     if (P.kind == IRK_OP_NLDIFF_2D) {
         k_residual<S, IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
-        reduce_partials(st, partials, g, 2, out);
+        reduce_partials(st, partials, g, 2, out, 0, nullptr, hout);
     } else if (P.kind == IRK_OP_BURGERS_1D) {
         k_residual<S, IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
-        reduce_partials(st, partials, g, 2, out);
+        reduce_partials(st, partials, g, 2, out, 0, nullptr, hout);
     } else {
         k_residual<S, IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, U, K, Fh, C, means, partials);
-        reduce_partials(st, partials, g, 2 + S, out, S, gmax);
+        reduce_partials(st, partials, g, 2 + S, out, S, gmax, hout, hgmax);
     }
 }
 
 void launch_residual(hipStream_t st, int s, const DeviceProblem &P, const double *U, const double *K, double *Fh,
-                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax) {
+                     const StageCoefs &C, const double *means, double *partials, double *out, double *gmax,
+                     double *hout, double *hgmax) {
     switch (s) {
-        case 1: residual_s<1>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
-        case 2: residual_s<2>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
-        case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
-        case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
-        case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, gmax); break;
+        case 1: residual_s<1>(st, P, U, K, Fh, C, means, partials, out, gmax, hout, hgmax); break;
+        case 2: residual_s<2>(st, P, U, K, Fh, C, means, partials, out, gmax, hout, hgmax); break;
+        case 3: residual_s<3>(st, P, U, K, Fh, C, means, partials, out, gmax, hout, hgmax); break;
+        case 4: residual_s<4>(st, P, U, K, Fh, C, means, partials, out, gmax, hout, hgmax); break;
+        case 5: residual_s<5>(st, P, U, K, Fh, C, means, partials, out, gmax, hout, hgmax); break;
     }
 }
 
 template <int S>
 static void stage_residual_s(hipStream_t st, const DeviceProblem &P, const double *un, const double *K,
                              double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
-                             int fold, double *partials, double *out) {
+                             int fold, double *partials, double *out, double *hout) {
     unsigned g;
     if (P.kind == IRK_OP_NLDIFF_2D) {
         if (P.g.nx >= 64) {
@@ -1182,7 +1192,7 @@ static void stage_residual_s(hipStream_t st, const DeviceProblem &P, const doubl
         k_stage_residual<S, IRK_OP_BURGERS_1D, 256, 1><<<g, IRK_WG, 0, st>>>(P, un, K, Kout, Y, U, Fh, C, dt, fold,
                                                                           partials);
     }
-    reduce_partials(st, partials, g, 2, out);
+    reduce_partials(st, partials, g, 2, out, 0, nullptr, hout);
 }
 
 bool stage_residual_fused(const DeviceProblem &P) {
@@ -1197,13 +1207,13 @@ size_t stage_residual_blocks(int kind, int nx, int ny) {
 
 void launch_stage_residual(hipStream_t st, int s, const DeviceProblem &P, const double *un, const double *K,
                            double *Kout, const double *Y, double *U, double *Fh, const StageCoefs &C, double dt,
-                           int fold, double *partials, double *out) {
+                           int fold, double *partials, double *out, double *hout) {
     switch (s) {
-        case 1: stage_residual_s<1>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
-        case 2: stage_residual_s<2>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
-        case 3: stage_residual_s<3>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
-        case 4: stage_residual_s<4>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
-        case 5: stage_residual_s<5>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out); break;
+        case 1: stage_residual_s<1>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out, hout); break;
+        case 2: stage_residual_s<2>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out, hout); break;
+        case 3: stage_residual_s<3>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out, hout); break;
+        case 4: stage_residual_s<4>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out, hout); break;
+        case 5: stage_residual_s<5>(st, P, un, K, Kout, Y, U, Fh, C, dt, fold, partials, out, hout); break;
     }
 }
 
@@ -1282,7 +1292,7 @@ static void block_matvec_dot_nv(hipStream_t st, unsigned g, const DeviceProblem 
 
 bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                              const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans,
-                             const double *V, size_t ldv, int nv, double *partials, double *out) {
+                             const double *V, size_t ldv, int nv, double *partials, double *out, double *hout) {
     if (nv < 1 || nv > DOT_CHUNK) return false;
     const size_t npts = (size_t)P.g.nx * P.g.ny;
     const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
@@ -1292,7 +1302,7 @@ bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, 
         block_matvec_dot_nv<IRK_OP_BURGERS_1D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
     else
         block_matvec_dot_nv<IRK_OP_VSF_2D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
-    reduce_partials(st, partials, g, nv, out);
+    reduce_partials(st, partials, g, nv, out, 0, nullptr, hout);
     return true;
 }
 
@@ -1353,7 +1363,7 @@ void launch_block_couple(hipStream_t st, const DeviceProblem &P, int s, const Bl
 }
 
 void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const double *w, size_t len,
-                      int with_norm, double *partials, double *out, unsigned *ctr) {
+                      int with_norm, double *partials, double *out, double *hout) {
     // chunks of DOT_CHUNK vectors; the norm (if any) rides on the last chunk
     int done = 0;
     do {
@@ -1364,18 +1374,18 @@ void launch_dot_multi(hipStream_t st, const double *V, size_t ldv, int nv, const
         if (c <= 4) k_dot_multi<4, 4><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
         else if (c <= 8) k_dot_multi<8, 2><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
         else k_dot_multi<DOT_CHUNK, 1><<<g, IRK_WG, 0, st>>>(V + done * ldv, ldv, c, w, len, wn, partials);
-        reduce_partials(st, partials, g, c + wn, out + done);
+        reduce_partials(st, partials, g, c + wn, out + done, 0, nullptr, hout ? hout + done : nullptr);
         done += c;
     } while (done < nv);
 }
 
 void launch_axpy_dot(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h1, size_t len,
-                     double *partials, double *out, unsigned *ctr) {
+                     double *partials, double *out, double *hout) {
     const unsigned g = grid_for(len, IRK_RED_BLOCKS);
     if (nv <= 4) k_axpy_dot<4, 4><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
     else if (nv <= 8) k_axpy_dot<8, 2><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
     else k_axpy_dot<DOT_CHUNK, 1><<<g, IRK_WG, 0, st>>>(w, V, ldv, nv, h1, len, partials);
-    reduce_partials(st, partials, g, nv + 1, out);
+    reduce_partials(st, partials, g, nv + 1, out, 0, nullptr, hout);
 }
 
 void launch_axpy_scale(hipStream_t st, double *w, const double *V, size_t ldv, int nv, const double *h2,
