@@ -188,6 +188,16 @@ typedef struct irk_options {
                                the solve is exact only to about the
                                Laplacian's condition number times float32
                                rounding (1e-2 at 1024^2)                  */
+    int lane_threads;       /* 1: a context made by irk_create with two or
+                               more independent eigen-blocks (eigenbasis,
+                               no batch_mg) drives each block's solve from
+                               a host thread of its own, so that the
+                               blocks' kernel launches are issued in
+                               parallel; the threads live as long as the
+                               context and sleep between steps.  Off while
+                               irk_profile_enable is on.  0: the calling
+                               thread drives every block.  The device work
+                               and its results are the same either way    */
 } irk_options;
 
 /* Per-step counters.  "Preconditioner applications" follow the paper's

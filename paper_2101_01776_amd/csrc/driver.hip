@@ -15,14 +15,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fft_poisson.h"
@@ -126,7 +130,7 @@ static bool valid_options(const irk_options &o) {
            o.krylov_rtol < 1 && o.newton_rtol >= 0 && o.newton_atol >= 0 && (o.batch_mg == 0 || o.batch_mg == 1) &&
            (o.start_extrapolate == 0 || o.start_extrapolate == 1) && (o.krylov_adaptive == 0 || o.krylov_adaptive == 1) &&
            (o.dae_reorder == 0 || o.dae_reorder == 1) && (o.transform == 0 || o.transform == 1) &&
-           (o.psi_solve == 0 || o.psi_solve == 1);
+           (o.psi_solve == 0 || o.psi_solve == 1) && (o.lane_threads == 0 || o.lane_threads == 1);
 }
 
 static irk_status make_plan(int family, int s, const irk_operator *op, const irk_options *opt, Plan *P) {
@@ -373,6 +377,7 @@ struct Lane {
 };
 
 struct StepperBase;
+struct LaneWorkers;
 
 // Streams, events and pinned host staging a context runs on.  irk_create
 // makes a private set; a server makes one per slot when it is created, so
@@ -402,6 +407,7 @@ struct irk_ctx {
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
     hipEvent_t ev_res = nullptr;        // Newton-level readbacks
     StepperBase *stepper = nullptr;
+    LaneWorkers *workers = nullptr;      // host threads of the eigen-block lanes (lane_threads)
     // V-cycle batching: a broker of the context's precision (PrecBroker<T>),
     // private (owned, batches this context's blocks) or a server's (shared)
     void *broker = nullptr;
@@ -515,11 +521,10 @@ template <class T> static std::string kn(const char *base, int opk = -1) {
 // IRK_DEBUG=1 in the environment traces the Newton iterations on stderr, 2
 // also every block solve.
 static int debug_level() {
-    static int lvl = -1;
-    if (lvl < 0) {
+    static const int lvl = [] {
         const char *e = getenv("IRK_DEBUG");
-        lvl = e ? atoi(e) : 0;
-    }
+        return e ? atoi(e) : 0;
+    }();
     return lvl;
 }
 
@@ -1474,8 +1479,52 @@ struct StepperBase {
     virtual void begin(const double *u_n, double t_n, double dt, double rtol, double *u_np1) = 0;
     // advance as far as possible without blocking; true when finished
     virtual bool poll() = 0;
+    // on a lane's host thread: block b's solve of this Newton iteration, to
+    // its end
+    virtual void run_lane(int b) { (void)b; }
     irk_status status = IRK_OK;
     irk_stats stats;
+};
+
+// Host threads of a context, one per eigen-block lane (option lane_threads).
+// In a Newton iteration each drives its block's FGMRES -- the launches, the
+// waits for its readbacks and the host's Hessenberg work -- while the
+// calling thread keeps the Newton level: the blocks' launches, the larger
+// part of the host's time, are issued in parallel (HIP launches onto
+// separate streams from separate threads do not serialize).  A worker waits
+// for a request, first spinning (a Newton iteration's blocks follow each
+// other closely), then sleeping; runs the lane's solve to its end; and marks
+// the request finished.
+struct LaneWorkers {
+    irk_ctx *c = nullptr;
+    int n = 0;
+    std::thread th[IRK_MAX_STAGES];
+    std::atomic<unsigned> req[IRK_MAX_STAGES];
+    std::atomic<unsigned> fin[IRK_MAX_STAGES];
+    std::atomic<bool> quit{false};
+    std::mutex m;
+    std::condition_variable cv;
+
+    LaneWorkers() {
+        for (int b = 0; b < IRK_MAX_STAGES; ++b) {
+            req[b].store(0);
+            fin[b].store(0);
+        }
+    }
+    void request(int b) {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            req[b].store(req[b].load(std::memory_order_relaxed) + 1, std::memory_order_release);
+        }
+        cv.notify_all();
+    }
+    bool finished(int b) const {
+        return fin[b].load(std::memory_order_acquire) == req[b].load(std::memory_order_relaxed);
+    }
+    void wait_all() const {
+        for (int b = 0; b < n; ++b)
+            while (!finished(b)) std::this_thread::yield();
+    }
 };
 
 template <class T>
@@ -1495,11 +1544,16 @@ struct Stepper : StepperBase {
     Fgmres<T> fg[IRK_MAX_STAGES];
     bool lane_done[IRK_MAX_STAGES];
     bool lane_started[IRK_MAX_STAGES];
+    // this Newton iteration's block solves run on the lanes' host threads
+    bool threaded = false;
+    irk_status lane_err[IRK_MAX_STAGES];
     double block_ktol = 1e-5;
 
     explicit Stepper(irk_ctx *cc) : c(cc) {}
 
     bool fail(irk_status e) {
+        if (threaded) c->workers->wait_all();      // no lane still issuing work
+        threaded = false;
         status = e;
         phase = DONE;
         if (c->broker) static_cast<PrecBroker<T> *>(c->broker)->forget(c);   // lanes left waiting in a batch
@@ -1718,17 +1772,46 @@ struct Stepper : StepperBase {
         double ktol = P.opt.krylov_rtol;
         if (P.opt.krylov_adaptive) ktol = std::min(0.1, std::max(ktol, 0.1 * std::max(thresh, floor_res) / res));
         block_ktol = ktol;
+        threaded = c->workers && !c->prof && !c->broker && !P.eb.schur;
         for (int b = 0; b < c->nlanes; ++b) {
             lane_done[b] = false;
             lane_started[b] = false;
             if (hipStreamWaitEvent(c->lanes[b].stream, c->ev_main, 0) != hipSuccess) return fail(IRK_E_DEVICE);
             // real Schur basis: back-substitution, the last block first
             if (P.eb.schur && b != c->nlanes - 1) continue;
+            if (threaded) {
+                lane_started[b] = true;
+                lane_err[b] = IRK_OK;
+                fg[b].init(c, &c->lanes[b], block_ktol, c->P.opt.max_krylov);
+                c->workers->request(b);
+                continue;
+            }
             const irk_status e = start_block(b);
             if (e != IRK_OK) return fail(e);
         }
         phase = BLOCKS;
         return false;
+    }
+
+    void run_lane(int b) override {
+        irk_status e = fg[b].start();
+        while (e == IRK_OK && fg[b].phase != Fgmres<T>::DONE) {
+            const hipError_t q = hipEventQuery(c->lanes[b].ev);
+            if (q == hipErrorNotReady) {
+                std::this_thread::yield();
+                continue;
+            }
+            if (q != hipSuccess) {
+                e = IRK_E_DEVICE;
+                break;
+            }
+            e = fg[b].advance();
+            // reordered DAE system: the streamfunction rows next
+            if (e == IRK_OK && fg[b].phase == Fgmres<T>::DONE && fg[b].mode == 1) e = fg[b].to_psi();
+        }
+        // launch errors are recorded per host thread
+        if (e == IRK_OK && hipGetLastError() != hipSuccess) e = IRK_E_DEVICE;
+        lane_err[b] = e;
     }
 
     irk_status start_block(int b) {
@@ -1775,18 +1858,26 @@ struct Stepper : StepperBase {
             bool progressed = false;
             for (int b = 0; b < c->nlanes; ++b) {
                 if (lane_done[b] || !lane_started[b]) continue;
-                if (fg[b].deferred != IRK_OK) return fail(fg[b].deferred);
-                if (fg[b].phase == Fgmres<T>::WAIT_PREC) continue;      // in a broker batch
-                const hipError_t q = hipEventQuery(c->lanes[b].ev);
-                if (q == hipErrorNotReady) continue;
-                if (q != hipSuccess) return fail(IRK_E_DEVICE);
-                progressed = true;
-                irk_status e = fg[b].advance();
-                if (e != IRK_OK) return fail(e);
-                if (fg[b].phase == Fgmres<T>::DONE && fg[b].mode == 1) {
-                    // reordered DAE system: the streamfunction rows next
-                    e = fg[b].to_psi();
+                irk_status e = IRK_OK;
+                if (threaded) {
+                    // the lane's host thread ran its solve to the end
+                    if (!c->workers->finished(b)) continue;
+                    if (lane_err[b] != IRK_OK) return fail(lane_err[b]);
+                    progressed = true;
+                } else {
+                    if (fg[b].deferred != IRK_OK) return fail(fg[b].deferred);
+                    if (fg[b].phase == Fgmres<T>::WAIT_PREC) continue;      // in a broker batch
+                    const hipError_t q = hipEventQuery(c->lanes[b].ev);
+                    if (q == hipErrorNotReady) continue;
+                    if (q != hipSuccess) return fail(IRK_E_DEVICE);
+                    progressed = true;
+                    e = fg[b].advance();
                     if (e != IRK_OK) return fail(e);
+                    if (fg[b].phase == Fgmres<T>::DONE && fg[b].mode == 1) {
+                        // reordered DAE system: the streamfunction rows next
+                        e = fg[b].to_psi();
+                        if (e != IRK_OK) return fail(e);
+                    }
                 }
                 if (fg[b].phase == Fgmres<T>::DONE) {
                     lane_done[b] = true;
@@ -1815,6 +1906,7 @@ struct Stepper : StepperBase {
                 progressed = true;
             }
             if (active == 0) {
+                threaded = false;
                 stats.newton_its++;
                 fold = 1;
                 ++it;
@@ -1962,6 +2054,7 @@ extern "C" void irk_default_options(irk_options *o) {
     o->dae_reorder = 0;
     o->transform = 0;
     o->psi_solve = 0;
+    o->lane_threads = 1;
 }
 
 extern "C" size_t irk_workspace_bytes(irk_family family, int s, const irk_operator *op, const irk_options *opt) {
@@ -2051,8 +2144,66 @@ static void res_destroy(CtxRes *r) {
     *r = CtxRes();
 }
 
+static void lane_worker_main(LaneWorkers *W, int b) {
+    unsigned seen = 0;
+    for (;;) {
+        unsigned g = W->req[b].load(std::memory_order_acquire);
+        for (int spin = 0; g == seen; ++spin) {
+            if (W->quit.load(std::memory_order_acquire)) return;
+            if (spin < 20000) {
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> lk(W->m);
+                W->cv.wait(lk, [&] {
+                    return W->req[b].load(std::memory_order_acquire) != seen || W->quit.load(std::memory_order_acquire);
+                });
+            }
+            g = W->req[b].load(std::memory_order_acquire);
+        }
+        seen = g;
+        W->c->stepper->run_lane(b);
+        W->fin[b].store(g, std::memory_order_release);
+    }
+}
+
+static void stop_workers(irk_ctx *c) {
+    LaneWorkers *W = c->workers;
+    if (!W) return;
+    W->wait_all();
+    {
+        std::lock_guard<std::mutex> lk(W->m);
+        W->quit.store(true, std::memory_order_release);
+    }
+    W->cv.notify_all();
+    for (int b = 0; b < W->n; ++b)
+        if (W->th[b].joinable()) W->th[b].join();
+    delete W;
+    c->workers = nullptr;
+}
+
+// a host thread per eigen-block lane, where they can run concurrently (two
+// or more blocks of the eigenbasis, no shared V-cycle batches); none if a
+// thread cannot be made
+static void start_workers(irk_ctx *c) {
+    const Plan &P = c->P;
+    if (!P.opt.lane_threads || c->nlanes < 2 || P.sd_s > 0 || P.eb.schur || c->broker) return;
+    LaneWorkers *W = new (std::nothrow) LaneWorkers();
+    if (!W) return;
+    W->c = c;
+    c->workers = W;
+    try {
+        for (int b = 0; b < c->nlanes; ++b) {
+            W->th[b] = std::thread(lane_worker_main, W, b);
+            W->n = b + 1;
+        }
+    } catch (...) {
+        stop_workers(c);
+    }
+}
+
 static void release(irk_ctx *c) {
     if (!c) return;
+    stop_workers(c);
     if (c->broker) {
         if (c->P.opt.prec_fp32) {
             auto *b = static_cast<PrecBroker<float> *>(c->broker);
@@ -2303,6 +2454,7 @@ extern "C" irk_status irk_create(irk_family family, int s, const irk_operator *o
         release(c);
         return stt == IRK_E_NOMEM ? IRK_E_NOMEM : IRK_E_DEVICE;
     }
+    start_workers(c);
     *out = c;
     return IRK_OK;
 }

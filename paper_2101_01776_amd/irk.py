@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("mg_coarsest", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("batch_mg", ctypes.c_int),
                 ("start_extrapolate", ctypes.c_int), ("krylov_adaptive", ctypes.c_int),
                 ("dae_reorder", ctypes.c_int), ("transform", ctypes.c_int),
-                ("psi_solve", ctypes.c_int)]
+                ("psi_solve", ctypes.c_int), ("lane_threads", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -241,3 +241,14 @@ def test_streamfunction_solve_option():
     f64 = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=0, prec_fp32=0))
     f64_mg = irk.irk_workspace_bytes("radau", 3, big, irk.make_options(psi_solve=1, prec_fp32=0))
     assert f32 != f32_mg and f64 == f64_mg
+
+
+def test_lane_threads_option():
+    """lane_threads: 1 (default) a host thread per eigen-block solve, 0 the
+    calling thread only; other values are refused.  It needs no device
+    memory of its own."""
+    assert irk.irk_default_options().lane_threads == 1
+    nl = irk.make_operator(irk.OP_NLDIFF_2D, 64)
+    assert irk.irk_workspace_bytes("gauss", 5, nl, irk.make_options(lane_threads=2)) == 0
+    sizes = [irk.irk_workspace_bytes("gauss", 5, nl, irk.make_options(lane_threads=t)) for t in (0, 1)]
+    assert sizes[0] == sizes[1] > 0
