@@ -206,6 +206,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
                      ? P->tsz : 0;
     P->fft_psi = P->fft_tsz > 0;
     static_assert(2 * 2048 <= IRK_RED_BLOCKS * 32, "the spectral solve's row sums use a lane's partials");
+    static_assert(IRK_LANE_PARTIALS >= IRK_RED_BLOCKS * 32, "a lane's partials hold every reduction's");
     if (o.kind == IRK_OP_VSF_2D && !P->fft_psi)
         for (int l = 1; l <= P->l0 && l < P->lg.nlev; ++l)
             if (P->lg.nx[l] <= IRK_FDM_MAX && P->lg.nx[l] % 4 == 0 && P->lg.nx[l] == P->lg.ny[l]) {
@@ -305,7 +306,7 @@ static irk_status make_plan(int family, int s, const irk_operator *op, const irk
         ln.ldv = (size_t)P->eb.width[b] * P->nf;
         ln.V = take((size_t)(P->m + 1) * ln.ldv * f64);
         ln.Z = take((size_t)P->m * ln.ldv * f64);
-        ln.part = take((size_t)IRK_RED_BLOCKS * 32 * f64);
+        ln.part = take((size_t)IRK_LANE_PARTIALS * f64);
         ln.dv = take(512 * f64);
         ln.tmp = (P->weighted && P->opt.newton_like == 3 && P->eb.width[b] == 2) ? take(P->nf * f64) : 0;
         ln.spec = spec_bytes ? take(spec_bytes) : 0;

@@ -10,6 +10,8 @@
 #define IRK_MAX_LEVELS 14
 #define IRK_WG 256
 #define IRK_RED_BLOCKS 512   // work-groups of the reduction kernels
+#define IRK_MATVEC_DOT_BLOCKS 2048   // of the matvec fused with a projection (a stencil needs more waves)
+#define IRK_LANE_PARTIALS (IRK_MATVEC_DOT_BLOCKS * 16)   // doubles of a lane's partial sums
 
 namespace irk {
 

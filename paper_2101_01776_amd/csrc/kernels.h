@@ -52,7 +52,8 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, cons
                          const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans);
 // The same matvec fused with the first Gram-Schmidt pass: out[k] = (V_k, w)
 // for k < nv (basis vectors at stride ldv), through per-work-group partials
-// and their reduction; false (nothing launched) when nv > 16
+// (up to IRK_MATVEC_DOT_BLOCKS work-groups: partials holds IRK_LANE_PARTIALS
+// values) and their reduction; false (nothing launched) when nv > 16
 bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, const BlockLam &lam, double dt,
                              const double *Ua, const double *Ub, const double *x, double *w, const double *xmeans,
                              const double *V, size_t ldv, int nv, double *partials, double *out,

@@ -34,6 +34,19 @@ __device__ __forceinline__ int xcd_block() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// (i, j) of point p of an nx-wide grid, by 32-bit division where p fits
+// (64-bit integer division is a long instruction sequence on the GPU)
+__device__ __forceinline__ void point_ij(size_t p, int nx, int &i, int &j) {
+    if (p <= 0xffffffffu) {
+        const unsigned q = (unsigned)p / (unsigned)nx;
+        i = (int)((unsigned)p - q * (unsigned)nx);
+        j = (int)q;
+    } else {
+        i = (int)(p % nx);
+        j = (int)(p / nx);
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -252,7 +265,8 @@ __global__ void __launch_bounds__(IRK_WG) k_residual(DeviceProblem P, const doub
     for (int st = 0; st < S; ++st) gmax[st] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
+        int i, j;
+        point_ij(p, nx, i, j);
         double F[S][NV];
 #pragma unroll
         for (int st = 0; st < S; ++st) {
@@ -461,7 +475,8 @@ __global__ void __launch_bounds__(IRK_WG) k_rhs_init(DeviceProblem P, const doub
     const double h = P.g.h, inv_h2 = 1.0 / (h * h);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
+        int i, j;
+        point_ij(p, nx, i, j);
         double N;
         if constexpr (OP == IRK_OP_NLDIFF_2D) {
             const int ip = wrapm(i + 1, nx), im = wrapm(i - 1, nx), jp = wrapm(j + 1, ny), jm = wrapm(j - 1, ny);
@@ -606,7 +621,8 @@ __device__ __forceinline__ void block_matvec_point(const DeviceProblem &P, int w
     constexpr int NV = (OP == IRK_OP_VSF_2D) ? 2 : 1;
     const size_t nf = NV * npts;
     const double h = P.g.h, inv_h2 = 1.0 / (h * h);
-    const int i = (int)(p % nx), j = (int)(p / nx);
+    int i, j;
+    point_ij(p, nx, i, j);
     double Lx[2], xc[2];
     for (int comp = 0; comp < width; ++comp) {
         const double *Uc = comp == 0 ? Ua : Ub;
@@ -651,6 +667,88 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec(DeviceProblem P, int wi
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
         double wv[4];
         block_matvec_point<OP>(P, width, lam, dt, Ua, Ub, x, w, xmeans, p, wv);
+    }
+}
+
+// The DAE's eigen-block matvec over 64 x 4 tiles: a work-group stages, for
+// each component, the linearization's streamfunction and both variables of
+// x over its tile and a one-cell halo (periodic wrap) in LDS, then every
+// thread evaluates its point from there -- its 3x3 neighbourhoods come from
+// LDS instead of three times nine loads through the caches.  The arithmetic
+// is block_matvec_point's (arakawa9, lap5, the 5-point Laplacian).
+constexpr int VM_TX = 64, VM_TY = IRK_WG / VM_TX;
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec_vsf(DeviceProblem P, int width, BlockLam lam, double dt,
+                                                             const double *__restrict__ Ua,
+                                                             const double *__restrict__ Ub,
+                                                             const double *__restrict__ x, double *__restrict__ w,
+                                                             const double *__restrict__ xmeans) {
+    constexpr int HX = VM_TX + 2, HY = VM_TY + 2, HN = HX * HY, PT = (HN + IRK_WG - 1) / IRK_WG;
+    __shared__ double sp[2][HN], so[2][HN], sq[2][HN];
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny, nf = 2 * npts;
+    const int tiles_x = (nx + VM_TX - 1) / VM_TX;
+    const int t = xcd_block();
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int i0 = tx * VM_TX, j0 = ty * VM_TY;
+    for (int comp = 0; comp < width; ++comp) {
+        const double *Psi = (comp == 0 ? Ua : Ub) + npts;
+        const double *xo = x + comp * nf, *xp = xo + npts;
+        double vp[PT], vo[PT], vq[PT];
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int q = u * IRK_WG + (int)threadIdx.x;
+            if (q < HN) {
+                const int hj = q / HX, hi = q - hj * HX;
+                int gi = i0 - 1 + hi, gj = j0 - 1 + hj;
+                gi = gi < 0 ? gi + nx : (gi >= nx ? gi % nx : gi);
+                gj = gj < 0 ? gj + ny : (gj >= ny ? gj % ny : gj);
+                const size_t e = (size_t)gj * nx + gi;
+                vp[u] = Psi[e];
+                vo[u] = xo[e];
+                vq[u] = xp[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int q = u * IRK_WG + (int)threadIdx.x;
+            if (q < HN) {
+                sp[comp][q] = vp[u];
+                so[comp][q] = vo[u];
+                sq[comp][q] = vq[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int li = (int)threadIdx.x % VM_TX, lj = (int)threadIdx.x / VM_TX;
+    const int gi = i0 + li, gj = j0 + lj;
+    if (gi >= nx || gj >= ny) return;
+    const size_t p = (size_t)gj * nx + gi;
+    const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+    double Lx[2], xc[2];
+    for (int comp = 0; comp < width; ++comp) {
+        double pp[3][3], ww[3][3];
+#pragma unroll
+        for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+            for (int di = 0; di < 3; ++di) {
+                pp[dj][di] = sp[comp][(lj + dj) * HX + li + di];
+                ww[dj][di] = so[comp][(lj + dj) * HX + li + di];
+            }
+        Lx[comp] = arakawa9(pp, ww, inv_h2 / 12.0) + P.g.nu * lap5(ww, inv_h2);
+        xc[comp] = ww[1][1];
+    }
+    if (width == 1) {
+        w[p] = lam.eta * xc[0] - dt * Lx[0];
+    } else {
+        w[p] = lam.eta * xc[0] + lam.c12 * xc[1] - dt * Lx[0];
+        w[nf + p] = lam.c21 * xc[0] + lam.eta * xc[1] - dt * Lx[1];
+    }
+    for (int comp = 0; comp < width; ++comp) {
+        const double *q = sq[comp];
+        const int c0 = (lj + 1) * HX + li + 1;
+        const double lp = (q[c0 + 1] + q[c0 - 1] + q[c0 + HX] + q[c0 - HX] - 4.0 * q[c0]) * inv_h2;
+        const double mw = xmeans[2 * comp], mp = xmeans[2 * comp + 1];
+        w[comp * nf + npts + p] = -dt * ((xc[comp] - mw) + lp - mp);
     }
 }
 
@@ -715,7 +813,8 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_w(DeviceProblem P, int 
     const int nin = coupling ? 1 : width;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
+        int i, j;
+        point_ij(p, nx, i, j);
         double acc[2] = {0.0, 0.0}, xc[2] = {0.0, 0.0};
         for (int b = 0; b < nin; ++b) {
             const double *xx = x + b * nf;
@@ -772,7 +871,8 @@ __global__ void __launch_bounds__(IRK_WG) k_block_couple(DeviceProblem P, BlockC
     const double h = P.g.h, inv_h2 = 1.0 / (h * h);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)xcd_block() * blockDim.x + threadIdx.x; p < nf; p += stride) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
+        int i, j;
+        point_ij(p, nx, i, j);
         double acc[2] = {0.0, 0.0};
         for (int b = 0; b < C.wj; ++b) {
             const double *yb = y + b * nf;
@@ -981,7 +1081,8 @@ __global__ void __launch_bounds__(IRK_WG) k_mg_coef_restrict_multi(int nxf, int 
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const T wgt[3] = {T(0.25), T(0.5), T(0.25)};
     for (size_t q = (size_t)xcd_block() * blockDim.x + threadIdx.x; q < npc; q += stride) {
-        const int I = (int)(q % nxc), J = (int)(q / nxc);
+        int I, J;
+        point_ij(q, nxc, I, J);
         T acc = 0;
         if (nyf == 1) {
             for (int a = -1; a <= 1; ++a) acc += wgt[a + 1] * cf[wrapm(2 * I + a, nxf)];
@@ -1295,7 +1396,7 @@ bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, 
                              const double *V, size_t ldv, int nv, double *partials, double *out, double *hout) {
     if (nv < 1 || nv > DOT_CHUNK) return false;
     const size_t npts = (size_t)P.g.nx * P.g.ny;
-    const unsigned g = grid_for(npts, IRK_RED_BLOCKS);
+    const unsigned g = grid_for(npts, IRK_MATVEC_DOT_BLOCKS);    // partials: g * nv <= IRK_LANE_PARTIALS
     if (P.kind == IRK_OP_NLDIFF_2D)
         block_matvec_dot_nv<IRK_OP_NLDIFF_2D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
     else if (P.kind == IRK_OP_BURGERS_1D)
@@ -1314,8 +1415,10 @@ void launch_block_matvec(hipStream_t st, const DeviceProblem &P, int width, cons
         k_block_matvec<IRK_OP_NLDIFF_2D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
     else if (P.kind == IRK_OP_BURGERS_1D)
         k_block_matvec<IRK_OP_BURGERS_1D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
-    else
-        k_block_matvec<IRK_OP_VSF_2D><<<g, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
+    else {
+        const unsigned tiles = (unsigned)(((P.g.nx + VM_TX - 1) / VM_TX) * ((P.g.ny + VM_TY - 1) / VM_TY));
+        k_block_matvec_vsf<<<tiles, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, xmeans);
+    }
 }
 
 template <int OP>
