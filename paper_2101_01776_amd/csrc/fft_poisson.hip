@@ -35,6 +35,13 @@ namespace {
 constexpr int FFT_NT = 256;
 constexpr size_t FFT_LDS_MAX = 64 * 1024;
 
+// The vectors in LDS carry one padding slot per 2^FFT_PAD values: index i
+// lives at pidx(i).  The radix-4 passes write with strides 4, 16, ... and
+// without it several lanes of a wave hit one LDS bank (up to 16-way).
+constexpr int FFT_PAD = 4;
+__host__ __device__ constexpr int padded(int n) { return n + (n >> FFT_PAD); }
+__device__ __forceinline__ int pidx(int i) { return i + (i >> FFT_PAD); }
+
 template <class T>
 struct cx {
     T re, im;
@@ -60,10 +67,10 @@ int log2_exact(int n) {
 }
 
 // LDS bytes of a row work-group (one row pair: a complex vector and its
-// ping-pong copy) with the n twiddles, and of a column work-group (one
-// column, its copy, the twiddles, the n eigenvalues)
-size_t row_lds(int n, size_t tsz) { return (3 * (size_t)n) * 2 * tsz; }
-size_t col_lds(int n, size_t tsz) { return (3 * (size_t)n) * 2 * tsz + n * tsz; }
+// ping-pong copy, padded) with the n - 1 stage twiddles, and of a column
+// work-group (one column, its copy, the twiddles, the n eigenvalues)
+size_t row_lds(int n, size_t tsz) { return (2 * (size_t)padded(n) + n) * 2 * tsz; }
+size_t col_lds(int n, size_t tsz) { return row_lds(n, tsz) + n * tsz; }
 
 // XCD-aware work-group order: consecutive logical indices on one XCD (work
 // groups are dealt to the 8 XCDs round-robin; neighbours share cache lines
@@ -106,13 +113,14 @@ bool fft_poisson_supported(int n, size_t tsz) {
 size_t fft_poisson_spectrum_values(int n) { return (size_t)2 * n * (n / 2 + 1); }
 
 // Mixed radix-4/2 Stockham transform (self-sorting: natural order in and
-// out) of one vector of length N = 2^LG in X; Y is the ping-pong buffer, tw
-// the N twiddles w^j = exp(-2 pi i j / N).  A stage of radix r (4 while
-// N / Ns >= 4, a last radix-2 stage for odd LG) and span Ns takes
-// x[j + q N/r], q < r, times w^(q k N / (r Ns)) with k = j mod Ns, through an
-// r-point DFT into y[(j - k) r + k + q Ns].  INV: conjugate twiddles and DFTs
-// (unnormalized inverse).  The size is a template parameter: every stage
-// and thread loop is unrolled.  Returns the buffer holding the result.
+// out) of one vector of length N = 2^LG in X (padded: value i at pidx(i));
+// Y is the ping-pong buffer, tw the stage twiddle table (load_twiddles).  A
+// stage of radix r (4 while N / Ns >= 4, a last radix-2 stage for odd LG)
+// and span Ns takes x[j + q N/r], q < r, times w^(q k N / (r Ns)) with
+// k = j mod Ns and w = exp(-2 pi i / N), through an r-point DFT into
+// y[(j - k) r + k + q Ns].  INV: conjugate twiddles and DFTs (unnormalized
+// inverse).  The size is a template parameter: every stage and thread loop
+// is unrolled.  Returns the buffer holding the result.
 template <class T, bool INV, int LG>
 __device__ __forceinline__ cx<T> *fft_lds(cx<T> *X, cx<T> *Y, const cx<T> *tw) {
     constexpr int N = 1 << LG;
@@ -121,7 +129,6 @@ __device__ __forceinline__ cx<T> *fft_lds(cx<T> *X, cx<T> *Y, const cx<T> *tw) {
         const bool r4 = LG - lgNs >= 2;
         const int lgr = r4 ? 2 : 1;
         const int lgm = LG - lgr, m = 1 << lgm;          // butterflies
-        const int lgstep = LG - lgr - lgNs;              // twiddle step N / (r Ns)
         const int Ns = 1 << lgNs;
 #pragma unroll
         for (int t0 = 0; t0 < m; t0 += FFT_NT) {
@@ -130,26 +137,26 @@ __device__ __forceinline__ cx<T> *fft_lds(cx<T> *X, cx<T> *Y, const cx<T> *tw) {
                 const int k = j & (Ns - 1);
                 const int base = ((j - k) << lgr) + k;
                 auto twq = [&](int q) {
-                    cx<T> w = tw[(q * k) << lgstep];
+                    cx<T> w = tw[(Ns - 1) + (q - 1) * Ns + k];
                     if (INV) w.im = -w.im;
                     return w;
                 };
                 if (r4) {
-                    cx<T> a0 = X[j], a1 = X[j + m], a2 = X[j + 2 * m], a3 = X[j + 3 * m];
+                    cx<T> a0 = X[pidx(j)], a1 = X[pidx(j + m)], a2 = X[pidx(j + 2 * m)], a3 = X[pidx(j + 3 * m)];
                     a1 = cmul(a1, twq(1));
                     a2 = cmul(a2, twq(2));
                     a3 = cmul(a3, twq(3));
                     const cx<T> s0 = cadd(a0, a2), s1 = csub(a0, a2), s2 = cadd(a1, a3), s3 = csub(a1, a3);
                     // forward: y1 = s1 - i s3, y3 = s1 + i s3 (inverse: swapped)
                     const cx<T> mi = {s3.im, -s3.re};
-                    Y[base] = cadd(s0, s2);
-                    Y[base + Ns] = INV ? csub(s1, mi) : cadd(s1, mi);
-                    Y[base + 2 * Ns] = csub(s0, s2);
-                    Y[base + 3 * Ns] = INV ? cadd(s1, mi) : csub(s1, mi);
+                    Y[pidx(base)] = cadd(s0, s2);
+                    Y[pidx(base + Ns)] = INV ? csub(s1, mi) : cadd(s1, mi);
+                    Y[pidx(base + 2 * Ns)] = csub(s0, s2);
+                    Y[pidx(base + 3 * Ns)] = INV ? cadd(s1, mi) : csub(s1, mi);
                 } else {
-                    cx<T> a0 = X[j], a1 = cmul(X[j + m], twq(1));
-                    Y[base] = cadd(a0, a1);
-                    Y[base + Ns] = csub(a0, a1);
+                    cx<T> a0 = X[pidx(j)], a1 = cmul(X[pidx(j + m)], twq(1));
+                    Y[pidx(base)] = cadd(a0, a1);
+                    Y[pidx(base + Ns)] = csub(a0, a1);
                 }
             }
         }
@@ -162,12 +169,25 @@ __device__ __forceinline__ cx<T> *fft_lds(cx<T> *X, cx<T> *Y, const cx<T> *tw) {
     return X;
 }
 
+// The stage twiddle table in LDS: stage span Ns (the radix-4 stages' spans
+// are powers of 4, and so is the last radix-2 stage's for odd LG) keeps
+// w^((q k) N / (r Ns)) for q = 1 .. r - 1, k < Ns at (Ns - 1) + (q - 1) Ns + k
+// -- consecutive in k, so a stage's lanes read consecutive entries -- n - 1
+// values in all, gathered from the n natural twiddles twg (w^j as (re, im)).
 template <class T, int N>
 __device__ __forceinline__ void load_twiddles(const T *__restrict__ twg, cx<T> *tw) {
+    constexpr int LG = __builtin_ctz(N);
 #pragma unroll
-    for (int j0 = 0; j0 < N; j0 += FFT_NT) {
-        const int j = j0 + (int)threadIdx.x;
-        if (N % FFT_NT == 0 || j < N) tw[j] = {twg[2 * j], twg[2 * j + 1]};
+    for (int e0 = 0; e0 < N - 1; e0 += FFT_NT) {
+        const int e = e0 + (int)threadIdx.x;
+        if (e < N - 1) {
+            const int v = e + 1;
+            const int lgNs = (31 - __builtin_clz(v)) & ~1;
+            const int lgr = ((LG & 1) && lgNs == LG - 1) ? 1 : 2;
+            const int q = v >> lgNs, k = v - (q << lgNs);
+            const int idx = (q * k) << (LG - lgr - lgNs);
+            tw[e] = {twg[2 * idx], twg[2 * idx + 1]};
+        }
     }
 }
 
@@ -180,8 +200,8 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ t
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[4 * (FFT_NT / 64)];
     cx<T> *X = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *Y = X + N;
-    cx<T> *tw = Y + N;
+    cx<T> *Y = X + padded(N);
+    cx<T> *tw = Y + padded(N);
     const size_t r0 = 2 * (size_t)xcd_order();
     // rows r0, r0 + 1 of v1 and v2 (every global load in flight before the
     // first is used), their sums in float64, and q = a1 v1 + a2 v2 less the
@@ -229,14 +249,14 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_fwd(const T *__restrict__ t
     for (int u = 0; u < PT; ++u) {
         const int j = u * FFT_NT + (int)threadIdx.x;
         if (N % FFT_NT == 0 || j < N)
-            X[j] = {(T)(in.a1 * qa[u] + in.a2 * va[u] - ma), (T)(in.a1 * qb[u] + in.a2 * vb[u] - mb)};
+            X[pidx(j)] = {(T)(in.a1 * qa[u] + in.a2 * va[u] - ma), (T)(in.a1 * qb[u] + in.a2 * vb[u] - mb)};
     }
     __syncthreads();
     const cx<T> *R = fft_lds<T, false, LG>(X, Y, tw);
     // Z = FFT(q_a + i q_b): Q_a,k = (Z_k + conj Z_{n-k}) / 2,
     // Q_b,k = -i (Z_k - conj Z_{n-k}) / 2, stored side by side
     for (int k = threadIdx.x; k <= HALF; k += FFT_NT) {
-        const cx<T> z = R[k], zr = R[(N - k) & (N - 1)];
+        const cx<T> z = R[pidx(k)], zr = R[pidx((N - k) & (N - 1))];
         cx<T> *dst = spec + (size_t)k * N + r0;
         dst[0] = {T(0.5) * (z.re + zr.re), T(0.5) * (z.im - zr.im)};
         dst[1] = {T(0.5) * (z.im + zr.im), T(0.5) * (zr.re - z.re)};
@@ -249,8 +269,8 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
     constexpr int N = 1 << LG, PT = (N + FFT_NT - 1) / FFT_NT;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *X = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *Y = X + N;
-    cx<T> *tw = Y + N;
+    cx<T> *Y = X + padded(N);
+    cx<T> *tw = Y + padded(N);
     T *lam = reinterpret_cast<T *>(tw + N);
     const int k = blockIdx.x;                     // mode of the column, 0..n/2
     cx<T> *col = spec + (size_t)k * N;
@@ -300,7 +320,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
     for (int u = 0; u < PT; ++u) {
         const int r = u * FFT_NT + (int)threadIdx.x;
         if (N % FFT_NT == 0 || r < N) {
-            X[r] = v[u];
+            X[pidx(r)] = v[u];
             lam[r] = lv[u];
         }
     }
@@ -316,7 +336,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
         const int a = u * FFT_NT + (int)threadIdx.x;
         if (N % FFT_NT == 0 || a < N) {
             const T s = (a == 0 && k == 0) ? T(0) : inv_n2 / (dt * (lam[a] + lk));
-            R[a] = {R[a].re * s, R[a].im * s};
+            R[pidx(a)] = {R[pidx(a)].re * s, R[pidx(a)].im * s};
         }
     }
     __syncthreads();
@@ -324,7 +344,7 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_cols(const T *__restrict__ twg, 
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
         const int r = u * FFT_NT + (int)threadIdx.x;
-        if (N % FFT_NT == 0 || r < N) col[r] = R[r];
+        if (N % FFT_NT == 0 || r < N) col[r] = R[pidx(r)];
     }
 }
 
@@ -335,8 +355,8 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ t
     constexpr int PH = (HALF + 1 + FFT_NT - 1) / FFT_NT;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *X = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *Y = X + N;
-    cx<T> *tw = Y + N;
+    cx<T> *Y = X + padded(N);
+    cx<T> *tw = Y + padded(N);
     const size_t r0 = 2 * (size_t)xcd_order();
     // the full spectra of rows r0, r0 + 1 (X_{n-k} = conj X_k), packed
     // X + i Y: a loaded mode k fills entries k and n - k
@@ -354,8 +374,8 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ t
         const int k = u * FFT_NT + (int)threadIdx.x;
         if (k <= HALF) {
             const cx<T> a = ha[u], b = hb[u];
-            X[k] = {a.re - b.im, a.im + b.re};
-            if (k > 0 && k < HALF) X[N - k] = {a.re + b.im, b.re - a.im};
+            X[pidx(k)] = {a.re - b.im, a.im + b.re};
+            if (k > 0 && k < HALF) X[pidx(N - k)] = {a.re + b.im, b.re - a.im};
         }
     }
     __syncthreads();
@@ -366,8 +386,8 @@ __global__ void __launch_bounds__(FFT_NT) k_fft_rows_inv(const T *__restrict__ t
     for (int u = 0; u < PT; ++u) {
         const int j = u * FFT_NT + (int)threadIdx.x;
         if (N % FFT_NT == 0 || j < N) {
-            z[j] = (double)R[j].re + shift;
-            z[N + j] = (double)R[j].im + shift;
+            z[j] = (double)R[pidx(j)].re + shift;
+            z[N + j] = (double)R[pidx(j)].im + shift;
         }
     }
 }
