@@ -388,7 +388,7 @@ struct CtxRes {
     hipStream_t lane_st[IRK_MAX_STAGES] = {}, aux_st[IRK_MAX_STAGES] = {};
     hipEvent_t ev[IRK_MAX_STAGES] = {}, done[IRK_MAX_STAGES] = {}, prec[IRK_MAX_STAGES] = {};
     hipEvent_t fork[IRK_MAX_STAGES] = {}, join[IRK_MAX_STAGES] = {};
-    hipEvent_t ev_main = nullptr, ev_res = nullptr;
+    hipEvent_t ev_main = nullptr, ev_res = nullptr, ev_coef = nullptr;
     double *pinned = nullptr;                        // readback/upload staging, then the upload area
     double *pinned_dev = nullptr;                    // pinned as a device address
     size_t upload = 0;                               // doubles of the upload area
@@ -407,6 +407,7 @@ struct irk_ctx {
     bool res_owned = false;              // made by irk_create (else a server slot's)
     hipEvent_t ev_main = nullptr;       // Newton level -> lanes
     hipEvent_t ev_res = nullptr;        // Newton-level readbacks
+    hipEvent_t ev_coef = nullptr;       // the Newton iteration's coefficient hierarchies -> V-cycles
     StepperBase *stepper = nullptr;
     LaneWorkers *workers = nullptr;      // host threads of the eigen-block lanes (lane_threads)
     // V-cycle batching: a broker of the context's precision (PrecBroker<T>),
@@ -1104,6 +1105,7 @@ struct Fgmres {
     int mode = 0;
     bool beta0_set = false;
     double *pend_v = nullptr, *pend_z = nullptr;    // preconditioner input/output waiting in a broker
+    hipEvent_t prec_wait = nullptr;                  // waited on before the first preconditioner application
     irk_status deferred = IRK_OK;                    // error raised while resumed by a broker
 
     void init(irk_ctx *cc, Lane *l, double rt, int mx) {
@@ -1128,6 +1130,7 @@ struct Fgmres {
         beta0 = 0.0;
         beta0_set = false;
         mode = (P.op.kind == IRK_OP_VSF_2D && P.opt.dae_reorder) ? 1 : 0;
+        prec_wait = nullptr;
     }
 
     // after the vorticity solve of the reordered system: the streamfunction
@@ -1184,6 +1187,12 @@ struct Fgmres {
     // With a broker the preconditioner waits for a shared V-cycle batch.
     irk_status issue_iteration() {
         double *vj = Vv(j), *zj = Zv(j);
+        if (prec_wait) {
+            // the V-cycles read the coefficient hierarchies, which the Newton
+            // level builds while the solve's first sweeps run
+            if (hipStreamWaitEvent(ln->stream, prec_wait, 0) != hipSuccess) return IRK_E_DEVICE;
+            prec_wait = nullptr;
+        }
         if (c->broker && c->P.op.kind != IRK_OP_VSF_2D) {
             pend_v = vj;
             pend_z = zj;
@@ -1547,6 +1556,7 @@ struct Stepper : StepperBase {
     bool lane_started[IRK_MAX_STAGES];
     // this Newton iteration's block solves run on the lanes' host threads
     bool threaded = false;
+    hipEvent_t coef_wait = nullptr;      // the hierarchies' event the solves' V-cycles wait on
     irk_status lane_err[IRK_MAX_STAGES];
     double block_ktol = 1e-5;
 
@@ -1763,8 +1773,15 @@ struct Stepper : StepperBase {
                 c->hier_g[h] = g;
                 if (!std::isfinite(g)) c->hier_g_valid = false;
             }
+        // the block solves start (||r0||, the first basis vector) as soon as
+        // the residual is in; only their V-cycles wait for the coefficient
+        // hierarchies built meanwhile (with shared V-cycle batches, which run
+        // on other streams, everything waits as before)
+        const bool split = !c->broker;
+        if (split && hipEventRecord(c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
         setup_hierarchies<T>(c);
-        if (hipEventRecord(c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
+        if (hipEventRecord(split ? c->ev_coef : c->ev_main, c->stream) != hipSuccess) return fail(IRK_E_DEVICE);
+        coef_wait = split ? c->ev_coef : nullptr;
         active = c->nlanes;
         // relative Krylov tolerance of the block solves: the fixed one, or
         // (krylov_adaptive) never tighter than a tenth of the reduction the
@@ -1784,6 +1801,7 @@ struct Stepper : StepperBase {
                 lane_started[b] = true;
                 lane_err[b] = IRK_OK;
                 fg[b].init(c, &c->lanes[b], block_ktol, c->P.opt.max_krylov);
+                fg[b].prec_wait = coef_wait;
                 c->workers->request(b);
                 continue;
             }
@@ -1818,6 +1836,7 @@ struct Stepper : StepperBase {
     irk_status start_block(int b) {
         lane_started[b] = true;
         fg[b].init(c, &c->lanes[b], block_ktol, c->P.opt.max_krylov);
+        fg[b].prec_wait = coef_wait;
         return fg[b].start();
     }
 
@@ -2117,7 +2136,7 @@ static irk_status res_create(CtxRes *r, int nlanes, size_t upload) {
     }
     if (hipHostGetDevicePointer((void **)&r->pinned_dev, r->pinned, 0) != hipSuccess) return IRK_E_DEVICE;
     auto ev = [](hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess; };
-    if (!ev(&r->ev_main) || !ev(&r->ev_res)) return IRK_E_DEVICE;
+    if (!ev(&r->ev_main) || !ev(&r->ev_res) || !ev(&r->ev_coef)) return IRK_E_DEVICE;
     for (int b = 0; b < nlanes; ++b) {
         if (hipStreamCreateWithFlags(&r->lane_st[b], hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&r->aux_st[b], hipStreamNonBlocking) != hipSuccess || !ev(&r->ev[b]) ||
@@ -2140,6 +2159,7 @@ static void res_destroy(CtxRes *r) {
             if (e) (void)hipEventDestroy(e);
     }
     if (r->ev_main) (void)hipEventDestroy(r->ev_main);
+    if (r->ev_coef) (void)hipEventDestroy(r->ev_coef);
     if (r->ev_res) (void)hipEventDestroy(r->ev_res);
     if (r->pinned) (void)hipHostFree(r->pinned);
     *r = CtxRes();
@@ -2340,6 +2360,7 @@ static irk_status ctx_init(irk_ctx *c, hipStream_t stream, CtxRes *r, bool wait,
     c->pinned = r->pinned;
     c->pinned_dev = r->pinned_dev;
     c->ev_main = r->ev_main;
+    c->ev_coef = r->ev_coef;
     c->ev_res = r->ev_res;
     if (P.sd_s > 0) {
         if (P.opt.prec_fp32) c->stepper = new (std::nothrow) SdirkStepper<float>(c);
