@@ -790,6 +790,104 @@ __global__ void __launch_bounds__(IRK_WG) k_block_matvec_dot(DeviceProblem P, in
     finish_multi<NVMAX + 1>(mine, nv, partials);
 }
 
+// The nonlinear-diffusion matvec fused with the first Gram-Schmidt pass over
+// 64 x 4 tiles: each component's linearization field U and x over the tile
+// and its one-cell halo (periodic wrap) staged in LDS, the point's 5-point
+// stencils read from there (nldiff_lin's arithmetic), then the partial sums
+// of (V_k, w), k < nv <= NVMAX, one per work-group and k.
+template <int NVMAX>
+__global__ void __launch_bounds__(IRK_WG) k_block_matvec_dot_nl(DeviceProblem P, int width, BlockLam lam,
+                                                                double dt, const double *__restrict__ Ua,
+                                                                const double *__restrict__ Ub,
+                                                                const double *__restrict__ x,
+                                                                double *__restrict__ w,
+                                                                const double *__restrict__ V, size_t ldv, int nv,
+                                                                double *partials) {
+    constexpr int HX = VM_TX + 2, HY = VM_TY + 2, HN = HX * HY, PT = (HN + IRK_WG - 1) / IRK_WG;
+    __shared__ double su[2][HN], sx[2][HN];
+    const int nx = P.g.nx, ny = P.g.ny;
+    const size_t npts = (size_t)nx * ny;
+    const int tiles_x = (nx + VM_TX - 1) / VM_TX;
+    const int t = xcd_block();
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int i0 = tx * VM_TX, j0 = ty * VM_TY;
+    for (int comp = 0; comp < width; ++comp) {
+        const double *Uc = comp == 0 ? Ua : Ub;
+        const double *xc = x + comp * npts;
+        double vu[PT], vx[PT];
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int q = u * IRK_WG + (int)threadIdx.x;
+            if (q < HN) {
+                const int hj = q / HX, hi = q - hj * HX;
+                int gi = i0 - 1 + hi, gj = j0 - 1 + hj;
+                gi = gi < 0 ? gi + nx : (gi >= nx ? gi % nx : gi);
+                gj = gj < 0 ? gj + ny : (gj >= ny ? gj % ny : gj);
+                const size_t e = (size_t)gj * nx + gi;
+                vu[u] = Uc[e];
+                vx[u] = xc[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int q = u * IRK_WG + (int)threadIdx.x;
+            if (q < HN) {
+                su[comp][q] = vu[u];
+                sx[comp][q] = vx[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int li = (int)threadIdx.x % VM_TX, lj = (int)threadIdx.x / VM_TX;
+    const int gi = i0 + li, gj = j0 + lj;
+    double acc[NVMAX + 1];
+#pragma unroll
+    for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
+    if (gi < nx && gj < ny) {
+        const size_t p = (size_t)gj * nx + gi;
+        const double h = P.g.h, inv_h2 = 1.0 / (h * h);
+        const int c0 = (lj + 1) * HX + li + 1;
+        const int nb[4] = {c0 + 1, c0 - 1, c0 + HX, c0 - HX};     // e, w, n, s as nldiff_lin
+        double Lx[2], xcv[2], wv[2];
+        for (int comp = 0; comp < width; ++comp) {
+            const double uc = su[comp][c0], xcc = sx[comp][c0];
+            double lx = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double un = su[comp][nb[q]];
+                const double kf = 1.0 + 0.5 * (uc * uc + un * un);
+                const double du = un - uc;
+                const double xn = sx[comp][nb[q]];
+                lx += kf * (xn - xcc) + du * (uc * xcc + un * xn);
+            }
+            Lx[comp] = lx * inv_h2;
+            xcv[comp] = xcc;
+        }
+        if (width == 1) {
+            wv[0] = lam.eta * xcv[0] - dt * Lx[0];
+            w[p] = wv[0];
+        } else {
+            wv[0] = lam.eta * xcv[0] + lam.c12 * xcv[1] - dt * Lx[0];
+            wv[1] = lam.c21 * xcv[0] + lam.eta * xcv[1] - dt * Lx[1];
+            w[p] = wv[0];
+            w[npts + p] = wv[1];
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            if (f < width) {
+                const size_t e = (size_t)f * npts + p;
+#pragma unroll
+                for (int k = 0; k < NVMAX; ++k)
+                    if (k < nv) acc[k] += V[k * ldv + e] * wv[f];
+            }
+        }
+    }
+    __shared__ double shr[4 * (NVMAX + 1)];
+    double mine;
+    block_reduce_multi<NVMAX + 1>(acc, nv, false, shr, mine);
+    finish_multi<NVMAX + 1>(mine, nv, partials);
+}
+
 // Eigen-block operator with stage-weighted linearizations (Newton-like (2),
 // (3)): L_kb = L(U_k) x_b at the point for every stage k and component b,
 //   coupling = 0:  w_a = eta M x_a (+ c12 M x_1 | + c21 M x_0)
@@ -1396,6 +1494,23 @@ bool launch_block_matvec_dot(hipStream_t st, const DeviceProblem &P, int width, 
                              const double *V, size_t ldv, int nv, double *partials, double *out, double *hout) {
     if (nv < 1 || nv > DOT_CHUNK) return false;
     const size_t npts = (size_t)P.g.nx * P.g.ny;
+    if (P.kind == IRK_OP_NLDIFF_2D) {
+        // over LDS tiles while their partials (one per tile and basis vector) fit
+        const unsigned tiles = (unsigned)(((P.g.nx + VM_TX - 1) / VM_TX) * ((P.g.ny + VM_TY - 1) / VM_TY));
+        if ((size_t)tiles * nv <= IRK_LANE_PARTIALS) {
+            if (nv <= 4)
+                k_block_matvec_dot_nl<4><<<tiles, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, V, ldv, nv,
+                                                                   partials);
+            else if (nv <= 8)
+                k_block_matvec_dot_nl<8><<<tiles, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, V, ldv, nv,
+                                                                   partials);
+            else
+                k_block_matvec_dot_nl<DOT_CHUNK><<<tiles, IRK_WG, 0, st>>>(P, width, lam, dt, Ua, Ub, x, w, V, ldv,
+                                                                           nv, partials);
+            reduce_partials(st, partials, tiles, nv, out, 0, nullptr, hout);
+            return true;
+        }
+    }
     const unsigned g = grid_for(npts, IRK_MATVEC_DOT_BLOCKS);    // partials: g * nv <= IRK_LANE_PARTIALS
     if (P.kind == IRK_OP_NLDIFF_2D)
         block_matvec_dot_nv<IRK_OP_NLDIFF_2D>(st, g, P, width, lam, dt, Ua, Ub, x, w, xmeans, V, ldv, nv, partials);
