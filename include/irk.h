@@ -22,10 +22,15 @@
  *     memory.  All device pointers must be 8-byte aligned; the workspace
  *     256-byte aligned.
  *   - The caller owns every buffer it passes; the library owns only the
- *     context (host memory plus a small pinned host staging buffer).
- *   - All device work is issued on the HIP stream given to irk_create.
- *     Calls on one context must not overlap; distinct contexts may run
- *     concurrently on distinct streams.
+ *     context: host memory, a small pinned host staging buffer (fine-
+ *     grained and mapped: the reduction kernels write the scalars the host
+ *     reads there), the streams and events of its eigen-blocks and, with
+ *     the option lane_threads, one host thread per eigen-block.
+ *   - All device work is ordered with the HIP stream given to irk_create:
+ *     the eigen-blocks run on the context's own streams, which wait for
+ *     and are joined back into that stream through events.  Calls on one
+ *     context must not overlap; distinct contexts may run concurrently on
+ *     distinct streams.
  *
  * Field layout: a scalar field is row-major [ny][nx] float64, x fastest
  * (1-D problems have ny = 1).  The vorticity-streamfunction state is
@@ -33,9 +38,9 @@
  *
  * Mapping onto the proposed boundary (irk_create / irk_step / irk_destroy
  * plus a serving interface): the stages are always transformed into the
- * real eigenbasis of A0^{-1} (its blocks are independent, so they run
- * concurrently), so irk_options has no basis selector (the paper's real
- * Schur basis needs back-substitution between blocks); serving polls with
+ * real eigenbasis of A0^{-1} by default (its blocks are independent, so
+ * they run concurrently; irk_options.transform selects the paper's real
+ * Schur basis, solved by back-substitution between blocks); serving polls with
  * irk_server_progress (one pass for all requests) and reads a request's
  * state with irk_server_info, its result landing in the request's own
  * output buffer, instead of a per-request poll and result call.
